@@ -1,0 +1,206 @@
+"""CPU oracle for the batched Lorentz-vector path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check in ``__graft_entry__`` and the CPU-baseline
+leg of ``bench.py`` may import this package.  The GPU library never does, and
+this package imports nothing from it.
+
+Thin ctypes wrapper around ``liborc.so`` (built from ``glv_oracle.c`` by
+``oracle/build.py``).  Inputs are numpy arrays; FP32 inputs are widened to
+float64 first (exactly), so every result is the exact-input result computed
+in binary64 (or binary128 for the ``*_q`` functions).
+
+Coordinate codes: 0 = PxPyPzE, 1 = PtEtaPhiM, 2 = PtEtaPhiE.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+PXPYPZE, PTETAPHIM, PTETAPHIE = 0, 1, 2
+PLAIN, ACCURATE = 0, 1
+COORDS = {"PxPyPzE": PXPYPZE, "PtEtaPhiM": PTETAPHIM, "PtEtaPhiE": PTETAPHIE}
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = _build.library_path()
+        if not os.path.exists(path):
+            _build.build()
+        _lib = ctypes.CDLL(path)
+        _lib.orc_get_threads.restype = ctypes.c_int
+    return _lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _p(x):
+    return x.ctypes.data_as(ctypes.c_void_p) if x is not None else None
+
+
+def _coords(c):
+    return COORDS[c] if isinstance(c, str) else int(c)
+
+
+def set_threads(k: int) -> None:
+    _load().orc_set_threads(ctypes.c_int(int(k)))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+def to_cartesian(coords, cols):
+    c = [_f64(x) for x in cols]
+    n = c[0].size
+    out = [np.empty(n) for _ in range(4)]
+    _load().orc_to_cartesian(ctypes.c_int(_coords(coords)), ctypes.c_int64(n), *map(_p, c), *map(_p, out))
+    return tuple(out)
+
+
+def mass_plain(coords, a, b, scale=False):
+    """Pair mass by the definition (binary64); optionally S = E^2 + |P|^2."""
+    a = [_f64(x) for x in a]
+    b = [_f64(x) for x in b]
+    n = a[0].size
+    m = np.empty(n)
+    s = np.empty(n) if scale else None
+    _load().orc_mass_plain(ctypes.c_int(_coords(coords)), ctypes.c_int64(n), *map(_p, a), *map(_p, b), _p(m), _p(s))
+    return (m, s) if scale else m
+
+
+def mass_plain_q(coords, a, b, lo=False):
+    """Pair mass by the definition in binary128, rounded to binary64.
+    With ``lo=True`` also the rounding remainder (m + lo ~ 106 bits)."""
+    a = [_f64(x) for x in a]
+    b = [_f64(x) for x in b]
+    n = a[0].size
+    m = np.empty(n)
+    ml = np.empty(n) if lo else None
+    _load().orc_mass_plain_q(ctypes.c_int(_coords(coords)), ctypes.c_int64(n), *map(_p, a), *map(_p, b), _p(m),
+                             _p(ml))
+    return (m, ml) if lo else m
+
+
+def mass_accurate(a, b):
+    """Pair mass of PtEtaPhiM legs by the cancellation-free form (binary64)."""
+    a = [_f64(x) for x in a]
+    b = [_f64(x) for x in b]
+    n = a[0].size
+    m = np.empty(n)
+    _load().orc_mass_accurate(ctypes.c_int64(n), *map(_p, a), *map(_p, b), _p(m))
+    return m
+
+
+def _boost_call(fn, x, beta, beta_stride, extra=()):
+    x = [_f64(v) for v in x]
+    beta = [_f64(v) for v in beta]
+    n = x[0].size
+    if beta_stride == 1:
+        assert beta[0].size == n
+    out = [np.empty(n) for _ in range(4)]
+    fn(ctypes.c_int64(n), *map(_p, x), *map(_p, beta), ctypes.c_int64(beta_stride), *map(_p, out), *extra)
+    return tuple(out)
+
+
+def boost(x, beta, beta_stride=1):
+    return _boost_call(_load().orc_boost, x, beta, beta_stride)
+
+
+def boost_q(x, beta, beta_stride=1, lo=False):
+    """Boost in binary128; with ``lo=True`` also the rounding remainders."""
+    if not lo:
+        return _boost_call(_load().orc_boost_q, x, beta, beta_stride, (None,))
+    n = np.asarray(x[0]).size
+    rem = [np.empty(n) for _ in range(4)]
+    arr = (ctypes.c_void_p * 4)(*[r.ctypes.data for r in rem])
+    y = _boost_call(_load().orc_boost_q, x, beta, beta_stride, (arr,))
+    return y, tuple(rem)
+
+
+def boost_scale(x, beta, beta_stride=1):
+    return _boost_call(_load().orc_boost_scale, x, beta, beta_stride)
+
+
+def mass_vjp(coords, a, b, gm):
+    a = [_f64(x) for x in a]
+    b = [_f64(x) for x in b]
+    gm = _f64(gm)
+    n = a[0].size
+    ga = [np.empty(n) for _ in range(4)]
+    gb = [np.empty(n) for _ in range(4)]
+    _load().orc_mass_vjp(ctypes.c_int(_coords(coords)), ctypes.c_int64(n), *map(_p, a), *map(_p, b), _p(gm),
+                         *map(_p, ga), *map(_p, gb))
+    return tuple(ga), tuple(gb)
+
+
+def boost_vjp(x, beta, gy):
+    x = [_f64(v) for v in x]
+    beta = [_f64(v) for v in beta]
+    gy = [_f64(v) for v in gy]
+    n = x[0].size
+    gx = [np.empty(n) for _ in range(4)]
+    gbeta = [np.empty(n) for _ in range(3)]
+    _load().orc_boost_vjp(ctypes.c_int64(n), *map(_p, x), *map(_p, beta), *map(_p, gy), *map(_p, gx),
+                          *map(_p, gbeta))
+    return tuple(gx), tuple(gbeta)
+
+
+def _i64(x):
+    return np.ascontiguousarray(x, dtype=np.int64)
+
+
+def pair_offsets(offsets):
+    offsets = _i64(offsets)
+    ne = offsets.size - 1
+    po = np.empty(ne + 1, dtype=np.int64)
+    _load().orc_pair_offsets(ctypes.c_int64(ne), _p(offsets), _p(po))
+    return po
+
+
+def event_reduce(coords, offsets, p, mode=PLAIN):
+    """Returns (total (4 arrays), event_m, pair_m, pair_offsets)."""
+    offsets = _i64(offsets)
+    p = [_f64(x) for x in p]
+    ne = offsets.size - 1
+    po = pair_offsets(offsets)
+    tot = [np.empty(ne) for _ in range(4)]
+    em = np.empty(ne)
+    pm = np.empty(int(po[-1]))
+    _load().orc_event_reduce(ctypes.c_int(_coords(coords)), ctypes.c_int(int(mode)), ctypes.c_int64(ne),
+                             _p(offsets), _p(po), *map(_p, p), *map(_p, tot), _p(em), _p(pm))
+    return tuple(tot), em, pm, po
+
+
+def event_reduce_q(coords, offsets, p):
+    """Totals and event masses of the plain definition in binary128."""
+    offsets = _i64(offsets)
+    p = [_f64(x) for x in p]
+    ne = offsets.size - 1
+    tot = [np.empty(ne) for _ in range(4)]
+    em = np.empty(ne)
+    _load().orc_event_reduce_q(ctypes.c_int(_coords(coords)), ctypes.c_int64(ne), _p(offsets), *map(_p, p),
+                               *map(_p, tot), _p(em))
+    return tuple(tot), em
+
+
+def event_reduce_vjp(coords, offsets, p, g_total=None, g_em=None, g_pair=None):
+    offsets = _i64(offsets)
+    p = [_f64(x) for x in p]
+    ne = offsets.size - 1
+    po = pair_offsets(offsets)
+    gt = [None] * 4 if g_total is None else [_f64(x) for x in g_total]
+    gem = None if g_em is None else _f64(g_em)
+    gpr = None if g_pair is None else _f64(g_pair)
+    n = p[0].size
+    gp = [np.empty(n) for _ in range(4)]
+    _load().orc_event_reduce_vjp(ctypes.c_int(_coords(coords)), ctypes.c_int64(ne), _p(offsets), _p(po),
+                                 *map(_p, p), *map(_p, gt), _p(gem), _p(gpr), *map(_p, gp))
+    return tuple(gp)
