@@ -1,0 +1,217 @@
+/*
+ * glv.h -- C ABI of the batched Lorentz-vector library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library computes, over millions of independent items held as
+ * structure-of-arrays (SoA) columns in GPU memory,
+ *   - the invariant mass of pairs of 4-vectors given in any of three 4D
+ *     coordinate systems (GenVectorX, arXiv 2312.02756, Sec. 3.1 and Fig. 1:
+ *     m[i] = mass(v1[i] + v2[i]); coordinate systems Sec. 2.1),
+ *   - the Lorentz boost of Cartesian 4-vectors (Sec. 3.1, ApplyBoost: a 4D
+ *     Lorentz transformation held as a 4x4 matrix),
+ *   - a per-event reduction over jagged (CSR) events: each event's total
+ *     4-vector, its mass and the masses of all its particle pairs (the pair
+ *     mass of Fig. 1 applied inside every event),
+ * and the reverse-mode derivative (vector-Jacobian product, "_bwd") of each.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every data pointer is a DEVICE pointer owned by the caller.  The
+ *   library never allocates, frees or copies between host and device, and
+ *   never synchronises (except glv_autotune_event_reduce, which times kernels
+ *   and therefore waits for `stream`).  Each call validates its arguments on
+ *   the host without reading device memory, enqueues its kernels on `stream`
+ *   (a hipStream_t; NULL = the default stream) and returns.
+ * Layout.  A 4-vector column set is four separate contiguous arrays, one per
+ *   component, each of n elements of the call's dtype.  Component order:
+ *     GLV_PXPYPZE   (px, py, pz, E)
+ *     GLV_PTETAPHIM (pt, eta, phi, M)   E = sqrt((pt cosh eta)^2 + M^2)
+ *     GLV_PTETAPHIE (pt, eta, phi, E)
+ *   with px = pt cos(phi), py = pt sin(phi), pz = pt sinh(eta).
+ * Sums are formed in Cartesian components, never converted back.
+ * Mass.  q = E^2 - |P|^2; m = sqrt(q), and m = -sqrt(-q) for a spacelike
+ *   q < 0 (values are not validated: NaN in gives NaN out, |beta| >= 1 gives
+ *   inf/NaN).  The derivative of m is taken as 0 where m = 0.
+ * Sizes are int64_t element counts; 0 is valid and launches nothing; a
+ *   negative count returns GLV_EINVAL_SIZE.
+ * Alignment.  Any element-aligned pointer is accepted; columns aligned to 16
+ *   bytes take the vectorised path.
+ * Errors.  A glv_status is returned; on GLV_EHIP the HIP error code is
+ *   available from glv_last_hip_error() (per thread).  Nothing is enqueued
+ *   when validation fails.
+ */
+#ifndef GLV_H
+#define GLV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GLV_ABI_VERSION 1
+
+typedef enum glv_status {
+  GLV_OK = 0,
+  GLV_EINVAL_NULL = 1,    /* a required pointer is NULL                        */
+  GLV_EINVAL_SIZE = 2,    /* negative element or event count                   */
+  GLV_EINVAL_DTYPE = 3,   /* dtype is not GLV_F32 / GLV_F64                    */
+  GLV_EINVAL_COORDS = 4,  /* coords is not one of glv_coords                   */
+  GLV_EINVAL_MODE = 5,    /* mode unknown, or not available for these coords  */
+  GLV_EINVAL_ALIAS = 6,   /* an output overlaps an input (or another output)   */
+  GLV_EINVAL_STRIDE = 7,  /* beta_stride not 0 or 1, or 0 where 1 is required  */
+  GLV_EINVAL_OFFSETS = 8, /* offsets / pair_offsets missing where needed       */
+  GLV_EINVAL_TILING = 9,  /* a glv_tiling field is outside its allowed set     */
+  GLV_EHIP = 10           /* a HIP call failed (see glv_last_hip_error)        */
+} glv_status;
+
+typedef enum glv_dtype { GLV_F32 = 1, GLV_F64 = 2 } glv_dtype;
+
+typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2 } glv_coords;
+
+/* GLV_PLAIN: the definition (convert, add, E^2 - |P|^2).
+ * GLV_COMPENSATED (PtEtaPhiM only): the cancellation-free form
+ *   m^2 = Ma^2 + Mb^2 + 2 (t1 + t2 + t3),
+ *   t1 = 2 mTa mTb sinh^2(dy/2), t2 = 2 pta ptb sin^2(dphi/2),
+ *   t3 = (pta^2 Mb^2 + ptb^2 Ma^2 + Ma^2 Mb^2) / (mTa mTb + pta ptb),
+ * with mT = sqrt(pt^2 + M^2) and the rapidity difference
+ *   dy = (eta_a - eta_b) + (delta_a - delta_b),
+ *   delta = y - eta = -asinh(M^2 sinh(eta) / (mT (pt cosh(eta) + E))).
+ * Every term is >= 0, so light, nearly collinear pairs keep their digits.
+ * In FP32 each item carries a running bound on the relative error of m^2;
+ * an item whose bound exceeds 2^-18 is recomputed in FP64 from its widened
+ * inputs and counted in *fallback_count.  In FP64 the same form is evaluated
+ * throughout (no fallback). */
+typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
+
+/* Work decomposition of glv_event_reduce / glv_event_reduce_bwd.  It changes
+ * speed only: pair masses and totals are identical for every tiling; the
+ * compensated event mass (a sum of per-pair terms) may differ in the last bit
+ * between tilings but is reproducible for a given tiling.
+ *   block            threads per workgroup: 64, 128, 256, 512 or 1024
+ *   events_per_tile  events a workgroup takes at a time: 1 .. block
+ *   lds_particles    particles staged in LDS at once: 64 .. 4096
+ * Fields set to 0 take the library's current choice (the autotuned one if
+ * glv_autotune_event_reduce ran for this device/dtype/coords/mode, otherwise a
+ * built-in default). */
+typedef struct glv_tiling {
+  int32_t block;
+  int32_t events_per_tile;
+  int32_t lds_particles;
+  int32_t reserved; /* must be 0 */
+} glv_tiling;
+
+/* Pair invariant mass (Sec. 3.1, Fig. 1): m[i] = mass(conv(a_i) + conv(b_i)),
+ * i in [0, n).
+ *   a, b            4 column pointers each (component order of `coords`)
+ *   m               n outputs; must not overlap any input
+ *   fallback_count  device uint64; if not NULL and mode is GLV_COMPENSATED with
+ *                   GLV_F32, the number of items recomputed in FP64 is ADDED to
+ *                   it (the caller zeroes it).  Ignored otherwise.
+ * GLV_COMPENSATED requires GLV_PTETAPHIM (else GLV_EINVAL_MODE). */
+glv_status glv_invariant_mass(glv_dtype dtype, glv_coords coords, glv_mode mode, int64_t n,
+                              const void* const a[4], const void* const b[4], void* m,
+                              unsigned long long* fallback_count, void* stream);
+
+/* Reverse mode of the pair mass (plain definition; any coords):
+ *   grad_a[k][i] = grad_m[i] * dm_i / d a_k[i], grad_b likewise.
+ * With (P, E) the summed vector, dm/d(Cartesian leg) = (-P, E) / |m|, chained
+ * through the conversion's Jacobian.  Gradient columns must not overlap any
+ * input or each other. */
+glv_status glv_invariant_mass_bwd(glv_dtype dtype, glv_coords coords, int64_t n,
+                                  const void* const a[4], const void* const b[4],
+                                  const void* grad_m, void* const grad_a[4], void* const grad_b[4],
+                                  void* stream);
+
+/* Active Lorentz boost (Sec. 3.1, ApplyBoost) of Cartesian vectors x by
+ * velocity beta: with g = 1/sqrt(1 - beta^2), k = g^2/(1 + g), s = beta.p,
+ *   E' = g (E + s),   p' = p + (k s + g E) beta.
+ *   x, y        4 columns (px, py, pz, E); y may equal x column for column
+ *               (in place); any other overlap is GLV_EINVAL_ALIAS
+ *   beta        3 columns (bx, by, bz)
+ *   beta_stride 1: n velocities, one per item; 0: beta[k][0] for every item
+ * In FP32, g and k are formed in FP64 from the widened velocity. */
+glv_status glv_boost(glv_dtype dtype, int64_t n, const void* const x[4], const void* const beta[3],
+                     int64_t beta_stride, void* const y[4], void* stream);
+
+/* Reverse mode of the boost, y = L(beta) x:
+ *   grad_x = L(beta) grad_y        (L is symmetric),
+ *   grad_beta = gE [g^3 (E + s) beta + g p]
+ *             + (gp.beta) [k' g^3 s beta + k p + g^3 E beta] + (k s + g E) gp,
+ *   k' = g (g + 2)/(1 + g)^2, grad_y = (gp, gE).
+ * grad_beta may be NULL (not wanted); if given, beta_stride must be 1
+ * (GLV_EINVAL_STRIDE otherwise).  Outputs must not overlap inputs. */
+glv_status glv_boost_bwd(glv_dtype dtype, int64_t n, const void* const x[4],
+                         const void* const beta[3], int64_t beta_stride,
+                         const void* const grad_y[4], void* const grad_x[4],
+                         void* const grad_beta[3], void* stream);
+
+/* Pair offsets of CSR events: pair_offsets[0] = 0,
+ * pair_offsets[e+1] = pair_offsets[e] + c_e (c_e - 1) / 2 with
+ * c_e = offsets[e+1] - offsets[e].  Both arrays hold n_events + 1 int64. */
+glv_status glv_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* pair_offsets,
+                            void* stream);
+
+/* Per-event reduction of CSR events, one launch.
+ *   offsets       n_events + 1 int64, offsets[0] = 0, non-decreasing
+ *                 (trusted: see glv_validate_offsets)
+ *   pair_offsets  from glv_pair_offsets; required when pair_m or a
+ *                 GLV_COMPENSATED event mass is requested
+ *   p             4 particle columns in `coords`, offsets[n_events] entries
+ * Outputs (each may be NULL = not wanted):
+ *   total[4]  per-event sum of the particles' Cartesian vectors, in CSR order
+ *   event_m   mass of the total: GLV_PLAIN from total; GLV_COMPENSATED as
+ *             m^2 = sum_i M_i^2 + 2 sum_{i<j} (E_i E_j - p_i.p_j) with each pair
+ *             product from the cancellation-free form
+ *   pair_m    masses of the pairs i < j of each event, at
+ *             pair_offsets[e] + i (2n - i - 1)/2 + (j - i - 1)
+ *   fallback_count  as in glv_invariant_mass (pairs recomputed in FP64)
+ *   tiling    NULL or a glv_tiling (fields 0 = library's choice) */
+glv_status glv_event_reduce(glv_dtype dtype, glv_coords coords, glv_mode mode, int64_t n_events,
+                            const int64_t* offsets, const int64_t* pair_offsets,
+                            const void* const p[4], void* const total[4], void* event_m,
+                            void* pair_m, unsigned long long* fallback_count,
+                            const glv_tiling* tiling, void* stream);
+
+/* Reverse mode of the plain per-event reduction.  For particle i of event e,
+ *   g_i = grad_total[e] + grad_event_m[e] dm(V_e)/dV
+ *       + sum_{j != i} grad_pair_m[pair(i, j)] dm(v_i + v_j)/dv,
+ * chained to the particle's coordinates.  Any upstream pointer may be NULL
+ * (zero); grad_total is all-or-nothing (4 columns or NULL).  grad_p[4] must
+ * not overlap inputs. */
+glv_status glv_event_reduce_bwd(glv_dtype dtype, glv_coords coords, int64_t n_events,
+                                const int64_t* offsets, const int64_t* pair_offsets,
+                                const void* const p[4], const void* const grad_total[4],
+                                const void* grad_event_m, const void* grad_pair_m,
+                                void* const grad_p[4], const glv_tiling* tiling, void* stream);
+
+/* Debug helper: counts violations of offsets[0] = 0, offsets non-decreasing,
+ * offsets[n_events] = n_particles, and ADDS the count to *bad_count (device
+ * int64, zeroed by the caller).  Asynchronous like every other call. */
+glv_status glv_validate_offsets(int64_t n_events, const int64_t* offsets, int64_t n_particles,
+                                long long* bad_count, void* stream);
+
+/* Times candidate tilings of glv_event_reduce on the caller's data (the
+ * arguments are those of glv_event_reduce, outputs included, which end up
+ * holding a valid result), keeps the fastest as this process's choice for
+ * (current device, dtype, coords, mode) and writes it to *best if not NULL.
+ * Synchronises `stream`. */
+glv_status glv_autotune_event_reduce(glv_dtype dtype, glv_coords coords, glv_mode mode,
+                                     int64_t n_events, const int64_t* offsets,
+                                     const int64_t* pair_offsets, const void* const p[4],
+                                     void* const total[4], void* event_m, void* pair_m,
+                                     glv_tiling* best, void* stream);
+
+/* The tiling glv_event_reduce would use for these arguments (the autotuned
+ * choice or the default), written to *out. */
+glv_status glv_current_tiling(glv_dtype dtype, glv_coords coords, glv_mode mode, glv_tiling* out);
+
+const char* glv_status_str(glv_status s);
+int glv_abi_version(void);
+int glv_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLV_H */

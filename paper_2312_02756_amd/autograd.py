@@ -1,0 +1,81 @@
+"""torch.autograd wrappers: forward and backward both run the library's
+hand-written kernels (the backward calls the "_bwd" entry points, which
+recompute the forward pass from the saved inputs instead of storing
+intermediates)."""
+
+import torch
+
+from . import glv
+
+
+class InvariantMass(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, coords, mode, *cols):
+        a, b = cols[:4], cols[4:]
+        ctx.coords = coords
+        ctx.save_for_backward(*cols)
+        return glv.glv_invariant_mass(a, b, coords=coords, mode=mode)
+
+    @staticmethod
+    def backward(ctx, gm):
+        cols = ctx.saved_tensors
+        ga, gb = glv.glv_invariant_mass_bwd(cols[:4], cols[4:], gm.contiguous(), coords=ctx.coords)
+        return (None, None) + tuple(ga) + tuple(gb)
+
+
+class Boost(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, *cols):
+        x, beta = cols[:4], cols[4:]
+        ctx.save_for_backward(*cols)
+        return glv.glv_boost(x, beta)
+
+    @staticmethod
+    def backward(ctx, *gy):
+        cols = ctx.saved_tensors
+        x, beta = cols[:4], cols[4:]
+        gy = tuple(g.contiguous() if g is not None else torch.zeros_like(x[0]) for g in gy)
+        per_item = beta[0].numel() == x[0].numel()
+        gx, gbeta = glv.glv_boost_bwd(x, beta, gy, want_beta=per_item and any(ctx.needs_input_grad[4:]))
+        if gbeta is None:
+            gbeta = (None, None, None)
+        return tuple(gx) + tuple(gbeta)
+
+
+class EventReduce(torch.autograd.Function):
+    """(total (4), event_m, pair_m) of CSR events; differentiable w.r.t. the
+    particle columns (plain mode)."""
+
+    @staticmethod
+    def forward(ctx, offsets, pair_offsets, coords, *p):
+        total, em, pm = glv.glv_event_reduce(p, offsets, pair_offsets, coords=coords, mode="plain")
+        ctx.coords = coords
+        ctx.save_for_backward(offsets, pair_offsets, *p)
+        return (*total, em, pm)
+
+    @staticmethod
+    def backward(ctx, g0, g1, g2, g3, gem, gpm):
+        offsets, pair_offsets, *p = ctx.saved_tensors
+        ne = offsets.numel() - 1
+        gt = [g if g is not None else torch.zeros(ne, dtype=p[0].dtype, device=p[0].device) for g in (g0, g1, g2, g3)]
+        gp = glv.glv_event_reduce_bwd(p, offsets, pair_offsets, grad_total=[g.contiguous() for g in gt],
+                                      grad_event_m=gem.contiguous() if gem is not None else None,
+                                      grad_pair_m=gpm.contiguous() if gpm is not None else None, coords=ctx.coords)
+        return (None, None, None) + tuple(gp)
+
+
+def invariant_mass(a, b, coords="PtEtaPhiM", mode="plain"):
+    """Differentiable pair mass of two 4-column legs."""
+    return InvariantMass.apply(coords, mode, *a, *b)
+
+
+def boost(x, beta):
+    """Differentiable boost of (px, py, pz, E) columns by beta columns."""
+    return Boost.apply(*x, *beta)
+
+
+def event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM"):
+    if pair_offsets is None:
+        pair_offsets = glv.glv_pair_offsets(offsets)
+    out = EventReduce.apply(offsets, pair_offsets, coords, *p)
+    return tuple(out[:4]), out[4], out[5]

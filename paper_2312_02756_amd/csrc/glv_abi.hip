@@ -1,0 +1,423 @@
+// C ABI of the library (declared in include/glv.h): argument validation on
+// the host, dispatch to the gfx950 launchers, the per-process tiling choice
+// of the jagged reduction and its autotuner.
+//
+// Validation never touches device memory and runs before any HIP call, so
+// every error path can be exercised on a machine without a GPU.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "glv.h"
+#include "glv_launch.h"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+glv_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return GLV_OK;
+  g_last_hip = (int)e;
+  return GLV_EHIP;
+}
+
+bool dtype_ok(glv_dtype d) { return d == GLV_F32 || d == GLV_F64; }
+bool coords_ok(glv_coords c) { return c == GLV_PXPYPZE || c == GLV_PTETAPHIM || c == GLV_PTETAPHIE; }
+size_t elem(glv_dtype d) { return d == GLV_F64 ? 8 : 4; }
+
+glv_status mode_ok(glv_mode m, glv_coords c) {
+  if (m == GLV_PLAIN) return GLV_OK;
+  if (m == GLV_COMPENSATED) return c == GLV_PTETAPHIM ? GLV_OK : GLV_EINVAL_MODE;
+  return GLV_EINVAL_MODE;
+}
+
+// Byte ranges for overlap checks.
+struct Range {
+  uintptr_t lo, hi;  // [lo, hi)
+};
+Range rng(const void* p, int64_t n, size_t es) {
+  uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  return {a, a + (uintptr_t)n * es};
+}
+bool overlap(const Range& a, const Range& b) { return a.lo < b.hi && b.lo < a.hi; }
+
+bool any_overlap(const std::vector<Range>& outs, const std::vector<Range>& ins) {
+  for (size_t i = 0; i < outs.size(); ++i) {
+    for (size_t j = i + 1; j < outs.size(); ++j)
+      if (overlap(outs[i], outs[j])) return true;
+    for (const Range& r : ins)
+      if (overlap(outs[i], r)) return true;
+  }
+  return false;
+}
+
+template <int N>
+bool nonnull(const void* const* p) {
+  if (!p) return false;
+  for (int k = 0; k < N; ++k)
+    if (!p[k]) return false;
+  return true;
+}
+
+// ----------------------------------------------------------- tiling state
+
+struct TileKey {
+  int device, dtype, coords, mode;
+  bool operator<(const TileKey& o) const {
+    return std::tie(device, dtype, coords, mode) < std::tie(o.device, o.dtype, o.coords, o.mode);
+  }
+};
+std::mutex g_tile_mu;
+std::map<TileKey, glv::Tiling> g_tiles;
+
+glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
+  glv::Tiling t;
+  t.block = 256;
+  t.events_per_tile = 128;
+  // staged bytes per particle: 4 or 10 columns of the dtype; keep <= 40 KiB
+  size_t per = (mode == GLV_COMPENSATED ? 10 : 4) * elem(dt);
+  t.lds_particles = (int)std::min<size_t>(2048, (40 * 1024) / per);
+  t.lds_particles = std::max(64, t.lds_particles & ~63);
+  return t;
+}
+
+constexpr size_t kMaxLds = 64 * 1024;
+
+bool block_ok(int b) { return b == 64 || b == 128 || b == 256 || b == 512 || b == 1024; }
+
+// Resolve a user tiling (fields 0 = current choice) and validate it.
+glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,
+                          glv::Tiling* out) {
+  glv::Tiling base = default_tiling(dt, mode);
+  if (!bwd) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tiles.find({dev, (int)dt, (int)co, (int)mode});
+    if (it != g_tiles.end()) base = it->second;
+  }
+  if (user) {
+    if (user->reserved != 0) return GLV_EINVAL_TILING;
+    if (user->block) base.block = user->block;
+    if (user->events_per_tile) base.events_per_tile = user->events_per_tile;
+    if (user->lds_particles) base.lds_particles = user->lds_particles;
+  }
+  if (!block_ok(base.block)) return GLV_EINVAL_TILING;
+  if (base.events_per_tile < 1 || base.events_per_tile > base.block) return GLV_EINVAL_TILING;
+  if (base.lds_particles < 64 || base.lds_particles > 4096) return GLV_EINVAL_TILING;
+  size_t lds = bwd ? glv::event_reduce_bwd_lds_bytes(dt, base) : glv::event_reduce_lds_bytes(dt, mode, base);
+  if (lds > kMaxLds) return GLV_EINVAL_TILING;
+  *out = base;
+  return GLV_OK;
+}
+
+glv_status check_event_args(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
+                            const void* const p[4]) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  glv_status ms = mode_ok(mode, co);
+  if (ms != GLV_OK) return ms;
+  if (ne < 0) return GLV_EINVAL_SIZE;
+  if (!off) return GLV_EINVAL_OFFSETS;
+  if (!nonnull<4>(p)) return GLV_EINVAL_NULL;
+  return GLV_OK;
+}
+
+glv_status validate_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
+                                 const int64_t* poff, const void* const p[4], void* const total[4], void* em,
+                                 void* pm) {
+  glv_status st = check_event_args(dt, co, mode, ne, off, p);
+  if (st != GLV_OK) return st;
+  if (total && !nonnull<4>((const void* const*)total)) return GLV_EINVAL_NULL;
+  if ((pm || (mode == GLV_COMPENSATED && em)) && !poff) return GLV_EINVAL_OFFSETS;
+  // outputs must not overlap each other or the offsets (their lengths are
+  // known on the host: n_events; pair and particle counts are not, so only
+  // the start addresses of those are compared)
+  std::vector<Range> outs, ins;
+  size_t es = elem(dt);
+  if (total)
+    for (int k = 0; k < 4; ++k) outs.push_back(rng(total[k], ne, es));
+  if (em) outs.push_back(rng(em, ne, es));
+  ins.push_back(rng(off, ne + 1, 8));
+  if (poff) ins.push_back(rng(poff, ne + 1, 8));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  for (int k = 0; k < 4; ++k) {
+    for (const Range& r : outs)
+      if (reinterpret_cast<uintptr_t>(p[k]) >= r.lo && reinterpret_cast<uintptr_t>(p[k]) < r.hi)
+        return GLV_EINVAL_ALIAS;
+    if (pm == p[k]) return GLV_EINVAL_ALIAS;
+  }
+  if (pm) {
+    uintptr_t a = reinterpret_cast<uintptr_t>(pm);
+    for (const Range& r : outs)
+      if (a >= r.lo && a < r.hi) return GLV_EINVAL_ALIAS;
+    for (const Range& r : ins)
+      if (a >= r.lo && a < r.hi) return GLV_EINVAL_ALIAS;
+  }
+  return GLV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int glv_abi_version(void) { return GLV_ABI_VERSION; }
+
+int glv_last_hip_error(void) { return g_last_hip; }
+
+const char* glv_status_str(glv_status s) {
+  switch (s) {
+    case GLV_OK: return "ok";
+    case GLV_EINVAL_NULL: return "a required pointer is NULL";
+    case GLV_EINVAL_SIZE: return "negative element or event count";
+    case GLV_EINVAL_DTYPE: return "unknown dtype";
+    case GLV_EINVAL_COORDS: return "unknown coordinate system";
+    case GLV_EINVAL_MODE: return "mode unknown or not available for these coordinates";
+    case GLV_EINVAL_ALIAS: return "an output overlaps an input or another output";
+    case GLV_EINVAL_STRIDE: return "beta_stride must be 0 or 1 (1 when grad_beta is requested)";
+    case GLV_EINVAL_OFFSETS: return "offsets or pair_offsets missing";
+    case GLV_EINVAL_TILING: return "tiling field outside its allowed set";
+    case GLV_EHIP: return "HIP error";
+  }
+  return "unknown status";
+}
+
+glv_status glv_invariant_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                              const void* const b[4], void* m, unsigned long long* fallback, void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  glv_status ms = mode_ok(mode, co);
+  if (ms != GLV_OK) return ms;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (!nonnull<4>(a) || !nonnull<4>(b) || !m) return GLV_EINVAL_NULL;
+  size_t es = elem(dt);
+  std::vector<Range> ins;
+  for (int k = 0; k < 4; ++k) {
+    ins.push_back(rng(a[k], n, es));
+    ins.push_back(rng(b[k], n, es));
+  }
+  if (fallback) ins.push_back(rng(fallback, 1, 8));
+  if (any_overlap({rng(m, n, es)}, ins)) return GLV_EINVAL_ALIAS;
+  if (n == 0) return GLV_OK;
+  return hip_status(glv::launch_mass(dt, co, mode, n, a, b, m, fallback, (hipStream_t)stream));
+}
+
+glv_status glv_invariant_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* const a[4],
+                                  const void* const b[4], const void* gm, void* const ga[4], void* const gb[4],
+                                  void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (!nonnull<4>(a) || !nonnull<4>(b) || !gm || !nonnull<4>((const void* const*)ga) ||
+      !nonnull<4>((const void* const*)gb))
+    return GLV_EINVAL_NULL;
+  size_t es = elem(dt);
+  std::vector<Range> ins, outs;
+  for (int k = 0; k < 4; ++k) {
+    ins.push_back(rng(a[k], n, es));
+    ins.push_back(rng(b[k], n, es));
+    outs.push_back(rng(ga[k], n, es));
+    outs.push_back(rng(gb[k], n, es));
+  }
+  ins.push_back(rng(gm, n, es));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  if (n == 0) return GLV_OK;
+  return hip_status(glv::launch_mass_bwd(dt, co, n, a, b, gm, ga, gb, (hipStream_t)stream));
+}
+
+glv_status glv_boost(glv_dtype dt, int64_t n, const void* const x[4], const void* const beta[3],
+                     int64_t beta_stride, void* const y[4], void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (!nonnull<4>(x) || !nonnull<3>(beta) || !nonnull<4>((const void* const*)y)) return GLV_EINVAL_NULL;
+  if (beta_stride != 0 && beta_stride != 1) return GLV_EINVAL_STRIDE;
+  size_t es = elem(dt);
+  bool inplace = true;
+  for (int k = 0; k < 4; ++k) inplace = inplace && (y[k] == x[k]);
+  std::vector<Range> outs, ins;
+  for (int k = 0; k < 4; ++k) outs.push_back(rng(y[k], n, es));
+  for (int k = 0; k < 3; ++k) ins.push_back(rng(beta[k], beta_stride ? n : 1, es));
+  if (!inplace)
+    for (int k = 0; k < 4; ++k) ins.push_back(rng(x[k], n, es));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  if (inplace) {
+    // in place is column for column; the x columns must still be disjoint
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        if (overlap(rng(x[i], n, es), rng(x[j], n, es))) return GLV_EINVAL_ALIAS;
+  }
+  if (n == 0) return GLV_OK;
+  return hip_status(glv::launch_boost(dt, n, x, beta, beta_stride, y, (hipStream_t)stream));
+}
+
+glv_status glv_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4], const void* const beta[3],
+                         int64_t beta_stride, const void* const gy[4], void* const gx[4], void* const gbeta[3],
+                         void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (!nonnull<3>(beta) || !nonnull<4>(gy) || !nonnull<4>((const void* const*)gx)) return GLV_EINVAL_NULL;
+  if (gbeta && (!nonnull<3>((const void* const*)gbeta) || !nonnull<4>(x))) return GLV_EINVAL_NULL;
+  if (beta_stride != 0 && beta_stride != 1) return GLV_EINVAL_STRIDE;
+  if (gbeta && beta_stride != 1) return GLV_EINVAL_STRIDE;
+  size_t es = elem(dt);
+  std::vector<Range> outs, ins;
+  for (int k = 0; k < 4; ++k) {
+    outs.push_back(rng(gx[k], n, es));
+    ins.push_back(rng(gy[k], n, es));
+    if (gbeta) ins.push_back(rng(x[k], n, es));
+  }
+  for (int k = 0; k < 3; ++k) {
+    ins.push_back(rng(beta[k], beta_stride ? n : 1, es));
+    if (gbeta) outs.push_back(rng(gbeta[k], n, es));
+  }
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  if (n == 0) return GLV_OK;
+  return hip_status(glv::launch_boost_bwd(dt, n, x, beta, beta_stride, gy, gx, gbeta, (hipStream_t)stream));
+}
+
+glv_status glv_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, void* stream) {
+  if (ne < 0) return GLV_EINVAL_SIZE;
+  if (!off || !po) return GLV_EINVAL_NULL;
+  if (overlap(rng(off, ne + 1, 8), rng(po, ne + 1, 8))) return GLV_EINVAL_ALIAS;
+  return hip_status(glv::launch_pair_offsets(ne, off, po, (hipStream_t)stream));
+}
+
+glv_status glv_validate_offsets(int64_t ne, const int64_t* off, int64_t np, long long* bad, void* stream) {
+  if (ne < 0 || np < 0) return GLV_EINVAL_SIZE;
+  if (!off || !bad) return GLV_EINVAL_NULL;
+  if (overlap(rng(off, ne + 1, 8), rng(bad, 1, 8))) return GLV_EINVAL_ALIAS;
+  return hip_status(glv::launch_validate_offsets(ne, off, np, bad, (hipStream_t)stream));
+}
+
+glv_status glv_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
+                            const int64_t* poff, const void* const p[4], void* const total[4], void* em, void* pm,
+                            unsigned long long* fallback, const glv_tiling* tiling, void* stream) {
+  glv_status st = validate_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm);
+  if (st != GLV_OK) return st;
+  glv::Tiling t;
+  st = resolve_tiling(dt, co, mode, tiling, false, &t);
+  if (st != GLV_OK) return st;
+  if (ne == 0 || (!total && !em && !pm)) return GLV_OK;
+  return hip_status(
+      glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, fallback, t, (hipStream_t)stream));
+}
+
+glv_status glv_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off, const int64_t* poff,
+                                const void* const p[4], const void* const gt[4], const void* gem,
+                                const void* gpair, void* const gp[4], const glv_tiling* tiling, void* stream) {
+  glv_status st = check_event_args(dt, co, GLV_PLAIN, ne, off, p);
+  if (st != GLV_OK) return st;
+  if (!nonnull<4>((const void* const*)gp)) return GLV_EINVAL_NULL;
+  if (gt && !nonnull<4>(gt)) return GLV_EINVAL_NULL;
+  if (gpair && !poff) return GLV_EINVAL_OFFSETS;
+  for (int k = 0; k < 4; ++k) {
+    for (int j = 0; j < 4; ++j)
+      if (gp[k] == p[j] || (j != k && gp[k] == gp[j])) return GLV_EINVAL_ALIAS;
+    if (gp[k] == gpair || gp[k] == gem || (gt && gp[k] == gt[0])) return GLV_EINVAL_ALIAS;
+    if (overlap(rng(off, ne + 1, 8), rng(gp[k], 1, elem(dt)))) return GLV_EINVAL_ALIAS;
+  }
+  glv::Tiling t;
+  st = resolve_tiling(dt, co, GLV_PLAIN, tiling, true, &t);
+  if (st != GLV_OK) return st;
+  if (ne == 0) return GLV_OK;
+  return hip_status(
+      glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t, (hipStream_t)stream));
+}
+
+glv_status glv_current_tiling(glv_dtype dt, glv_coords co, glv_mode mode, glv_tiling* out) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  glv_status ms = mode_ok(mode, co);
+  if (ms != GLV_OK) return ms;
+  if (!out) return GLV_EINVAL_NULL;
+  glv::Tiling t;
+  glv_status st = resolve_tiling(dt, co, mode, nullptr, false, &t);
+  if (st != GLV_OK) return st;
+  out->block = t.block;
+  out->events_per_tile = t.events_per_tile;
+  out->lds_particles = t.lds_particles;
+  out->reserved = 0;
+  return GLV_OK;
+}
+
+glv_status glv_autotune_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
+                                     const int64_t* poff, const void* const p[4], void* const total[4], void* em,
+                                     void* pm, glv_tiling* best, void* stream) {
+  glv_status st = validate_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm);
+  if (st != GLV_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // candidates: workgroup size x events per tile x LDS capacity
+  std::vector<glv::Tiling> cands;
+  const int blocks[] = {128, 256, 512};
+  const int epbs[] = {32, 64, 128, 256, 512};
+  const int caps[] = {256, 512, 1024, 2048};
+  for (int b : blocks)
+    for (int e : epbs)
+      for (int c : caps) {
+        if (e > b) continue;
+        glv::Tiling t{b, e, c};
+        if (glv::event_reduce_lds_bytes(dt, mode, t) > kMaxLds) continue;
+        // a tile's expected particles (8 per event on collider data) should
+        // fit the capacity at least once
+        if (c < e) continue;
+        cands.push_back(t);
+      }
+  glv::Tiling chosen = default_tiling(dt, mode);
+  if (ne > 0 && (total || em || pm)) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError());
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return hip_status(hipGetLastError());
+    }
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (const glv::Tiling& t : cands) {
+      // one warm-up, then the best of three
+      err = glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
+      if (err != hipSuccess) break;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess) err = glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess) tmin = std::min(tmin, ms);
+      }
+      if (err != hipSuccess) break;
+      if (tmin < best_ms) {
+        best_ms = tmin;
+        chosen = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_status(err);
+    // leave the outputs holding the chosen tiling's result
+    err = glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, chosen, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return hip_status(err);
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tiles[{dev, (int)dt, (int)co, (int)mode}] = chosen;
+  }
+  if (best) {
+    best->block = chosen.block;
+    best->events_per_tile = chosen.events_per_tile;
+    best->lds_particles = chosen.lds_particles;
+    best->reserved = 0;
+  }
+  return GLV_OK;
+}
+
+}  // extern "C"

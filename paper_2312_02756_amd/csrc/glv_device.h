@@ -1,0 +1,289 @@
+// Device-side building blocks shared by the gfx950 kernels: SoA column
+// bundles, streaming (non-temporal) 16-byte loads/stores, the coordinate
+// conversions of a 4D vector (GenVectorX Sec. 2.1: Cartesian and
+// pt/eta/phi systems, templated on the scalar type) and the mass of a
+// Cartesian vector (Fig. 1, `w.mass()`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glv.h"
+
+namespace glv {
+
+template <typename T>
+struct Cols4 {
+  const T* c[4];
+};
+template <typename T>
+struct Cols3 {
+  const T* c[3];
+};
+template <typename T>
+struct OutCols4 {
+  T* c[4];
+};
+template <typename T>
+struct OutCols3 {
+  T* c[3];
+};
+
+// 16 bytes per lane per column: 2 doubles or 4 floats.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int N = 2;
+};
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int N = 4;
+};
+
+// A pack of V consecutive elements of one column.
+template <typename T, int V>
+struct Pack {
+  T v[V];
+};
+
+// Streaming load of elements [V*i, V*i + V) of column p.  The data is read
+// once per launch, so it bypasses the caches' retention (non-temporal).
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> load_pack(const T* __restrict__ p, int64_t i) {
+  Pack<T, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = __builtin_nontemporal_load(p + i);
+  } else {
+    static_assert(V == Vec16<T>::N, "vector width must be 16 bytes");
+    typedef typename Vec16<T>::type VT;
+    VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(p) + i);
+#pragma unroll
+    for (int k = 0; k < V; ++k) r.v[k] = x[k];
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void store_pack(T* __restrict__ p, int64_t i, const Pack<T, V>& r) {
+  if constexpr (V == 1) {
+    __builtin_nontemporal_store(r.v[0], p + i);
+  } else {
+    typedef typename Vec16<T>::type VT;
+    VT x;
+#pragma unroll
+    for (int k = 0; k < V; ++k) x[k] = r.v[k];
+    __builtin_nontemporal_store(x, reinterpret_cast<VT*>(p) + i);
+  }
+}
+
+// ------------------------------------------------------------ scalar math
+
+__device__ __forceinline__ void d_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void d_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ double d_sinh(double x) { return sinh(x); }
+__device__ __forceinline__ float d_sinh(float x) { return sinhf(x); }
+__device__ __forceinline__ double d_cosh(double x) { return cosh(x); }
+__device__ __forceinline__ float d_cosh(float x) { return coshf(x); }
+__device__ __forceinline__ double d_asinh(double x) { return asinh(x); }
+__device__ __forceinline__ float d_asinh(float x) { return asinhf(x); }
+__device__ __forceinline__ double d_sin(double x) { return sin(x); }
+__device__ __forceinline__ float d_sin(float x) { return sinf(x); }
+__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double d_abs(double x) { return fabs(x); }
+__device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
+
+// ------------------------------------------------------------ conversion
+
+// Cartesian (px, py, pz, E) of one vector given in COORDS.
+template <int COORDS, typename T>
+__device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
+  if constexpr (COORDS == GLV_PXPYPZE) {
+    v[0] = c0;
+    v[1] = c1;
+    v[2] = c2;
+    v[3] = c3;
+  } else {
+    T s, c;
+    d_sincos(c2, &s, &c);
+    v[0] = c0 * c;
+    v[1] = c0 * s;
+    v[2] = c0 * d_sinh(c1);
+    if constexpr (COORDS == GLV_PTETAPHIM) {
+      T pc = c0 * d_cosh(c1);
+      v[3] = d_sqrt(pc * pc + c3 * c3);
+    } else {
+      v[3] = c3;
+    }
+  }
+}
+
+// Conversion together with the pieces its Jacobian needs.
+template <typename T>
+struct LegJ {
+  T v[4];            // px, py, pz, E
+  T cp, sp, sh, ch;  // cos phi, sin phi, sinh eta, cosh eta
+};
+
+template <int COORDS, typename T>
+__device__ __forceinline__ LegJ<T> to_cart_j(T c0, T c1, T c2, T c3) {
+  LegJ<T> L;
+  if constexpr (COORDS == GLV_PXPYPZE) {
+    L.v[0] = c0;
+    L.v[1] = c1;
+    L.v[2] = c2;
+    L.v[3] = c3;
+    L.cp = L.sp = L.sh = L.ch = T(0);
+  } else {
+    d_sincos(c2, &L.sp, &L.cp);
+    L.sh = d_sinh(c1);
+    L.ch = d_cosh(c1);
+    L.v[0] = c0 * L.cp;
+    L.v[1] = c0 * L.sp;
+    L.v[2] = c0 * L.sh;
+    if constexpr (COORDS == GLV_PTETAPHIM) {
+      T pc = c0 * L.ch;
+      L.v[3] = d_sqrt(pc * pc + c3 * c3);
+    } else {
+      L.v[3] = c3;
+    }
+  }
+  return L;
+}
+
+// Chain u = dL/d(px, py, pz, E) of one vector to its own coordinates.
+template <int COORDS, typename T>
+__device__ __forceinline__ void chain_coords(const LegJ<T>& L, T c0, T c3, const T u[4], T g[4]) {
+  if constexpr (COORDS == GLV_PXPYPZE) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = u[k];
+  } else {
+    T pt = c0;
+    T g0 = u[0] * L.cp + u[1] * L.sp + u[2] * L.sh;
+    T g1 = u[2] * pt * L.ch;
+    T g2 = u[1] * L.v[0] - u[0] * L.v[1];
+    T g3;
+    if constexpr (COORDS == GLV_PTETAPHIM) {
+      // E = sqrt((pt ch)^2 + M^2): dE/dpt = pt ch^2/E, dE/deta = pt^2 sh ch/E, dE/dM = M/E
+      T e = L.v[3];
+      T ue = (e > T(0)) ? u[3] / e : T(0);
+      g0 += ue * pt * L.ch * L.ch;
+      g1 += ue * pt * pt * L.sh * L.ch;
+      g3 = ue * c3;
+    } else {
+      g3 = u[3];
+    }
+    g[0] = g0;
+    g[1] = g1;
+    g[2] = g2;
+    g[3] = g3;
+  }
+}
+
+// Mass of a Cartesian vector: q = E^2 - |P|^2, m = sqrt(q) or -sqrt(-q).
+template <typename T>
+__device__ __forceinline__ T mass_of(const T w[4]) {
+  T q = w[3] * w[3] - w[0] * w[0] - w[1] * w[1] - w[2] * w[2];
+  return q >= T(0) ? d_sqrt(q) : -d_sqrt(-q);
+}
+
+// dm/d(Cartesian) = (-P, E)/|m| times the upstream gradient; zero at m = 0.
+template <typename T>
+__device__ __forceinline__ void dmass(const T w[4], T m, T g, T u[4]) {
+  T am = d_abs(m);
+  T s = (am > T(0)) ? g / am : T(0);
+  u[0] = -w[0] * s;
+  u[1] = -w[1] * s;
+  u[2] = -w[2] * s;
+  u[3] = w[3] * s;
+}
+
+// ------------------------------------------------- cancellation-free mass
+
+// pi split into the nearest T and the remainder.
+template <typename T>
+struct Pi;
+template <>
+struct Pi<double> {
+  static constexpr double hi = 3.141592653589793116;
+  static constexpr double lo = 1.2246467991473532e-16;
+};
+template <>
+struct Pi<float> {
+  static constexpr float hi = 3.14159274101257324f;
+  static constexpr float lo = -8.74227765734758577e-08f;
+};
+
+// a - b reduced to (-pi, pi]; next to the seam both angles are moved by the
+// head of pi separately (exact subtractions), then the tail is applied.
+template <typename T>
+__device__ __forceinline__ T dphi_reduced(T a, T b) {
+  T d = a - b;
+  if (d > Pi<T>::hi) return ((a - Pi<T>::hi) - (b + Pi<T>::hi)) - T(2) * Pi<T>::lo;
+  if (d <= -Pi<T>::hi) return ((a + Pi<T>::hi) - (b - Pi<T>::hi)) + T(2) * Pi<T>::lo;
+  return d;
+}
+
+// Per-leg terms: pt, eta, phi, M^2, mT = sqrt(pt^2 + M^2) and
+// delta = y - eta = -asinh(M^2 sinh(eta) / (mT (pt cosh(eta) + E))).
+template <typename T>
+struct LegC {
+  T pt, eta, phi, m2, mt, delta;
+};
+
+template <typename T>
+__device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
+  LegC<T> L;
+  L.pt = pt;
+  L.eta = eta;
+  L.phi = phi;
+  T mm = mass * mass;
+  L.m2 = mm;
+  L.mt = d_sqrt(pt * pt + mm);
+  T sh = d_sinh(eta), ch = d_cosh(eta);
+  T pc = pt * ch;
+  T e = d_sqrt(pc * pc + mm);
+  T den = L.mt * (pc + e);
+  L.delta = (den > T(0)) ? -d_asinh(mm * sh / den) : T(0);
+  return L;
+}
+
+// Pair m^2 = Ma^2 + Mb^2 + 2 (t1 + t2 + t3) (all terms >= 0); *k receives
+// t1 + t2 + t3 = E_a E_b - p_a.p_b.  If `bound` is not NULL it receives a
+// running bound on the relative error of m^2 in units of the rounding unit:
+// every term is a product/quotient of accurately computed positive factors
+// (16 units covers them) except the rapidity difference dy, whose absolute
+// error is a few units of |d1| + |d2| + |dy| plus that of the deltas; t1
+// moves with dy as 2 mTa mTb |sinh dy|.
+template <typename T>
+__device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T* k, T* bound) {
+  T d1 = a.eta - b.eta;
+  T d2 = a.delta - b.delta;
+  T dy = d1 + d2;
+  T s1 = d_sinh(T(0.5) * dy);
+  T t1 = T(2) * a.mt * b.mt * (s1 * s1);
+  T s2 = d_sin(T(0.5) * dphi_reduced(a.phi, b.phi));
+  T t2 = T(2) * a.pt * b.pt * (s2 * s2);
+  T num = a.pt * a.pt * b.m2 + b.pt * b.pt * a.m2 + a.m2 * b.m2;
+  T den = a.mt * b.mt + a.pt * b.pt;
+  T t3 = (num == T(0)) ? T(0) : num / den;
+  T kk = t1 + t2 + t3;
+  T m2 = a.m2 + b.m2 + T(2) * kk;
+  *k = kk;
+  if (bound) {
+    T edy = (d_abs(d1) + d_abs(d2) + d_abs(dy)) + T(16) * (d_abs(a.delta) + d_abs(b.delta));
+    T c1 = d_sqrt(T(1) + s1 * s1);
+    T sens = T(4) * a.mt * b.mt * d_abs(s1 * c1);  // 2 * d(t1)/d(dy)
+    *bound = (m2 > T(0)) ? (sens * edy + T(16) * m2) / m2 : T(0);
+  }
+  return m2;
+}
+
+// Relative-error bound (units of u32) above which an FP32 pair is redone in
+// FP64: 2^-18 / 2^-24 = 64.
+constexpr float kFallbackUnits = 64.0f;
+
+}  // namespace glv

@@ -1,0 +1,57 @@
+// Host-side launchers of the gfx950 kernels.  Called by the C ABI after the
+// arguments have been validated; each enqueues on `s` and returns the first
+// HIP error seen (hipSuccess otherwise).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glv.h"
+
+namespace glv {
+
+hipError_t launch_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                       const void* const b[4], void* m, unsigned long long* fallback, hipStream_t s);
+
+hipError_t launch_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* const a[4],
+                           const void* const b[4], const void* gm, void* const ga[4],
+                           void* const gb[4], hipStream_t s);
+
+hipError_t launch_boost(glv_dtype dt, int64_t n, const void* const x[4], const void* const beta[3],
+                        int64_t beta_stride, void* const y[4], hipStream_t s);
+
+hipError_t launch_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4],
+                            const void* const beta[3], int64_t beta_stride,
+                            const void* const gy[4], void* const gx[4], void* const gbeta[3],
+                            hipStream_t s);
+
+hipError_t launch_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* pair_offsets,
+                               hipStream_t s);
+
+hipError_t launch_validate_offsets(int64_t n_events, const int64_t* offsets, int64_t n_particles,
+                                   long long* bad, hipStream_t s);
+
+// Tiling with every field resolved (non-zero, inside its allowed set).
+struct Tiling {
+  int block;
+  int events_per_tile;
+  int lds_particles;
+};
+
+// LDS bytes one workgroup of the forward reduction needs for a tiling.
+size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t);
+size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t);
+
+hipError_t launch_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n_events,
+                               const int64_t* offsets, const int64_t* pair_offsets,
+                               const void* const p[4], void* const total[4], void* event_m,
+                               void* pair_m, unsigned long long* fallback, const Tiling& t,
+                               hipStream_t s);
+
+hipError_t launch_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t n_events,
+                                   const int64_t* offsets, const int64_t* pair_offsets,
+                                   const void* const p[4], const void* const gt[4],
+                                   const void* gem, const void* gpair, void* const gp[4],
+                                   const Tiling& t, hipStream_t s);
+
+}  // namespace glv

@@ -1,0 +1,417 @@
+// Element-wise gfx950 kernels over SoA columns: pair invariant mass (plain
+// and cancellation-free), its reverse mode, and the Lorentz boost with its
+// reverse mode (GenVectorX Sec. 3.1: InvariantMasses and ApplyBoost, one
+// independent result per item).
+//
+// Every op streams its columns exactly once, so the kernels are built for
+// HBM bandwidth: each lane moves 16 bytes per column per step (2 doubles or
+// 4 floats) with non-temporal loads and stores, one wavefront covers a
+// contiguous 1 KiB of every column, and the grid has one lane per pack (a
+// grid-stride loop only takes over beyond 2^31 workgroups).  Columns not
+// aligned to 16 bytes take the same code with one element per lane.
+#include "glv_device.h"
+#include "glv_launch.h"
+
+namespace glv {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------- driver
+
+// Runs op.run<V>(i) over packs i in [0, n / V), then op.run<1>(t) over the
+// tail elements t in [V (n / V), n).  run() returns how many of its items
+// were recomputed in FP64; the total is added to *counter (one atomic per
+// wavefront with a non-zero count).
+template <typename Op, int V>
+__global__ __launch_bounds__(kBlock) void k_stream(Op op, int64_t n, unsigned long long* counter) {
+  const int64_t nv = n / V;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned cnt = 0;
+  for (int64_t i = tid; i < nv; i += stride) cnt += op.template run<V>(i);
+  if constexpr (V > 1) {
+    const int64_t t = nv * V + tid;
+    if (t < n) cnt += op.template run<1>(t);
+  }
+  if constexpr (Op::kCounts) {
+    if (counter) {
+      // wavefront sum, then lane 0 adds it with one vector atomic
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+      if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(counter, (unsigned long long)cnt);
+    }
+  }
+}
+
+template <typename Op, int V>
+hipError_t run_stream(const Op& op, int64_t n, unsigned long long* counter, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t packs = n / V;
+  int64_t blocks = (packs + kBlock - 1) / kBlock;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 0x7fffffff) blocks = 0x7fffffff;
+  hipLaunchKernelGGL((k_stream<Op, V>), dim3((unsigned)blocks), dim3(kBlock), 0, s, op, n, counter);
+  return hipGetLastError();
+}
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+template <typename T, typename Op>
+hipError_t dispatch_width(const Op& op, bool all_aligned, int64_t n, unsigned long long* counter,
+                          hipStream_t s) {
+  if (all_aligned) return run_stream<Op, Vec16<T>::N>(op, n, counter, s);
+  return run_stream<Op, 1>(op, n, counter, s);
+}
+
+// ------------------------------------------------------------ pair mass
+
+template <typename T, int COORDS>
+struct MassPlain {
+  static constexpr bool kCounts = false;
+  Cols4<T> a, b;
+  T* m;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pa[4], pb[4], out;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pa[k] = load_pack<T, V>(a.c[k], i);
+      pb[k] = load_pack<T, V>(b.c[k], i);
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T va[4], vb[4], w[4];
+      to_cart<COORDS>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e], va);
+      to_cart<COORDS>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e], vb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = va[k] + vb[k];
+      out.v[e] = mass_of(w);
+    }
+    store_pack<T, V>(m, i, out);
+    return 0;
+  }
+};
+
+// Cancellation-free pair mass of PtEtaPhiM legs.  FP32 items whose running
+// error bound exceeds kFallbackUnits are recomputed in FP64.
+template <typename T>
+struct MassComp {
+  static constexpr bool kCounts = true;
+  Cols4<T> a, b;
+  T* m;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pa[4], pb[4], out;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pa[k] = load_pack<T, V>(a.c[k], i);
+      pb[k] = load_pack<T, V>(b.c[k], i);
+    }
+    unsigned cnt = 0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      LegC<T> la = comp_leg<T>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
+      LegC<T> lb = comp_leg<T>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
+      T k;
+      if constexpr (sizeof(T) == 4) {
+        T bound;
+        T m2 = comp_pair_m2<T>(la, lb, &k, &bound);
+        if (!(bound <= kFallbackUnits)) {
+          LegC<double> da = comp_leg<double>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
+          LegC<double> db = comp_leg<double>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
+          double kd;
+          double m2d = comp_pair_m2<double>(da, db, &kd, nullptr);
+          m2 = (T)m2d;
+          out.v[e] = (T)sqrt(m2d);
+          ++cnt;
+        } else {
+          out.v[e] = d_sqrt(m2);
+        }
+      } else {
+        out.v[e] = d_sqrt(comp_pair_m2<T>(la, lb, &k, nullptr));
+      }
+    }
+    store_pack<T, V>(m, i, out);
+    return cnt;
+  }
+};
+
+// Reverse mode: recompute the legs, then (-P, E)/|m| chained per leg.
+template <typename T, int COORDS>
+struct MassBwd {
+  static constexpr bool kCounts = false;
+  Cols4<T> a, b;
+  const T* gm;
+  OutCols4<T> ga, gb;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pa[4], pb[4], pg, oa[4], ob[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pa[k] = load_pack<T, V>(a.c[k], i);
+      pb[k] = load_pack<T, V>(b.c[k], i);
+    }
+    pg = load_pack<T, V>(gm, i);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      LegJ<T> la = to_cart_j<COORDS, T>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
+      LegJ<T> lb = to_cart_j<COORDS, T>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
+      T w[4], u[4], g[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = la.v[k] + lb.v[k];
+      dmass<T>(w, mass_of(w), pg.v[e], u);
+      chain_coords<COORDS, T>(la, pa[0].v[e], pa[3].v[e], u, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) oa[k].v[e] = g[k];
+      chain_coords<COORDS, T>(lb, pb[0].v[e], pb[3].v[e], u, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ob[k].v[e] = g[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      store_pack<T, V>(ga.c[k], i, oa[k]);
+      store_pack<T, V>(gb.c[k], i, ob[k]);
+    }
+    return 0;
+  }
+};
+
+// ----------------------------------------------------------------- boost
+
+// gamma and kappa = gamma^2/(1 + gamma) from the velocity, formed in FP64
+// (for FP32 data the rounding of beta^2 would otherwise be magnified by
+// gamma^2 in 1 - beta^2).
+struct BoostCoef {
+  double g, k;
+};
+__device__ __forceinline__ BoostCoef boost_coef(double bx, double by, double bz) {
+  double b2 = bx * bx + by * by + bz * bz;
+  double g = 1.0 / sqrt(1.0 - b2);
+  return {g, g * g / (1.0 + g)};
+}
+
+template <typename T, int BSTRIDE>
+struct BoostFwd {
+  static constexpr bool kCounts = false;
+  Cols4<T> x;
+  Cols3<T> beta;
+  OutCols4<T> y;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> px[4], pb[3], out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) px[k] = load_pack<T, V>(x.c[k], i);
+    if constexpr (BSTRIDE == 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pb[k] = load_pack<T, V>(beta.c[k], i);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T v = beta.c[k][0];
+#pragma unroll
+        for (int e = 0; e < V; ++e) pb[k].v[e] = v;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T bx = pb[0].v[e], by = pb[1].v[e], bz = pb[2].v[e];
+      BoostCoef c = boost_coef(bx, by, bz);
+      T g = (T)c.g, kap = (T)c.k;
+      T p0 = px[0].v[e], p1 = px[1].v[e], p2 = px[2].v[e], en = px[3].v[e];
+      T sdot = bx * p0 + by * p1 + bz * p2;
+      T cc = kap * sdot + g * en;
+      out[3].v[e] = g * (en + sdot);
+      out[0].v[e] = p0 + cc * bx;
+      out[1].v[e] = p1 + cc * by;
+      out[2].v[e] = p2 + cc * bz;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_pack<T, V>(y.c[k], i, out[k]);
+    return 0;
+  }
+};
+
+// Reverse mode of the boost: grad_x = L(beta) grad_y; grad_beta in closed form.
+template <typename T, int BSTRIDE, bool WANT_GB>
+struct BoostBwd {
+  static constexpr bool kCounts = false;
+  Cols4<T> x;
+  Cols3<T> beta;
+  Cols4<T> gy;
+  OutCols4<T> gx;
+  OutCols3<T> gb;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> px[4], pb[3], pg[4], ox[4], ob[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pg[k] = load_pack<T, V>(gy.c[k], i);
+    if constexpr (WANT_GB) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) px[k] = load_pack<T, V>(x.c[k], i);
+    }
+    if constexpr (BSTRIDE == 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pb[k] = load_pack<T, V>(beta.c[k], i);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T v = beta.c[k][0];
+#pragma unroll
+        for (int e = 0; e < V; ++e) pb[k].v[e] = v;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T b[3] = {pb[0].v[e], pb[1].v[e], pb[2].v[e]};
+      BoostCoef c = boost_coef(b[0], b[1], b[2]);
+      T g = (T)c.g, kap = (T)c.k;
+      T gp[3] = {pg[0].v[e], pg[1].v[e], pg[2].v[e]};
+      T ge = pg[3].v[e];
+      T gdb = gp[0] * b[0] + gp[1] * b[1] + gp[2] * b[2];
+      T cc = kap * gdb + g * ge;
+      ox[3].v[e] = g * (ge + gdb);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) ox[d].v[e] = gp[d] + cc * b[d];
+      if constexpr (WANT_GB) {
+        double gd = c.g;
+        T g3 = (T)(gd * gd * gd);
+        T kp = (T)(gd * (gd + 2.0) / ((1.0 + gd) * (1.0 + gd)));
+        T p[3] = {px[0].v[e], px[1].v[e], px[2].v[e]};
+        T en = px[3].v[e];
+        T sdot = b[0] * p[0] + b[1] * p[1] + b[2] * p[2];
+        T ce = g3 * (en + sdot);
+        T cq = kp * g3 * sdot + g3 * en;
+        T cr = kap * sdot + g * en;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          ob[d].v[e] = ge * (ce * b[d] + g * p[d]) + gdb * (cq * b[d] + kap * p[d]) + cr * gp[d];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_pack<T, V>(gx.c[k], i, ox[k]);
+    if constexpr (WANT_GB) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) store_pack<T, V>(gb.c[k], i, ob[k]);
+    }
+    return 0;
+  }
+};
+
+template <typename T>
+Cols4<T> cols4(const void* const p[4]) {
+  return {{(const T*)p[0], (const T*)p[1], (const T*)p[2], (const T*)p[3]}};
+}
+template <typename T>
+Cols3<T> cols3(const void* const p[3]) {
+  return {{(const T*)p[0], (const T*)p[1], (const T*)p[2]}};
+}
+template <typename T>
+OutCols4<T> out4(void* const p[4]) {
+  return {{(T*)p[0], (T*)p[1], (T*)p[2], (T*)p[3]}};
+}
+template <typename T>
+OutCols3<T> out3(void* const p[3]) {
+  if (!p) return {{nullptr, nullptr, nullptr}};
+  return {{(T*)p[0], (T*)p[1], (T*)p[2]}};
+}
+
+template <int N>
+bool all16(const void* const* p) {
+  for (int k = 0; k < N; ++k)
+    if (!aligned16(p[k])) return false;
+  return true;
+}
+
+template <typename T>
+hipError_t mass_typed(glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                      const void* const b[4], void* m, unsigned long long* fb, hipStream_t s) {
+  bool al = all16<4>(a) && all16<4>(b) && aligned16(m);
+  Cols4<T> ca = cols4<T>(a), cb = cols4<T>(b);
+  if (mode == GLV_COMPENSATED) return dispatch_width<T>(MassComp<T>{ca, cb, (T*)m}, al, n, fb, s);
+  switch (co) {
+    case GLV_PXPYPZE:
+      return dispatch_width<T>(MassPlain<T, GLV_PXPYPZE>{ca, cb, (T*)m}, al, n, nullptr, s);
+    case GLV_PTETAPHIM:
+      return dispatch_width<T>(MassPlain<T, GLV_PTETAPHIM>{ca, cb, (T*)m}, al, n, nullptr, s);
+    default:
+      return dispatch_width<T>(MassPlain<T, GLV_PTETAPHIE>{ca, cb, (T*)m}, al, n, nullptr, s);
+  }
+}
+
+template <typename T>
+hipError_t mass_bwd_typed(glv_coords co, int64_t n, const void* const a[4], const void* const b[4],
+                          const void* gm, void* const ga[4], void* const gb[4], hipStream_t s) {
+  bool al = all16<4>(a) && all16<4>(b) && aligned16(gm) && all16<4>((const void* const*)ga) &&
+            all16<4>((const void* const*)gb);
+  Cols4<T> ca = cols4<T>(a), cb = cols4<T>(b);
+  OutCols4<T> oa = out4<T>(ga), ob = out4<T>(gb);
+  const T* g = (const T*)gm;
+  switch (co) {
+    case GLV_PXPYPZE:
+      return dispatch_width<T>(MassBwd<T, GLV_PXPYPZE>{ca, cb, g, oa, ob}, al, n, nullptr, s);
+    case GLV_PTETAPHIM:
+      return dispatch_width<T>(MassBwd<T, GLV_PTETAPHIM>{ca, cb, g, oa, ob}, al, n, nullptr, s);
+    default:
+      return dispatch_width<T>(MassBwd<T, GLV_PTETAPHIE>{ca, cb, g, oa, ob}, al, n, nullptr, s);
+  }
+}
+
+template <typename T>
+hipError_t boost_typed(int64_t n, const void* const x[4], const void* const beta[3], int64_t bs,
+                       void* const y[4], hipStream_t s) {
+  bool al = all16<4>(x) && all16<4>((const void* const*)y) && (bs == 0 || all16<3>(beta));
+  if (bs == 1) return dispatch_width<T>(BoostFwd<T, 1>{cols4<T>(x), cols3<T>(beta), out4<T>(y)}, al, n, nullptr, s);
+  return dispatch_width<T>(BoostFwd<T, 0>{cols4<T>(x), cols3<T>(beta), out4<T>(y)}, al, n, nullptr, s);
+}
+
+template <typename T>
+hipError_t boost_bwd_typed(int64_t n, const void* const x[4], const void* const beta[3], int64_t bs,
+                           const void* const gy[4], void* const gx[4], void* const gb[3],
+                           hipStream_t s) {
+  bool want = gb != nullptr;
+  bool al = all16<4>(gy) && all16<4>((const void* const*)gx) && (bs == 0 || all16<3>(beta)) &&
+            (!want || (all16<4>(x) && all16<3>((const void* const*)gb)));
+  Cols4<T> cx = want ? cols4<T>(x) : Cols4<T>{{nullptr, nullptr, nullptr, nullptr}};
+  Cols3<T> cbeta = cols3<T>(beta);
+  if (want) {
+    // grad_beta is per item: beta_stride 1 only (checked by the caller)
+    return dispatch_width<T>(BoostBwd<T, 1, true>{cx, cbeta, cols4<T>(gy), out4<T>(gx), out3<T>(gb)}, al, n,
+                             nullptr, s);
+  }
+  if (bs == 1)
+    return dispatch_width<T>(BoostBwd<T, 1, false>{cx, cbeta, cols4<T>(gy), out4<T>(gx), out3<T>(nullptr)}, al,
+                             n, nullptr, s);
+  return dispatch_width<T>(BoostBwd<T, 0, false>{cx, cbeta, cols4<T>(gy), out4<T>(gx), out3<T>(nullptr)}, al, n,
+                           nullptr, s);
+}
+
+}  // namespace
+
+hipError_t launch_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                       const void* const b[4], void* m, unsigned long long* fb, hipStream_t s) {
+  if (dt == GLV_F64) return mass_typed<double>(co, mode, n, a, b, m, nullptr, s);
+  return mass_typed<float>(co, mode, n, a, b, m, fb, s);
+}
+
+hipError_t launch_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* const a[4],
+                           const void* const b[4], const void* gm, void* const ga[4],
+                           void* const gb[4], hipStream_t s) {
+  if (dt == GLV_F64) return mass_bwd_typed<double>(co, n, a, b, gm, ga, gb, s);
+  return mass_bwd_typed<float>(co, n, a, b, gm, ga, gb, s);
+}
+
+hipError_t launch_boost(glv_dtype dt, int64_t n, const void* const x[4], const void* const beta[3],
+                        int64_t bs, void* const y[4], hipStream_t s) {
+  if (dt == GLV_F64) return boost_typed<double>(n, x, beta, bs, y, s);
+  return boost_typed<float>(n, x, beta, bs, y, s);
+}
+
+hipError_t launch_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4],
+                            const void* const beta[3], int64_t bs, const void* const gy[4],
+                            void* const gx[4], void* const gb[3], hipStream_t s) {
+  if (dt == GLV_F64) return boost_bwd_typed<double>(n, x, beta, bs, gy, gx, gb, s);
+  return boost_bwd_typed<float>(n, x, beta, bs, gy, gx, gb, s);
+}
+
+}  // namespace glv

@@ -1,0 +1,773 @@
+// Jagged (CSR) event kernels for gfx950: pair-offset scan, offset checks,
+// and the one-launch per-event reduction -- each event's total 4-vector,
+// its mass and the masses of all its particle pairs (the pair mass of
+// GenVectorX Fig. 1 applied to every i < j inside an event) -- with its
+// reverse mode.
+//
+// Work decomposition of the reduction.  A workgroup takes a tile of
+// consecutive events.  Their particles are contiguous in the columns, so the
+// workgroup streams them once (coalesced), converts each particle once and
+// stages the results in LDS in event-aligned chunks of at most
+// `lds_particles` particles.  Then
+//   * one lane per event sums its particles in CSR order (totals, and the
+//     event mass of the plain mode);
+//   * the chunk's pairs -- contiguous in the output too -- are split into
+//     equal contiguous slices, one per wavefront; lanes take consecutive pair
+//     indices, locate their event by binary search over the staged pair
+//     offsets, decode (i, j) from the in-event rank and store the pair mass
+//     (consecutive lanes write consecutive addresses);
+//   * in the compensated mode the event mass is
+//     m^2 = sum_i M_i^2 + 2 sum_{i<j} K_ij (all terms >= 0); each wavefront
+//     folds its lanes' K_ij by a segmented shuffle scan keyed by event and
+//     adds the segment sums to a per-(wavefront, event) LDS slot, and the
+//     event lane adds the slots in wavefront order: the result depends on
+//     the tiling only, never on timing.
+// An event with more particles than fit in LDS is handled by the whole
+// workgroup straight from global memory (correct for any size, slower).
+#include "glv_device.h"
+#include "glv_launch.h"
+
+namespace glv {
+namespace {
+
+__device__ __forceinline__ int64_t npairs(int64_t c) { return c * (c - 1) / 2; }
+
+// ------------------------------------------------------------ pair offsets
+
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 4;
+
+// Exclusive scan of n_e (n_e - 1)/2 by one workgroup walking the events in
+// chunks of kScanBlock * kScanItems with a running carry.
+__global__ __launch_bounds__(kScanBlock) void k_pair_offsets(const int64_t* __restrict__ off,
+                                                             int64_t* __restrict__ po, int64_t ne) {
+  __shared__ int64_t wsum[kScanBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  constexpr int kWaves = kScanBlock / 64;
+  if (tid == 0) po[0] = 0;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < ne; base += (int64_t)kScanBlock * kScanItems) {
+    int64_t c[kScanItems];
+    int64_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      int64_t e = base + (int64_t)tid * kScanItems + j;
+      c[j] = (e < ne) ? npairs(off[e + 1] - off[e]) : 0;
+      local += c[j];
+    }
+    int64_t x = local;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int64_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+      int64_t v = (lane < kWaves) ? wsum[lane] : 0;
+#pragma unroll
+      for (int d = 1; d < kWaves; d <<= 1) {
+        int64_t y = __shfl_up(v, d);
+        if (lane >= d) v += y;
+      }
+      if (lane < kWaves) wsum[lane] = v;
+    }
+    __syncthreads();
+    int64_t run = carry + (wid > 0 ? wsum[wid - 1] : 0) + (x - local);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      int64_t e = base + (int64_t)tid * kScanItems + j;
+      run += c[j];
+      if (e < ne) po[e + 1] = run;
+    }
+    carry += wsum[kWaves - 1];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_validate_offsets(const int64_t* __restrict__ off, int64_t ne,
+                                                          int64_t np, long long* bad) {
+  long long cnt = 0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e <= ne; e += stride) {
+    int64_t v = off[e];
+    if (e == 0 && v != 0) ++cnt;
+    if (e == ne && v != np) ++cnt;
+    if (e < ne && off[e + 1] < v) ++cnt;
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd((unsigned long long*)bad, (unsigned long long)cnt);
+}
+
+// --------------------------------------------------------------- helpers
+
+// i of the pair with in-event rank r among n particles (lexicographic i < j):
+// the largest i with R(i) = i (2n - i - 1)/2 <= r.
+__device__ __forceinline__ int64_t row_start(int64_t i, int64_t n) { return i * (2 * n - i - 1) / 2; }
+
+__device__ __forceinline__ void decode_pair(int64_t r, int64_t n, int64_t* pi, int64_t* pj) {
+  double b = (double)(2 * n - 1);
+  int64_t i = (int64_t)((b - sqrt(b * b - 8.0 * (double)r)) * 0.5);
+  if (i < 0) i = 0;
+  if (i > n - 2) i = n - 2;
+  while (i > 0 && row_start(i, n) > r) --i;
+  while (i < n - 2 && row_start(i + 1, n) <= r) ++i;
+  *pi = i;
+  *pj = i + 1 + (r - row_start(i, n));
+}
+
+// Fast decode for events staged in LDS (n <= 4096): the same search in FP32.
+__device__ __forceinline__ void decode_pair_small(int r, int n, int* pi, int* pj) {
+  float b = (float)(2 * n - 1);
+  int i = (int)((b - sqrtf(fmaxf(b * b - 8.0f * (float)r, 0.0f))) * 0.5f);
+  i = max(0, min(i, n - 2));
+  while (i > 0 && i * (2 * n - i - 1) / 2 > r) --i;
+  while (i < n - 2 && (i + 1) * (2 * n - i - 2) / 2 <= r) ++i;
+  *pi = i;
+  *pj = i + 1 + (r - i * (2 * n - i - 1) / 2);
+}
+
+// Last index e in [lo, hi) with a[e] <= key (a non-decreasing, a[lo] <= key).
+__device__ __forceinline__ int search_le(const int64_t* a, int lo, int hi, int64_t key) {
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] <= key)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Per-particle staged values.
+//   plain:        px py pz E
+//   compensated:  px py pz E  pt eta phi M  mt delta
+template <typename T, int MODE>
+struct Stage {
+  static constexpr int kCols = (MODE == GLV_COMPENSATED) ? 10 : 4;
+  T* col[kCols];
+};
+
+template <typename T, int COORDS, int MODE>
+__device__ __forceinline__ void stage_particle(const Cols4<T>& p, int64_t gi, const Stage<T, MODE>& s,
+                                               int slot) {
+  T c0 = p.c[0][gi], c1 = p.c[1][gi], c2 = p.c[2][gi], c3 = p.c[3][gi];
+  T v[4];
+  to_cart<COORDS>(c0, c1, c2, c3, v);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s.col[k][slot] = v[k];
+  if constexpr (MODE == GLV_COMPENSATED) {
+    LegC<T> L = comp_leg<T>(c0, c1, c2, c3);
+    s.col[4][slot] = c0;
+    s.col[5][slot] = c1;
+    s.col[6][slot] = c2;
+    s.col[7][slot] = c3;
+    s.col[8][slot] = L.mt;
+    s.col[9][slot] = L.delta;
+  }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ LegC<T> staged_leg(const Stage<T, MODE>& s, int slot) {
+  LegC<T> L;
+  L.pt = s.col[4][slot];
+  L.eta = s.col[5][slot];
+  L.phi = s.col[6][slot];
+  T mass = s.col[7][slot];
+  L.m2 = mass * mass;
+  L.mt = s.col[8][slot];
+  L.delta = s.col[9][slot];
+  return L;
+}
+
+// Compensated pair mass and K = E_i E_j - p_i.p_j (as double) from two legs,
+// with the FP64 redo of an FP32 pair whose error bound is too large.
+template <typename T>
+__device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma, T mb, double* kout,
+                                       unsigned* fb) {
+  T k;
+  if constexpr (sizeof(T) == 4) {
+    T bound;
+    T m2 = comp_pair_m2<T>(a, b, &k, &bound);
+    if (!(bound <= kFallbackUnits)) {
+      LegC<double> da = comp_leg<double>(a.pt, a.eta, a.phi, ma);
+      LegC<double> db = comp_leg<double>(b.pt, b.eta, b.phi, mb);
+      double kd;
+      double m2d = comp_pair_m2<double>(da, db, &kd, nullptr);
+      *kout = kd;
+      ++*fb;
+      return (T)sqrt(m2d);
+    }
+    *kout = (double)k;
+    return d_sqrt(m2);
+  } else {
+    T m2 = comp_pair_m2<T>(a, b, &k, nullptr);
+    *kout = (double)k;
+    return d_sqrt(m2);
+  }
+}
+
+// Deterministic workgroup sum of one double per thread (fixed tree).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_out(T* p, int64_t i, T v) {
+  __builtin_nontemporal_store(v, p + i);
+}
+
+// ---------------------------------------------------------------- forward
+
+struct FwdOut {
+  void* total[4];
+  void* event_m;
+  void* pair_m;
+};
+
+template <typename T, int COORDS, int MODE>
+struct FwdArgs {
+  Cols4<T> p;
+  const int64_t* off;
+  const int64_t* poff;
+  T* total[4];
+  T* event_m;
+  T* pair_m;
+  unsigned long long* fallback;
+  int64_t ne;
+  int epb;  // events per tile
+  int cap;  // particles staged per chunk
+};
+
+// One event too large for LDS: the whole workgroup, from global memory.
+template <typename T, int COORDS, int MODE>
+__device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t lo, int64_t hi, double* red,
+                          unsigned* fb) {
+  const int64_t n = hi - lo;
+  double acc[4] = {0, 0, 0, 0};
+  double msum = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    T v[4];
+    to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += (double)v[k];
+    if constexpr (MODE == GLV_COMPENSATED) msum += (double)A.p.c[3][i] * (double)A.p.c[3][i];
+  }
+  T tot[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
+  if constexpr (MODE == GLV_COMPENSATED) msum = block_sum(msum, red);
+  double ksum = 0.0;
+  const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m;
+  if (A.pair_m || want_k) {
+    const int64_t q = npairs(n);
+    const int64_t base = A.poff ? A.poff[e] : 0;
+    for (int64_t r = threadIdx.x; r < q; r += blockDim.x) {
+      int64_t i, j;
+      decode_pair(r, n, &i, &j);
+      i += lo;
+      j += lo;
+      T m;
+      if constexpr (MODE == GLV_COMPENSATED) {
+        LegC<T> a = comp_leg<T>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i]);
+        LegC<T> b = comp_leg<T>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j]);
+        double kd;
+        m = comp_pair<T>(a, b, A.p.c[3][i], A.p.c[3][j], &kd, fb);
+        ksum += kd;
+      } else {
+        T va[4], vb[4], w[4];
+        to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], va);
+        to_cart<COORDS>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j], vb);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = va[k] + vb[k];
+        m = mass_of(w);
+      }
+      if (A.pair_m) store_out(A.pair_m, base + r, m);
+    }
+    if (want_k) ksum = block_sum(ksum, red);
+  }
+  if (threadIdx.x == 0) {
+    if (A.total[0]) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) A.total[k][e] = tot[k];
+    }
+    if (A.event_m) {
+      if constexpr (MODE == GLV_COMPENSATED)
+        A.event_m[e] = (T)sqrt(msum + 2.0 * ksum);
+      else
+        A.event_m[e] = mass_of(tot);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int COORDS, int MODE>
+__global__ __launch_bounds__(1024) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int epb = A.epb, cap = A.cap;
+  const int nwaves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // LDS: s_off[epb+1], s_poff[epb+1] (int64); red[16], acc[nwaves*epb] (double);
+  //      staged particle columns (T).
+  int64_t* s_off = reinterpret_cast<int64_t*>(lds);
+  int64_t* s_poff = s_off + (epb + 1);
+  double* red = reinterpret_cast<double*>(s_poff + (epb + 1));
+  double* acc = red + 16;
+  T* colbase = reinterpret_cast<T*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
+  Stage<T, MODE> st;
+#pragma unroll
+  for (int k = 0; k < Stage<T, MODE>::kCols; ++k) st.col[k] = colbase + (size_t)k * cap;
+
+  const bool want_pairs = A.pair_m != nullptr;
+  const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m != nullptr;
+  unsigned fb = 0;
+  const int64_t ntiles = (A.ne + epb - 1) / epb;
+
+  if constexpr (MODE == GLV_COMPENSATED) {
+    for (int i = threadIdx.x; i < nwaves * epb; i += blockDim.x) acc[i] = 0.0;
+  }
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t e0 = tile * epb;
+    const int nev = (int)min((int64_t)epb, A.ne - e0);
+    for (int i = threadIdx.x; i <= nev; i += blockDim.x) {
+      s_off[i] = A.off[e0 + i];
+      if (want_pairs || want_k) s_poff[i] = A.poff[e0 + i];
+    }
+    __syncthreads();
+    int ca = 0;
+    while (ca < nev) {
+      if (s_off[ca + 1] - s_off[ca] > cap) {
+        big_event<T, COORDS, MODE>(A, e0 + ca, s_off[ca], s_off[ca + 1], red, &fb);
+        ++ca;
+        continue;
+      }
+      // largest cb with s_off[cb] - s_off[ca] <= cap (cb > ca)
+      const int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
+      const int64_t pbase = s_off[ca];
+      const int np = (int)(s_off[cb] - pbase);
+      for (int t = threadIdx.x; t < np; t += blockDim.x) stage_particle<T, COORDS, MODE>(A.p, pbase + t, st, t);
+      __syncthreads();
+
+      // one lane per event: totals in CSR order, plain event mass
+      double msum = 0.0;
+      const int my = ca + (int)threadIdx.x;
+      if (my < cb) {
+        const int lo = (int)(s_off[my] - pbase), hi = (int)(s_off[my + 1] - pbase);
+        T tot[4];
+        if constexpr (sizeof(T) == 4) {
+          double d[4] = {0, 0, 0, 0};
+          for (int t = lo; t < hi; ++t)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] += (double)st.col[k][t];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tot[k] = T(0);
+          for (int t = lo; t < hi; ++t)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tot[k] += st.col[k][t];
+        }
+        if constexpr (MODE == GLV_COMPENSATED) {
+          for (int t = lo; t < hi; ++t) msum += (double)st.col[7][t] * (double)st.col[7][t];
+        }
+        const int64_t e = e0 + my;
+        if (A.total[0]) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) store_out(A.total[k], e, tot[k]);
+        }
+        if constexpr (MODE != GLV_COMPENSATED) {
+          if (A.event_m) store_out(A.event_m, e, mass_of(tot));
+        }
+      }
+
+      // pairs: one contiguous slice of the chunk's pairs per wavefront
+      if (want_pairs || want_k) {
+        const int64_t q0 = s_poff[ca];
+        const int64_t q = s_poff[cb] - q0;
+        const int64_t lo = q * wid / nwaves, hi = q * (wid + 1) / nwaves;
+        for (int64_t it = lo; it < hi; it += 64) {
+          const int64_t r = it + lane;
+          const bool valid = r < hi;
+          int ev = 0;
+          double kd = 0.0;
+          if (valid) {
+            const int64_t k = q0 + r;
+            ev = search_le(s_poff, ca, cb, k);
+            const int n = (int)(s_off[ev + 1] - s_off[ev]);
+            int i, j;
+            decode_pair_small((int)(k - s_poff[ev]), n, &i, &j);
+            const int si = (int)(s_off[ev] - pbase) + i, sj = (int)(s_off[ev] - pbase) + j;
+            T m;
+            if constexpr (MODE == GLV_COMPENSATED) {
+              LegC<T> a = staged_leg<T, MODE>(st, si), b = staged_leg<T, MODE>(st, sj);
+              m = comp_pair<T>(a, b, st.col[7][si], st.col[7][sj], &kd, &fb);
+            } else {
+              T w[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) w[c] = st.col[c][si] + st.col[c][sj];
+              m = mass_of(w);
+            }
+            if (want_pairs) store_out(A.pair_m, k, m);
+          }
+          if constexpr (MODE == GLV_COMPENSATED) {
+            if (want_k) {
+              // segmented inclusive scan of kd keyed by event (keys ascend with lane)
+              int key = valid ? ev : 0x7fffffff;
+#pragma unroll
+              for (int d = 1; d < 64; d <<= 1) {
+                double y = __shfl_up(kd, d);
+                int ky = __shfl_up(key, d);
+                if (lane >= d && ky == key) kd += y;
+              }
+              int knext = __shfl_down(key, 1);
+              bool seg_end = valid && (lane == 63 || knext != key);
+              if (seg_end) acc[wid * epb + (ev - 0)] += kd;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if constexpr (MODE == GLV_COMPENSATED) {
+        if (want_k && my < cb) {
+          double ks = 0.0;
+          for (int w = 0; w < nwaves; ++w) {
+            ks += acc[w * epb + my];
+            acc[w * epb + my] = 0.0;
+          }
+          store_out(A.event_m, e0 + my, (T)sqrt(msum + 2.0 * ks));
+        }
+      }
+      __syncthreads();
+      ca = cb;
+    }
+  }
+  if constexpr (MODE == GLV_COMPENSATED && sizeof(T) == 4) {
+    if (A.fallback) {
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
+      if (lane == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
+    }
+  }
+}
+
+// --------------------------------------------------------------- backward
+
+template <typename T, int COORDS>
+struct BwdArgs {
+  Cols4<T> p;
+  const int64_t* off;
+  const int64_t* poff;
+  const T* gt[4];
+  const T* gem;
+  const T* gpair;
+  T* gp[4];
+  int64_t ne;
+  int epb;
+  int cap;
+};
+
+// Cartesian gradient of particle i from its partners (global memory path).
+template <typename T, int COORDS>
+__device__ __forceinline__ void partner_sum_global(const BwdArgs<T, COORDS>& A, int64_t lo, int64_t n,
+                                                   int64_t pbase, int64_t ai, const T vi[4], T u[4]) {
+  for (int64_t bj = 0; bj < n; ++bj) {
+    if (bj == ai) continue;
+    const int64_t r = ai < bj ? ai : bj, c = ai < bj ? bj : ai;
+    const T g = A.gpair[pbase + row_start(r, n) + (c - r - 1)];
+    T vj[4], w[4], uw[4];
+    const int64_t j = lo + bj;
+    to_cart<COORDS>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j], vj);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = vi[k] + vj[k];
+    dmass<T>(w, mass_of(w), g, uw);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] += uw[k];
+  }
+}
+
+template <typename T, int COORDS>
+__device__ void big_event_bwd(const BwdArgs<T, COORDS>& A, int64_t e, int64_t lo, int64_t hi, double* red) {
+  const int64_t n = hi - lo;
+  // total 4-vector for the event-mass term
+  double acc[4] = {0, 0, 0, 0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    T v[4];
+    to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += (double)v[k];
+  }
+  T tot[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
+  T ut[4] = {0, 0, 0, 0};
+  if (A.gem) dmass<T>(tot, mass_of(tot), A.gem[e], ut);
+  if (A.gt[0]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ut[k] += A.gt[k][e];
+  }
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    T c0 = A.p.c[0][i], c3 = A.p.c[3][i];
+    LegJ<T> L = to_cart_j<COORDS, T>(c0, A.p.c[1][i], A.p.c[2][i], c3);
+    T u[4] = {ut[0], ut[1], ut[2], ut[3]};
+    if (A.gpair) partner_sum_global<T, COORDS>(A, lo, n, A.poff[e], i - lo, L.v, u);
+    T g[4];
+    chain_coords<COORDS, T>(L, c0, c3, u, g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_out(A.gp[k], i, g[k]);
+  }
+  __syncthreads();
+}
+
+// LDS-staged backward: per particle, Cartesian vector and Jacobian pieces.
+template <typename T, int COORDS>
+__global__ __launch_bounds__(1024) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int epb = A.epb, cap = A.cap;
+  int64_t* s_off = reinterpret_cast<int64_t*>(lds);
+  double* red = reinterpret_cast<double*>(s_off + (epb + 1));
+  T* s_ut = reinterpret_cast<T*>(red + 16);  // 4 * epb: per-event upstream in Cartesian
+  T* col = s_ut + 4 * epb;                    // 8 * cap: px py pz E cp sp sh ch
+  const int64_t ntiles = (A.ne + epb - 1) / epb;
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t e0 = tile * epb;
+    const int nev = (int)min((int64_t)epb, A.ne - e0);
+    for (int i = threadIdx.x; i <= nev; i += blockDim.x) s_off[i] = A.off[e0 + i];
+    __syncthreads();
+    int ca = 0;
+    while (ca < nev) {
+      if (s_off[ca + 1] - s_off[ca] > cap) {
+        big_event_bwd<T, COORDS>(A, e0 + ca, s_off[ca], s_off[ca + 1], red);
+        ++ca;
+        continue;
+      }
+      const int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
+      const int64_t pbase = s_off[ca];
+      const int np = (int)(s_off[cb] - pbase);
+      for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const int64_t gi = pbase + t;
+        LegJ<T> L = to_cart_j<COORDS, T>(A.p.c[0][gi], A.p.c[1][gi], A.p.c[2][gi], A.p.c[3][gi]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) col[k * cap + t] = L.v[k];
+        col[4 * cap + t] = L.cp;
+        col[5 * cap + t] = L.sp;
+        col[6 * cap + t] = L.sh;
+        col[7 * cap + t] = L.ch;
+      }
+      __syncthreads();
+      // per-event upstream: g_total + g_em dm(V)/dV
+      const int my = ca + (int)threadIdx.x;
+      if (my < cb) {
+        const int lo = (int)(s_off[my] - pbase), hi = (int)(s_off[my + 1] - pbase);
+        const int64_t e = e0 + my;
+        T ut[4] = {0, 0, 0, 0};
+        if (A.gem) {
+          T tot[4];
+          if constexpr (sizeof(T) == 4) {
+            double d[4] = {0, 0, 0, 0};
+            for (int t = lo; t < hi; ++t)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) d[k] += (double)col[k * cap + t];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tot[k] = T(0);
+            for (int t = lo; t < hi; ++t)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) tot[k] += col[k * cap + t];
+          }
+          dmass<T>(tot, mass_of(tot), A.gem[e], ut);
+        }
+        if (A.gt[0]) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ut[k] += A.gt[k][e];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_ut[k * epb + (my - ca)] = ut[k];
+      }
+      __syncthreads();
+      // one lane per particle: own upstream plus the pair terms of its partners
+      for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const int ev = search_le(s_off, ca, cb, pbase + t);
+        const int lo = (int)(s_off[ev] - pbase);
+        const int n = (int)(s_off[ev + 1] - s_off[ev]);
+        const int ai = t - lo;
+        T vi[4] = {col[t], col[cap + t], col[2 * cap + t], col[3 * cap + t]};
+        T u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = s_ut[k * epb + (ev - ca)];
+        if (A.gpair) {
+          const int64_t pb = A.poff[e0 + ev];
+          for (int bj = 0; bj < n; ++bj) {
+            if (bj == ai) continue;
+            const int r = ai < bj ? ai : bj, c = ai < bj ? bj : ai;
+            const T g = A.gpair[pb + r * (2 * n - r - 1) / 2 + (c - r - 1)];
+            const int sj = lo + bj;
+            T w[4], uw[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w[k] = vi[k] + col[k * cap + sj];
+            dmass<T>(w, mass_of(w), g, uw);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k] += uw[k];
+          }
+        }
+        LegJ<T> L;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) L.v[k] = vi[k];
+        L.cp = col[4 * cap + t];
+        L.sp = col[5 * cap + t];
+        L.sh = col[6 * cap + t];
+        L.ch = col[7 * cap + t];
+        const int64_t gi = pbase + t;
+        T g[4];
+        chain_coords<COORDS, T>(L, A.p.c[0][gi], A.p.c[3][gi], u, g);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store_out(A.gp[k], gi, g[k]);
+      }
+      __syncthreads();
+      ca = cb;
+    }
+  }
+}
+
+int grid_for(int64_t ne, int epb) {
+  int64_t tiles = (ne + epb - 1) / epb;
+  if (tiles < 1) tiles = 1;
+  if (tiles > 0x7fffffff) tiles = 0x7fffffff;
+  return (int)tiles;
+}
+
+template <typename T, int COORDS, int MODE>
+hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
+                     void* const total[4], void* em, void* pm, unsigned long long* fb, const Tiling& t,
+                     size_t lds, hipStream_t s) {
+  FwdArgs<T, COORDS, MODE> A;
+  for (int k = 0; k < 4; ++k) {
+    A.p.c[k] = (const T*)p[k];
+    A.total[k] = total ? (T*)total[k] : nullptr;
+  }
+  A.off = off;
+  A.poff = poff;
+  A.event_m = (T*)em;
+  A.pair_m = (T*)pm;
+  A.fallback = fb;
+  A.ne = ne;
+  A.epb = t.events_per_tile;
+  A.cap = t.lds_particles;
+  hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block),
+                     lds, s, A);
+  return hipGetLastError();
+}
+
+template <typename T, int COORDS>
+hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
+                     const void* const gt[4], const void* gem, const void* gpair, void* const gp[4],
+                     const Tiling& t, size_t lds, hipStream_t s) {
+  BwdArgs<T, COORDS> A;
+  for (int k = 0; k < 4; ++k) {
+    A.p.c[k] = (const T*)p[k];
+    A.gt[k] = gt ? (const T*)gt[k] : nullptr;
+    A.gp[k] = (T*)gp[k];
+  }
+  A.off = off;
+  A.poff = poff;
+  A.gem = (const T*)gem;
+  A.gpair = (const T*)gpair;
+  A.ne = ne;
+  A.epb = t.events_per_tile;
+  A.cap = t.lds_particles;
+  hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block), lds,
+                     s, A);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fwd_dt(glv_coords co, glv_mode mode, int64_t ne, const int64_t* off, const int64_t* poff,
+                  const void* const p[4], void* const total[4], void* em, void* pm, unsigned long long* fb,
+                  const Tiling& t, size_t lds, hipStream_t s) {
+  if (mode == GLV_COMPENSATED)
+    return fwd_typed<T, GLV_PTETAPHIM, GLV_COMPENSATED>(ne, off, poff, p, total, em, pm, fb, t, lds, s);
+  switch (co) {
+    case GLV_PXPYPZE:
+      return fwd_typed<T, GLV_PXPYPZE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+    case GLV_PTETAPHIM:
+      return fwd_typed<T, GLV_PTETAPHIM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+    default:
+      return fwd_typed<T, GLV_PTETAPHIE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+  }
+}
+
+template <typename T>
+hipError_t bwd_dt(glv_coords co, int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
+                  const void* const gt[4], const void* gem, const void* gpair, void* const gp[4],
+                  const Tiling& t, size_t lds, hipStream_t s) {
+  switch (co) {
+    case GLV_PXPYPZE:
+      return bwd_typed<T, GLV_PXPYPZE>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+    case GLV_PTETAPHIM:
+      return bwd_typed<T, GLV_PTETAPHIM>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+    default:
+      return bwd_typed<T, GLV_PTETAPHIE>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+  }
+}
+
+}  // namespace
+
+size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
+  size_t tsz = (dt == GLV_F64) ? 8 : 4;
+  size_t cols = (mode == GLV_COMPENSATED) ? 10 : 4;
+  size_t nwaves = (size_t)t.block / 64;
+  size_t acc = (mode == GLV_COMPENSATED) ? nwaves * (size_t)t.events_per_tile * 8 : 0;
+  return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + cols * (size_t)t.lds_particles * tsz;
+}
+
+size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
+  size_t tsz = (dt == GLV_F64) ? 8 : 4;
+  return ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + 4 * (size_t)t.events_per_tile * tsz +
+         8 * (size_t)t.lds_particles * tsz;
+}
+
+hipError_t launch_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_offsets, dim3(1), dim3(kScanBlock), 0, s, off, po, ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_offsets(int64_t ne, const int64_t* off, int64_t np, long long* bad, hipStream_t s) {
+  int64_t blocks = (ne + 1 + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)blocks), dim3(256), 0, s, off, ne, np, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
+                               const int64_t* poff, const void* const p[4], void* const total[4], void* em,
+                               void* pm, unsigned long long* fb, const Tiling& t, hipStream_t s) {
+  size_t lds = event_reduce_lds_bytes(dt, mode, t);
+  if (dt == GLV_F64) return fwd_dt<double>(co, mode, ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+  return fwd_dt<float>(co, mode, ne, off, poff, p, total, em, pm, fb, t, lds, s);
+}
+
+hipError_t launch_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,
+                                   const int64_t* poff, const void* const p[4], const void* const gt[4],
+                                   const void* gem, const void* gpair, void* const gp[4], const Tiling& t,
+                                   hipStream_t s) {
+  size_t lds = event_reduce_bwd_lds_bytes(dt, t);
+  if (dt == GLV_F64) return bwd_dt<double>(co, ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+  return bwd_dt<float>(co, ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+}
+
+}  // namespace glv

@@ -1,0 +1,267 @@
+"""Python binding of the C ABI (include/glv.h), one function per entry point
+with the same name.  Argument marshalling only: tensors are checked (same GPU,
+dtype, contiguous) and their device pointers handed to the library together
+with torch's current HIP stream; every step of the computation runs in the
+library's gfx950 kernels.  Outputs are allocated here with torch (the
+library itself never allocates).
+
+Coordinates are given as "PxPyPzE", "PtEtaPhiM" or "PtEtaPhiE"; modes as
+"plain" or "compensated".
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import P3, P4, check, glv_tiling
+
+COORDS = {"PxPyPzE": _lib.GLV_PXPYPZE, "PtEtaPhiM": _lib.GLV_PTETAPHIM, "PtEtaPhiE": _lib.GLV_PTETAPHIE}
+MODES = {"plain": _lib.GLV_PLAIN, "compensated": _lib.GLV_COMPENSATED}
+DTYPES = {torch.float32: _lib.GLV_F32, torch.float64: _lib.GLV_F64}
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _cols(ts, n_expected, dtype, device, name):
+    ts = tuple(ts)
+    for t in ts:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected tensors")
+        if t.device != device or t.dtype != dtype:
+            raise ValueError(f"{name}: all columns must be {dtype} on {device}")
+        if not t.is_contiguous() or t.dim() != 1:
+            raise ValueError(f"{name}: columns must be contiguous 1-D tensors")
+        if n_expected is not None and t.numel() != n_expected:
+            raise ValueError(f"{name}: expected {n_expected} elements, got {t.numel()}")
+    return ts
+
+
+def _dtype_code(dtype):
+    if dtype not in DTYPES:
+        raise ValueError(f"unsupported dtype {dtype}")
+    return DTYPES[dtype]
+
+
+def _coords_code(coords):
+    return COORDS[coords] if isinstance(coords, str) else int(coords)
+
+
+def _mode_code(mode):
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _check_device(t):
+    if t.device.type != "cuda":
+        raise ValueError("inputs must be GPU tensors")
+
+
+# ---------------------------------------------------------------- pair mass
+
+def glv_invariant_mass(a, b, coords="PtEtaPhiM", mode="plain", out=None, fallback_count=None):
+    """m[i] = mass(conv(a_i) + conv(b_i)).  ``fallback_count``: optional int64
+    GPU tensor of one element, incremented by the number of FP32 items the
+    compensated mode recomputed in FP64."""
+    dev, dt = a[0].device, a[0].dtype
+    _check_device(a[0])
+    n = a[0].numel()
+    a = _cols(a, n, dt, dev, "a")
+    b = _cols(b, n, dt, dev, "b")
+    m = torch.empty(n, dtype=dt, device=dev) if out is None else _cols([out], n, dt, dev, "out")[0]
+    fb = None
+    if fallback_count is not None:
+        if fallback_count.dtype != torch.int64 or fallback_count.device != dev or fallback_count.numel() != 1:
+            raise ValueError("fallback_count must be one int64 element on the inputs' device")
+        fb = fallback_count
+    lib = _lib.load()
+    check("glv_invariant_mass",
+          lib.glv_invariant_mass(_dtype_code(dt), _coords_code(coords), _mode_code(mode), n,
+                                 P4(*[t.data_ptr() for t in a]), P4(*[t.data_ptr() for t in b]), _ptr(m), _ptr(fb),
+                                 _stream(dev)))
+    return m
+
+
+def glv_invariant_mass_bwd(a, b, grad_m, coords="PtEtaPhiM"):
+    dev, dt = a[0].device, a[0].dtype
+    _check_device(a[0])
+    n = a[0].numel()
+    a = _cols(a, n, dt, dev, "a")
+    b = _cols(b, n, dt, dev, "b")
+    (grad_m,) = _cols([grad_m], n, dt, dev, "grad_m")
+    ga = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    gb = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    lib = _lib.load()
+    check("glv_invariant_mass_bwd",
+          lib.glv_invariant_mass_bwd(_dtype_code(dt), _coords_code(coords), n, P4(*[t.data_ptr() for t in a]),
+                                     P4(*[t.data_ptr() for t in b]), _ptr(grad_m),
+                                     P4(*[t.data_ptr() for t in ga]), P4(*[t.data_ptr() for t in gb]),
+                                     _stream(dev)))
+    return ga, gb
+
+
+# -------------------------------------------------------------------- boost
+
+def glv_boost(x, beta, out=None):
+    """Active boost of Cartesian (px, py, pz, E) columns by beta (3 columns of
+    n items, or of 1 element = one velocity for all).  ``out`` may be ``x``
+    itself (in place)."""
+    dev, dt = x[0].device, x[0].dtype
+    _check_device(x[0])
+    n = x[0].numel()
+    x = _cols(x, n, dt, dev, "x")
+    bs = 1 if beta[0].numel() == n else 0
+    beta = _cols(beta, n if bs else 1, dt, dev, "beta")
+    y = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4)) if out is None else _cols(out, n, dt, dev, "out")
+    lib = _lib.load()
+    check("glv_boost", lib.glv_boost(_dtype_code(dt), n, P4(*[t.data_ptr() for t in x]),
+                                     P3(*[t.data_ptr() for t in beta]), bs, P4(*[t.data_ptr() for t in y]),
+                                     _stream(dev)))
+    return y
+
+
+def glv_boost_bwd(x, beta, grad_y, want_beta=True):
+    dev, dt = x[0].device, x[0].dtype
+    _check_device(x[0])
+    n = x[0].numel()
+    x = _cols(x, n, dt, dev, "x")
+    bs = 1 if beta[0].numel() == n else 0
+    beta = _cols(beta, n if bs else 1, dt, dev, "beta")
+    gy = _cols(grad_y, n, dt, dev, "grad_y")
+    gx = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    gbeta = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(3)) if want_beta else None
+    lib = _lib.load()
+    gb_arg = P3(*[t.data_ptr() for t in gbeta]) if want_beta else None
+    check("glv_boost_bwd", lib.glv_boost_bwd(_dtype_code(dt), n, P4(*[t.data_ptr() for t in x]),
+                                             P3(*[t.data_ptr() for t in beta]), bs, P4(*[t.data_ptr() for t in gy]),
+                                             P4(*[t.data_ptr() for t in gx]), gb_arg, _stream(dev)))
+    return gx, gbeta
+
+
+# ------------------------------------------------------------ jagged events
+
+def _offsets(offsets, dev):
+    if offsets.dtype != torch.int64 or offsets.device != dev or not offsets.is_contiguous() or offsets.dim() != 1:
+        raise ValueError("offsets must be a contiguous 1-D int64 tensor on the particles' device")
+    return offsets
+
+
+def glv_pair_offsets(offsets):
+    _check_device(offsets)
+    offsets = _offsets(offsets, offsets.device)
+    ne = offsets.numel() - 1
+    po = torch.empty(ne + 1, dtype=torch.int64, device=offsets.device)
+    check("glv_pair_offsets", _lib.load().glv_pair_offsets(ne, _ptr(offsets), _ptr(po), _stream(offsets.device)))
+    return po
+
+
+def glv_validate_offsets(offsets, n_particles):
+    """Number of violations (GPU int64 tensor of one element; 0 = valid)."""
+    _check_device(offsets)
+    offsets = _offsets(offsets, offsets.device)
+    bad = torch.zeros(1, dtype=torch.int64, device=offsets.device)
+    check("glv_validate_offsets",
+          _lib.load().glv_validate_offsets(offsets.numel() - 1, _ptr(offsets), int(n_particles), _ptr(bad),
+                                           _stream(offsets.device)))
+    return bad
+
+
+def _tiling(t):
+    if t is None:
+        return None
+    if isinstance(t, glv_tiling):
+        return ctypes.byref(t)
+    block, epb, cap = t
+    return ctypes.byref(glv_tiling(block, epb, cap, 0))
+
+
+def glv_event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM", mode="plain", want_total=True,
+                     want_event_m=True, want_pair_m=True, tiling=None, fallback_count=None, n_pairs=None):
+    """Returns (total (4 tensors) or None, event_m or None, pair_m or None).
+    ``n_pairs`` (the last pair offset) avoids a device-to-host read when given."""
+    dev, dt = p[0].device, p[0].dtype
+    _check_device(p[0])
+    offsets = _offsets(offsets, dev)
+    ne = offsets.numel() - 1
+    p = _cols(p, p[0].numel(), dt, dev, "p")
+    need_po = want_pair_m or (_mode_code(mode) == _lib.GLV_COMPENSATED and want_event_m)
+    if need_po and pair_offsets is None:
+        pair_offsets = glv_pair_offsets(offsets)
+    if pair_offsets is not None:
+        pair_offsets = _offsets(pair_offsets, dev)
+    total = tuple(torch.empty(ne, dtype=dt, device=dev) for _ in range(4)) if want_total else None
+    em = torch.empty(ne, dtype=dt, device=dev) if want_event_m else None
+    pm = None
+    if want_pair_m:
+        if n_pairs is None:
+            n_pairs = int(pair_offsets[-1].item()) if ne > 0 else 0
+        pm = torch.empty(int(n_pairs), dtype=dt, device=dev)
+    lib = _lib.load()
+    check("glv_event_reduce",
+          lib.glv_event_reduce(_dtype_code(dt), _coords_code(coords), _mode_code(mode), ne, _ptr(offsets),
+                               _ptr(pair_offsets), P4(*[t.data_ptr() for t in p]),
+                               P4(*[t.data_ptr() for t in total]) if total else None, _ptr(em), _ptr(pm),
+                               _ptr(fallback_count), _tiling(tiling), _stream(dev)))
+    return total, em, pm
+
+
+def glv_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None, grad_event_m=None, grad_pair_m=None,
+                         coords="PtEtaPhiM", tiling=None):
+    dev, dt = p[0].device, p[0].dtype
+    _check_device(p[0])
+    offsets = _offsets(offsets, dev)
+    ne = offsets.numel() - 1
+    n = p[0].numel()
+    p = _cols(p, n, dt, dev, "p")
+    if grad_pair_m is not None and pair_offsets is None:
+        pair_offsets = glv_pair_offsets(offsets)
+    gt = _cols(grad_total, ne, dt, dev, "grad_total") if grad_total is not None else None
+    gem = _cols([grad_event_m], ne, dt, dev, "grad_event_m")[0] if grad_event_m is not None else None
+    gpm = _cols([grad_pair_m], None, dt, dev, "grad_pair_m")[0] if grad_pair_m is not None else None
+    gp = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    lib = _lib.load()
+    check("glv_event_reduce_bwd",
+          lib.glv_event_reduce_bwd(_dtype_code(dt), _coords_code(coords), ne, _ptr(offsets), _ptr(pair_offsets),
+                                   P4(*[t.data_ptr() for t in p]), P4(*[t.data_ptr() for t in gt]) if gt else None,
+                                   _ptr(gem), _ptr(gpm), P4(*[t.data_ptr() for t in gp]), _tiling(tiling),
+                                   _stream(dev)))
+    return gp
+
+
+def glv_autotune_event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM", mode="plain"):
+    """Times candidate tilings on these inputs, keeps the fastest for this
+    process (device, dtype, coords, mode) and returns it as (block,
+    events_per_tile, lds_particles)."""
+    dev, dt = p[0].device, p[0].dtype
+    _check_device(p[0])
+    offsets = _offsets(offsets, dev)
+    ne = offsets.numel() - 1
+    if pair_offsets is None:
+        pair_offsets = glv_pair_offsets(offsets)
+    n_pairs = int(pair_offsets[-1].item()) if ne > 0 else 0
+    total = tuple(torch.empty(ne, dtype=dt, device=dev) for _ in range(4))
+    em = torch.empty(ne, dtype=dt, device=dev)
+    pm = torch.empty(n_pairs, dtype=dt, device=dev)
+    best = glv_tiling()
+    check("glv_autotune_event_reduce",
+          _lib.load().glv_autotune_event_reduce(_dtype_code(dt), _coords_code(coords), _mode_code(mode), ne,
+                                                _ptr(offsets), _ptr(pair_offsets), P4(*[t.data_ptr() for t in p]),
+                                                P4(*[t.data_ptr() for t in total]), _ptr(em), _ptr(pm),
+                                                ctypes.byref(best), _stream(dev)))
+    return (best.block, best.events_per_tile, best.lds_particles)
+
+
+def glv_current_tiling(dtype=torch.float64, coords="PtEtaPhiM", mode="plain"):
+    t = glv_tiling()
+    check("glv_current_tiling", _lib.load().glv_current_tiling(_dtype_code(dtype), _coords_code(coords),
+                                                               _mode_code(mode), ctypes.byref(t)))
+    return (t.block, t.events_per_tile, t.lds_particles)
+
+
+def glv_abi_version():
+    return _lib.load().glv_abi_version()

@@ -1,0 +1,129 @@
+"""The C ABI on the host (no GPU needed): the library loads, exports every
+symbol include/glv.h declares, and rejects invalid arguments with the
+documented status before any kernel could be launched.  Pointers here are
+fake addresses; no call below reaches a launch."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2312_02756_amd import _lib, build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glv.h")
+
+OK, NULL, SIZE, DTYPE, COORDS, MODE, ALIAS, STRIDE, OFFSETS, TILING = range(10)
+GiB = 1 << 30
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(build.library_path()):
+        build.build()
+    return _lib.load()
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(glv_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_strings(lib):
+    assert lib.glv_abi_version() == 1
+    for code in range(11):
+        assert lib.glv_status_str(code)
+    assert lib.glv_status_str(0) == b"ok"
+
+
+def cols(base, k=4):
+    arr = _lib.P4 if k == 4 else _lib.P3
+    return arr(*[base + i * GiB for i in range(k)])
+
+
+A, B, M = 16 * GiB, 32 * GiB, 48 * GiB
+N = 1000
+
+
+def test_mass_validation(lib):
+    f = lib.glv_invariant_mass
+    assert f(7, 1, 0, N, cols(A), cols(B), M, None, None) == DTYPE
+    assert f(2, 9, 0, N, cols(A), cols(B), M, None, None) == COORDS
+    assert f(2, 0, 1, N, cols(A), cols(B), M, None, None) == MODE   # compensated needs PtEtaPhiM
+    assert f(2, 2, 1, N, cols(A), cols(B), M, None, None) == MODE
+    assert f(2, 1, 5, N, cols(A), cols(B), M, None, None) == MODE
+    assert f(2, 1, 0, -1, cols(A), cols(B), M, None, None) == SIZE
+    bad = cols(A)
+    bad[2] = None
+    assert f(2, 1, 0, N, bad, cols(B), M, None, None) == NULL
+    assert f(2, 1, 0, N, cols(A), cols(B), None, None, None) == NULL
+    assert f(2, 1, 0, N, cols(A), cols(B), A + 8 * (N - 1), None, None) == ALIAS  # m overlaps a[0]
+    assert f(2, 1, 0, 0, cols(A), cols(B), M, None, None) == OK                    # empty: nothing to do
+
+
+def test_mass_bwd_validation(lib):
+    f = lib.glv_invariant_mass_bwd
+    G = 64 * GiB
+    assert f(2, 1, -3, cols(A), cols(B), M, cols(G), cols(G + 8 * GiB), None) == SIZE
+    assert f(2, 1, N, cols(A), cols(B), None, cols(G), cols(G + 8 * GiB), None) == NULL
+    assert f(2, 1, N, cols(A), cols(B), M, cols(G), cols(G), None) == ALIAS          # grad_a = grad_b
+    assert f(2, 1, N, cols(A), cols(B), M, cols(A), cols(G), None) == ALIAS          # grad over input
+    assert f(2, 1, 0, cols(A), cols(B), M, cols(G), cols(G + 8 * GiB), None) == OK
+
+
+def test_boost_validation(lib):
+    f = lib.glv_boost
+    X, BETA, Y = A, B, 80 * GiB
+    assert f(2, N, cols(X), cols(BETA, 3), 2, cols(Y), None) == STRIDE
+    assert f(2, N, cols(X), cols(BETA, 3), -1, cols(Y), None) == STRIDE
+    y = cols(X)
+    y[0], y[1] = y[1], y[0]
+    assert f(2, N, cols(X), cols(BETA, 3), 1, y, None) == ALIAS                      # permuted in place
+    assert f(2, N, cols(X), cols(X, 3), 1, cols(X), None) == ALIAS                   # beta inside y
+    assert f(2, 0, cols(X), cols(BETA, 3), 1, cols(X), None) == OK                   # in place, empty
+    g = lib.glv_boost_bwd
+    assert g(2, N, cols(X), cols(BETA, 3), 0, cols(Y), cols(Y + 8 * GiB), cols(Y + 16 * GiB, 3), None) == STRIDE
+    assert g(2, N, None, cols(BETA, 3), 1, cols(Y), cols(Y + 8 * GiB), cols(Y + 16 * GiB, 3), None) == NULL
+    assert g(2, 0, None, cols(BETA, 3), 0, cols(Y), cols(Y + 8 * GiB), None, None) == OK
+
+
+def test_jagged_validation(lib):
+    OFF, PO, P, T, EM, PM = A, B, 100 * GiB, 140 * GiB, 180 * GiB, 190 * GiB
+    f = lib.glv_event_reduce
+    assert f(2, 1, 0, 10, None, PO, cols(P), cols(T), EM, PM, None, None, None) == OFFSETS
+    assert f(2, 1, 0, 10, OFF, None, cols(P), cols(T), EM, PM, None, None, None) == OFFSETS  # pairs need po
+    assert f(2, 1, 1, 10, OFF, None, cols(P), None, EM, None, None, None, None) == OFFSETS   # comp event mass
+    assert f(2, 0, 1, 10, OFF, PO, cols(P), cols(T), EM, PM, None, None, None) == MODE
+    assert f(2, 1, 0, -2, OFF, PO, cols(P), cols(T), EM, PM, None, None, None) == SIZE
+    assert f(2, 1, 0, 10, OFF, PO, cols(P), cols(T), OFF, PM, None, None, None) == ALIAS    # event_m over offsets
+    for bad in ((100, 0, 0, 0), (256, 512, 0, 0), (256, 128, 32, 0), (256, 128, 8192, 0), (256, 128, 1024, 1),
+                (1024, 1024, 4096, 0)):
+        t = _lib.glv_tiling(*bad)
+        assert f(2, 1, 0, 10, OFF, PO, cols(P), cols(T), EM, PM, None, ctypes.byref(t), None) == TILING, bad
+    g = lib.glv_pair_offsets
+    assert g(-1, OFF, PO, None) == SIZE
+    assert g(10, None, PO, None) == NULL
+    assert g(10, OFF, OFF + 8, None) == ALIAS
+    h = lib.glv_event_reduce_bwd
+    assert h(2, 1, 10, OFF, None, cols(P), None, None, PM, cols(T), None, None) == OFFSETS
+    assert h(2, 1, 10, OFF, PO, cols(P), None, None, None, cols(P), None, None) == ALIAS
+    v = lib.glv_validate_offsets
+    assert v(10, OFF, -1, EM, None) == SIZE
+    assert v(10, OFF, 5, None, None) == NULL
+
+
+def test_current_tiling_default(lib):
+    t = _lib.glv_tiling()
+    assert lib.glv_current_tiling(2, 1, 0, ctypes.byref(t)) == OK
+    assert t.block in (64, 128, 256, 512, 1024) and 1 <= t.events_per_tile <= t.block
+    assert 64 <= t.lds_particles <= 4096
+    assert lib.glv_current_tiling(2, 0, 1, ctypes.byref(t)) == MODE

@@ -1,0 +1,232 @@
+"""GPU parity of the jagged per-event reduction (one launch: totals, event
+mass, all pair masses), its reverse mode, the pair-offset scan, the offset
+check and the autotuner, against the CPU oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import event_abs_scale, gpu, host, widened
+from tolerances import U32, U64, mass_tol_comp_f32, mass_tol_f32, mass_tol_f64, worst
+
+pytestmark = pytest.mark.gpu
+
+glv = pytest.importorskip("paper_2312_02756_amd.glv")
+
+DEV = "cuda:0"
+
+
+def _off(off):
+    return torch.from_numpy(off).to(DEV)
+
+
+def _events(ne, seed, mean=8.0, cap=64):
+    return synth.jagged_events(synth.rng(seed), ne, mean=mean, cap=cap)
+
+
+def _pairs_or(off, p, coords, accurate=False):
+    """Oracle pair masses and their scales by brute force over i < j."""
+    ii, jj = [np.zeros(0, dtype=np.int64)], [np.zeros(0, dtype=np.int64)]
+    for e in range(off.size - 1):
+        n = int(off[e + 1] - off[e])
+        if n >= 2:
+            r, c = np.triu_indices(n, 1)  # row-major upper triangle: lexicographic i < j
+            ii.append(off[e] + r)
+            jj.append(off[e] + c)
+    ii, jj = np.concatenate(ii), np.concatenate(jj)
+    a, b = tuple(c[ii] for c in p), tuple(c[jj] for c in p)
+    if accurate:
+        return oracle.mass_accurate(a, b), None
+    return oracle.mass_plain(coords, a, b, scale=True)
+
+
+def _check_forward(off, p, dtype, coords, mode, total, em, pm, label):
+    wp = widened(p, dtype)
+    tot_or, em_or, pm_or, po = oracle.event_reduce(coords, off, wp,
+                                                   mode=oracle.ACCURATE if mode == "compensated" else oracle.PLAIN)
+    cart = oracle.to_cartesian(coords, wp)
+    S_abs, sums = event_abs_scale(cart, off)
+    n = np.maximum(np.diff(off), 1)
+    u = U64 if dtype == torch.float64 else U32
+    # totals
+    for k in range(4):
+        tol = (1e-12 * sums[k]) if dtype == torch.float64 else (4 * U32 * sums[k] + U32 * np.abs(tot_or[k]))
+        r, i = worst(np.abs(host(total[k]).astype(np.float64) - tot_or[k]), tol + 1e-300)
+        assert r <= 1.0, (label, "total", k, i)
+    # event masses
+    if mode == "compensated":
+        tol = mass_tol_comp_f32(em_or) if dtype == torch.float32 else 64 * U64 * em_or + 1e-300
+    else:
+        tol = 1e-12 * np.abs(em_or) + 64 * u * n * S_abs / (2 * np.maximum(np.abs(em_or), 1e-300))
+        if dtype == torch.float32:
+            tol = tol + 1e-5 * np.abs(em_or)
+    r, i = worst(np.abs(host(em).astype(np.float64) - em_or), tol)
+    assert r <= 1.0, (label, "event_m", i, host(em)[i], em_or[i], off[i], off[i + 1])
+    # pair masses
+    assert pm.numel() == pm_or.size
+    if mode == "compensated":
+        tol = mass_tol_comp_f32(pm_or) if dtype == torch.float32 else 64 * U64 * pm_or + 1e-300
+    else:
+        _, s = _pairs_or(off, wp, coords)
+        tol = mass_tol_f64(pm_or, s) if dtype == torch.float64 else mass_tol_f32(pm_or, s)
+    r, i = worst(np.abs(host(pm).astype(np.float64) - pm_or), tol)
+    assert r <= 1.0, (label, "pair_m", i)
+    return po
+
+
+def test_pair_offsets_bitwise():
+    for ne in (0, 1, 5, 4095, 4096, 4097, 100000):
+        off, _ = _events(ne, 700 + ne)
+        po = host(glv.glv_pair_offsets(_off(off)))
+        assert np.array_equal(po, oracle.pair_offsets(off)), ne
+
+
+def test_validate_offsets():
+    off, p = _events(1000, 701)
+    assert int(glv.glv_validate_offsets(_off(off), p[0].size).item()) == 0
+    bad = off.copy()
+    bad[10], bad[11] = bad[11] + 5, bad[10]  # not monotone
+    assert int(glv.glv_validate_offsets(_off(bad), p[0].size).item()) > 0
+    assert int(glv.glv_validate_offsets(_off(off), p[0].size + 1).item()) == 1
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PtEtaPhiE"])
+def test_event_reduce_plain(coords, dtype):
+    off, p = _events(3000, 702)
+    if coords != "PtEtaPhiM":
+        c = oracle.to_cartesian("PtEtaPhiM", p)
+        p = c if coords == "PxPyPzE" else (p[0], p[1], p[2], c[3])
+    total, em, pm = glv.glv_event_reduce(gpu(p, dtype), _off(off), coords=coords)
+    _check_forward(off, p, dtype, coords, "plain", total, em, pm, f"{coords} {dtype}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_event_reduce_compensated(dtype):
+    off, p = _events(3000, 703)
+    fb = torch.zeros(1, dtype=torch.int64, device=DEV)
+    total, em, pm = glv.glv_event_reduce(gpu(p, dtype), _off(off), mode="compensated", fallback_count=fb)
+    _check_forward(off, p, dtype, "PtEtaPhiM", "compensated", total, em, pm, f"comp {dtype}")
+
+
+def test_event_reduce_edge_events():
+    """Empty events, single particles, events larger than the LDS capacity
+    (handled from global memory) and a trailing empty event."""
+    counts = np.array([0, 1, 2, 0, 3, 700, 64, 0, 1, 65, 1500, 2, 0], dtype=np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    a, _ = synth.pairs_generic(synth.rng(704), int(off[-1]))
+    for dtype in (torch.float64, torch.float32):
+        for tiling in (None, (256, 4, 512), (64, 1, 64), (1024, 13, 1024)):
+            total, em, pm = glv.glv_event_reduce(gpu(a, dtype), _off(off), tiling=tiling)
+            _check_forward(off, a, dtype, "PtEtaPhiM", "plain", total, em, pm, f"edge {dtype} {tiling}")
+        total, em, pm = glv.glv_event_reduce(gpu(a, torch.float32), _off(off), mode="compensated",
+                                             tiling=(128, 8, 256))
+        _check_forward(off, a, torch.float32, "PtEtaPhiM", "compensated", total, em, pm, "edge comp")
+
+
+def test_tilings_give_identical_pair_masses_and_totals():
+    off, p = _events(20000, 705)
+    gp, go = gpu(p, torch.float64), _off(off)
+    ref = None
+    for tiling in [(256, 128, 1024), (128, 32, 256), (512, 512, 1536), (64, 64, 512), (1024, 100, 1024)]:
+        total, em, pm = glv.glv_event_reduce(gp, go, tiling=tiling)
+        out = [host(pm)] + [host(t) for t in total] + [host(em)]
+        if ref is None:
+            ref = out
+        else:
+            for u, v in zip(out, ref):
+                assert np.array_equal(u, v), tiling
+    # compensated FP32: pair masses identical; event masses reproducible per tiling
+    gp32 = gpu(p, torch.float32)
+    ref = None
+    for tiling in [(256, 128, 1024), (128, 32, 256), (512, 256, 512)]:
+        _, em1, pm1 = glv.glv_event_reduce(gp32, go, mode="compensated", tiling=tiling)
+        _, em2, pm2 = glv.glv_event_reduce(gp32, go, mode="compensated", tiling=tiling)
+        assert torch.equal(em1, em2) and torch.equal(pm1, pm2)
+        if ref is None:
+            ref = host(pm1)
+        else:
+            assert np.array_equal(host(pm1), ref), tiling
+
+
+def test_event_reduce_full_size_sampled():
+    """2^20 events (Poisson(8), clipped at 64) in the benchmark's launch shape;
+    a sample of events checked against the oracle, every pair of each."""
+    off, p = _events(1 << 20, synth.JAGGED)
+    po_all = oracle.pair_offsets(off)
+    for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
+        total, em, pm = glv.glv_event_reduce(gpu(p, dtype), _off(off), mode=mode)
+        total, em, pm = host(total), host(em), host(pm)
+        assert pm.size == po_all[-1]
+        sel = np.sort(np.random.default_rng(11).choice(off.size - 1, 20000, replace=False))
+        # rebuild a compact CSR of the sampled events
+        cnt = off[sel + 1] - off[sel]
+        soff = np.zeros(sel.size + 1, dtype=np.int64)
+        soff[1:] = np.cumsum(cnt)
+        pidx = np.concatenate([np.arange(off[e], off[e + 1]) for e in sel])
+        sp = tuple(c[pidx] for c in p)
+        pair_idx = np.concatenate([np.arange(po_all[e], po_all[e + 1]) for e in sel])
+        stot = tuple(torch.from_numpy(t[sel]) for t in total)
+        _check_forward(soff, sp, dtype, "PtEtaPhiM", mode, stot, torch.from_numpy(em[sel]),
+                       torch.from_numpy(pm[pair_idx]), f"full {mode}")
+
+
+def test_autotune_picks_a_valid_tiling():
+    off, p = _events(1 << 16, 706)
+    gp, go = gpu(p, torch.float64), _off(off)
+    best = glv.glv_autotune_event_reduce(gp, go)
+    assert best[0] in (128, 256, 512) and 1 <= best[1] <= best[0]
+    assert glv.glv_current_tiling(torch.float64, "PtEtaPhiM", "plain") == best
+    total, em, pm = glv.glv_event_reduce(gp, go)
+    _, em2, pm2 = glv.glv_event_reduce(gp, go, tiling=best)
+    assert torch.equal(pm, pm2) and torch.equal(em, em2)
+
+
+# ---------------------------------------------------------------- backward
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE"])
+def test_event_reduce_bwd(coords, dtype):
+    counts = np.concatenate([np.minimum(synth.rng(707).poisson(8, 2000), 64), [0, 1, 300, 2]]).astype(np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    g = synth.rng(708)
+    p, _ = synth.pairs_generic(g, int(off[-1]))
+    if coords == "PxPyPzE":
+        p = oracle.to_cartesian("PtEtaPhiM", p)
+    ne = counts.size
+    po = oracle.pair_offsets(off)
+    gt = synth.upstream(g, ne, 4)
+    gem = g.standard_normal(ne)
+    gpr = g.standard_normal(int(po[-1]))
+    wp = widened(p, dtype)
+    want = oracle.event_reduce_vjp(coords, off, wp, widened(gt, dtype), widened([gem], dtype)[0],
+                                   widened([gpr], dtype)[0])
+    # scale: the same vjp with absolute upstreams and conditioning of the masses
+    S_abs, _ = event_abs_scale(oracle.to_cartesian(coords, wp), off)
+    u = U64 if dtype == torch.float64 else U32
+    base = 1e-12 if dtype == torch.float64 else 1e-5
+    for tiling in (None, (128, 16, 128)):
+        got = glv.glv_event_reduce_bwd(gpu(p, dtype), _off(off), grad_total=gpu(gt, dtype),
+                                       grad_event_m=gpu([gem], dtype)[0], grad_pair_m=gpu([gpr], dtype)[0],
+                                       coords=coords, tiling=tiling)
+        got = [host(c).astype(np.float64) for c in got]
+        # per particle: infinity norm over its 4 components, conditioning of its event
+        cnt = np.diff(off)
+        ev = np.repeat(np.arange(ne), cnt)
+        em_or = oracle.event_reduce(coords, off, wp)[1]
+        kappa_ev = S_abs / np.maximum(em_or ** 2, 1e-300)
+        _, s_pairs = _pairs_or(off, wp, coords)
+        pm_or = oracle.event_reduce(coords, off, wp)[2]
+        kp = s_pairs / np.maximum(pm_or ** 2, 1e-300)
+        kappa_pair_ev = np.zeros(ne)
+        pev = np.repeat(np.arange(ne), np.diff(po))
+        np.maximum.at(kappa_pair_ev, pev, kp)
+        kappa = np.maximum(kappa_ev, kappa_pair_ev)[ev] * np.maximum(cnt[ev], 1)
+        err = np.max(np.abs(np.stack(got) - np.stack(want)), axis=0)
+        ref = np.max(np.abs(np.stack(want)), axis=0)
+        r, i = worst(err, (base + 64 * u * kappa) * ref + 1e-300)
+        assert r <= 1.0, (tiling, i, [c[i] for c in got], [c[i] for c in want])
