@@ -32,8 +32,10 @@
  * Mass.  q = E^2 - |P|^2; m = sqrt(q), and m = -sqrt(-q) for a spacelike
  *   q < 0 (values are not validated: NaN in gives NaN out, |beta| >= 1 gives
  *   inf/NaN).  The derivative of m is taken as 0 where m = 0.
- * Sizes are int64_t element counts; 0 is valid and launches nothing; a
- *   negative count returns GLV_EINVAL_SIZE.
+ * Sizes are int64_t element counts; a negative count returns
+ *   GLV_EINVAL_SIZE.  A count of 0 is valid, launches nothing and reads no
+ *   pointer (they may be NULL), except that glv_pair_offsets still writes
+ *   pair_offsets[0] and glv_validate_offsets still reads offsets[0].
  * Alignment.  Any element-aligned pointer is accepted; columns aligned to 16
  *   bytes take the vectorised path.
  * Errors.  A glv_status is returned; on GLV_EHIP the HIP error code is

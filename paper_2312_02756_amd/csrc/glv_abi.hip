@@ -86,6 +86,15 @@ glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
   return t;
 }
 
+// The backward stages 8 columns per particle (vector and Jacobian pieces).
+glv::Tiling default_tiling_bwd(glv_dtype dt) {
+  glv::Tiling t;
+  t.block = 256;
+  t.events_per_tile = 128;
+  t.lds_particles = std::max(64, (int)std::min<size_t>(2048, (40 * 1024) / (8 * elem(dt))) & ~63);
+  return t;
+}
+
 constexpr size_t kMaxLds = 64 * 1024;
 
 bool block_ok(int b) { return b == 64 || b == 128 || b == 256 || b == 512 || b == 1024; }
@@ -93,7 +102,7 @@ bool block_ok(int b) { return b == 64 || b == 128 || b == 256 || b == 512 || b =
 // Resolve a user tiling (fields 0 = current choice) and validate it.
 glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,
                           glv::Tiling* out) {
-  glv::Tiling base = default_tiling(dt, mode);
+  glv::Tiling base = bwd ? default_tiling_bwd(dt) : default_tiling(dt, mode);
   if (!bwd) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
@@ -123,6 +132,7 @@ glv_status check_event_args(glv_dtype dt, glv_coords co, glv_mode mode, int64_t 
   glv_status ms = mode_ok(mode, co);
   if (ms != GLV_OK) return ms;
   if (ne < 0) return GLV_EINVAL_SIZE;
+  if (ne == 0) return GLV_OK;  // nothing is read or written
   if (!off) return GLV_EINVAL_OFFSETS;
   if (!nonnull<4>(p)) return GLV_EINVAL_NULL;
   return GLV_OK;
@@ -132,7 +142,7 @@ glv_status validate_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int
                                  const int64_t* poff, const void* const p[4], void* const total[4], void* em,
                                  void* pm) {
   glv_status st = check_event_args(dt, co, mode, ne, off, p);
-  if (st != GLV_OK) return st;
+  if (st != GLV_OK || ne == 0) return st;
   if (total && !nonnull<4>((const void* const*)total)) return GLV_EINVAL_NULL;
   if ((pm || (mode == GLV_COMPENSATED && em)) && !poff) return GLV_EINVAL_OFFSETS;
   // outputs must not overlap each other or the offsets (their lengths are
@@ -194,6 +204,7 @@ glv_status glv_invariant_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_
   glv_status ms = mode_ok(mode, co);
   if (ms != GLV_OK) return ms;
   if (n < 0) return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
   if (!nonnull<4>(a) || !nonnull<4>(b) || !m) return GLV_EINVAL_NULL;
   size_t es = elem(dt);
   std::vector<Range> ins;
@@ -203,7 +214,6 @@ glv_status glv_invariant_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_
   }
   if (fallback) ins.push_back(rng(fallback, 1, 8));
   if (any_overlap({rng(m, n, es)}, ins)) return GLV_EINVAL_ALIAS;
-  if (n == 0) return GLV_OK;
   return hip_status(glv::launch_mass(dt, co, mode, n, a, b, m, fallback, (hipStream_t)stream));
 }
 
@@ -213,6 +223,7 @@ glv_status glv_invariant_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const 
   if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
   if (!coords_ok(co)) return GLV_EINVAL_COORDS;
   if (n < 0) return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
   if (!nonnull<4>(a) || !nonnull<4>(b) || !gm || !nonnull<4>((const void* const*)ga) ||
       !nonnull<4>((const void* const*)gb))
     return GLV_EINVAL_NULL;
@@ -226,7 +237,6 @@ glv_status glv_invariant_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const 
   }
   ins.push_back(rng(gm, n, es));
   if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
-  if (n == 0) return GLV_OK;
   return hip_status(glv::launch_mass_bwd(dt, co, n, a, b, gm, ga, gb, (hipStream_t)stream));
 }
 
@@ -234,8 +244,9 @@ glv_status glv_boost(glv_dtype dt, int64_t n, const void* const x[4], const void
                      int64_t beta_stride, void* const y[4], void* stream) {
   if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
   if (n < 0) return GLV_EINVAL_SIZE;
-  if (!nonnull<4>(x) || !nonnull<3>(beta) || !nonnull<4>((const void* const*)y)) return GLV_EINVAL_NULL;
   if (beta_stride != 0 && beta_stride != 1) return GLV_EINVAL_STRIDE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<4>(x) || !nonnull<3>(beta) || !nonnull<4>((const void* const*)y)) return GLV_EINVAL_NULL;
   size_t es = elem(dt);
   bool inplace = true;
   for (int k = 0; k < 4; ++k) inplace = inplace && (y[k] == x[k]);
@@ -251,7 +262,6 @@ glv_status glv_boost(glv_dtype dt, int64_t n, const void* const x[4], const void
       for (int j = i + 1; j < 4; ++j)
         if (overlap(rng(x[i], n, es), rng(x[j], n, es))) return GLV_EINVAL_ALIAS;
   }
-  if (n == 0) return GLV_OK;
   return hip_status(glv::launch_boost(dt, n, x, beta, beta_stride, y, (hipStream_t)stream));
 }
 
@@ -260,10 +270,11 @@ glv_status glv_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4], const 
                          void* stream) {
   if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
   if (n < 0) return GLV_EINVAL_SIZE;
-  if (!nonnull<3>(beta) || !nonnull<4>(gy) || !nonnull<4>((const void* const*)gx)) return GLV_EINVAL_NULL;
-  if (gbeta && (!nonnull<3>((const void* const*)gbeta) || !nonnull<4>(x))) return GLV_EINVAL_NULL;
   if (beta_stride != 0 && beta_stride != 1) return GLV_EINVAL_STRIDE;
   if (gbeta && beta_stride != 1) return GLV_EINVAL_STRIDE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<3>(beta) || !nonnull<4>(gy) || !nonnull<4>((const void* const*)gx)) return GLV_EINVAL_NULL;
+  if (gbeta && (!nonnull<3>((const void* const*)gbeta) || !nonnull<4>(x))) return GLV_EINVAL_NULL;
   size_t es = elem(dt);
   std::vector<Range> outs, ins;
   for (int k = 0; k < 4; ++k) {
@@ -276,7 +287,6 @@ glv_status glv_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4], const 
     if (gbeta) outs.push_back(rng(gbeta[k], n, es));
   }
   if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
-  if (n == 0) return GLV_OK;
   return hip_status(glv::launch_boost_bwd(dt, n, x, beta, beta_stride, gy, gx, gbeta, (hipStream_t)stream));
 }
 
@@ -311,7 +321,7 @@ glv_status glv_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const i
                                 const void* const p[4], const void* const gt[4], const void* gem,
                                 const void* gpair, void* const gp[4], const glv_tiling* tiling, void* stream) {
   glv_status st = check_event_args(dt, co, GLV_PLAIN, ne, off, p);
-  if (st != GLV_OK) return st;
+  if (st != GLV_OK || ne == 0) return st;
   if (!nonnull<4>((const void* const*)gp)) return GLV_EINVAL_NULL;
   if (gt && !nonnull<4>(gt)) return GLV_EINVAL_NULL;
   if (gpair && !poff) return GLV_EINVAL_OFFSETS;

@@ -183,6 +183,16 @@ __device__ __forceinline__ void chain_coords(const LegJ<T>& L, T c0, T c3, const
   }
 }
 
+// w = a + b componentwise, each sum rounded on its own: no multiply-add may
+// fuse one leg's product (pt cos(phi), ...) into the sum, so the pair mass
+// is bitwise symmetric in its two legs.
+template <typename T>
+__device__ __forceinline__ void add4(const T a[4], const T b[4], T w[4]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = a[k] + b[k];
+}
+
 // Mass of a Cartesian vector: q = E^2 - |P|^2, m = sqrt(q) or -sqrt(-q).
 template <typename T>
 __device__ __forceinline__ T mass_of(const T w[4]) {

@@ -84,8 +84,7 @@ struct MassPlain {
       T va[4], vb[4], w[4];
       to_cart<COORDS>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e], va);
       to_cart<COORDS>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e], vb);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) w[k] = va[k] + vb[k];
+      add4<T>(va, vb, w);
       out.v[e] = mass_of(w);
     }
     store_pack<T, V>(m, i, out);
@@ -122,7 +121,6 @@ struct MassComp {
           LegC<double> db = comp_leg<double>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
           double kd;
           double m2d = comp_pair_m2<double>(da, db, &kd, nullptr);
-          m2 = (T)m2d;
           out.v[e] = (T)sqrt(m2d);
           ++cnt;
         } else {
@@ -158,8 +156,7 @@ struct MassBwd {
       LegJ<T> la = to_cart_j<COORDS, T>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
       LegJ<T> lb = to_cart_j<COORDS, T>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
       T w[4], u[4], g[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) w[k] = la.v[k] + lb.v[k];
+      add4<T>(la.v, lb.v, w);
       dmass<T>(w, mass_of(w), pg.v[e], u);
       chain_coords<COORDS, T>(la, pa[0].v[e], pa[3].v[e], u, g);
 #pragma unroll

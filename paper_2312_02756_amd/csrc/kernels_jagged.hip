@@ -288,8 +288,7 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
         T va[4], vb[4], w[4];
         to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], va);
         to_cart<COORDS>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j], vb);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = va[k] + vb[k];
+        add4<T>(va, vb, w);
         m = mass_of(w);
       }
       if (A.pair_m) store_out(A.pair_m, base + r, m);

@@ -44,7 +44,10 @@ def boost_tol(scale, dtype):
 
 def worst(err, tol):
     """Largest err/tol ratio (<= 1 passes) and its index."""
-    r = np.asarray(err) / np.asarray(tol)
+    err = np.asarray(err, dtype=np.float64)
+    tol = np.asarray(tol, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(err == 0, 0.0, err / tol)  # an exact match passes even at zero tolerance
     r = np.where(np.isnan(r), np.inf, r)
     i = int(np.argmax(r)) if r.size else 0
     return (float(r[i]) if r.size else 0.0), i
