@@ -1,0 +1,288 @@
+"""Benchmark of the batched Lorentz-vector hot path on one MI355X.
+
+One step is one pass of every kernel of the path over one batch of synthetic,
+collider-shaped input already resident in HBM:
+
+  mass_fwd     FP64 pair mass, PtEtaPhiM, 2^24 pairs           (72 B/pair)
+  mass_bwd     FP64 reverse mode of the same pairs              (136 B/pair)
+  boost_fwd    FP64 boost, per-item beta, 2^24 vectors          (88 B/vector)
+  boost_bwd    FP64 reverse mode of the boost                   (144 B/vector)
+  mass_comp32  FP32 compensated pair mass, 2^24 light pairs     (36 B/pair)
+  event_reduce FP64 jagged reduction, 2^20 Poisson(8) events:
+               totals, event mass and all pair masses           (~568 B/event)
+
+value = items processed per second, in Gevents/s, where an item is a pair
+(through forward and backward), a vector (forward and backward), a
+compensated pair or a collider event; every kernel is also reported
+separately with its algorithmic bytes, achieved GB/s and fraction of the
+8 TB/s HBM peak.  Per-kernel times come from HIP events recorded on the
+stream the kernels run on, inside the timed steps.
+
+cpu_baseline: the CPU oracle (test infrastructure) timed on the host cores on
+half of one step's workload (2^23 items per element-wise kernel, 2^19 events),
+scaled to the same unit.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--calib-copy]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gevents/s & HBM GB/s (% of peak): mass/boost fwd+bwd, FP32-comp vs FP64 plain"
+HBM_PEAK_GBS = 8000.0
+N_ITEMS = 1 << 24
+N_EVENTS = 1 << 20
+KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_comp32", "event_reduce"]
+KERNEL_SYMBOL = {
+    "mass_fwd": "MassPlain<double, 1>", "mass_bwd": "MassBwd<double, 1>", "boost_fwd": "BoostFwd<double, 1>",
+    "boost_bwd": "BoostBwd<double, 1, true>", "mass_comp32": "MassComp<float>",
+    "event_reduce": "k_event_reduce<double, 1, 0>",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def source_digest():
+    """Digest of the kernel sources, to tell whether stored counter readings
+    still describe the current kernels."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2312_02756_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from profiles/hbm_traffic.txt (rocprofv3
+    FETCH_SIZE / WRITE_SIZE, scaled by a copy-kernel calibration), or None if
+    absent or recorded for other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = source_digest()
+    for line in open(path):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        if kv.get("kernel") == kernel and kv.get("sources") == digest:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no cross-GPU step: "
+              "shards would run independently, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2312_02756_amd import glv
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def gpu(cols, dt):
+        return tuple(torch.from_numpy(np.ascontiguousarray(c)).to(dev).to(dt).contiguous() for c in cols)
+
+    # ---------------------------------------------------------- inputs (host)
+    t0 = time.time()
+    a, b = synth.pairs_generic(synth.rng(synth.LARGE), N_ITEMS)
+    x, beta = synth.boost_items(synth.rng(synth.LARGE), N_ITEMS)
+    gr = synth.rng(synth.GRADS)
+    gm = synth.upstream(gr, N_ITEMS, 1)[0]
+    gy = synth.upstream(gr, N_ITEMS, 4)
+    sa, sb, _ = synth.pairs_stress(synth.rng(synth.STRESS), N_ITEMS)
+    sa, sb = synth.as_dtype(sa, np.float32), synth.as_dtype(sb, np.float32)
+    off, parts = synth.jagged_events(synth.rng(synth.JAGGED), N_EVENTS)
+    gen_s = time.time() - t0
+
+    # -------------------------------------------------------- inputs (device)
+    A, B = gpu(a, torch.float64), gpu(b, torch.float64)
+    GM = gpu([gm], torch.float64)[0]
+    X, BETA = gpu(x, torch.float64), gpu(beta, torch.float64)
+    GY = gpu(gy, torch.float64)
+    SA, SB = gpu(sa, torch.float32), gpu(sb, torch.float32)
+    P = gpu(parts, torch.float64)
+    OFF = torch.from_numpy(off).to(dev)
+    PO = glv.glv_pair_offsets(OFF)
+    n_pairs = int(PO[-1].item())
+    n_part = int(off[-1])
+    # outputs preallocated once, reused every step
+    M = torch.empty(N_ITEMS, dtype=torch.float64, device=dev)
+    MC = torch.empty(N_ITEMS, dtype=torch.float32, device=dev)
+    FB = torch.zeros(1, dtype=torch.int64, device=dev)
+    Y = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
+    torch.cuda.synchronize()
+
+    from paper_2312_02756_amd import _lib
+    lib = _lib.load()
+    P4, P3 = _lib.P4, _lib.P3
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+    ptr4 = lambda cols: P4(*[t.data_ptr() for t in cols])  # noqa: E731
+    ptr3 = lambda cols: P3(*[t.data_ptr() for t in cols])  # noqa: E731
+    GA = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
+    GB = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
+    GX = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
+    GBETA = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(3))
+    TOT = tuple(torch.empty(N_EVENTS, dtype=torch.float64, device=dev) for _ in range(4))
+    EM = torch.empty(N_EVENTS, dtype=torch.float64, device=dev)
+    PM = torch.empty(n_pairs, dtype=torch.float64, device=dev)
+
+    # C-ABI calls with pointers marshalled once
+    cA, cB, cX, cBETA, cGY = ptr4(A), ptr4(B), ptr4(X), ptr3(BETA), ptr4(GY)
+    cGA, cGB, cY, cGX, cGBETA = ptr4(GA), ptr4(GB), ptr4(Y), ptr4(GX), ptr3(GBETA)
+    cSA, cSB, cP, cTOT = ptr4(SA), ptr4(SB), ptr4(P), ptr4(TOT)
+    F32, F64, PTM, CART = _lib.GLV_F32, _lib.GLV_F64, _lib.GLV_PTETAPHIM, _lib.GLV_PXPYPZE
+    PLAIN, COMP = _lib.GLV_PLAIN, _lib.GLV_COMPENSATED
+
+    calls = {
+        "mass_fwd": lambda: lib.glv_invariant_mass(F64, PTM, PLAIN, N_ITEMS, cA, cB, M.data_ptr(), None, sp),
+        "mass_bwd": lambda: lib.glv_invariant_mass_bwd(F64, PTM, N_ITEMS, cA, cB, GM.data_ptr(), cGA, cGB, sp),
+        "boost_fwd": lambda: lib.glv_boost(F64, N_ITEMS, cX, cBETA, 1, cY, sp),
+        "boost_bwd": lambda: lib.glv_boost_bwd(F64, N_ITEMS, cX, cBETA, 1, cGY, cGX, cGBETA, sp),
+        "mass_comp32": lambda: lib.glv_invariant_mass(F32, PTM, COMP, N_ITEMS, cSA, cSB, MC.data_ptr(),
+                                                      FB.data_ptr(), sp),
+        "event_reduce": lambda: lib.glv_event_reduce(F64, PTM, PLAIN, N_EVENTS, OFF.data_ptr(), PO.data_ptr(), cP,
+                                                     cTOT, EM.data_ptr(), PM.data_ptr(), None, None, sp),
+    }
+    # algorithmic bytes per launch: what each kernel must read and write once
+    alg_bytes = {
+        "mass_fwd": 72 * N_ITEMS, "mass_bwd": 136 * N_ITEMS, "boost_fwd": 88 * N_ITEMS,
+        "boost_bwd": 144 * N_ITEMS, "mass_comp32": 36 * N_ITEMS,
+        "event_reduce": 32 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
+    }
+    units = {"mass_fwd": 0, "mass_bwd": N_ITEMS, "boost_fwd": 0, "boost_bwd": N_ITEMS, "mass_comp32": N_ITEMS,
+             "event_reduce": N_EVENTS}
+    # a pair / vector counts once for its forward + backward pass
+    items_per_step = sum(units.values())
+
+    def step(evs=None):
+        for k in KERNELS:
+            if evs is not None:
+                evs[k][0].record(stream)
+            rc = calls[k]()
+            if rc != 0:
+                raise RuntimeError(f"{k}: status {rc}")
+            if evs is not None:
+                evs[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in KERNELS}
+           for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(K):
+        step(evs[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    per_kernel = {}
+    for k in KERNELS:
+        ts = np.array([e[k][0].elapsed_time(e[k][1]) for e in evs]) * 1e-3  # seconds
+        avg = float(ts.mean())
+        gbs = alg_bytes[k] / avg / 1e9
+        per_kernel[k] = {
+            "avg_us": round(avg * 1e6, 2), "min_us": round(float(ts.min()) * 1e6, 2),
+            "alg_bytes": int(alg_bytes[k]), "alg_GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "units": N_EVENTS if k == "event_reduce" else N_ITEMS,
+            "Gunits_per_s": round((N_EVENTS if k == "event_reduce" else N_ITEMS) / avg / 1e9, 3),
+        }
+    per_kernel["event_reduce"]["pairs"] = n_pairs
+    per_kernel["event_reduce"]["particles"] = n_part
+    per_kernel["mass_comp32"]["fp64_redo_per_launch"] = int(FB.item()) // max(1, args.warmup + K)
+
+    ms_per_step = elapsed / K * 1e3
+    value = items_per_step / (elapsed / K) / 1e9
+    dom = max(KERNELS, key=lambda k: per_kernel[k]["avg_us"])
+    ach = per_kernel[dom]["alg_GBps"]
+    roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom)}
+
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gevents/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {
+            "workload": "2^24 FP64 PtEtaPhiM pairs (mass fwd+bwd) + 2^24 FP64 PxPyPzE vectors with per-item beta "
+                        "(boost fwd+bwd) + 2^24 FP32 light/collinear pairs (compensated mass) + 2^20 FP64 jagged "
+                        "events, Poisson(8) particles (totals, event mass, all pair masses) per step",
+            "items_per_step": items_per_step, "pairs_in_events": n_pairs, "particles": n_part,
+            "parallelism": "single GPU", "input_gen_s": round(gen_s, 1),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": per_kernel,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts):
+    """The oracle on the host cores over half a step (2^23 items per
+    element-wise kernel, 2^19 events), in the benchmark's unit."""
+    import oracle
+
+    n = N_ITEMS // 2
+    ne = N_EVENTS // 2
+    threads = len(os.sched_getaffinity(0))
+    oracle.set_threads(threads)
+    used = oracle.get_threads()
+    cut = lambda cols: tuple(c[:n] for c in cols)  # noqa: E731
+    ca, cb, cx, cbeta, cgy, csa, csb = cut(a), cut(b), cut(x), cut(beta), cut(gy), cut(sa), cut(sb)
+    cgm = gm[:n]
+    coff = off[: ne + 1]
+    cparts = tuple(c[: coff[-1]] for c in parts)
+    t = time.perf_counter()
+    oracle.mass_plain("PtEtaPhiM", ca, cb)
+    oracle.mass_vjp("PtEtaPhiM", ca, cb, cgm)
+    oracle.boost(cx, cbeta)
+    oracle.boost_vjp(cx, cbeta, cgy)
+    oracle.mass_accurate(csa, csb)
+    oracle.event_reduce("PtEtaPhiM", coff, cparts)
+    dt = time.perf_counter() - t
+    items = 3 * n + ne
+    return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle",
+            "sample": f"half a step: 2^23 items through mass fwd+bwd, boost fwd+bwd and the accurate mass "
+                      f"(binary64 oracle), plus 2^19 jagged events; {dt:.2f} s wall on {used} threads"}
+
+
+if __name__ == "__main__":
+    main()
