@@ -58,7 +58,58 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--calib-copy run into profiles/hbm_traffic.txt and exit")
     return ap.parse_args()
+
+
+COPY_BYTES = 1 << 30
+
+
+def summarize_pmc(fetch_csv, write_csv):
+    """Per-kernel HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled so that the 1 GiB calibration copy reads and
+    writes exactly 1 GiB."""
+    import collections
+    import csv
+    import re
+
+    def load(path, counter):
+        vals = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                vals[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    f_copy = max(max(fetch[k]) for k in copy)
+    w_copy = max(max(write[k]) for k in copy)
+    f_scale, w_scale = COPY_BYTES / f_copy, COPY_BYTES / w_copy
+    digest = source_digest()
+    lines = [f"# HBM traffic per launch: rocprofv3 FETCH_SIZE x {f_scale:.4f} + WRITE_SIZE x {w_scale:.4f}",
+             "# (scales from a 1 GiB device copy in the same runs).  Commands, from the repository root R:",
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o fetch -- "
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --calib-copy",
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_write -o write -- "
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --calib-copy",
+             "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/fetch_counter_collection.csv "
+             "gpurun_out/pmc_write/write_counter_collection.csv",
+             f"# sources = digest of paper_2312_02756_amd/csrc at measurement time ({digest})"]
+    for key, sym in KERNEL_SYMBOL.items():
+        names = [k for k in fetch if sym in re.sub(r"glv::\(anonymous namespace\)::", "", k)]
+        if not names:
+            continue
+        n = names[0]
+        fb = float(np.median(fetch[n])) * f_scale
+        wb = float(np.median(write.get(n, [0.0]))) * w_scale
+        lines.append(f"traffic kernel={key} sources={digest} fetch_bytes={fb:.0f} write_bytes={wb:.0f} "
+                     f"bytes_per_launch={fb + wb:.0f}")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def source_digest():
@@ -91,6 +142,9 @@ def stored_traffic(kernel):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no cross-GPU step: "
               "shards would run independently, see the design notes)", file=sys.stderr)
