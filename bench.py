@@ -185,6 +185,8 @@ def main():
     PO = glv.glv_pair_offsets(OFF)
     n_pairs = int(PO[-1].item())
     n_part = int(off[-1])
+    # the jagged reduction runs with the tiling the autotuner picks on these events
+    tiling = glv.glv_autotune_event_reduce(P, OFF, PO)
     # outputs preallocated once, reused every step
     M = torch.empty(N_ITEMS, dtype=torch.float64, device=dev)
     MC = torch.empty(N_ITEMS, dtype=torch.float32, device=dev)
@@ -300,6 +302,7 @@ def main():
                         "(boost fwd+bwd) + 2^24 FP32 light/collinear pairs (compensated mass) + 2^20 FP64 jagged "
                         "events, Poisson(8) particles (totals, event mass, all pair masses) per step",
             "items_per_step": items_per_step, "pairs_in_events": n_pairs, "particles": n_part,
+            "event_tiling": {"block": tiling[0], "events_per_tile": tiling[1], "lds_particles": tiling[2]},
             "parallelism": "single GPU", "input_gen_s": round(gen_s, 1),
         },
         "roofline": roofline,

@@ -90,7 +90,7 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  * speed only: pair masses and totals are identical for every tiling; the
  * compensated event mass (a sum of per-pair terms) may differ in the last bit
  * between tilings but is reproducible for a given tiling.
- *   block            threads per workgroup: 64, 128, 256, 512 or 1024
+ *   block            threads per workgroup: 64, 128, 256 or 512
  *   events_per_tile  events a workgroup takes at a time: 1 .. block
  *   lds_particles    particles staged in LDS at once: 64 .. 4096
  * Fields set to 0 take the library's current choice (the autotuned one if

@@ -141,6 +141,20 @@ def mass_vjp(coords, a, b, gm):
     return tuple(ga), tuple(gb)
 
 
+def mass_vjp_scale(coords, a, b, gm):
+    """Absolute-value evaluation of the mass VJP's chain rule (rounding scale
+    of each gradient component)."""
+    a = [_f64(x) for x in a]
+    b = [_f64(x) for x in b]
+    gm = _f64(gm)
+    n = a[0].size
+    ga = [np.empty(n) for _ in range(4)]
+    gb = [np.empty(n) for _ in range(4)]
+    _load().orc_mass_vjp_scale(ctypes.c_int(_coords(coords)), ctypes.c_int64(n), *map(_p, a), *map(_p, b),
+                               _p(gm), *map(_p, ga), *map(_p, gb))
+    return tuple(ga), tuple(gb)
+
+
 def boost_vjp(x, beta, gy):
     x = [_f64(v) for v in x]
     beta = [_f64(v) for v in beta]

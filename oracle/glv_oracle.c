@@ -396,6 +396,63 @@ void orc_mass_vjp(int coords, int64_t n, const double* a0, const double* a1, con
   }
 }
 
+/* Rounding scale of the pair-mass VJP: the same chain rule with every factor
+ * replaced by its absolute value, |gm| sum_k |u_k| |d v_k / d c|, u = (-P, E)/|m|.
+ * The terms of one gradient component can cancel (the eta component subtracts
+ * P.dp/deta from E dE/deta), so its rounding error is a few ulps of this sum,
+ * not of the result. */
+static void chain_coords_abs(int coords, double c0, double c1, double c2, double c3, const double u[4],
+                             double g[4]) {
+  if (coords == ORC_PXPYPZE) {
+    for (int k = 0; k < 4; ++k) g[k] = fabs(u[k]);
+    return;
+  }
+  double pt = fabs(c0), eta = c1, phi = c2;
+  double cp = fabs(cos(phi)), sp = fabs(sin(phi)), sh = fabs(sinh(eta)), ch = cosh(eta);
+  double au[4] = {fabs(u[0]), fabs(u[1]), fabs(u[2]), fabs(u[3])};
+  g[0] = au[0] * cp + au[1] * sp + au[2] * sh;
+  g[1] = au[2] * pt * ch;
+  g[2] = au[0] * pt * sp + au[1] * pt * cp;
+  g[3] = 0.0;
+  if (coords == ORC_PTETAPHIM) {
+    double pc = pt * ch;
+    double e = sqrt(pc * pc + c3 * c3);
+    if (e > 0.0) {
+      g[0] += au[3] * pt * ch * ch / e;
+      g[1] += au[3] * pt * pt * sh * ch / e;
+      g[3] = au[3] * fabs(c3) / e;
+    }
+  } else {
+    g[3] = au[3];
+  }
+}
+
+void orc_mass_vjp_scale(int coords, int64_t n, const double* a0, const double* a1, const double* a2,
+                        const double* a3, const double* b0, const double* b1, const double* b2,
+                        const double* b3, const double* gm, double* ga0, double* ga1, double* ga2,
+                        double* ga3, double* gb0, double* gb1, double* gb2, double* gb3) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double va[4], vb[4], w[4], u[4], g[4];
+    cart(coords, a0[i], a1[i], a2[i], a3[i], va);
+    cart(coords, b0[i], b1[i], b2[i], b3[i], vb);
+    for (int k = 0; k < 4; ++k) w[k] = va[k] + vb[k];
+    double m = mass_of(w);
+    dmass_dcart(w, m, u);
+    for (int k = 0; k < 4; ++k) u[k] *= fabs(gm[i]);
+    chain_coords_abs(coords, a0[i], a1[i], a2[i], a3[i], u, g);
+    ga0[i] = g[0];
+    ga1[i] = g[1];
+    ga2[i] = g[2];
+    ga3[i] = g[3];
+    chain_coords_abs(coords, b0[i], b1[i], b2[i], b3[i], u, g);
+    gb0[i] = g[0];
+    gb1[i] = g[1];
+    gb2[i] = g[2];
+    gb3[i] = g[3];
+  }
+}
+
 /* Reverse-mode derivative of the boost y = L(beta) x (per-item beta).
  *   grad_x = L(beta)^T gy = L(beta) gy   (L is symmetric);
  *   grad_beta from dg/dbeta = g^3 beta and dk/dbeta = k' g^3 beta with

@@ -97,7 +97,7 @@ glv::Tiling default_tiling_bwd(glv_dtype dt) {
 
 constexpr size_t kMaxLds = 64 * 1024;
 
-bool block_ok(int b) { return b == 64 || b == 128 || b == 256 || b == 512 || b == 1024; }
+bool block_ok(int b) { return (b == 64 || b == 128 || b == 256 || b == 512) && b <= glv::kMaxBlock; }
 
 // Resolve a user tiling (fields 0 = current choice) and validate it.
 glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,

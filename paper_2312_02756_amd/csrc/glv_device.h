@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include "glv.h"
+#include "glv_math.h"
 
 namespace glv {
 
@@ -81,16 +82,6 @@ __device__ __forceinline__ void store_pack(T* __restrict__ p, int64_t i, const P
 
 // ------------------------------------------------------------ scalar math
 
-__device__ __forceinline__ void d_sincos(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ void d_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ double d_sinh(double x) { return sinh(x); }
-__device__ __forceinline__ float d_sinh(float x) { return sinhf(x); }
-__device__ __forceinline__ double d_cosh(double x) { return cosh(x); }
-__device__ __forceinline__ float d_cosh(float x) { return coshf(x); }
-__device__ __forceinline__ double d_asinh(double x) { return asinh(x); }
-__device__ __forceinline__ float d_asinh(float x) { return asinhf(x); }
-__device__ __forceinline__ double d_sin(double x) { return sin(x); }
-__device__ __forceinline__ float d_sin(float x) { return sinf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_abs(double x) { return fabs(x); }
@@ -107,13 +98,14 @@ __device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
     v[2] = c2;
     v[3] = c3;
   } else {
-    T s, c;
-    d_sincos(c2, &s, &c);
+    T s, c, sh, ch;
+    fast_sincos(c2, &s, &c);
+    fast_sinhcosh(c1, &sh, &ch);
     v[0] = c0 * c;
     v[1] = c0 * s;
-    v[2] = c0 * d_sinh(c1);
+    v[2] = c0 * sh;
     if constexpr (COORDS == GLV_PTETAPHIM) {
-      T pc = c0 * d_cosh(c1);
+      T pc = c0 * ch;
       v[3] = d_sqrt(pc * pc + c3 * c3);
     } else {
       v[3] = c3;
@@ -138,9 +130,8 @@ __device__ __forceinline__ LegJ<T> to_cart_j(T c0, T c1, T c2, T c3) {
     L.v[3] = c3;
     L.cp = L.sp = L.sh = L.ch = T(0);
   } else {
-    d_sincos(c2, &L.sp, &L.cp);
-    L.sh = d_sinh(c1);
-    L.ch = d_cosh(c1);
+    fast_sincos(c2, &L.sp, &L.cp);
+    fast_sinhcosh(c1, &L.sh, &L.ch);
     L.v[0] = c0 * L.cp;
     L.v[1] = c0 * L.sp;
     L.v[2] = c0 * L.sh;
@@ -213,6 +204,32 @@ __device__ __forceinline__ void dmass(const T w[4], T m, T g, T u[4]) {
 
 // ------------------------------------------------- cancellation-free mass
 
+// sinh alone (small arguments by the odd polynomial, else from one exp).
+__device__ __forceinline__ double fast_sinh(double x) {
+  if (fabs(x) < 0.5) return poly_sinh_d(x);
+  double sh, ch;
+  fast_sinhcosh(x, &sh, &ch);
+  return sh;
+}
+__device__ __forceinline__ float fast_sinh(float x) {
+  if (fabsf(x) < 0.5f) return poly_sinh_f(x);
+  float sh, ch;
+  fast_sinhcosh(x, &sh, &ch);
+  return sh;
+}
+
+// asinh of the small argument of delta.  FP32: for |x| < 1/8 the Taylor
+// series x - x^3/6 + 3x^5/40 - 5x^7/112 (next term below 2e-9 relative);
+// otherwise, and always in FP64, the device library's asinh.
+__device__ __forceinline__ double small_asinh(double x) { return asinh(x); }
+__device__ __forceinline__ float small_asinh(float x) {
+  if (!(fabsf(x) < 0.125f)) return asinhf(x);
+  const float z = x * x;
+  float p = fmaf(z, -5.0f / 112.0f, 3.0f / 40.0f);
+  p = fmaf(p, z, -1.0f / 6.0f);
+  return fmaf(x * z, p, x);
+}
+
 // pi split into the nearest T and the remainder.
 template <typename T>
 struct Pi;
@@ -253,11 +270,12 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   T mm = mass * mass;
   L.m2 = mm;
   L.mt = d_sqrt(pt * pt + mm);
-  T sh = d_sinh(eta), ch = d_cosh(eta);
+  T sh, ch;
+  fast_sinhcosh(eta, &sh, &ch);
   T pc = pt * ch;
   T e = d_sqrt(pc * pc + mm);
   T den = L.mt * (pc + e);
-  L.delta = (den > T(0)) ? -d_asinh(mm * sh / den) : T(0);
+  L.delta = (den > T(0)) ? -small_asinh(mm * sh / den) : T(0);
   return L;
 }
 
@@ -273,9 +291,10 @@ __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T*
   T d1 = a.eta - b.eta;
   T d2 = a.delta - b.delta;
   T dy = d1 + d2;
-  T s1 = d_sinh(T(0.5) * dy);
+  T s1 = fast_sinh(T(0.5) * dy);
   T t1 = T(2) * a.mt * b.mt * (s1 * s1);
-  T s2 = d_sin(T(0.5) * dphi_reduced(a.phi, b.phi));
+  T s2, c2;
+  fast_sincos(T(0.5) * dphi_reduced(a.phi, b.phi), &s2, &c2);
   T t2 = T(2) * a.pt * b.pt * (s2 * s2);
   T num = a.pt * a.pt * b.m2 + b.pt * b.pt * a.m2 + a.m2 * b.m2;
   T den = a.mt * b.mt + a.pt * b.pt;

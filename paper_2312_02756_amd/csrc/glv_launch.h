@@ -31,6 +31,10 @@ hipError_t launch_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t
 hipError_t launch_validate_offsets(int64_t n_events, const int64_t* offsets, int64_t n_particles,
                                    long long* bad, hipStream_t s);
 
+// Largest workgroup of the jagged kernels (their register budget is sized
+// for it: 512 threads leave up to 256 VGPRs per lane).
+constexpr int kMaxBlock = 512;
+
 // Tiling with every field resolved (non-zero, inside its allowed set).
 struct Tiling {
   int block;

@@ -1,0 +1,192 @@
+// Elementary functions for the conversion of a (pt, eta, phi) vector to
+// Cartesian components on gfx950, written for this library:
+//
+//   sincos  Cody and Waite's additive argument reduction by pi/2 (Cody & Waite,
+//           "Software Manual for the Elementary Functions", 1980), with the
+//           multiples of pi/2 subtracted by fused multiply-adds against a
+//           three-part split of pi/2, then Taylor polynomials of sin and cos on
+//           |r| <= pi/4 (truncation below 1e-18 relative in FP64, 1e-9 in FP32);
+//   exp     the same reduction by ln 2 (two-part split) and the Taylor
+//           polynomial of e^r on |r| <= ln2/2, scaled by 2^k;
+//   sinh / cosh from one exp and one reciprocal; sinh by its odd Taylor
+//           polynomial for |x| < 1/2, where e^x - e^-x would cancel.
+//
+// Split constants are the leading double / float of pi/2 and ln 2 and the
+// remainders; Taylor coefficients are 1/n!, written as quotients the compiler
+// folds exactly.  Arguments outside the reduction's range (|x| beyond 1e5 for
+// sincos in FP64, 1e4 in FP32) take the device library's functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace glv {
+
+// ------------------------------------------------------------------- FP64
+
+__device__ __forceinline__ double poly_sin_d(double r) {
+  const double z = r * r;
+  double p = -1.0 / 355687428096000.0;  // -1/17!
+  p = fma(p, z, 1.0 / 1307674368000.0);
+  p = fma(p, z, -1.0 / 6227020800.0);
+  p = fma(p, z, 1.0 / 39916800.0);
+  p = fma(p, z, -1.0 / 362880.0);
+  p = fma(p, z, 1.0 / 5040.0);
+  p = fma(p, z, -1.0 / 120.0);
+  p = fma(p, z, 1.0 / 6.0);
+  // sin r = r - r^3 (1/6 - r^2/120 + ...)
+  return fma(-r * z, p, r);
+}
+
+__device__ __forceinline__ double poly_cos_d(double r) {
+  const double z = r * r;
+  double p = 1.0 / 20922789888000.0;  // 1/16!
+  p = fma(p, z, -1.0 / 87178291200.0);
+  p = fma(p, z, 1.0 / 479001600.0);
+  p = fma(p, z, -1.0 / 3628800.0);
+  p = fma(p, z, 1.0 / 40320.0);
+  p = fma(p, z, -1.0 / 720.0);
+  p = fma(p, z, 1.0 / 24.0);
+  p = fma(p, z, -0.5);
+  return fma(z, p, 1.0);
+}
+
+__device__ __forceinline__ void fast_sincos(double x, double* s, double* c) {
+  if (!(fabs(x) < 1.0e5)) {  // large or non-finite: the library's reduction
+    sincos(x, s, c);
+    return;
+  }
+  const double kd = rint(x * 0.6366197723675814);  // x * 2/pi
+  double r = fma(-kd, 1.5707963267948966, x);
+  r = fma(-kd, 6.123233995736766e-17, r);
+  r = fma(-kd, -1.4973849048591698e-33, r);
+  const double sr = poly_sin_d(r), cr = poly_cos_d(r);
+  const int q = (int)kd & 3;
+  const double ss = (q & 1) ? cr : sr;
+  const double cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// e^x for |x| <= 709; overflows to inf beyond, underflows to 0.
+__device__ __forceinline__ double fast_exp(double x) {
+  const double kd = rint(x * 1.4426950408889634);  // x / ln2
+  double r = fma(-kd, 0.6931471805599453, x);
+  r = fma(-kd, 2.3190468138462996e-17, r);
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)kd);
+}
+
+// sinh(x) for |x| < 1/2 (odd Taylor polynomial to x^15).
+__device__ __forceinline__ double poly_sinh_d(double x) {
+  const double z = x * x;
+  double p = 1.0 / 1307674368000.0;  // 1/15!
+  p = fma(p, z, 1.0 / 6227020800.0);
+  p = fma(p, z, 1.0 / 39916800.0);
+  p = fma(p, z, 1.0 / 362880.0);
+  p = fma(p, z, 1.0 / 5040.0);
+  p = fma(p, z, 1.0 / 120.0);
+  p = fma(p, z, 1.0 / 6.0);
+  return fma(x * z, p, x);
+}
+
+__device__ __forceinline__ void fast_sinhcosh(double x, double* sh, double* ch) {
+  if (!(fabs(x) < 700.0)) {  // e^|x| near or beyond overflow, or NaN
+    *sh = sinh(x);
+    *ch = cosh(x);
+    return;
+  }
+  const double e = fast_exp(x);
+  const double ei = 1.0 / e;
+  *ch = 0.5 * (e + ei);
+  *sh = (fabs(x) < 0.5) ? poly_sinh_d(x) : 0.5 * (e - ei);
+}
+
+// ------------------------------------------------------------------- FP32
+
+__device__ __forceinline__ float poly_sin_f(float r) {
+  const float z = r * r;
+  float p = 1.0f / 362880.0f;  // 1/9!
+  p = fmaf(p, z, -1.0f / 5040.0f);
+  p = fmaf(p, z, 1.0f / 120.0f);
+  p = fmaf(p, z, -1.0f / 6.0f);
+  return fmaf(r * z, p, r);
+}
+
+__device__ __forceinline__ float poly_cos_f(float r) {
+  const float z = r * r;
+  float p = -1.0f / 3628800.0f;  // -1/10!
+  p = fmaf(p, z, 1.0f / 40320.0f);
+  p = fmaf(p, z, -1.0f / 720.0f);
+  p = fmaf(p, z, 1.0f / 24.0f);
+  p = fmaf(p, z, -0.5f);
+  return fmaf(z, p, 1.0f);
+}
+
+__device__ __forceinline__ void fast_sincos(float x, float* s, float* c) {
+  if (!(fabsf(x) < 1.0e4f)) {
+    sincosf(x, s, c);
+    return;
+  }
+  const float kf = rintf(x * 0.63661975f);
+  float r = fmaf(-kf, 1.5707964f, x);
+  r = fmaf(-kf, -4.371139e-08f, r);
+  r = fmaf(-kf, -1.7151245e-15f, r);
+  const float sr = poly_sin_f(r), cr = poly_cos_f(r);
+  const int q = (int)kf & 3;
+  const float ss = (q & 1) ? cr : sr;
+  const float cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+__device__ __forceinline__ float fast_exp(float x) {
+  const float kf = rintf(x * 1.442695f);
+  float r = fmaf(-kf, 0.6931472f, x);
+  r = fmaf(-kf, -1.9046542e-09f, r);
+  float p = 1.0f / 40320.0f;  // 1/8!
+  p = fmaf(p, r, 1.0f / 5040.0f);
+  p = fmaf(p, r, 1.0f / 720.0f);
+  p = fmaf(p, r, 1.0f / 120.0f);
+  p = fmaf(p, r, 1.0f / 24.0f);
+  p = fmaf(p, r, 1.0f / 6.0f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
+  return ldexpf(p, (int)kf);
+}
+
+__device__ __forceinline__ float poly_sinh_f(float x) {
+  const float z = x * x;
+  float p = 1.0f / 362880.0f;  // 1/9!
+  p = fmaf(p, z, 1.0f / 5040.0f);
+  p = fmaf(p, z, 1.0f / 120.0f);
+  p = fmaf(p, z, 1.0f / 6.0f);
+  return fmaf(x * z, p, x);
+}
+
+__device__ __forceinline__ void fast_sinhcosh(float x, float* sh, float* ch) {
+  if (!(fabsf(x) < 85.0f)) {
+    *sh = sinhf(x);
+    *ch = coshf(x);
+    return;
+  }
+  const float e = fast_exp(x);
+  const float ei = 1.0f / e;
+  *ch = 0.5f * (e + ei);
+  *sh = (fabsf(x) < 0.5f) ? poly_sinh_f(x) : 0.5f * (e - ei);
+}
+
+}  // namespace glv

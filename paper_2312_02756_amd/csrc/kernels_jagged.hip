@@ -311,7 +311,7 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
 }
 
 template <typename T, int COORDS, int MODE>
-__global__ __launch_bounds__(1024) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
+__global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int epb = A.epb, cap = A.cap;
   const int nwaves = blockDim.x >> 6;
@@ -396,14 +396,23 @@ __global__ __launch_bounds__(1024) void k_event_reduce(FwdArgs<T, COORDS, MODE> 
         const int64_t q0 = s_poff[ca];
         const int64_t q = s_poff[cb] - q0;
         const int64_t lo = q * wid / nwaves, hi = q * (wid + 1) / nwaves;
+        // A lane's pair index grows by 64 per iteration, so its event is found
+        // once by binary search and afterwards by stepping forward (a few
+        // events at most per iteration on collider-sized events).
+        int ev = ca;
+        bool located = false;
         for (int64_t it = lo; it < hi; it += 64) {
           const int64_t r = it + lane;
           const bool valid = r < hi;
-          int ev = 0;
           double kd = 0.0;
           if (valid) {
             const int64_t k = q0 + r;
-            ev = search_le(s_poff, ca, cb, k);
+            if (!located) {
+              ev = search_le(s_poff, ca, cb, k);
+              located = true;
+            } else {
+              while (s_poff[ev + 1] <= k) ++ev;
+            }
             const int n = (int)(s_off[ev + 1] - s_off[ev]);
             int i, j;
             decode_pair_small((int)(k - s_poff[ev]), n, &i, &j);
@@ -531,7 +540,7 @@ __device__ void big_event_bwd(const BwdArgs<T, COORDS>& A, int64_t e, int64_t lo
 
 // LDS-staged backward: per particle, Cartesian vector and Jacobian pieces.
 template <typename T, int COORDS>
-__global__ __launch_bounds__(1024) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
+__global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int epb = A.epb, cap = A.cap;
   int64_t* s_off = reinterpret_cast<int64_t*>(lds);

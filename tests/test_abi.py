@@ -106,7 +106,7 @@ def test_jagged_validation(lib):
     assert f(2, 1, 0, -2, OFF, PO, cols(P), cols(T), EM, PM, None, None, None) == SIZE
     assert f(2, 1, 0, 10, OFF, PO, cols(P), cols(T), OFF, PM, None, None, None) == ALIAS    # event_m over offsets
     for bad in ((100, 0, 0, 0), (256, 512, 0, 0), (256, 128, 32, 0), (256, 128, 8192, 0), (256, 128, 1024, 1),
-                (1024, 1024, 4096, 0)):
+                (1024, 16, 256, 0), (512, 512, 4096, 0)):
         t = _lib.glv_tiling(*bad)
         assert f(2, 1, 0, 10, OFF, PO, cols(P), cols(T), EM, PM, None, ctypes.byref(t), None) == TILING, bad
     g = lib.glv_pair_offsets
@@ -124,6 +124,6 @@ def test_jagged_validation(lib):
 def test_current_tiling_default(lib):
     t = _lib.glv_tiling()
     assert lib.glv_current_tiling(2, 1, 0, ctypes.byref(t)) == OK
-    assert t.block in (64, 128, 256, 512, 1024) and 1 <= t.events_per_tile <= t.block
+    assert t.block in (64, 128, 256, 512) and 1 <= t.events_per_tile <= t.block
     assert 64 <= t.lds_particles <= 4096
     assert lib.glv_current_tiling(2, 0, 1, ctypes.byref(t)) == MODE

@@ -167,3 +167,22 @@ def test_boost_vjp_grad_x_is_forward_boost_of_upstream():
     fwd = oracle.boost(gy, beta)
     for k in range(4):
         assert np.array_equal(gx[k], fwd[k])
+
+
+def test_mass_vjp_scale_bounds_the_vjp():
+    """The absolute-value evaluation dominates the VJP componentwise
+    (triangle inequality) and equals |VJP| for Cartesian legs."""
+    g = synth.rng(305)
+    n = 5000
+    a, b = synth.pairs_generic(g, n)
+    gm = g.standard_normal(n)
+    for coords in ("PtEtaPhiM", "PtEtaPhiE"):
+        va, vb = oracle.mass_vjp(coords, a, b, gm)
+        sa, sb = oracle.mass_vjp_scale(coords, a, b, gm)
+        for v, s in zip(va + vb, sa + sb):
+            assert np.all(s >= np.abs(v) * (1 - 1e-14))
+    ca, cb = oracle.to_cartesian("PtEtaPhiM", a), oracle.to_cartesian("PtEtaPhiM", b)
+    va, vb = oracle.mass_vjp("PxPyPzE", ca, cb, gm)
+    sa, sb = oracle.mass_vjp_scale("PxPyPzE", ca, cb, gm)
+    for v, s in zip(va + vb, sa + sb):
+        assert np.array_equal(s, np.abs(v))
