@@ -188,7 +188,9 @@ __device__ __forceinline__ void add4(const T a[4], const T b[4], T w[4]) {
 template <typename T>
 __device__ __forceinline__ T mass_of(const T w[4]) {
   T q = w[3] * w[3] - w[0] * w[0] - w[1] * w[1] - w[2] * w[2];
-  return q >= T(0) ? d_sqrt(q) : -d_sqrt(-q);
+  // one square root of |q|, then the sign (a zero q gives +0)
+  T m = d_sqrt(d_abs(q));
+  return (q < T(0)) ? -m : m;
 }
 
 // dm/d(Cartesian) = (-P, E)/|m| times the upstream gradient; zero at m = 0.
@@ -205,10 +207,11 @@ __device__ __forceinline__ void dmass(const T w[4], T m, T g, T u[4]) {
 // ------------------------------------------------- cancellation-free mass
 
 // sinh alone (small arguments by the odd polynomial, else from one exp).
+template <bool kCold = false>
 __device__ __forceinline__ double fast_sinh(double x) {
-  if (fabs(x) < 0.5) return poly_sinh_d(x);
+  if (fabs(x) < 0.5) return poly_sinh_d<kCold>(x);
   double sh, ch;
-  fast_sinhcosh(x, &sh, &ch);
+  fast_sinhcosh<kCold>(x, &sh, &ch);
   return sh;
 }
 __device__ __forceinline__ float fast_sinh(float x) {
@@ -261,7 +264,8 @@ struct LegC {
   T pt, eta, phi, m2, mt, delta;
 };
 
-template <typename T>
+// kCold: this evaluation is the rarely taken FP64 redo of an FP32 item.
+template <typename T, bool kCold = false>
 __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   LegC<T> L;
   L.pt = pt;
@@ -271,7 +275,10 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   L.m2 = mm;
   L.mt = d_sqrt(pt * pt + mm);
   T sh, ch;
-  fast_sinhcosh(eta, &sh, &ch);
+  if constexpr (sizeof(T) == 8)
+    fast_sinhcosh<kCold>(eta, &sh, &ch);
+  else
+    fast_sinhcosh(eta, &sh, &ch);
   T pc = pt * ch;
   T e = d_sqrt(pc * pc + mm);
   T den = L.mt * (pc + e);
@@ -286,15 +293,22 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
 // (16 units covers them) except the rapidity difference dy, whose absolute
 // error is a few units of |d1| + |d2| + |dy| plus that of the deltas; t1
 // moves with dy as 2 mTa mTb |sinh dy|.
-template <typename T>
+template <typename T, bool kCold = false>
 __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T* k, T* bound) {
   T d1 = a.eta - b.eta;
   T d2 = a.delta - b.delta;
   T dy = d1 + d2;
-  T s1 = fast_sinh(T(0.5) * dy);
+  T s1;
+  if constexpr (sizeof(T) == 8)
+    s1 = fast_sinh<kCold>(T(0.5) * dy);
+  else
+    s1 = fast_sinh(T(0.5) * dy);
   T t1 = T(2) * a.mt * b.mt * (s1 * s1);
   T s2, c2;
-  fast_sincos(T(0.5) * dphi_reduced(a.phi, b.phi), &s2, &c2);
+  if constexpr (sizeof(T) == 8)
+    fast_sincos<kCold>(T(0.5) * dphi_reduced(a.phi, b.phi), &s2, &c2);
+  else
+    fast_sincos(T(0.5) * dphi_reduced(a.phi, b.phi), &s2, &c2);
   T t2 = T(2) * a.pt * b.pt * (s2 * s2);
   T num = a.pt * a.pt * b.m2 + b.pt * b.pt * a.m2 + a.m2 * b.m2;
   T den = a.mt * b.mt + a.pt * b.pt;

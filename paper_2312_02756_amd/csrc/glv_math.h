@@ -13,8 +13,16 @@
 //
 // Split constants are the leading double / float of pi/2 and ln 2 and the
 // remainders; Taylor coefficients are 1/n!, written as quotients the compiler
-// folds exactly.  Arguments outside the reduction's range (|x| beyond 1e5 for
-// sincos in FP64, 1e4 in FP32) take the device library's functions.
+// folds exactly.
+//
+// Range.  The multiples k of pi/2 are removed with exact products inside the
+// fused multiply-adds, so the reduced argument carries an absolute error of
+// about |k| 2^-107 plus one rounding: within an ulp of the result for
+// |x| < 2^40 rad in FP64 (2^20 in FP32), which is where the quadrant k is
+// found exactly.  Beyond that (never for an azimuth) accuracy degrades.
+// exp overflows to inf / underflows to 0 on its own (so sinh and cosh of
+// |x| > 709.78 are +-inf, a little early near the double limit); NaN
+// propagates.  There is no fallback to library code, so no call sites.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,44 +31,55 @@ namespace glv {
 
 // ------------------------------------------------------------------- FP64
 
+// FP64 constants.  gfx9 has no 64-bit literals, so each one occupies a
+// scalar-register pair, and the compiler hoists them to the top of the
+// kernel.  That is right for the hot path, but on a rarely taken FP64 branch
+// (the FP64 redo of an FP32 item) the hoisted constants would stay live
+// across the whole kernel.  With kCold the value is marked as produced at
+// its point of use (the asm statement emits nothing), which keeps it there.
+template <bool kCold>
+__device__ __forceinline__ double kd(double c) {
+  if constexpr (kCold) asm volatile("" : "+s"(c));
+  return c;
+}
+
+template <bool kCold = false>
 __device__ __forceinline__ double poly_sin_d(double r) {
   const double z = r * r;
-  double p = -1.0 / 355687428096000.0;  // -1/17!
-  p = fma(p, z, 1.0 / 1307674368000.0);
-  p = fma(p, z, -1.0 / 6227020800.0);
-  p = fma(p, z, 1.0 / 39916800.0);
-  p = fma(p, z, -1.0 / 362880.0);
-  p = fma(p, z, 1.0 / 5040.0);
-  p = fma(p, z, -1.0 / 120.0);
-  p = fma(p, z, 1.0 / 6.0);
+  double p = kd<kCold>(-1.0 / 355687428096000.0);  // -1/17!
+  p = fma(p, z, kd<kCold>(1.0 / 1307674368000.0));
+  p = fma(p, z, kd<kCold>(-1.0 / 6227020800.0));
+  p = fma(p, z, kd<kCold>(1.0 / 39916800.0));
+  p = fma(p, z, kd<kCold>(-1.0 / 362880.0));
+  p = fma(p, z, kd<kCold>(1.0 / 5040.0));
+  p = fma(p, z, kd<kCold>(-1.0 / 120.0));
+  p = fma(p, z, kd<kCold>(1.0 / 6.0));
   // sin r = r - r^3 (1/6 - r^2/120 + ...)
   return fma(-r * z, p, r);
 }
 
+template <bool kCold = false>
 __device__ __forceinline__ double poly_cos_d(double r) {
   const double z = r * r;
-  double p = 1.0 / 20922789888000.0;  // 1/16!
-  p = fma(p, z, -1.0 / 87178291200.0);
-  p = fma(p, z, 1.0 / 479001600.0);
-  p = fma(p, z, -1.0 / 3628800.0);
-  p = fma(p, z, 1.0 / 40320.0);
-  p = fma(p, z, -1.0 / 720.0);
-  p = fma(p, z, 1.0 / 24.0);
+  double p = kd<kCold>(1.0 / 20922789888000.0);  // 1/16!
+  p = fma(p, z, kd<kCold>(-1.0 / 87178291200.0));
+  p = fma(p, z, kd<kCold>(1.0 / 479001600.0));
+  p = fma(p, z, kd<kCold>(-1.0 / 3628800.0));
+  p = fma(p, z, kd<kCold>(1.0 / 40320.0));
+  p = fma(p, z, kd<kCold>(-1.0 / 720.0));
+  p = fma(p, z, kd<kCold>(1.0 / 24.0));
   p = fma(p, z, -0.5);
   return fma(z, p, 1.0);
 }
 
+template <bool kCold = false>
 __device__ __forceinline__ void fast_sincos(double x, double* s, double* c) {
-  if (!(fabs(x) < 1.0e5)) {  // large or non-finite: the library's reduction
-    sincos(x, s, c);
-    return;
-  }
-  const double kd = rint(x * 0.6366197723675814);  // x * 2/pi
-  double r = fma(-kd, 1.5707963267948966, x);
-  r = fma(-kd, 6.123233995736766e-17, r);
-  r = fma(-kd, -1.4973849048591698e-33, r);
-  const double sr = poly_sin_d(r), cr = poly_cos_d(r);
-  const int q = (int)kd & 3;
+  const double kn = rint(x * kd<kCold>(0.6366197723675814));  // x * 2/pi
+  double r = fma(-kn, kd<kCold>(1.5707963267948966), x);
+  r = fma(-kn, kd<kCold>(6.123233995736766e-17), r);
+  r = fma(-kn, kd<kCold>(-1.4973849048591698e-33), r);
+  const double sr = poly_sin_d<kCold>(r), cr = poly_cos_d<kCold>(r);
+  const int q = (int)(kn - 4.0 * floor(0.25 * kn));  // k mod 4, exact
   const double ss = (q & 1) ? cr : sr;
   const double cc = (q & 1) ? sr : cr;
   *s = (q & 2) ? -ss : ss;
@@ -68,50 +87,48 @@ __device__ __forceinline__ void fast_sincos(double x, double* s, double* c) {
 }
 
 // e^x for |x| <= 709; overflows to inf beyond, underflows to 0.
+template <bool kCold = false>
 __device__ __forceinline__ double fast_exp(double x) {
-  const double kd = rint(x * 1.4426950408889634);  // x / ln2
-  double r = fma(-kd, 0.6931471805599453, x);
-  r = fma(-kd, 2.3190468138462996e-17, r);
-  double p = 1.0 / 6227020800.0;  // 1/13!
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
+  const double kn = rint(x * kd<kCold>(1.4426950408889634));  // x / ln2
+  double r = fma(-kn, kd<kCold>(0.6931471805599453), x);
+  r = fma(-kn, kd<kCold>(2.3190468138462996e-17), r);
+  double p = kd<kCold>(1.0 / 6227020800.0);  // 1/13!
+  p = fma(p, r, kd<kCold>(1.0 / 479001600.0));
+  p = fma(p, r, kd<kCold>(1.0 / 39916800.0));
+  p = fma(p, r, kd<kCold>(1.0 / 3628800.0));
+  p = fma(p, r, kd<kCold>(1.0 / 362880.0));
+  p = fma(p, r, kd<kCold>(1.0 / 40320.0));
+  p = fma(p, r, kd<kCold>(1.0 / 5040.0));
+  p = fma(p, r, kd<kCold>(1.0 / 720.0));
+  p = fma(p, r, kd<kCold>(1.0 / 120.0));
+  p = fma(p, r, kd<kCold>(1.0 / 24.0));
+  p = fma(p, r, kd<kCold>(1.0 / 6.0));
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  return ldexp(p, (int)kd);
+  return ldexp(p, (int)kn);
 }
 
 // sinh(x) for |x| < 1/2 (odd Taylor polynomial to x^15).
+template <bool kCold = false>
 __device__ __forceinline__ double poly_sinh_d(double x) {
   const double z = x * x;
-  double p = 1.0 / 1307674368000.0;  // 1/15!
-  p = fma(p, z, 1.0 / 6227020800.0);
-  p = fma(p, z, 1.0 / 39916800.0);
-  p = fma(p, z, 1.0 / 362880.0);
-  p = fma(p, z, 1.0 / 5040.0);
-  p = fma(p, z, 1.0 / 120.0);
-  p = fma(p, z, 1.0 / 6.0);
+  double p = kd<kCold>(1.0 / 1307674368000.0);  // 1/15!
+  p = fma(p, z, kd<kCold>(1.0 / 6227020800.0));
+  p = fma(p, z, kd<kCold>(1.0 / 39916800.0));
+  p = fma(p, z, kd<kCold>(1.0 / 362880.0));
+  p = fma(p, z, kd<kCold>(1.0 / 5040.0));
+  p = fma(p, z, kd<kCold>(1.0 / 120.0));
+  p = fma(p, z, kd<kCold>(1.0 / 6.0));
   return fma(x * z, p, x);
 }
 
+template <bool kCold = false>
 __device__ __forceinline__ void fast_sinhcosh(double x, double* sh, double* ch) {
-  if (!(fabs(x) < 700.0)) {  // e^|x| near or beyond overflow, or NaN
-    *sh = sinh(x);
-    *ch = cosh(x);
-    return;
-  }
-  const double e = fast_exp(x);
+  const double e = fast_exp<kCold>(x);
   const double ei = 1.0 / e;
   *ch = 0.5 * (e + ei);
-  *sh = (fabs(x) < 0.5) ? poly_sinh_d(x) : 0.5 * (e - ei);
+  *sh = (fabs(x) < 0.5) ? poly_sinh_d<kCold>(x) : 0.5 * (e - ei);
 }
 
 // ------------------------------------------------------------------- FP32
@@ -136,16 +153,12 @@ __device__ __forceinline__ float poly_cos_f(float r) {
 }
 
 __device__ __forceinline__ void fast_sincos(float x, float* s, float* c) {
-  if (!(fabsf(x) < 1.0e4f)) {
-    sincosf(x, s, c);
-    return;
-  }
   const float kf = rintf(x * 0.63661975f);
   float r = fmaf(-kf, 1.5707964f, x);
   r = fmaf(-kf, -4.371139e-08f, r);
   r = fmaf(-kf, -1.7151245e-15f, r);
   const float sr = poly_sin_f(r), cr = poly_cos_f(r);
-  const int q = (int)kf & 3;
+  const int q = (int)(kf - 4.0f * floorf(0.25f * kf));
   const float ss = (q & 1) ? cr : sr;
   const float cc = (q & 1) ? sr : cr;
   *s = (q & 2) ? -ss : ss;
@@ -178,11 +191,6 @@ __device__ __forceinline__ float poly_sinh_f(float x) {
 }
 
 __device__ __forceinline__ void fast_sinhcosh(float x, float* sh, float* ch) {
-  if (!(fabsf(x) < 85.0f)) {
-    *sh = sinhf(x);
-    *ch = coshf(x);
-    return;
-  }
   const float e = fast_exp(x);
   const float ei = 1.0f / e;
   *ch = 0.5f * (e + ei);

@@ -117,10 +117,10 @@ struct MassComp {
         T bound;
         T m2 = comp_pair_m2<T>(la, lb, &k, &bound);
         if (!(bound <= kFallbackUnits)) {
-          LegC<double> da = comp_leg<double>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
-          LegC<double> db = comp_leg<double>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
+          LegC<double> da = comp_leg<double, true>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
+          LegC<double> db = comp_leg<double, true>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
           double kd;
-          double m2d = comp_pair_m2<double>(da, db, &kd, nullptr);
+          double m2d = comp_pair_m2<double, true>(da, db, &kd, nullptr);
           out.v[e] = (T)sqrt(m2d);
           ++cnt;
         } else {

@@ -117,18 +117,37 @@ __device__ __forceinline__ void decode_pair(int64_t r, int64_t n, int64_t* pi, i
   *pj = i + 1 + (r - row_start(i, n));
 }
 
-// Fast decode for events staged in LDS (n <= 4096): the same search in FP32.
+// Decode for events staged in LDS (2 <= n <= 4096).  With b = 2n - 1 the
+// row is the floor of the root x = (b - sqrt(b^2 - 8r))/2 of R(x) = r.  In
+// FP32 b^2 - 8r (< 2^27, one rounding by the fused multiply-add) is off by at
+// most 4 and is at least 9, so the hardware square root (1 ulp) puts the
+// estimate within one row of the answer: one step down and one step up fix it.
+// Products stay below 2^25, so 24-bit multiplies are exact.
+__device__ __forceinline__ int row_start32(int i, int n) { return (int)(__umul24(i, 2 * n - i - 1) >> 1); }
+
 __device__ __forceinline__ void decode_pair_small(int r, int n, int* pi, int* pj) {
-  float b = (float)(2 * n - 1);
-  int i = (int)((b - sqrtf(fmaxf(b * b - 8.0f * (float)r, 0.0f))) * 0.5f);
+  const float b = (float)(2 * n - 1);
+  const float d = fmaf(b, b, -8.0f * (float)r);
+  int i = (int)((b - __builtin_amdgcn_sqrtf(fmaxf(d, 0.0f))) * 0.5f);
   i = max(0, min(i, n - 2));
-  while (i > 0 && i * (2 * n - i - 1) / 2 > r) --i;
-  while (i < n - 2 && (i + 1) * (2 * n - i - 2) / 2 <= r) ++i;
+  if (row_start32(i, n) > r) --i;
+  if (i < n - 2 && row_start32(i + 1, n) <= r) ++i;
   *pi = i;
-  *pj = i + 1 + (r - i * (2 * n - i - 1) / 2);
+  *pj = i + 1 + (r - row_start32(i, n));
 }
 
 // Last index e in [lo, hi) with a[e] <= key (a non-decreasing, a[lo] <= key).
+__device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key) {
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] <= key)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ int search_le(const int64_t* a, int lo, int hi, int64_t key) {
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
@@ -191,10 +210,10 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
     T bound;
     T m2 = comp_pair_m2<T>(a, b, &k, &bound);
     if (!(bound <= kFallbackUnits)) {
-      LegC<double> da = comp_leg<double>(a.pt, a.eta, a.phi, ma);
-      LegC<double> db = comp_leg<double>(b.pt, b.eta, b.phi, mb);
+      LegC<double> da = comp_leg<double, true>(a.pt, a.eta, a.phi, ma);
+      LegC<double> db = comp_leg<double, true>(b.pt, b.eta, b.phi, mb);
       double kd;
-      double m2d = comp_pair_m2<double>(da, db, &kd, nullptr);
+      double m2d = comp_pair_m2<double, true>(da, db, &kd, nullptr);
       *kout = kd;
       ++*fb;
       return (T)sqrt(m2d);
@@ -316,13 +335,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   const int epb = A.epb, cap = A.cap;
   const int nwaves = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // LDS: s_off[epb+1], s_poff[epb+1] (int64); red[16], acc[nwaves*epb] (double);
-  //      staged particle columns (T).
+  // LDS: s_off[epb+1], s_poff[epb+1] (int64, the tile's offsets); red[16],
+  //      acc[nwaves*epb] (double); ch_o[epb+1], ch_p[epb+1] (int32, offsets
+  //      relative to the current chunk); staged particle columns (T).
   int64_t* s_off = reinterpret_cast<int64_t*>(lds);
   int64_t* s_poff = s_off + (epb + 1);
   double* red = reinterpret_cast<double*>(s_poff + (epb + 1));
   double* acc = red + 16;
-  T* colbase = reinterpret_cast<T*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
+  int* ch_o = reinterpret_cast<int*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
+  int* ch_p = ch_o + (epb + 1);
+  T* colbase = reinterpret_cast<T*>(ch_p + (epb + 1));  // 8 (epb + 1) bytes of int32: stays 8-aligned
   Stage<T, MODE> st;
 #pragma unroll
   for (int k = 0; k < Stage<T, MODE>::kCols; ++k) st.col[k] = colbase + (size_t)k * cap;
@@ -353,16 +375,23 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       }
       // largest cb with s_off[cb] - s_off[ca] <= cap (cb > ca)
       const int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
+      const int nch = cb - ca;
       const int64_t pbase = s_off[ca];
+      const int64_t q0 = (want_pairs || want_k) ? s_poff[ca] : 0;
       const int np = (int)(s_off[cb] - pbase);
+      // chunk-relative offsets, so the pair loop works in 32-bit integers
+      for (int t = threadIdx.x; t <= nch; t += blockDim.x) {
+        ch_o[t] = (int)(s_off[ca + t] - pbase);
+        ch_p[t] = (want_pairs || want_k) ? (int)(s_poff[ca + t] - q0) : 0;
+      }
       for (int t = threadIdx.x; t < np; t += blockDim.x) stage_particle<T, COORDS, MODE>(A.p, pbase + t, st, t);
       __syncthreads();
 
       // one lane per event: totals in CSR order, plain event mass
       double msum = 0.0;
-      const int my = ca + (int)threadIdx.x;
-      if (my < cb) {
-        const int lo = (int)(s_off[my] - pbase), hi = (int)(s_off[my + 1] - pbase);
+      const int my = (int)threadIdx.x;  // event ca + my of the tile
+      if (my < nch) {
+        const int lo = ch_o[my], hi = ch_o[my + 1];
         T tot[4];
         if constexpr (sizeof(T) == 4) {
           double d[4] = {0, 0, 0, 0};
@@ -381,7 +410,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
         if constexpr (MODE == GLV_COMPENSATED) {
           for (int t = lo; t < hi; ++t) msum += (double)st.col[7][t] * (double)st.col[7][t];
         }
-        const int64_t e = e0 + my;
+        const int64_t e = e0 + ca + my;
         if (A.total[0]) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) store_out(A.total[k], e, tot[k]);
@@ -393,30 +422,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
 
       // pairs: one contiguous slice of the chunk's pairs per wavefront
       if (want_pairs || want_k) {
-        const int64_t q0 = s_poff[ca];
-        const int64_t q = s_poff[cb] - q0;
-        const int64_t lo = q * wid / nwaves, hi = q * (wid + 1) / nwaves;
+        const int q = ch_p[nch];
+        const int lo = (int)((int64_t)q * wid / nwaves), hi = (int)((int64_t)q * (wid + 1) / nwaves);
         // A lane's pair index grows by 64 per iteration, so its event is found
         // once by binary search and afterwards by stepping forward (a few
         // events at most per iteration on collider-sized events).
-        int ev = ca;
+        int ev = 0;
         bool located = false;
-        for (int64_t it = lo; it < hi; it += 64) {
-          const int64_t r = it + lane;
-          const bool valid = r < hi;
+        for (int it = lo; it < hi; it += 64) {
+          const int k = it + lane;  // chunk-relative pair index
+          const bool valid = k < hi;
           double kd = 0.0;
           if (valid) {
-            const int64_t k = q0 + r;
             if (!located) {
-              ev = search_le(s_poff, ca, cb, k);
+              ev = search_le32(ch_p, 0, nch, k);
               located = true;
             } else {
-              while (s_poff[ev + 1] <= k) ++ev;
+              while (ch_p[ev + 1] <= k) ++ev;
             }
-            const int n = (int)(s_off[ev + 1] - s_off[ev]);
+            const int base = ch_o[ev];
             int i, j;
-            decode_pair_small((int)(k - s_poff[ev]), n, &i, &j);
-            const int si = (int)(s_off[ev] - pbase) + i, sj = (int)(s_off[ev] - pbase) + j;
+            decode_pair_small(k - ch_p[ev], ch_o[ev + 1] - base, &i, &j);
+            const int si = base + i, sj = base + j;
             T m;
             if constexpr (MODE == GLV_COMPENSATED) {
               LegC<T> a = staged_leg<T, MODE>(st, si), b = staged_leg<T, MODE>(st, sj);
@@ -427,7 +454,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
               for (int c = 0; c < 4; ++c) w[c] = st.col[c][si] + st.col[c][sj];
               m = mass_of(w);
             }
-            if (want_pairs) store_out(A.pair_m, k, m);
+            if (want_pairs) store_out(A.pair_m, q0 + k, m);
           }
           if constexpr (MODE == GLV_COMPENSATED) {
             if (want_k) {
@@ -441,20 +468,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
               }
               int knext = __shfl_down(key, 1);
               bool seg_end = valid && (lane == 63 || knext != key);
-              if (seg_end) acc[wid * epb + (ev - 0)] += kd;
+              if (seg_end) acc[wid * epb + ev] += kd;
             }
           }
         }
       }
       __syncthreads();
       if constexpr (MODE == GLV_COMPENSATED) {
-        if (want_k && my < cb) {
+        if (want_k && my < nch) {
           double ks = 0.0;
           for (int w = 0; w < nwaves; ++w) {
             ks += acc[w * epb + my];
             acc[w * epb + my] = 0.0;
           }
-          store_out(A.event_m, e0 + my, (T)sqrt(msum + 2.0 * ks));
+          store_out(A.event_m, e0 + ca + my, (T)sqrt(msum + 2.0 * ks));
         }
       }
       __syncthreads();
@@ -739,7 +766,8 @@ size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
   size_t cols = (mode == GLV_COMPENSATED) ? 10 : 4;
   size_t nwaves = (size_t)t.block / 64;
   size_t acc = (mode == GLV_COMPENSATED) ? nwaves * (size_t)t.events_per_tile * 8 : 0;
-  return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + cols * (size_t)t.lds_particles * tsz;
+  return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + 2 * ((size_t)t.events_per_tile + 1) * 4 +
+         cols * (size_t)t.lds_particles * tsz;
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
