@@ -15,7 +15,10 @@
 namespace glv {
 namespace {
 
-constexpr int kBlock = 256;
+// Workgroup sizes (measured on MI355X: the streaming kernels run fastest with
+// 128 threads, the ALU-heavier compensated mass with 256).
+constexpr int kBlockStream = 128;
+constexpr int kBlockAlu = 256;
 
 // ---------------------------------------------------------------- driver
 
@@ -24,10 +27,10 @@ constexpr int kBlock = 256;
 // were recomputed in FP64; the total is added to *counter (one atomic per
 // wavefront with a non-zero count).
 template <typename Op, int V>
-__global__ __launch_bounds__(kBlock) void k_stream(Op op, int64_t n, unsigned long long* counter) {
+__global__ __launch_bounds__(Op::kBlock) void k_stream(Op op, int64_t n, unsigned long long* counter) {
   const int64_t nv = n / V;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * Op::kBlock;
+  const int64_t tid = (int64_t)blockIdx.x * Op::kBlock + threadIdx.x;
   unsigned cnt = 0;
   for (int64_t i = tid; i < nv; i += stride) cnt += op.template run<V>(i);
   if constexpr (V > 1) {
@@ -48,10 +51,10 @@ template <typename Op, int V>
 hipError_t run_stream(const Op& op, int64_t n, unsigned long long* counter, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t packs = n / V;
-  int64_t blocks = (packs + kBlock - 1) / kBlock;
+  int64_t blocks = (packs + Op::kBlock - 1) / Op::kBlock;
   if (blocks < 1) blocks = 1;
   if (blocks > 0x7fffffff) blocks = 0x7fffffff;
-  hipLaunchKernelGGL((k_stream<Op, V>), dim3((unsigned)blocks), dim3(kBlock), 0, s, op, n, counter);
+  hipLaunchKernelGGL((k_stream<Op, V>), dim3((unsigned)blocks), dim3(Op::kBlock), 0, s, op, n, counter);
   return hipGetLastError();
 }
 
@@ -69,6 +72,7 @@ hipError_t dispatch_width(const Op& op, bool all_aligned, int64_t n, unsigned lo
 template <typename T, int COORDS>
 struct MassPlain {
   static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
   Cols4<T> a, b;
   T* m;
   template <int V>
@@ -97,6 +101,7 @@ struct MassPlain {
 template <typename T>
 struct MassComp {
   static constexpr bool kCounts = true;
+  static constexpr int kBlock = kBlockAlu;
   Cols4<T> a, b;
   T* m;
   template <int V>
@@ -139,6 +144,7 @@ struct MassComp {
 template <typename T, int COORDS>
 struct MassBwd {
   static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
   Cols4<T> a, b;
   const T* gm;
   OutCols4<T> ga, gb;
@@ -191,6 +197,7 @@ __device__ __forceinline__ BoostCoef boost_coef(double bx, double by, double bz)
 template <typename T, int BSTRIDE>
 struct BoostFwd {
   static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
   Cols4<T> x;
   Cols3<T> beta;
   OutCols4<T> y;
@@ -233,6 +240,7 @@ struct BoostFwd {
 template <typename T, int BSTRIDE, bool WANT_GB>
 struct BoostBwd {
   static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
   Cols4<T> x;
   Cols3<T> beta;
   Cols4<T> gy;

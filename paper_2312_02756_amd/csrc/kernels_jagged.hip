@@ -34,54 +34,102 @@ __device__ __forceinline__ int64_t npairs(int64_t c) { return c * (c - 1) / 2; }
 
 // ------------------------------------------------------------ pair offsets
 
-constexpr int kScanBlock = 1024;
-constexpr int kScanItems = 4;
+// Multi-workgroup exclusive scan of n_e (n_e - 1)/2 in three launches, with
+// pair_offsets itself holding the per-tile totals between them (no scratch):
+//   1. workgroup b sums the pair counts of its kScanTile events and writes the
+//      total to pair_offsets[end_b], end_b = min((b + 1) kScanTile, ne);
+//   2. one workgroup turns those totals into running totals in place and sets
+//      pair_offsets[0] = 0;
+//   3. workgroup b scans its own events from pair_offsets[b kScanTile] and
+//      writes pair_offsets[e + 1] for its events except the last one, whose
+//      value step 2 left in place -- so no entry one workgroup reads is
+//      written by another.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
 
-// Exclusive scan of n_e (n_e - 1)/2 by one workgroup walking the events in
-// chunks of kScanBlock * kScanItems with a running carry.
-__global__ __launch_bounds__(kScanBlock) void k_pair_offsets(const int64_t* __restrict__ off,
-                                                             int64_t* __restrict__ po, int64_t ne) {
-  __shared__ int64_t wsum[kScanBlock / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int kWaves = kScanBlock / 64;
-  if (tid == 0) po[0] = 0;
+// Exclusive prefix over the workgroup of one int64 per thread; *total gets
+// the workgroup's sum.  ws holds one int64 per wavefront.
+__device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t* ws, int64_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t v = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t y = __shfl_up(v, d);
+    if (lane >= d) v += y;
+  }
+  if (lane == 63) ws[wid] = v;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (w < wid) before += ws[w];
+    all += ws[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + v - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_po_tile_totals(const int64_t* __restrict__ off,
+                                                                 int64_t* __restrict__ po, int64_t ne) {
+  __shared__ int64_t ws[kScanThreads / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+  int64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t e = b0 + j * kScanThreads + threadIdx.x;
+    if (e < ne) sum += npairs(off[e + 1] - off[e]);
+  }
+  int64_t total;
+  block_excl_scan(sum, ws, &total);
+  if (threadIdx.x == 0) po[min(b0 + kScanTile, ne)] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_po_scan_totals(int64_t* __restrict__ po, int64_t ne, int64_t ntiles) {
+  __shared__ int64_t ws[1024 / 64];
+  if (threadIdx.x == 0) po[0] = 0;
   int64_t carry = 0;
-  for (int64_t base = 0; base < ne; base += (int64_t)kScanBlock * kScanItems) {
-    int64_t c[kScanItems];
-    int64_t local = 0;
+  for (int64_t base = 0; base < ntiles; base += 1024) {
+    const int64_t b = base + threadIdx.x;
+    const int64_t at = min((b + 1) * kScanTile, ne);
+    const int64_t v = (b < ntiles) ? po[at] : 0;
+    int64_t total;
+    const int64_t ex = block_excl_scan(v, ws, &total);
+    if (b < ntiles) po[at] = carry + ex + v;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_po_tile_scan(const int64_t* __restrict__ off,
+                                                               int64_t* __restrict__ po, int64_t ne) {
+  __shared__ int64_t c[kScanTile];
+  __shared__ int64_t ws[kScanThreads / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+  const int64_t end = min(b0 + kScanTile, ne);
+  const int64_t base = (blockIdx.x == 0) ? 0 : po[b0];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      int64_t e = base + (int64_t)tid * kScanItems + j;
-      c[j] = (e < ne) ? npairs(off[e + 1] - off[e]) : 0;
-      local += c[j];
-    }
-    int64_t x = local;
+  for (int j = 0; j < kScanPer; ++j) {
+    const int idx = j * kScanThreads + threadIdx.x;
+    const int64_t e = b0 + idx;
+    c[idx] = (e < ne) ? npairs(off[e + 1] - off[e]) : 0;
+  }
+  __syncthreads();
+  int64_t run = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      int64_t y = __shfl_up(x, d);
-      if (lane >= d) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-      int64_t v = (lane < kWaves) ? wsum[lane] : 0;
+  for (int k = 0; k < kScanPer; ++k) run += c[threadIdx.x * kScanPer + k];
+  int64_t total;
+  int64_t pre = base + block_excl_scan(run, ws, &total);
 #pragma unroll
-      for (int d = 1; d < kWaves; d <<= 1) {
-        int64_t y = __shfl_up(v, d);
-        if (lane >= d) v += y;
-      }
-      if (lane < kWaves) wsum[lane] = v;
-    }
-    __syncthreads();
-    int64_t run = carry + (wid > 0 ? wsum[wid - 1] : 0) + (x - local);
+  for (int k = 0; k < kScanPer; ++k) {
+    pre += c[threadIdx.x * kScanPer + k];
+    c[threadIdx.x * kScanPer + k] = pre;  // inclusive: pair_offsets[e + 1]
+  }
+  __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      int64_t e = base + (int64_t)tid * kScanItems + j;
-      run += c[j];
-      if (e < ne) po[e + 1] = run;
-    }
-    carry += wsum[kWaves - 1];
-    __syncthreads();
+  for (int j = 0; j < kScanPer; ++j) {
+    const int idx = j * kScanThreads + threadIdx.x;
+    const int64_t e = b0 + idx;
+    if (e + 1 < end) po[e + 1] = c[idx];
   }
 }
 
@@ -159,13 +207,23 @@ __device__ __forceinline__ int search_le(const int64_t* a, int lo, int hi, int64
   return lo;
 }
 
-// Per-particle staged values.
-//   plain:        px py pz E
-//   compensated:  px py pz E  pt eta phi M  mt delta
+// Per-particle staged records in LDS, read with 16-byte LDS loads:
+//   cart[t] = (px, py, pz, E)                       every mode
+//   legA[t] = (pt, eta, phi, M), legB[t] = (mT, delta)   compensated mode
+template <typename T>
+struct V4 {
+  typedef T type __attribute__((ext_vector_type(4)));
+};
+template <typename T>
+struct V2 {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+
 template <typename T, int MODE>
 struct Stage {
-  static constexpr int kCols = (MODE == GLV_COMPENSATED) ? 10 : 4;
-  T* col[kCols];
+  typename V4<T>::type* cart;
+  typename V4<T>::type* legA;
+  typename V2<T>::type* legB;
 };
 
 template <typename T, int COORDS, int MODE>
@@ -174,29 +232,27 @@ __device__ __forceinline__ void stage_particle(const Cols4<T>& p, int64_t gi, co
   T c0 = p.c[0][gi], c1 = p.c[1][gi], c2 = p.c[2][gi], c3 = p.c[3][gi];
   T v[4];
   to_cart<COORDS>(c0, c1, c2, c3, v);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) s.col[k][slot] = v[k];
+  s.cart[slot] = typename V4<T>::type{v[0], v[1], v[2], v[3]};
   if constexpr (MODE == GLV_COMPENSATED) {
     LegC<T> L = comp_leg<T>(c0, c1, c2, c3);
-    s.col[4][slot] = c0;
-    s.col[5][slot] = c1;
-    s.col[6][slot] = c2;
-    s.col[7][slot] = c3;
-    s.col[8][slot] = L.mt;
-    s.col[9][slot] = L.delta;
+    s.legA[slot] = typename V4<T>::type{c0, c1, c2, c3};
+    s.legB[slot] = typename V2<T>::type{L.mt, L.delta};
   }
 }
 
+// Compensated leg terms of a staged particle; *mass receives M.
 template <typename T, int MODE>
-__device__ __forceinline__ LegC<T> staged_leg(const Stage<T, MODE>& s, int slot) {
+__device__ __forceinline__ LegC<T> staged_leg(const Stage<T, MODE>& s, int slot, T* mass) {
+  const typename V4<T>::type a = s.legA[slot];
+  const typename V2<T>::type b = s.legB[slot];
   LegC<T> L;
-  L.pt = s.col[4][slot];
-  L.eta = s.col[5][slot];
-  L.phi = s.col[6][slot];
-  T mass = s.col[7][slot];
-  L.m2 = mass * mass;
-  L.mt = s.col[8][slot];
-  L.delta = s.col[9][slot];
+  L.pt = a[0];
+  L.eta = a[1];
+  L.phi = a[2];
+  *mass = a[3];
+  L.m2 = a[3] * a[3];
+  L.mt = b[0];
+  L.delta = b[1];
   return L;
 }
 
@@ -331,23 +387,30 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
 
 template <typename T, int COORDS, int MODE>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
-  extern __shared__ __align__(16) unsigned char lds[];
+  extern __shared__ __align__(32) unsigned char lds[];
   const int epb = A.epb, cap = A.cap;
   const int nwaves = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // LDS: s_off[epb+1], s_poff[epb+1] (int64, the tile's offsets); red[16],
-  //      acc[nwaves*epb] (double); ch_o[epb+1], ch_p[epb+1] (int32, offsets
-  //      relative to the current chunk); staged particle columns (T).
-  int64_t* s_off = reinterpret_cast<int64_t*>(lds);
+  // LDS (cap is a multiple of 64, so every record array keeps the 32-byte
+  // alignment of the start):
+  //   cart[cap] (4 T), legA[cap] (4 T), legB[cap] (2 T)   staged records
+  //   s_off[epb+1], s_poff[epb+1]   int64, the tile's offsets
+  //   red[16], acc[nwaves*epb]      double
+  //   ch_o[epb+1], ch_p[epb+1]      int32, offsets relative to the chunk
+  Stage<T, MODE> st;
+  st.cart = reinterpret_cast<typename V4<T>::type*>(lds);
+  unsigned char* after = lds + (size_t)cap * 4 * sizeof(T);
+  if constexpr (MODE == GLV_COMPENSATED) {
+    st.legA = reinterpret_cast<typename V4<T>::type*>(after);
+    st.legB = reinterpret_cast<typename V2<T>::type*>(after + (size_t)cap * 4 * sizeof(T));
+    after += (size_t)cap * 6 * sizeof(T);
+  }
+  int64_t* s_off = reinterpret_cast<int64_t*>(after);
   int64_t* s_poff = s_off + (epb + 1);
   double* red = reinterpret_cast<double*>(s_poff + (epb + 1));
   double* acc = red + 16;
   int* ch_o = reinterpret_cast<int*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
   int* ch_p = ch_o + (epb + 1);
-  T* colbase = reinterpret_cast<T*>(ch_p + (epb + 1));  // 8 (epb + 1) bytes of int32: stays 8-aligned
-  Stage<T, MODE> st;
-#pragma unroll
-  for (int k = 0; k < Stage<T, MODE>::kCols; ++k) st.col[k] = colbase + (size_t)k * cap;
 
   const bool want_pairs = A.pair_m != nullptr;
   const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m != nullptr;
@@ -395,20 +458,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
         T tot[4];
         if constexpr (sizeof(T) == 4) {
           double d[4] = {0, 0, 0, 0};
-          for (int t = lo; t < hi; ++t)
+          for (int t = lo; t < hi; ++t) {
+            const typename V4<T>::type v = st.cart[t];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) d[k] += (double)st.col[k][t];
+            for (int k = 0; k < 4; ++k) d[k] += (double)v[k];
+          }
 #pragma unroll
           for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
         } else {
 #pragma unroll
           for (int k = 0; k < 4; ++k) tot[k] = T(0);
-          for (int t = lo; t < hi; ++t)
+          for (int t = lo; t < hi; ++t) {
+            const typename V4<T>::type v = st.cart[t];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) tot[k] += st.col[k][t];
+            for (int k = 0; k < 4; ++k) tot[k] += v[k];
+          }
         }
         if constexpr (MODE == GLV_COMPENSATED) {
-          for (int t = lo; t < hi; ++t) msum += (double)st.col[7][t] * (double)st.col[7][t];
+          for (int t = lo; t < hi; ++t) {
+            const double mt = (double)st.legA[t][3];
+            msum += mt * mt;
+          }
         }
         const int64_t e = e0 + ca + my;
         if (A.total[0]) {
@@ -446,12 +516,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
             const int si = base + i, sj = base + j;
             T m;
             if constexpr (MODE == GLV_COMPENSATED) {
-              LegC<T> a = staged_leg<T, MODE>(st, si), b = staged_leg<T, MODE>(st, sj);
-              m = comp_pair<T>(a, b, st.col[7][si], st.col[7][sj], &kd, &fb);
+              T ma, mb;
+              LegC<T> a = staged_leg<T, MODE>(st, si, &ma), b = staged_leg<T, MODE>(st, sj, &mb);
+              m = comp_pair<T>(a, b, ma, mb, &kd, &fb);
             } else {
+              const typename V4<T>::type va = st.cart[si], vb = st.cart[sj];
               T w[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) w[c] = st.col[c][si] + st.col[c][sj];
+              for (int c = 0; c < 4; ++c) w[c] = va[c] + vb[c];
               m = mass_of(w);
             }
             if (want_pairs) store_out(A.pair_m, q0 + k, m);
@@ -777,7 +849,14 @@ size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
 }
 
 hipError_t launch_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_offsets, dim3(1), dim3(kScanBlock), 0, s, off, po, ne);
+  const int64_t ntiles = (ne + kScanTile - 1) / kScanTile;
+  if (ntiles == 0) {  // no events: pair_offsets = {0}
+    hipLaunchKernelGGL(k_po_scan_totals, dim3(1), dim3(1024), 0, s, po, ne, (int64_t)0);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_po_tile_totals, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, off, po, ne);
+  hipLaunchKernelGGL(k_po_scan_totals, dim3(1), dim3(1024), 0, s, po, ne, ntiles);
+  hipLaunchKernelGGL(k_po_tile_scan, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, off, po, ne);
   return hipGetLastError();
 }
 
