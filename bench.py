@@ -19,8 +19,7 @@ separately with its algorithmic bytes, achieved GB/s and fraction of the
 stream the kernels run on, inside the timed steps.
 
 cpu_baseline: the CPU oracle (test infrastructure) timed on the host cores on
-half of one step's workload (2^23 items per element-wise kernel, 2^19 events),
-scaled to the same unit.
+one step's workload, repeated until about 10 s have passed, in the same unit.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--calib-copy]
 """
@@ -61,7 +60,70 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calib-copy run into profiles/hbm_traffic.txt and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
+                    help="turn a rocprofv3 --kernel-trace kernel_trace.csv and the JSON line the same run printed "
+                         "into profiles/step_kernel_trace.md and exit")
     return ap.parse_args()
+
+
+TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+             "-d $R/gpurun_out/prof_trace -o bench -- python3 $R/bench.py --steps 20 --warmup 3 --no-cpu "
+             "> $R/gpurun_out/trace_bench.json")
+
+
+def summarize_trace(trace_csv, bench_json):
+    """Per-kernel launch durations from a rocprofv3 kernel trace beside the
+    benchmark's own HIP-event averages of the same run.  For the step's
+    kernels only their last warmup + steps dispatches count (the jagged
+    autotuner's trial launches come before them)."""
+    import collections
+    import csv
+    import re
+
+    bench = None
+    for line in open(bench_json):
+        if line.startswith("{"):
+            bench = json.loads(line)
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        per[r["Kernel_Name"]].append((int(r["Dispatch_Id"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                                      * 1e-3, r["Workgroup_Size_X"], r["Grid_Size_X"], r["LDS_Block_Size"]))
+    n_step = bench["warmup"] + bench["steps"]
+    rows = []
+    for name, ds in per.items():
+        ds.sort()
+        short = re.sub(r"glv::\(anonymous namespace\)::", "", name)
+        key = next((k for k, sym in KERNEL_SYMBOL.items() if sym in short), None)
+        extra = len(ds) - n_step if key else 0
+        if key:
+            ds = ds[-n_step:]
+        us = np.array([d[1] for d in ds])
+        rows.append((us.sum(), short, key, len(ds), float(us.mean()), float(us.min()), extra, ds[-1][2:]))
+    total = sum(r[0] for r in rows)
+    out = ["# Kernel trace: one benchmark step (2^24 items per element-wise kernel, 2^20 jagged events)", "",
+           "Command (from the repository root `R` on one MI355X):", "", "```", TRACE_CMD, "```", "",
+           f"Source: `bench_kernel_trace.csv`; per step kernel its last {bench['warmup']} warm-up + "
+           f"{bench['steps']} timed dispatches; jagged tiling {bench['config']['event_tiling']} (autotuned on "
+           "these events, its trial launches excluded).  Algorithmic bytes per launch as in `bench.py`.", "",
+           "| kernel | calls | avg µs | min µs | share % | block, grid, LDS B | alg. bytes / launch | alg. GB/s (avg) "
+           "| % of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|"]
+    for tot, name, key, calls, avg, mn, extra, geo in sorted(rows, key=lambda r: -r[0]):
+        label = f"`{name[:100]}`" + (f" ({key})" if key else "")
+        g = f"{geo[0]}, {geo[1]}, {geo[2]}"
+        if key:
+            ab = bench["kernels"][key]["alg_bytes"]
+            gbs = ab / (avg * 1e-6) / 1e9
+            out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | {ab} | "
+                       f"{gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
+        else:
+            out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | — | — | — |")
+    out += ["", "The benchmark's own HIP-event averages in the same run (under the tracer):", ""]
+    for k, v in bench["kernels"].items():
+        out.append(f"* {k}: {v['avg_us']} µs, {v['alg_GBps']} GB/s ({100 * v['frac_hbm_peak']:.1f} % of peak)")
+    path = os.path.join(ROOT, "profiles", "step_kernel_trace.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
 
 
 COPY_BYTES = 1 << 30
@@ -87,7 +149,6 @@ def summarize_pmc(fetch_csv, write_csv):
     f_copy = max(max(fetch[k]) for k in copy)
     w_copy = max(max(write[k]) for k in copy)
     f_scale, w_scale = COPY_BYTES / f_copy, COPY_BYTES / w_copy
-    digest = source_digest()
     lines = [f"# HBM traffic per launch: rocprofv3 FETCH_SIZE x {f_scale:.4f} + WRITE_SIZE x {w_scale:.4f}",
              "# (scales from a 1 GiB device copy in the same runs).  Commands, from the repository root R:",
              "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o fetch -- "
@@ -96,7 +157,7 @@ def summarize_pmc(fetch_csv, write_csv):
              "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --calib-copy",
              "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/fetch_counter_collection.csv "
              "gpurun_out/pmc_write/write_counter_collection.csv",
-             f"# sources = digest of paper_2312_02756_amd/csrc at measurement time ({digest})"]
+             "# sources = digest of the kernel's source file and the shared headers at measurement time"]
     for key, sym in KERNEL_SYMBOL.items():
         names = [k for k in fetch if sym in re.sub(r"glv::\(anonymous namespace\)::", "", k)]
         if not names:
@@ -104,7 +165,7 @@ def summarize_pmc(fetch_csv, write_csv):
         n = names[0]
         fb = float(np.median(fetch[n])) * f_scale
         wb = float(np.median(write.get(n, [0.0]))) * w_scale
-        lines.append(f"traffic kernel={key} sources={digest} fetch_bytes={fb:.0f} write_bytes={wb:.0f} "
+        lines.append(f"traffic kernel={key} sources={source_digest(key)} fetch_bytes={fb:.0f} write_bytes={wb:.0f} "
                      f"bytes_per_launch={fb + wb:.0f}")
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     with open(path, "w") as fh:
@@ -112,12 +173,18 @@ def summarize_pmc(fetch_csv, write_csv):
     print("\n".join(lines))
 
 
-def source_digest():
-    """Digest of the kernel sources, to tell whether stored counter readings
-    still describe the current kernels."""
+# Sources that define each kernel and its launch configuration.
+KERNEL_SOURCES = {"event_reduce": ["kernels_jagged.hip", "glv_abi.hip"]}
+SHARED_SOURCES = ["glv_device.h", "glv_math.h", "glv_launch.h"]
+
+
+def source_digest(kernel):
+    """Digest of the sources that define `kernel` and its launch (its kernel
+    file and the shared headers), to tell whether stored counter readings still
+    describe it."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2312_02756_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in sorted(SHARED_SOURCES + KERNEL_SOURCES.get(kernel, ["kernels_elementwise.hip"])):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -130,7 +197,7 @@ def stored_traffic(kernel):
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    digest = source_digest()
+    digest = source_digest(kernel)
     for line in open(path):
         if not line.startswith("traffic "):
             continue
@@ -144,6 +211,9 @@ def main():
     args = parse()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no cross-GPU step: "
@@ -312,33 +382,33 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts):
-    """The oracle on the host cores over half a step (2^23 items per
-    element-wise kernel, 2^19 events), in the benchmark's unit."""
+def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, min_seconds=10.0, max_reps=20):
+    """The oracle on the host cores over one step's workload (2^24 items per
+    element-wise kernel, 2^20 events), repeated until at least `min_seconds`
+    have passed, in the benchmark's unit."""
     import oracle
 
-    n = N_ITEMS // 2
-    ne = N_EVENTS // 2
     threads = len(os.sched_getaffinity(0))
     oracle.set_threads(threads)
     used = oracle.get_threads()
-    cut = lambda cols: tuple(c[:n] for c in cols)  # noqa: E731
-    ca, cb, cx, cbeta, cgy, csa, csb = cut(a), cut(b), cut(x), cut(beta), cut(gy), cut(sa), cut(sb)
-    cgm = gm[:n]
-    coff = off[: ne + 1]
-    cparts = tuple(c[: coff[-1]] for c in parts)
+    reps = 0
     t = time.perf_counter()
-    oracle.mass_plain("PtEtaPhiM", ca, cb)
-    oracle.mass_vjp("PtEtaPhiM", ca, cb, cgm)
-    oracle.boost(cx, cbeta)
-    oracle.boost_vjp(cx, cbeta, cgy)
-    oracle.mass_accurate(csa, csb)
-    oracle.event_reduce("PtEtaPhiM", coff, cparts)
-    dt = time.perf_counter() - t
-    items = 3 * n + ne
+    while True:
+        oracle.mass_plain("PtEtaPhiM", a, b)
+        oracle.mass_vjp("PtEtaPhiM", a, b, gm)
+        oracle.boost(x, beta)
+        oracle.boost_vjp(x, beta, gy)
+        oracle.mass_accurate(sa, sb)
+        oracle.event_reduce("PtEtaPhiM", off, parts)
+        reps += 1
+        dt = time.perf_counter() - t
+        if dt >= min_seconds or reps >= max_reps:
+            break
+    items = reps * (3 * N_ITEMS + N_EVENTS)
     return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle",
-            "sample": f"half a step: 2^23 items through mass fwd+bwd, boost fwd+bwd and the accurate mass "
-                      f"(binary64 oracle), plus 2^19 jagged events; {dt:.2f} s wall on {used} threads"}
+            "sample": f"{reps} x one step's workload: 2^24 items through mass fwd+bwd, boost fwd+bwd and the "
+                      f"accurate mass (binary64 oracle), plus 2^20 jagged events; {dt:.2f} s wall on {used} "
+                      f"threads"}
 
 
 if __name__ == "__main__":
