@@ -10,10 +10,13 @@ collider-shaped input already resident in HBM:
   mass_comp32  FP32 compensated pair mass, 2^24 light pairs     (36 B/pair)
   event_reduce FP64 jagged reduction, 2^20 Poisson(8) events:
                totals, event mass and all pair masses           (~568 B/event)
+  event_reduce32c  the same events in FP32, compensated mode     (~292 B/event)
+  event_reduce_bwd FP64 reverse mode of the jagged reduction     (~824 B/event)
 
 value = items processed per second, in Gevents/s, where an item is a pair
 (through forward and backward), a vector (forward and backward), a
-compensated pair or a collider event; every kernel is also reported
+compensated pair, a collider event (FP64 forward and backward) or a collider
+event in the FP32 compensated mode; every kernel is also reported
 separately with its algorithmic bytes, achieved GB/s and fraction of the
 8 TB/s HBM peak.  Per-kernel times come from HIP events recorded on the
 stream the kernels run on, inside the timed steps.
@@ -41,11 +44,13 @@ METRIC = "Gevents/s & HBM GB/s (% of peak): mass/boost fwd+bwd, FP32-comp vs FP6
 HBM_PEAK_GBS = 8000.0
 N_ITEMS = 1 << 24
 N_EVENTS = 1 << 20
-KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_comp32", "event_reduce"]
+KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_comp32", "event_reduce", "event_reduce32c",
+           "event_reduce_bwd"]
 KERNEL_SYMBOL = {
     "mass_fwd": "MassPlain<double, 1>", "mass_bwd": "MassBwd<double, 1>", "boost_fwd": "BoostFwd<double, 1>",
     "boost_bwd": "BoostBwd<double, 1, true>", "mass_comp32": "MassComp<float>",
-    "event_reduce": "k_event_reduce<double, 1, 0>",
+    "event_reduce": "k_event_reduce<double, 1, 0>", "event_reduce32c": "k_event_reduce<float, 1, 1>",
+    "event_reduce_bwd": "k_event_reduce_bwd<double, 1>",
 }
 
 
@@ -174,7 +179,8 @@ def summarize_pmc(fetch_csv, write_csv):
 
 
 # Sources that define each kernel and its launch configuration.
-KERNEL_SOURCES = {"event_reduce": ["kernels_jagged.hip", "glv_abi.hip"]}
+KERNEL_SOURCES = {k: ["kernels_jagged.hip", "glv_abi.hip"] for k in ("event_reduce", "event_reduce32c",
+                                                                       "event_reduce_bwd")}
 SHARED_SOURCES = ["glv_device.h", "glv_math.h", "glv_launch.h"]
 
 
@@ -242,6 +248,12 @@ def main():
     sa, sb, _ = synth.pairs_stress(synth.rng(synth.STRESS), N_ITEMS)
     sa, sb = synth.as_dtype(sa, np.float32), synth.as_dtype(sb, np.float32)
     off, parts = synth.jagged_events(synth.rng(synth.JAGGED), N_EVENTS)
+    parts32 = synth.as_dtype(parts, np.float32)
+    n_pairs_h = int(np.sum((np.diff(off) * (np.diff(off) - 1)) // 2))
+    gj = synth.rng(synth.JAGGED_GRADS)
+    g_tot = synth.upstream(gj, N_EVENTS, 4)
+    g_em = synth.upstream(gj, N_EVENTS, 1)[0]
+    g_pair = synth.upstream(gj, n_pairs_h, 1)[0]
     gen_s = time.time() - t0
 
     # -------------------------------------------------------- inputs (device)
@@ -251,12 +263,18 @@ def main():
     GY = gpu(gy, torch.float64)
     SA, SB = gpu(sa, torch.float32), gpu(sb, torch.float32)
     P = gpu(parts, torch.float64)
+    P32 = gpu(parts32, torch.float32)
     OFF = torch.from_numpy(off).to(dev)
     PO = glv.glv_pair_offsets(OFF)
     n_pairs = int(PO[-1].item())
+    assert n_pairs == n_pairs_h
     n_part = int(off[-1])
-    # the jagged reduction runs with the tiling the autotuner picks on these events
+    GTOT = gpu(g_tot, torch.float64)
+    GEM = gpu([g_em], torch.float64)[0]
+    GPAIR = gpu([g_pair], torch.float64)[0]
+    # the jagged reductions run with the tilings the autotuner picks on these events
     tiling = glv.glv_autotune_event_reduce(P, OFF, PO)
+    tiling32c = glv.glv_autotune_event_reduce(P32, OFF, PO, mode="compensated")
     # outputs preallocated once, reused every step
     M = torch.empty(N_ITEMS, dtype=torch.float64, device=dev)
     MC = torch.empty(N_ITEMS, dtype=torch.float32, device=dev)
@@ -278,11 +296,17 @@ def main():
     TOT = tuple(torch.empty(N_EVENTS, dtype=torch.float64, device=dev) for _ in range(4))
     EM = torch.empty(N_EVENTS, dtype=torch.float64, device=dev)
     PM = torch.empty(n_pairs, dtype=torch.float64, device=dev)
+    TOT32 = tuple(torch.empty(N_EVENTS, dtype=torch.float32, device=dev) for _ in range(4))
+    EM32 = torch.empty(N_EVENTS, dtype=torch.float32, device=dev)
+    PM32 = torch.empty(n_pairs, dtype=torch.float32, device=dev)
+    FBJ = torch.zeros(1, dtype=torch.int64, device=dev)
+    GP = tuple(torch.empty(n_part, dtype=torch.float64, device=dev) for _ in range(4))
 
     # C-ABI calls with pointers marshalled once
     cA, cB, cX, cBETA, cGY = ptr4(A), ptr4(B), ptr4(X), ptr3(BETA), ptr4(GY)
     cGA, cGB, cY, cGX, cGBETA = ptr4(GA), ptr4(GB), ptr4(Y), ptr4(GX), ptr3(GBETA)
     cSA, cSB, cP, cTOT = ptr4(SA), ptr4(SB), ptr4(P), ptr4(TOT)
+    cP32, cTOT32, cGTOT, cGP = ptr4(P32), ptr4(TOT32), ptr4(GTOT), ptr4(GP)
     F32, F64, PTM, CART = _lib.GLV_F32, _lib.GLV_F64, _lib.GLV_PTETAPHIM, _lib.GLV_PXPYPZE
     PLAIN, COMP = _lib.GLV_PLAIN, _lib.GLV_COMPENSATED
 
@@ -295,16 +319,24 @@ def main():
                                                       FB.data_ptr(), sp),
         "event_reduce": lambda: lib.glv_event_reduce(F64, PTM, PLAIN, N_EVENTS, OFF.data_ptr(), PO.data_ptr(), cP,
                                                      cTOT, EM.data_ptr(), PM.data_ptr(), None, None, sp),
+        "event_reduce32c": lambda: lib.glv_event_reduce(F32, PTM, COMP, N_EVENTS, OFF.data_ptr(), PO.data_ptr(),
+                                                        cP32, cTOT32, EM32.data_ptr(), PM32.data_ptr(),
+                                                        FBJ.data_ptr(), None, sp),
+        "event_reduce_bwd": lambda: lib.glv_event_reduce_bwd(F64, PTM, N_EVENTS, OFF.data_ptr(), PO.data_ptr(), cP,
+                                                             cGTOT, GEM.data_ptr(), GPAIR.data_ptr(), cGP, None,
+                                                             sp),
     }
     # algorithmic bytes per launch: what each kernel must read and write once
     alg_bytes = {
         "mass_fwd": 72 * N_ITEMS, "mass_bwd": 136 * N_ITEMS, "boost_fwd": 88 * N_ITEMS,
         "boost_bwd": 144 * N_ITEMS, "mass_comp32": 36 * N_ITEMS,
         "event_reduce": 32 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
+        "event_reduce32c": 16 * n_part + 16 * (N_EVENTS + 1) + 20 * N_EVENTS + 4 * n_pairs,
+        "event_reduce_bwd": 64 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
     }
     units = {"mass_fwd": 0, "mass_bwd": N_ITEMS, "boost_fwd": 0, "boost_bwd": N_ITEMS, "mass_comp32": N_ITEMS,
-             "event_reduce": N_EVENTS}
-    # a pair / vector counts once for its forward + backward pass
+             "event_reduce": 0, "event_reduce32c": N_EVENTS, "event_reduce_bwd": N_EVENTS}
+    # a pair / vector / FP64 event counts once for its forward + backward pass
     items_per_step = sum(units.values())
 
     def step(evs=None):
@@ -339,12 +371,13 @@ def main():
         per_kernel[k] = {
             "avg_us": round(avg * 1e6, 2), "min_us": round(float(ts.min()) * 1e6, 2),
             "alg_bytes": int(alg_bytes[k]), "alg_GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "units": N_EVENTS if k == "event_reduce" else N_ITEMS,
-            "Gunits_per_s": round((N_EVENTS if k == "event_reduce" else N_ITEMS) / avg / 1e9, 3),
+            "units": N_EVENTS if k.startswith("event_reduce") else N_ITEMS,
+            "Gunits_per_s": round((N_EVENTS if k.startswith("event_reduce") else N_ITEMS) / avg / 1e9, 3),
         }
     per_kernel["event_reduce"]["pairs"] = n_pairs
     per_kernel["event_reduce"]["particles"] = n_part
     per_kernel["mass_comp32"]["fp64_redo_per_launch"] = int(FB.item()) // max(1, args.warmup + K)
+    per_kernel["event_reduce32c"]["fp64_redo_per_launch"] = int(FBJ.item()) // max(1, args.warmup + K)
 
     ms_per_step = elapsed / K * 1e3
     value = items_per_step / (elapsed / K) / 1e9
@@ -361,7 +394,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts)
+        cpu = cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em, g_pair)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gevents/s", "n_gpus": 1, "steps": K,
@@ -369,10 +402,13 @@ def main():
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {
             "workload": "2^24 FP64 PtEtaPhiM pairs (mass fwd+bwd) + 2^24 FP64 PxPyPzE vectors with per-item beta "
-                        "(boost fwd+bwd) + 2^24 FP32 light/collinear pairs (compensated mass) + 2^20 FP64 jagged "
-                        "events, Poisson(8) particles (totals, event mass, all pair masses) per step",
+                        "(boost fwd+bwd) + 2^24 FP32 light/collinear pairs (compensated mass) + 2^20 jagged "
+                        "events, Poisson(8) particles (totals, event mass, all pair masses; FP64 fwd+bwd and "
+                        "FP32 compensated fwd) per step",
             "items_per_step": items_per_step, "pairs_in_events": n_pairs, "particles": n_part,
             "event_tiling": {"block": tiling[0], "events_per_tile": tiling[1], "lds_particles": tiling[2]},
+            "event_tiling_fp32_comp": {"block": tiling32c[0], "events_per_tile": tiling32c[1],
+                                       "lds_particles": tiling32c[2]},
             "parallelism": "single GPU", "input_gen_s": round(gen_s, 1),
         },
         "roofline": roofline,
@@ -382,7 +418,8 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, min_seconds=10.0, max_reps=20):
+def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em, g_pair, min_seconds=10.0,
+                 max_reps=20):
     """The oracle on the host cores over one step's workload (2^24 items per
     element-wise kernel, 2^20 events), repeated until at least `min_seconds`
     have passed, in the benchmark's unit."""
@@ -400,15 +437,17 @@ def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, min_seconds=10.0, ma
         oracle.boost_vjp(x, beta, gy)
         oracle.mass_accurate(sa, sb)
         oracle.event_reduce("PtEtaPhiM", off, parts)
+        oracle.event_reduce("PtEtaPhiM", off, parts32, oracle.ACCURATE)
+        oracle.event_reduce_vjp("PtEtaPhiM", off, parts, g_tot, g_em, g_pair)
         reps += 1
         dt = time.perf_counter() - t
         if dt >= min_seconds or reps >= max_reps:
             break
-    items = reps * (3 * N_ITEMS + N_EVENTS)
+    items = reps * (3 * N_ITEMS + 2 * N_EVENTS)
     return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle",
             "sample": f"{reps} x one step's workload: 2^24 items through mass fwd+bwd, boost fwd+bwd and the "
-                      f"accurate mass (binary64 oracle), plus 2^20 jagged events; {dt:.2f} s wall on {used} "
-                      f"threads"}
+                      f"accurate mass, 2^20 jagged events through the plain reduction and its VJP and the accurate "
+                      f"reduction (binary64 oracle); {dt:.2f} s wall on {used} threads"}
 
 
 if __name__ == "__main__":

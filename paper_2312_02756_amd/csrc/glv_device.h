@@ -82,7 +82,24 @@ __device__ __forceinline__ void store_pack(T* __restrict__ p, int64_t i, const P
 
 // ------------------------------------------------------------ scalar math
 
-__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+// FP64 square root: the hardware reciprocal square root y ~ 1/sqrt(x)
+// (relative error below 2^-22), one Goldschmidt step (g -> sqrt x,
+// h -> 1/(2 sqrt x), error ~2^-45) and one Newton correction of g from the
+// residual x - g^2 formed by a fused multiply-add (error ~2^-90 before the
+// final rounding).  The result is the correctly rounded root unless that lies
+// within ~2^-90 (relative) of a rounding midpoint; the compiler's expansion
+// adds a second correction and subnormal scaling, seven more instructions on
+// the pair loops.  0 and +inf pass through, NaN propagates, x < 0 gives NaN;
+// subnormal x (never a mass squared here) may lose a few bits.
+__device__ __forceinline__ double d_sqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, x), h, g);
+  return (x == 0.0 || x == __builtin_huge_val()) ? x : g;
+}
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_abs(double x) { return fabs(x); }
 __device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
@@ -224,7 +241,11 @@ __device__ __forceinline__ float fast_sinh(float x) {
 // asinh of the small argument of delta.  FP32: for |x| < 1/8 the Taylor
 // series x - x^3/6 + 3x^5/40 - 5x^7/112 (next term below 2e-9 relative);
 // otherwise, and always in FP64, the device library's asinh.
-__device__ __forceinline__ double small_asinh(double x) { return asinh(x); }
+template <bool kCold>
+__device__ __forceinline__ double small_asinh(double x) {
+  return fast_asinh<kCold>(x);
+}
+template <bool kCold>
 __device__ __forceinline__ float small_asinh(float x) {
   if (!(fabsf(x) < 0.125f)) return asinhf(x);
   const float z = x * x;
@@ -282,7 +303,7 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   T pc = pt * ch;
   T e = d_sqrt(pc * pc + mm);
   T den = L.mt * (pc + e);
-  L.delta = (den > T(0)) ? -small_asinh(mm * sh / den) : T(0);
+  L.delta = (den > T(0)) ? -small_asinh<kCold>(mm * sh / den) : T(0);
   return L;
 }
 

@@ -9,7 +9,14 @@
 //   exp     the same reduction by ln 2 (two-part split) and the Taylor
 //           polynomial of e^r on |r| <= ln2/2, scaled by 2^k;
 //   sinh / cosh from one exp and one reciprocal; sinh by its odd Taylor
-//           polynomial for |x| < 1/2, where e^x - e^-x would cancel.
+//           polynomial for |x| < 1/2, where e^x - e^-x would cancel;
+//   log     (FP64) x = m 2^e with m in [sqrt(1/2), sqrt(2)), log m = 2 atanh s,
+//           s = (m - 1)/(m + 1), by the odd Taylor series of atanh (|s| <= 0.172,
+//           truncation below 2^-60 relative), e ln 2 added in two parts;
+//   asinh   (FP64) odd Taylor polynomial for |x| < 1/8; log1p(|x| + x^2 /
+//           (1 + sqrt(1 + x^2))) below 2^28, the log1p as log w plus the
+//           first-order correction for the rounding of w = 1 + u; log 2|x|
+//           beyond.  Within 3 ulp (checked against 200-bit references).
 //
 // Split constants are the leading double / float of pi/2 and ln 2 and the
 // remainders; Taylor coefficients are 1/n!, written as quotients the compiler
@@ -129,6 +136,66 @@ __device__ __forceinline__ void fast_sinhcosh(double x, double* sh, double* ch) 
   const double ei = 1.0 / e;
   *ch = 0.5 * (e + ei);
   *sh = (fabs(x) < 0.5) ? poly_sinh_d<kCold>(x) : 0.5 * (e - ei);
+}
+
+// log(x); x = 0 gives -inf, +inf gives +inf, x < 0 and NaN give NaN.  log
+// and asinh are used only once per leg, never in an inner loop, so their
+// constants are always materialized at their use (kd<true>) rather than held
+// in scalar registers for the whole kernel.
+template <bool kCold = false>
+__device__ __forceinline__ double fast_log(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  if (m < kd<true>(0.7071067811865476)) {
+    m = 2.0 * m;
+    e -= 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double p = kd<true>(1.0 / 23.0);
+  p = fma(p, z, kd<true>(1.0 / 21.0));
+  p = fma(p, z, kd<true>(1.0 / 19.0));
+  p = fma(p, z, kd<true>(1.0 / 17.0));
+  p = fma(p, z, kd<true>(1.0 / 15.0));
+  p = fma(p, z, kd<true>(1.0 / 13.0));
+  p = fma(p, z, kd<true>(1.0 / 11.0));
+  p = fma(p, z, kd<true>(1.0 / 9.0));
+  p = fma(p, z, kd<true>(1.0 / 7.0));
+  p = fma(p, z, kd<true>(1.0 / 5.0));
+  p = fma(p, z, kd<true>(1.0 / 3.0));
+  const double t = 2.0 * s;
+  const double lm = fma(t * z, p, t);  // log m
+  const double de = (double)e;
+  const double r = fma(de, kd<true>(0.6931471805599453), fma(de, kd<true>(2.3190468138462996e-17), lm));
+  if (x > 0.0 && x < __builtin_huge_val()) return r;
+  return (x == 0.0) ? -__builtin_huge_val() : ((x == __builtin_huge_val()) ? x : __builtin_nan(""));
+}
+
+template <bool kCold = false>
+__device__ __forceinline__ double fast_asinh(double x) {
+  const double ax = fabs(x);
+  double r;
+  if (ax < 0.125) {
+    const double z = ax * ax;
+    double p = kd<true>(-12155.0 / 1245184.0);  // coefficient of x^19
+    p = fma(p, z, kd<true>(6435.0 / 557056.0));
+    p = fma(p, z, kd<true>(-143.0 / 10240.0));
+    p = fma(p, z, kd<true>(231.0 / 13312.0));
+    p = fma(p, z, kd<true>(-63.0 / 2816.0));
+    p = fma(p, z, kd<true>(35.0 / 1152.0));
+    p = fma(p, z, kd<true>(-5.0 / 112.0));
+    p = fma(p, z, kd<true>(3.0 / 40.0));
+    p = fma(p, z, kd<true>(-1.0 / 6.0));
+    r = fma(ax * z, p, ax);
+  } else if (ax < kd<true>(268435456.0)) {  // 2^28
+    const double z = ax * ax;
+    const double u = ax + z / (1.0 + sqrt(1.0 + z));
+    const double w = 1.0 + u;
+    r = fast_log<kCold>(w) + (u - (w - 1.0)) / w;
+  } else {
+    r = fast_log<kCold>(ax) + kd<true>(0.6931471805599453);
+  }
+  return copysign(r, x);
 }
 
 // ------------------------------------------------------------------- FP32

@@ -13,8 +13,9 @@
 //     event mass of the plain mode);
 //   * the chunk's pairs -- contiguous in the output too -- are split into
 //     equal contiguous slices, one per wavefront; lanes take consecutive pair
-//     indices, locate their event by binary search over the staged pair
-//     offsets, decode (i, j) from the in-event rank and store the pair mass
+//     indices, locate their event (binary search once, then stepping forward
+//     over the staged per-event records), turn the in-event rank into (i, j)
+//     through a table of co-lexicographic pairs and store the pair mass
 //     (consecutive lanes write consecutive addresses);
 //   * in the compensated mode the event mass is
 //     m^2 = sum_i M_i^2 + 2 sum_{i<j} K_ij (all terms >= 0); each wavefront
@@ -22,8 +23,10 @@
 //     adds the segment sums to a per-(wavefront, event) LDS slot, and the
 //     event lane adds the slots in wavefront order: the result depends on
 //     the tiling only, never on timing.
-// An event with more particles than fit in LDS is handled by the whole
-// workgroup straight from global memory (correct for any size, slower).
+// An event with more particles than fit in LDS is left to a second, small
+// launch (k_event_reduce_big), where a whole workgroup takes it straight from
+// global memory (correct for any size, slower); on collider-sized events that
+// launch only reads the offsets.
 #include "glv_device.h"
 #include "glv_launch.h"
 
@@ -184,11 +187,46 @@ __device__ __forceinline__ void decode_pair_small(int r, int n, int* pi, int* pj
   *pj = i + 1 + (r - row_start32(i, n));
 }
 
-// Last index e in [lo, hi) with a[e] <= key (a non-decreasing, a[lo] <= key).
-__device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key) {
+// Pair of lexicographic rank r among n particles, through the mirrored pair
+// (n-1-j, n-1-i): the mirror reverses the order, so its rank in
+// co-lexicographic order (by the larger index, then the smaller) is
+// P - 1 - r with P = n(n-1)/2, and co-lexicographic ranks do not depend on
+// n.  One table of the kColexN(kColexN-1)/2 co-lexicographic pairs, built once
+// per workgroup in LDS, therefore serves every event of at most kColexN
+// particles; larger events take the square-root decode.
+constexpr int kColexN = 32;
+constexpr int kColexPairs = kColexN * (kColexN - 1) / 2;
+
+// Entry r of the table: the pair (a, b), a < b, with b(b-1)/2 + a = r, as
+// a | b << 8.
+__device__ __forceinline__ unsigned short colex_entry(int r) {
+  int b = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)r)) * 0.5f);
+  while (b * (b - 1) / 2 > r) --b;
+  while ((b + 1) * b / 2 <= r) ++b;
+  return (unsigned short)((r - b * (b - 1) / 2) | (b << 8));
+}
+
+__device__ __forceinline__ void pair_of_rank(int r, int n, const unsigned short* colex, int* pi, int* pj) {
+  if (n <= kColexN) {
+    const unsigned t = colex[(int)(__umul24(n, n - 1) >> 1) - 1 - r];
+    *pi = n - 1 - (int)(t >> 8);
+    *pj = n - 1 - (int)(t & 0xffu);
+  } else {
+    decode_pair_small(r, n, pi, pj);
+  }
+}
+
+// Per event of a chunk: first particle and first pair, relative to the chunk.
+struct EvRec {
+  int o;
+  int p;
+};
+
+// Last event e in [lo, hi) with rec[e].p <= key (p non-decreasing).
+__device__ __forceinline__ int search_rec(const EvRec* rec, int lo, int hi, int key) {
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
-    if (a[mid] <= key)
+    if (rec[mid].p <= key)
       lo = mid;
     else
       hi = mid;
@@ -237,6 +275,26 @@ __device__ __forceinline__ void stage_particle(const Cols4<T>& p, int64_t gi, co
     LegC<T> L = comp_leg<T>(c0, c1, c2, c3);
     s.legA[slot] = typename V4<T>::type{c0, c1, c2, c3};
     s.legB[slot] = typename V2<T>::type{L.mt, L.delta};
+  }
+}
+
+// acc += rec[lo] + rec[lo+1] + ... + rec[hi-1], component-wise and in index
+// order (each component's additions stay sequential), two records read per
+// LDS wait (four would cost the kernel its sixth wavefront per SIMD).
+template <typename A, typename V>
+__device__ __forceinline__ void sum_records(const V* rec, int lo, int hi, A acc[4]) {
+  int t = lo;
+  for (; t + 2 <= hi; t += 2) {
+    const V r0 = rec[t], r1 = rec[t + 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += (A)r0[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += (A)r1[k];
+  }
+  for (; t < hi; ++t) {
+    const V r = rec[t];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += (A)r[k];
   }
 }
 
@@ -396,7 +454,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   //   cart[cap] (4 T), legA[cap] (4 T), legB[cap] (2 T)   staged records
   //   s_off[epb+1], s_poff[epb+1]   int64, the tile's offsets
   //   red[16], acc[nwaves*epb]      double
-  //   ch_o[epb+1], ch_p[epb+1]      int32, offsets relative to the chunk
+  //   ch[epb+1]                     EvRec, offsets relative to the chunk
+  //   colex[kColexPairs]            uint16, the pair table
   Stage<T, MODE> st;
   st.cart = reinterpret_cast<typename V4<T>::type*>(lds);
   unsigned char* after = lds + (size_t)cap * 4 * sizeof(T);
@@ -409,8 +468,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   int64_t* s_poff = s_off + (epb + 1);
   double* red = reinterpret_cast<double*>(s_poff + (epb + 1));
   double* acc = red + 16;
-  int* ch_o = reinterpret_cast<int*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
-  int* ch_p = ch_o + (epb + 1);
+  EvRec* ch = reinterpret_cast<EvRec*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
+  unsigned short* colex = reinterpret_cast<unsigned short*>(ch + (epb + 1));
+  // a wave's share of a chunk's pairs is a shift: nwaves is a power of two
+  const int lg_waves = __builtin_ctz(nwaves);
+  const int wid_s = __builtin_amdgcn_readfirstlane(wid);
 
   const bool want_pairs = A.pair_m != nullptr;
   const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m != nullptr;
@@ -419,6 +481,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
 
   if constexpr (MODE == GLV_COMPENSATED) {
     for (int i = threadIdx.x; i < nwaves * epb; i += blockDim.x) acc[i] = 0.0;
+  }
+  if (want_pairs || want_k) {
+    for (int r = threadIdx.x; r < kColexPairs; r += blockDim.x) colex[r] = colex_entry(r);
   }
 
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -431,8 +496,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
     __syncthreads();
     int ca = 0;
     while (ca < nev) {
-      if (s_off[ca + 1] - s_off[ca] > cap) {
-        big_event<T, COORDS, MODE>(A, e0 + ca, s_off[ca], s_off[ca + 1], red, &fb);
+      if (s_off[ca + 1] - s_off[ca] > cap) {  // k_event_reduce_big's event
         ++ca;
         continue;
       }
@@ -444,8 +508,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       const int np = (int)(s_off[cb] - pbase);
       // chunk-relative offsets, so the pair loop works in 32-bit integers
       for (int t = threadIdx.x; t <= nch; t += blockDim.x) {
-        ch_o[t] = (int)(s_off[ca + t] - pbase);
-        ch_p[t] = (want_pairs || want_k) ? (int)(s_poff[ca + t] - q0) : 0;
+        ch[t] = EvRec{(int)(s_off[ca + t] - pbase), (want_pairs || want_k) ? (int)(s_poff[ca + t] - q0) : 0};
       }
       for (int t = threadIdx.x; t < np; t += blockDim.x) stage_particle<T, COORDS, MODE>(A.p, pbase + t, st, t);
       __syncthreads();
@@ -454,25 +517,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       double msum = 0.0;
       const int my = (int)threadIdx.x;  // event ca + my of the tile
       if (my < nch) {
-        const int lo = ch_o[my], hi = ch_o[my + 1];
+        const int lo = ch[my].o, hi = ch[my + 1].o;
         T tot[4];
         if constexpr (sizeof(T) == 4) {
           double d[4] = {0, 0, 0, 0};
-          for (int t = lo; t < hi; ++t) {
-            const typename V4<T>::type v = st.cart[t];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) d[k] += (double)v[k];
-          }
+          sum_records(st.cart, lo, hi, d);
 #pragma unroll
           for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
         } else {
 #pragma unroll
           for (int k = 0; k < 4; ++k) tot[k] = T(0);
-          for (int t = lo; t < hi; ++t) {
-            const typename V4<T>::type v = st.cart[t];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) tot[k] += v[k];
-          }
+          sum_records(st.cart, lo, hi, tot);
         }
         if constexpr (MODE == GLV_COMPENSATED) {
           for (int t = lo; t < hi; ++t) {
@@ -492,12 +547,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
 
       // pairs: one contiguous slice of the chunk's pairs per wavefront
       if (want_pairs || want_k) {
-        const int q = ch_p[nch];
-        const int lo = (int)((int64_t)q * wid / nwaves), hi = (int)((int64_t)q * (wid + 1) / nwaves);
+        const int q = __builtin_amdgcn_readfirstlane(ch[nch].p);  // < 2^22: cap <= 2048
+        const int lo = (q * wid_s) >> lg_waves, hi = (q * (wid_s + 1)) >> lg_waves;
         // A lane's pair index grows by 64 per iteration, so its event is found
         // once by binary search and afterwards by stepping forward (a few
         // events at most per iteration on collider-sized events).
         int ev = 0;
+        EvRec cur{0, 0}, nxt{0, 0};
         bool located = false;
         for (int it = lo; it < hi; it += 64) {
           const int k = it + lane;  // chunk-relative pair index
@@ -505,14 +561,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
           double kd = 0.0;
           if (valid) {
             if (!located) {
-              ev = search_le32(ch_p, 0, nch, k);
+              ev = search_rec(ch, 0, nch, k);
+              cur = ch[ev];
+              nxt = ch[ev + 1];
               located = true;
-            } else {
-              while (ch_p[ev + 1] <= k) ++ev;
             }
-            const int base = ch_o[ev];
+            while (nxt.p <= k) {
+              cur = nxt;
+              nxt = ch[++ev + 1];
+            }
+            const int base = cur.o;
             int i, j;
-            decode_pair_small(k - ch_p[ev], ch_o[ev + 1] - base, &i, &j);
+            pair_of_rank(k - cur.p, nxt.o - base, colex, &i, &j);
             const int si = base + i, sj = base + j;
             T m;
             if constexpr (MODE == GLV_COMPENSATED) {
@@ -565,6 +625,42 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
 #pragma unroll
       for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
       if (lane == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
+    }
+  }
+}
+
+// Events of more than cap particles, which k_event_reduce leaves out: the
+// workgroup scans the offsets for them and takes each one whole, from global
+// memory.  A separate launch, so that this rare path does not set the main
+// kernel's register budget; on collider-sized events it only reads the offsets.
+constexpr int kBigBlock = 256;
+
+template <typename T, int COORDS, int MODE>
+__global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORDS, MODE> A) {
+  __shared__ double red[16];
+  __shared__ int64_t list[kBigBlock];
+  __shared__ int count;
+  unsigned fb = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
+    const int64_t e = base + threadIdx.x;
+    const bool big = e < A.ne && A.off[e + 1] - A.off[e] > A.cap;
+    if (!__syncthreads_or(big)) continue;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    if (big) list[atomicAdd(&count, 1)] = e;
+    __syncthreads();
+    const int nbig = count;
+    for (int b = 0; b < nbig; ++b) {
+      const int64_t eb = list[b];
+      big_event<T, COORDS, MODE>(A, eb, A.off[eb], A.off[eb + 1], red, &fb);
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == GLV_COMPENSATED && sizeof(T) == 4) {
+    if (A.fallback) {
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
+      if ((threadIdx.x & 63) == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
     }
   }
 }
@@ -655,8 +751,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
     __syncthreads();
     int ca = 0;
     while (ca < nev) {
-      if (s_off[ca + 1] - s_off[ca] > cap) {
-        big_event_bwd<T, COORDS>(A, e0 + ca, s_off[ca], s_off[ca + 1], red);
+      if (s_off[ca + 1] - s_off[ca] > cap) {  // k_event_reduce_bwd_big's event
         ++ca;
         continue;
       }
@@ -750,6 +845,34 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
   }
 }
 
+// Backward of the events k_event_reduce_bwd leaves out (more than cap
+// particles), as k_event_reduce_big does for the forward.
+template <typename T, int COORDS>
+__global__ __launch_bounds__(kBigBlock) void k_event_reduce_bwd_big(BwdArgs<T, COORDS> A) {
+  __shared__ double red[16];
+  __shared__ int64_t list[kBigBlock];
+  __shared__ int count;
+  for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
+    const int64_t e = base + threadIdx.x;
+    const bool big = e < A.ne && A.off[e + 1] - A.off[e] > A.cap;
+    if (!__syncthreads_or(big)) continue;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    if (big) list[atomicAdd(&count, 1)] = e;
+    __syncthreads();
+    const int nbig = count;
+    for (int b = 0; b < nbig; ++b) {
+      const int64_t eb = list[b];
+      big_event_bwd<T, COORDS>(A, eb, A.off[eb], A.off[eb + 1], red);
+    }
+    __syncthreads();
+  }
+}
+
+int big_grid(int64_t ne) {
+  return (int)std::min<int64_t>(std::max<int64_t>(1, (ne + kBigBlock - 1) / kBigBlock), 2048);
+}
+
 int grid_for(int64_t ne, int epb) {
   int64_t tiles = (ne + epb - 1) / epb;
   if (tiles < 1) tiles = 1;
@@ -776,6 +899,9 @@ hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.cap = t.lds_particles;
   hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block),
                      lds, s, A);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_event_reduce_big<T, COORDS, MODE>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
   return hipGetLastError();
 }
 
@@ -798,6 +924,9 @@ hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.cap = t.lds_particles;
   hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block), lds,
                      s, A);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_event_reduce_bwd_big<T, COORDS>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
   return hipGetLastError();
 }
 
@@ -838,8 +967,8 @@ size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
   size_t cols = (mode == GLV_COMPENSATED) ? 10 : 4;
   size_t nwaves = (size_t)t.block / 64;
   size_t acc = (mode == GLV_COMPENSATED) ? nwaves * (size_t)t.events_per_tile * 8 : 0;
-  return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + 2 * ((size_t)t.events_per_tile + 1) * 4 +
-         cols * (size_t)t.lds_particles * tsz;
+  return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + ((size_t)t.events_per_tile + 1) * sizeof(EvRec) +
+         kColexPairs * sizeof(unsigned short) + cols * (size_t)t.lds_particles * tsz;
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {

@@ -35,6 +35,7 @@ LARGE = 1         # 2^24 boost items and 2^24 generic pairs, FP64
 STRESS = 2        # 2^26 light pairs, FP32
 GRADS = 3         # 2^24 items, upstream gradients
 JAGGED = 4        # 2^20 jagged events
+JAGGED_GRADS = 5  # upstream gradients of the jagged reduction (totals, event and pair masses)
 
 
 def rng(k: int) -> np.random.Generator:

@@ -74,6 +74,33 @@ def test_back_to_back_is_exactly_2E_and_swap_is_bitwise():
     assert torch.equal(m1, m2) and torch.equal(m1, m3)
 
 
+def test_fp64_square_root_is_correctly_rounded():
+    """Sums w = (p, 0, 0, E) with p and E of at most 26 significant bits: E^2
+    and p^2 are exact in binary64, so q = E^2 - p^2 is rounded once in any
+    evaluation order, and m must be the correctly rounded square root of that
+    q (Python's math.sqrt is IEEE-correct), with the sign convention for q < 0."""
+    import math
+
+    rng = synth.rng(503)
+    n = 100000
+    ke = rng.integers(1 << 25, 1 << 26, size=n)
+    kp = rng.integers(0, 1 << 26, size=n)
+    kp[: n // 4] = ke[: n // 4] - rng.integers(0, 1 << 12, size=n // 4)  # near-lightlike sums
+    sc = rng.integers(-40, 20, size=n)
+    e = np.ldexp(ke.astype(np.float64), sc)
+    pz = np.ldexp(kp.astype(np.float64), sc)
+    want = np.empty(n)
+    for t in range(n):
+        q = math.ldexp(float(int(ke[t]) ** 2 - int(kp[t]) ** 2), 2 * int(sc[t]))  # one rounding
+        want[t] = math.sqrt(q) if q >= 0 else -math.sqrt(-q)
+    zero = np.zeros(n)
+    a = gpu((pz, zero, zero, e), torch.float64)
+    b = gpu((zero, zero, zero, zero), torch.float64)
+    m = host(glv.glv_invariant_mass(a, b, coords="PxPyPzE"))
+    bad = np.flatnonzero(m != want)
+    assert bad.size == 0, f"{bad.size} items differ, first {bad[:4]}: gpu {m[bad[:4]]} want {want[bad[:4]]}"
+
+
 def test_plain_full_size_sampled():
     """2^24 FP64 pairs in the benchmark's launch shape; 65,536 sampled items
     checked one by one against the oracle."""
