@@ -95,7 +95,11 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  *   lds_particles    particles staged in LDS at once: 64 .. 4096
  * Fields set to 0 take the library's current choice (the autotuned one if
  * glv_autotune_event_reduce ran for this device/dtype/coords/mode, otherwise a
- * built-in default). */
+ * built-in default).  A tiling whose workgroup would need more than 64 KiB of
+ * LDS is rejected with GLV_EINVAL_TILING: per staged particle the forward
+ * keeps 4 values (10 in the compensated mode) and the backward 12 values (its
+ * two records and up to four pair gradients) plus 2 bytes; per event of a
+ * tile a few tens of bytes more. */
 typedef struct glv_tiling {
   int32_t block;
   int32_t events_per_tile;

@@ -163,7 +163,7 @@ struct MassBwd {
       LegJ<T> lb = to_cart_j<COORDS, T>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
       T w[4], u[4], g[4];
       add4<T>(la.v, lb.v, w);
-      dmass<T>(w, mass_of(w), pg.v[e], u);
+      dmass<T>(w, pg.v[e], u);
       chain_coords<COORDS, T>(la, pa[0].v[e], pa[3].v[e], u, g);
 #pragma unroll
       for (int k = 0; k < 4; ++k) oa[k].v[e] = g[k];

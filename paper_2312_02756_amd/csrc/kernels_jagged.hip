@@ -19,7 +19,7 @@
 //     (consecutive lanes write consecutive addresses);
 //   * in the compensated mode the event mass is
 //     m^2 = sum_i M_i^2 + 2 sum_{i<j} K_ij (all terms >= 0); each wavefront
-//     folds its lanes' K_ij by a segmented shuffle scan keyed by event and
+//     folds its lanes' K_ij by a segmented lane-move (DPP) scan keyed by event and
 //     adds the segment sums to a per-(wavefront, event) LDS slot, and the
 //     event lane adds the slots in wavefront order: the result depends on
 //     the tiling only, never on timing.
@@ -341,6 +341,51 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
   }
 }
 
+// Cross-lane moves within a wavefront (GFX9 DPP controls): shift right by d
+// lanes within each row of 16 lanes, lane 15 of each row to the next row,
+// lane 31 to rows 2 and 3, and the whole wavefront left by one lane.  A lane
+// whose source does not exist, or whose row is masked off, receives `old`.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShl1 = 0x130;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int x, int old) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x) {  // old = +0
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)b, 0);
+  const unsigned hi = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)(b >> 32), 0);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(double& x, int key) {
+  const double y = dpp_f64<CTRL, ROWS>(x);
+  const int ky = dpp_i32<CTRL, ROWS>(key, -1);  // -1: never a key
+  x = (ky == key) ? x + y : x;
+}
+
+// Inclusive segmented sum over a full wavefront: keys do not decrease with the
+// lane, and each lane receives the sum of x over the lanes at or below it with
+// its key.  Sums within rows by shifts of 1, 2, 4 and 8, then the running row
+// totals carried across rows (lane 15 into rows 1 and 3, lane 31 into rows 2
+// and 3); a source with another key adds nothing (keys are monotone, so the
+// lanes between agree too).  No LDS traffic; all 64 lanes must be active.
+__device__ __forceinline__ double seg_scan_wave(double x, int key) {
+  seg_scan_step<kDppRowShr + 1, 0xf>(x, key);
+  seg_scan_step<kDppRowShr + 2, 0xf>(x, key);
+  seg_scan_step<kDppRowShr + 4, 0xf>(x, key);
+  seg_scan_step<kDppRowShr + 8, 0xf>(x, key);
+  seg_scan_step<kDppRowBcast15, 0xa>(x, key);
+  seg_scan_step<kDppRowBcast31, 0xc>(x, key);
+  return x;
+}
+
 // Deterministic workgroup sum of one double per thread (fixed tree).
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -591,16 +636,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
           if constexpr (MODE == GLV_COMPENSATED) {
             if (want_k) {
               // segmented inclusive scan of kd keyed by event (keys ascend with lane)
-              int key = valid ? ev : 0x7fffffff;
-#pragma unroll
-              for (int d = 1; d < 64; d <<= 1) {
-                double y = __shfl_up(kd, d);
-                int ky = __shfl_up(key, d);
-                if (lane >= d && ky == key) kd += y;
-              }
-              int knext = __shfl_down(key, 1);
-              bool seg_end = valid && (lane == 63 || knext != key);
-              if (seg_end) acc[wid * epb + ev] += kd;
+              const int key = valid ? ev : 0x7fffffff;
+              kd = seg_scan_wave(kd, key);
+              const int knext = dpp_i32<kDppWaveShl1, 0xf>(key, -1);  // lane 63: -1
+              if (valid && knext != key) acc[wid * epb + ev] += kd;
             }
           }
         }
@@ -694,7 +733,7 @@ __device__ __forceinline__ void partner_sum_global(const BwdArgs<T, COORDS>& A, 
     to_cart<COORDS>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j], vj);
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = vi[k] + vj[k];
-    dmass<T>(w, mass_of(w), g, uw);
+    dmass<T>(w, g, uw);
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] += uw[k];
   }
@@ -715,7 +754,7 @@ __device__ void big_event_bwd(const BwdArgs<T, COORDS>& A, int64_t e, int64_t lo
 #pragma unroll
   for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
   T ut[4] = {0, 0, 0, 0};
-  if (A.gem) dmass<T>(tot, mass_of(tot), A.gem[e], ut);
+  if (A.gem) dmass<T>(tot, A.gem[e], ut);
   if (A.gt[0]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) ut[k] += A.gt[k][e];
@@ -733,106 +772,146 @@ __device__ void big_event_bwd(const BwdArgs<T, COORDS>& A, int64_t e, int64_t lo
   __syncthreads();
 }
 
-// LDS-staged backward: per particle, Cartesian vector and Jacobian pieces.
+// Pairs staged per chunk of the backward: at most this many per particle of
+// the chunk capacity (a chunk also ends where its pairs would exceed it).
+constexpr int kBwdPairsPerParticle = 4;
+
+__device__ __forceinline__ int64_t bwd_pair_cap(int cap) { return (int64_t)kBwdPairsPerParticle * cap; }
+
+// An event the tiled backward leaves to k_event_reduce_bwd_big.
+__device__ __forceinline__ bool bwd_big(int64_t n, int cap, bool pairs) {
+  return n > cap || (pairs && npairs(n) > bwd_pair_cap(cap));
+}
+
+// LDS-staged backward.  Per chunk of events (at most cap particles and, when
+// pair gradients are given, kBwdPairsPerParticle * cap pairs):
+//   * every particle is converted once; its Cartesian vector and Jacobian
+//     pieces (cos phi, sin phi, sinh eta, cosh eta) go to LDS as two records;
+//     the chunk's pair gradients -- contiguous in grad_pair -- are copied to
+//     LDS with coalesced loads; one lane per event records its particles'
+//     event (from the offsets, so all of this is one phase);
+//   * one lane per particle walks its event's particles in CSR order: it adds
+//     the pair terms g_ij dm(v_i + v_j)/dw of its partners (the same 4-vector
+//     for both legs of a pair), walking the pair indices incrementally, and
+//     sums the event total V on the way -- every particle of an event forms
+//     the same V in the same order -- then adds g_total + g_m dm(V)/dV and
+//     applies its own conversion Jacobian.
 template <typename T, int COORDS>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
-  extern __shared__ __align__(16) unsigned char lds[];
+  extern __shared__ __align__(32) unsigned char lds[];
+  using R4 = typename V4<T>::type;
+  // event totals of FP32 data are summed in FP64
+  using Acc = typename std::conditional<sizeof(T) == 4, double, T>::type;
   const int epb = A.epb, cap = A.cap;
-  int64_t* s_off = reinterpret_cast<int64_t*>(lds);
-  double* red = reinterpret_cast<double*>(s_off + (epb + 1));
-  T* s_ut = reinterpret_cast<T*>(red + 16);  // 4 * epb: per-event upstream in Cartesian
-  T* col = s_ut + 4 * epb;                    // 8 * cap: px py pz E cp sp sh ch
+  const bool pairs = A.gpair != nullptr;
+  const bool want_v = A.gem != nullptr;
+  const int qcap = pairs ? (int)bwd_pair_cap(cap) : 0;
+  // LDS: cart[cap], jac[cap] (R4), s_g[qcap] (T),
+  //      s_off[epb+1], s_poff[epb+1] (int64), ch[epb+1] (EvRec), ev_of[cap] (uint16)
+  R4* cart = reinterpret_cast<R4*>(lds);
+  R4* jac = cart + cap;
+  T* s_g = reinterpret_cast<T*>(jac + cap);
+  int64_t* s_off = reinterpret_cast<int64_t*>(s_g + ((qcap + 1) & ~1));
+  int64_t* s_poff = s_off + (epb + 1);
+  EvRec* ch = reinterpret_cast<EvRec*>(s_poff + (epb + 1));
+  unsigned short* ev_of = reinterpret_cast<unsigned short*>(ch + (epb + 1));
   const int64_t ntiles = (A.ne + epb - 1) / epb;
 
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = tile * epb;
     const int nev = (int)min((int64_t)epb, A.ne - e0);
-    for (int i = threadIdx.x; i <= nev; i += blockDim.x) s_off[i] = A.off[e0 + i];
+    for (int i = threadIdx.x; i <= nev; i += blockDim.x) {
+      s_off[i] = A.off[e0 + i];
+      if (pairs) s_poff[i] = A.poff[e0 + i];
+    }
     __syncthreads();
     int ca = 0;
     while (ca < nev) {
-      if (s_off[ca + 1] - s_off[ca] > cap) {  // k_event_reduce_bwd_big's event
+      if (bwd_big(s_off[ca + 1] - s_off[ca], cap, pairs)) {  // k_event_reduce_bwd_big's event
         ++ca;
         continue;
       }
-      const int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
+      // largest cb with at most cap particles (and qcap pairs) from ca
+      int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
+      if (pairs) cb = min(cb, search_le(s_poff, ca + 1, nev + 1, s_poff[ca] + qcap));
+      const int nch = cb - ca;
       const int64_t pbase = s_off[ca];
+      const int64_t q0 = pairs ? s_poff[ca] : 0;
       const int np = (int)(s_off[cb] - pbase);
+      const int nq = pairs ? (int)(s_poff[cb] - q0) : 0;
+      for (int t = threadIdx.x; t <= nch; t += blockDim.x)
+        ch[t] = EvRec{(int)(s_off[ca + t] - pbase), pairs ? (int)(s_poff[ca + t] - q0) : 0};
+      for (int t = threadIdx.x; t < nch; t += blockDim.x) {
+        const int lo = (int)(s_off[ca + t] - pbase), hi = (int)(s_off[ca + t + 1] - pbase);
+        for (int i = lo; i < hi; ++i) ev_of[i] = (unsigned short)t;
+      }
       for (int t = threadIdx.x; t < np; t += blockDim.x) {
         const int64_t gi = pbase + t;
-        LegJ<T> L = to_cart_j<COORDS, T>(A.p.c[0][gi], A.p.c[1][gi], A.p.c[2][gi], A.p.c[3][gi]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) col[k * cap + t] = L.v[k];
-        col[4 * cap + t] = L.cp;
-        col[5 * cap + t] = L.sp;
-        col[6 * cap + t] = L.sh;
-        col[7 * cap + t] = L.ch;
+        const LegJ<T> L = to_cart_j<COORDS, T>(A.p.c[0][gi], A.p.c[1][gi], A.p.c[2][gi], A.p.c[3][gi]);
+        cart[t] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
+        jac[t] = R4{L.cp, L.sp, L.sh, L.ch};
       }
+      for (int t = threadIdx.x; t < nq; t += blockDim.x) s_g[t] = A.gpair[q0 + t];
       __syncthreads();
-      // per-event upstream: g_total + g_em dm(V)/dV
-      const int my = ca + (int)threadIdx.x;
-      if (my < cb) {
-        const int lo = (int)(s_off[my] - pbase), hi = (int)(s_off[my + 1] - pbase);
-        const int64_t e = e0 + my;
-        T ut[4] = {0, 0, 0, 0};
-        if (A.gem) {
-          T tot[4];
-          if constexpr (sizeof(T) == 4) {
-            double d[4] = {0, 0, 0, 0};
-            for (int t = lo; t < hi; ++t)
+
+      // one lane per particle
+      for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const int ev = ev_of[t];
+        const EvRec rc = ch[ev];
+        const int n = ch[ev + 1].o - rc.o;
+        const int ai = t - rc.o;
+        const R4 vr = cart[t];
+        const T vi[4] = {vr[0], vr[1], vr[2], vr[3]};
+        T u[4] = {0, 0, 0, 0};
+        Acc vt[4] = {0, 0, 0, 0};  // event total, CSR order
+        if (pairs || want_v) {
+          // Partners in ascending order.  Pair (bj, ai), bj < ai, sits at rank
+          // R(bj) + ai - bj - 1, which grows by n - bj - 2 with bj; pair
+          // (ai, bj), bj > ai, at R(ai) + bj - ai - 1, consecutive from R(ai).
+          int qlo = rc.p + ai - 1;
+          int qhi = rc.p + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
+          for (int bj = 0; bj < n; ++bj) {
+            const R4 vj = cart[rc.o + bj];
+            if (want_v) {
 #pragma unroll
-              for (int k = 0; k < 4; ++k) d[k] += (double)col[k * cap + t];
+              for (int k = 0; k < 4; ++k) vt[k] += (Acc)vj[k];
+            }
+            if (!pairs || bj == ai) continue;
+            const bool below = bj < ai;
+            T w[4], uw[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
-          } else {
+            for (int k = 0; k < 4; ++k) w[k] = vi[k] + vj[k];
+            dmass<T>(w, s_g[below ? qlo : qhi], uw);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) tot[k] = T(0);
-            for (int t = lo; t < hi; ++t)
-#pragma unroll
-              for (int k = 0; k < 4; ++k) tot[k] += col[k * cap + t];
+            for (int k = 0; k < 4; ++k) u[k] += uw[k];
+            if (below)
+              qlo += n - bj - 2;
+            else
+              ++qhi;
           }
-          dmass<T>(tot, mass_of(tot), A.gem[e], ut);
+        }
+        const int64_t e = e0 + ca + ev;
+        T ut[4] = {0, 0, 0, 0};
+        if (want_v) {
+          T tot[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
+          dmass<T>(tot, A.gem[e], ut);
         }
         if (A.gt[0]) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) ut[k] += A.gt[k][e];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s_ut[k * epb + (my - ca)] = ut[k];
-      }
-      __syncthreads();
-      // one lane per particle: own upstream plus the pair terms of its partners
-      for (int t = threadIdx.x; t < np; t += blockDim.x) {
-        const int ev = search_le(s_off, ca, cb, pbase + t);
-        const int lo = (int)(s_off[ev] - pbase);
-        const int n = (int)(s_off[ev + 1] - s_off[ev]);
-        const int ai = t - lo;
-        T vi[4] = {col[t], col[cap + t], col[2 * cap + t], col[3 * cap + t]};
-        T u[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = s_ut[k * epb + (ev - ca)];
-        if (A.gpair) {
-          const int64_t pb = A.poff[e0 + ev];
-          for (int bj = 0; bj < n; ++bj) {
-            if (bj == ai) continue;
-            const int r = ai < bj ? ai : bj, c = ai < bj ? bj : ai;
-            const T g = A.gpair[pb + r * (2 * n - r - 1) / 2 + (c - r - 1)];
-            const int sj = lo + bj;
-            T w[4], uw[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = vi[k] + col[k * cap + sj];
-            dmass<T>(w, mass_of(w), g, uw);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) u[k] += uw[k];
-          }
-        }
+        for (int k = 0; k < 4; ++k) u[k] = ut[k] + u[k];
+        const R4 jr = jac[t];
         LegJ<T> L;
 #pragma unroll
         for (int k = 0; k < 4; ++k) L.v[k] = vi[k];
-        L.cp = col[4 * cap + t];
-        L.sp = col[5 * cap + t];
-        L.sh = col[6 * cap + t];
-        L.ch = col[7 * cap + t];
+        L.cp = jr[0];
+        L.sp = jr[1];
+        L.sh = jr[2];
+        L.ch = jr[3];
         const int64_t gi = pbase + t;
         T g[4];
         chain_coords<COORDS, T>(L, A.p.c[0][gi], A.p.c[3][gi], u, g);
@@ -854,7 +933,7 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_bwd_big(BwdArgs<T, C
   __shared__ int count;
   for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
     const int64_t e = base + threadIdx.x;
-    const bool big = e < A.ne && A.off[e + 1] - A.off[e] > A.cap;
+    const bool big = e < A.ne && bwd_big(A.off[e + 1] - A.off[e], A.cap, A.gpair != nullptr);
     if (!__syncthreads_or(big)) continue;
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
@@ -972,9 +1051,13 @@ size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
-  size_t tsz = (dt == GLV_F64) ? 8 : 4;
-  return ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + 4 * (size_t)t.events_per_tile * tsz +
-         8 * (size_t)t.lds_particles * tsz;
+  // the pair-gradient area is sized for pair gradients given; it is the
+  // bound the launch must satisfy either way
+  const size_t tsz = (dt == GLV_F64) ? 8 : 4;
+  const size_t cap = (size_t)t.lds_particles, epb = (size_t)t.events_per_tile;
+  const size_t qcap = (size_t)kBwdPairsPerParticle * cap;
+  return 8 * cap * tsz + ((qcap + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 + (epb + 1) * sizeof(EvRec) +
+         cap * sizeof(unsigned short);
 }
 
 hipError_t launch_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, hipStream_t s) {

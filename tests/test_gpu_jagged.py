@@ -230,3 +230,54 @@ def test_event_reduce_bwd(coords, dtype):
         ref = np.max(np.abs(np.stack(want)), axis=0)
         r, i = worst(err, (base + 64 * u * kappa) * ref + 1e-300)
         assert r <= 1.0, (tiling, i, [c[i] for c in got], [c[i] for c in want])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
+    """Events of 40-50 particles against a tiling of 256 staged particles and
+    1024 staged pair gradients: the pair cap, not the particle cap, ends the
+    chunks, and 50-particle events (1225 pairs) take the separate path.  Also
+    without pair upstreams (no pair offsets needed) and without any upstream."""
+    counts = np.array([40, 3, 50, 0, 45, 1, 2, 40, 41, 50, 7, 44] * 6, dtype=np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    g = synth.rng(709)
+    p, _ = synth.pairs_generic(g, int(off[-1]))
+    ne = counts.size
+    po = oracle.pair_offsets(off)
+    gt = synth.upstream(g, ne, 4)
+    gem = g.standard_normal(ne)
+    gpr = g.standard_normal(int(po[-1]))
+    wp = widened(p, dtype)
+    S_abs, _ = event_abs_scale(oracle.to_cartesian("PtEtaPhiM", wp), off)
+    em_or = oracle.event_reduce("PtEtaPhiM", off, wp)[1]
+    _, s_pairs = _pairs_or(off, wp, "PtEtaPhiM")
+    pm_or = oracle.event_reduce("PtEtaPhiM", off, wp)[2]
+    kp = s_pairs / np.maximum(pm_or ** 2, 1e-300)
+    kappa_pair_ev = np.zeros(ne)
+    np.maximum.at(kappa_pair_ev, np.repeat(np.arange(ne), np.diff(po)), kp)
+    cnt = np.diff(off)
+    ev = np.repeat(np.arange(ne), cnt)
+    kappa = np.maximum(S_abs / np.maximum(em_or ** 2, 1e-300), kappa_pair_ev)[ev] * np.maximum(cnt[ev], 1)
+    u = U64 if dtype == torch.float64 else U32
+    base = 1e-12 if dtype == torch.float64 else 1e-5
+    cases = [(gt, gem, gpr), (gt, gem, None), (None, None, None)]
+    for c_gt, c_gem, c_gpr in cases:
+        want = oracle.event_reduce_vjp("PtEtaPhiM", off, wp,
+                                       None if c_gt is None else widened(c_gt, dtype),
+                                       None if c_gem is None else widened([c_gem], dtype)[0],
+                                       None if c_gpr is None else widened([c_gpr], dtype)[0])
+        for tiling in ((128, 16, 256), None):
+            got = glv.glv_event_reduce_bwd(
+                gpu(p, dtype), _off(off), grad_total=None if c_gt is None else gpu(c_gt, dtype),
+                grad_event_m=None if c_gem is None else gpu([c_gem], dtype)[0],
+                grad_pair_m=None if c_gpr is None else gpu([c_gpr], dtype)[0], tiling=tiling)
+            got = np.stack([host(c).astype(np.float64) for c in got])
+            want_s = np.stack(want)
+            if c_gt is None and c_gem is None and c_gpr is None:
+                assert np.array_equal(got, np.zeros_like(got)), tiling
+                continue
+            err = np.max(np.abs(got - want_s), axis=0)
+            ref = np.max(np.abs(want_s), axis=0)
+            r, i = worst(err, (base + 64 * u * kappa) * ref + 1e-300)
+            assert r <= 1.0, (tiling, c_gpr is None, i, got[:, i], want_s[:, i])
