@@ -87,13 +87,15 @@ glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
 }
 
 // The backward stages 8 columns per particle (vector and Jacobian pieces).
-// Backward: per staged particle two records (8 values) and up to four pair
-// gradients, plus a 16-bit event index.
+// Backward: one staged particle per thread (the launch clamps lds_particles to
+// the workgroup size); 256 threads and 128 events per tile measured fastest on
+// collider-sized events.
 glv::Tiling default_tiling_bwd(glv_dtype dt) {
+  (void)dt;
   glv::Tiling t;
   t.block = 256;
   t.events_per_tile = 128;
-  t.lds_particles = std::max(64, (int)std::min<size_t>(2048, (40 * 1024) / (12 * elem(dt) + 2)) & ~63);
+  t.lds_particles = 256;
   return t;
 }
 

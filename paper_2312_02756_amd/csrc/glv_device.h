@@ -232,7 +232,8 @@ template <typename T>
 __device__ __forceinline__ void dmass(const T w[4], T g, T u[4]) {
   const T q = w[3] * w[3] - w[0] * w[0] - w[1] * w[1] - w[2] * w[2];
   const T a = d_abs(q);
-  const T s = (a > T(0)) ? g * inv_sqrt(a) : T(0);
+  const T r = inv_sqrt(a);  // evaluated for every lane: a select, not a branch
+  const T s = (a > T(0)) ? g * r : T(0);
   u[0] = -w[0] * s;
   u[1] = -w[1] * s;
   u[2] = -w[2] * s;

@@ -783,34 +783,36 @@ __device__ __forceinline__ bool bwd_big(int64_t n, int cap, bool pairs) {
   return n > cap || (pairs && npairs(n) > bwd_pair_cap(cap));
 }
 
-// LDS-staged backward.  Per chunk of events (at most cap particles and, when
-// pair gradients are given, kBwdPairsPerParticle * cap pairs):
-//   * every particle is converted once; its Cartesian vector and Jacobian
-//     pieces (cos phi, sin phi, sinh eta, cosh eta) go to LDS as two records;
-//     the chunk's pair gradients -- contiguous in grad_pair -- are copied to
-//     LDS with coalesced loads; one lane per event records its particles'
-//     event (from the offsets, so all of this is one phase);
-//   * one lane per particle walks its event's particles in CSR order: it adds
-//     the pair terms g_ij dm(v_i + v_j)/dw of its partners (the same 4-vector
-//     for both legs of a pair), walking the pair indices incrementally, and
-//     sums the event total V on the way -- every particle of an event forms
-//     the same V in the same order -- then adds g_total + g_m dm(V)/dV and
-//     applies its own conversion Jacobian.
+// LDS-staged backward.  A chunk holds at most one particle per thread (cap <=
+// block; the launch clamps the staging capacity to the workgroup) and, when
+// pair gradients are given, kBwdPairsPerParticle * cap pairs:
+//   * thread t converts particle t of the chunk once, keeps its Cartesian
+//     vector and Jacobian pieces (cos phi, sin phi, sinh eta, cosh eta) in
+//     registers and stages the vector in LDS for its partners; the chunk's
+//     pair gradients -- contiguous in grad_pair -- are copied to LDS, each
+//     thread issuing all of its loads before its stores; one lane per event
+//     records its particles' event (from the offsets: all one phase);
+//   * thread t then walks its event's particles in CSR order: it adds the
+//     pair terms g_ij dm(v_i + v_j)/dw of its partners (the same 4-vector for
+//     both legs of a pair), walking the pair indices incrementally, and sums
+//     the event total V on the way -- every particle of an event forms the
+//     same V in the same order -- then adds g_total + g_m dm(V)/dV and applies
+//     its own conversion Jacobian.
 template <typename T, int COORDS>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   using R4 = typename V4<T>::type;
   // event totals of FP32 data are summed in FP64
   using Acc = typename std::conditional<sizeof(T) == 4, double, T>::type;
-  const int epb = A.epb, cap = A.cap;
+  const int epb = A.epb, cap = A.cap;  // cap <= blockDim.x
   const bool pairs = A.gpair != nullptr;
   const bool want_v = A.gem != nullptr;
   const int qcap = pairs ? (int)bwd_pair_cap(cap) : 0;
-  // LDS: cart[cap], jac[cap] (R4), s_g[qcap] (T),
-  //      s_off[epb+1], s_poff[epb+1] (int64), ch[epb+1] (EvRec), ev_of[cap] (uint16)
+  const int tid = (int)threadIdx.x;
+  // LDS: cart[cap] (R4), s_g[qcap] (T), s_off[epb+1], s_poff[epb+1] (int64),
+  //      ch[epb+1] (EvRec), ev_of[cap] (uint16)
   R4* cart = reinterpret_cast<R4*>(lds);
-  R4* jac = cart + cap;
-  T* s_g = reinterpret_cast<T*>(jac + cap);
+  T* s_g = reinterpret_cast<T*>(cart + cap);
   int64_t* s_off = reinterpret_cast<int64_t*>(s_g + ((qcap + 1) & ~1));
   int64_t* s_poff = s_off + (epb + 1);
   EvRec* ch = reinterpret_cast<EvRec*>(s_poff + (epb + 1));
@@ -820,7 +822,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = tile * epb;
     const int nev = (int)min((int64_t)epb, A.ne - e0);
-    for (int i = threadIdx.x; i <= nev; i += blockDim.x) {
+    for (int i = tid; i <= nev; i += blockDim.x) {
       s_off[i] = A.off[e0 + i];
       if (pairs) s_poff[i] = A.poff[e0 + i];
     }
@@ -839,29 +841,40 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
       const int64_t q0 = pairs ? s_poff[ca] : 0;
       const int np = (int)(s_off[cb] - pbase);
       const int nq = pairs ? (int)(s_poff[cb] - q0) : 0;
-      for (int t = threadIdx.x; t <= nch; t += blockDim.x)
+      const bool mine = tid < np;
+      const int64_t gi = pbase + tid;
+      // loads first: own particle, up to kBwdPairsPerParticle pair gradients
+      T c[4] = {0, 0, 0, 0};
+      if (mine) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = A.p.c[k][gi];
+      }
+      T gv[kBwdPairsPerParticle];
+#pragma unroll
+      for (int r = 0; r < kBwdPairsPerParticle; ++r) {
+        const int idx = tid + r * (int)blockDim.x;
+        gv[r] = (idx < nq) ? A.gpair[q0 + idx] : T(0);
+      }
+      for (int t = tid; t <= nch; t += blockDim.x)
         ch[t] = EvRec{(int)(s_off[ca + t] - pbase), pairs ? (int)(s_poff[ca + t] - q0) : 0};
-      for (int t = threadIdx.x; t < nch; t += blockDim.x) {
+      for (int t = tid; t < nch; t += blockDim.x) {
         const int lo = (int)(s_off[ca + t] - pbase), hi = (int)(s_off[ca + t + 1] - pbase);
         for (int i = lo; i < hi; ++i) ev_of[i] = (unsigned short)t;
       }
-      for (int t = threadIdx.x; t < np; t += blockDim.x) {
-        const int64_t gi = pbase + t;
-        const LegJ<T> L = to_cart_j<COORDS, T>(A.p.c[0][gi], A.p.c[1][gi], A.p.c[2][gi], A.p.c[3][gi]);
-        cart[t] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
-        jac[t] = R4{L.cp, L.sp, L.sh, L.ch};
+#pragma unroll
+      for (int r = 0; r < kBwdPairsPerParticle; ++r) {
+        const int idx = tid + r * (int)blockDim.x;
+        if (idx < nq) s_g[idx] = gv[r];
       }
-      for (int t = threadIdx.x; t < nq; t += blockDim.x) s_g[t] = A.gpair[q0 + t];
+      LegJ<T> L = to_cart_j<COORDS, T>(c[0], c[1], c[2], c[3]);
+      if (mine) cart[tid] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
       __syncthreads();
 
-      // one lane per particle
-      for (int t = threadIdx.x; t < np; t += blockDim.x) {
-        const int ev = ev_of[t];
+      if (mine) {
+        const int ev = ev_of[tid];
         const EvRec rc = ch[ev];
         const int n = ch[ev + 1].o - rc.o;
-        const int ai = t - rc.o;
-        const R4 vr = cart[t];
-        const T vi[4] = {vr[0], vr[1], vr[2], vr[3]};
+        const int ai = tid - rc.o;
         T u[4] = {0, 0, 0, 0};
         Acc vt[4] = {0, 0, 0, 0};  // event total, CSR order
         if (pairs || want_v) {
@@ -870,18 +883,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
           // (ai, bj), bj > ai, at R(ai) + bj - ai - 1, consecutive from R(ai).
           int qlo = rc.p + ai - 1;
           int qhi = rc.p + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
+          const int qlast = nq > 0 ? nq - 1 : 0;
           for (int bj = 0; bj < n; ++bj) {
-            const R4 vj = cart[rc.o + bj];
-            if (want_v) {
-#pragma unroll
-              for (int k = 0; k < 4; ++k) vt[k] += (Acc)vj[k];
-            }
-            if (!pairs || bj == ai) continue;
+            // both LDS reads first, so that one wait covers them
             const bool below = bj < ai;
+            const T g = pairs ? s_g[min(below ? qlo : qhi, qlast)] : T(0);
+            const R4 vj = cart[rc.o + bj];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) vt[k] += (Acc)vj[k];  // unused without g_m
+            if (!pairs || bj == ai) continue;
             T w[4], uw[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = vi[k] + vj[k];
-            dmass<T>(w, s_g[below ? qlo : qhi], uw);
+            for (int k = 0; k < 4; ++k) w[k] = L.v[k] + vj[k];
+            dmass<T>(w, g, uw);
 #pragma unroll
             for (int k = 0; k < 4; ++k) u[k] += uw[k];
             if (below)
@@ -904,17 +918,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) u[k] = ut[k] + u[k];
-        const R4 jr = jac[t];
-        LegJ<T> L;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) L.v[k] = vi[k];
-        L.cp = jr[0];
-        L.sp = jr[1];
-        L.sh = jr[2];
-        L.ch = jr[3];
-        const int64_t gi = pbase + t;
         T g[4];
-        chain_coords<COORDS, T>(L, A.p.c[0][gi], A.p.c[3][gi], u, g);
+        chain_coords<COORDS, T>(L, c[0], c[3], u, g);
 #pragma unroll
         for (int k = 0; k < 4; ++k) store_out(A.gp[k], gi, g[k]);
       }
@@ -951,6 +956,9 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_bwd_big(BwdArgs<T, C
 int big_grid(int64_t ne) {
   return (int)std::min<int64_t>(std::max<int64_t>(1, (ne + kBigBlock - 1) / kBigBlock), 2048);
 }
+
+// The backward stages at most one particle per thread.
+int bwd_cap(const Tiling& t) { return std::min(t.lds_particles, t.block); }
 
 int grid_for(int64_t ne, int epb) {
   int64_t tiles = (ne + epb - 1) / epb;
@@ -1000,7 +1008,7 @@ hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.gpair = (const T*)gpair;
   A.ne = ne;
   A.epb = t.events_per_tile;
-  A.cap = t.lds_particles;
+  A.cap = bwd_cap(t);
   hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block), lds,
                      s, A);
   hipError_t err = hipGetLastError();
@@ -1054,9 +1062,9 @@ size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
   // the pair-gradient area is sized for pair gradients given; it is the
   // bound the launch must satisfy either way
   const size_t tsz = (dt == GLV_F64) ? 8 : 4;
-  const size_t cap = (size_t)t.lds_particles, epb = (size_t)t.events_per_tile;
+  const size_t cap = (size_t)bwd_cap(t), epb = (size_t)t.events_per_tile;
   const size_t qcap = (size_t)kBwdPairsPerParticle * cap;
-  return 8 * cap * tsz + ((qcap + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 + (epb + 1) * sizeof(EvRec) +
+  return 4 * cap * tsz + ((qcap + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 + (epb + 1) * sizeof(EvRec) +
          cap * sizeof(unsigned short);
 }
 
