@@ -341,6 +341,26 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
   }
 }
 
+// FP32 compensated pair with the redo left to k_event_reduce_fix: *redo is
+// set when the error bound asks for FP64.
+__device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC<float>& b, double* kout,
+                                                bool* redo) {
+  float k, bound;
+  const float m2 = comp_pair_m2<float>(a, b, &k, &bound);
+  *redo = !(bound <= kFallbackUnits);
+  *kout = (double)k;
+  return d_sqrt(m2);
+}
+
+// Marks an event of the tiled FP32 compensated reduction that holds a pair
+// needing the FP64 redo: written to the event's mass (or, without event
+// masses, to its first pair mass) for k_event_reduce_fix to find.  A quiet NaN
+// with a payload that arithmetic does not produce; should an input NaN carry
+// it, the event is merely recomputed.
+constexpr unsigned kRedoMarkBits = 0x7fd2e6b1u;
+__device__ __forceinline__ float redo_mark() { return __builtin_bit_cast(float, kRedoMarkBits); }
+__device__ __forceinline__ bool is_redo_mark(float x) { return __builtin_bit_cast(unsigned, x) == kRedoMarkBits; }
+
 // Cross-lane moves within a wavefront (GFX9 DPP controls): shift right by d
 // lanes within each row of 16 lanes, lane 15 of each row to the next row,
 // lane 31 to rows 2 and 3, and the whole wavefront left by one lane.  A lane
@@ -430,20 +450,24 @@ struct FwdArgs {
 // One event too large for LDS: the whole workgroup, from global memory.
 template <typename T, int COORDS, int MODE>
 __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t lo, int64_t hi, double* red,
-                          unsigned* fb) {
+                          unsigned* fb, bool totals = true) {
   const int64_t n = hi - lo;
   double acc[4] = {0, 0, 0, 0};
   double msum = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    T v[4];
-    to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], v);
+    if (totals) {
+      T v[4];
+      to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], v);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += (double)v[k];
+      for (int k = 0; k < 4; ++k) acc[k] += (double)v[k];
+    }
     if constexpr (MODE == GLV_COMPENSATED) msum += (double)A.p.c[3][i] * (double)A.p.c[3][i];
   }
-  T tot[4];
+  T tot[4] = {0, 0, 0, 0};
+  if (totals) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
+    for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
+  }
   if constexpr (MODE == GLV_COMPENSATED) msum = block_sum(msum, red);
   double ksum = 0.0;
   const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m;
@@ -474,7 +498,7 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
     if (want_k) ksum = block_sum(ksum, red);
   }
   if (threadIdx.x == 0) {
-    if (A.total[0]) {
+    if (totals && A.total[0]) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) A.total[k][e] = tot[k];
     }
@@ -501,6 +525,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   //   red[16], acc[nwaves*epb]      double
   //   ch[epb+1]                     EvRec, offsets relative to the chunk
   //   colex[kColexPairs]            uint16, the pair table
+  //   s_redo[epb]                   int, FP32 compensated only
   Stage<T, MODE> st;
   st.cart = reinterpret_cast<typename V4<T>::type*>(lds);
   unsigned char* after = lds + (size_t)cap * 4 * sizeof(T);
@@ -515,6 +540,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   double* acc = red + 16;
   EvRec* ch = reinterpret_cast<EvRec*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
   unsigned short* colex = reinterpret_cast<unsigned short*>(ch + (epb + 1));
+  // FP32 compensated: events of the chunk with a pair needing the FP64 redo
+  int* s_redo = reinterpret_cast<int*>(colex + ((kColexPairs + 1) & ~1));
+  constexpr bool kDefer = (MODE == GLV_COMPENSATED) && (sizeof(T) == 4);
   // a wave's share of a chunk's pairs is a shift: nwaves is a power of two
   const int lg_waves = __builtin_ctz(nwaves);
   const int wid_s = __builtin_amdgcn_readfirstlane(wid);
@@ -554,6 +582,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       // chunk-relative offsets, so the pair loop works in 32-bit integers
       for (int t = threadIdx.x; t <= nch; t += blockDim.x) {
         ch[t] = EvRec{(int)(s_off[ca + t] - pbase), (want_pairs || want_k) ? (int)(s_poff[ca + t] - q0) : 0};
+      if constexpr (kDefer) {
+        for (int t = threadIdx.x; t < nch; t += blockDim.x) s_redo[t] = 0;
+      }
       }
       for (int t = threadIdx.x; t < np; t += blockDim.x) stage_particle<T, COORDS, MODE>(A.p, pbase + t, st, t);
       __syncthreads();
@@ -623,7 +654,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
             if constexpr (MODE == GLV_COMPENSATED) {
               T ma, mb;
               LegC<T> a = staged_leg<T, MODE>(st, si, &ma), b = staged_leg<T, MODE>(st, sj, &mb);
-              m = comp_pair<T>(a, b, ma, mb, &kd, &fb);
+              if constexpr (kDefer) {
+                bool redo;
+                m = comp_pair_fp32(a, b, &kd, &redo);
+                if (redo) s_redo[ev] = 1;
+              } else {
+                m = comp_pair<T>(a, b, ma, mb, &kd, &fb);
+              }
             } else {
               const typename V4<T>::type va = st.cart[si], vb = st.cart[sj];
               T w[4];
@@ -652,8 +689,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
             ks += acc[w * epb + my];
             acc[w * epb + my] = 0.0;
           }
-          store_out(A.event_m, e0 + ca + my, (T)sqrt(msum + 2.0 * ks));
+          T em = (T)sqrt(msum + 2.0 * ks);
+          if constexpr (kDefer) {
+            if (s_redo[my]) em = redo_mark();
+          }
+          store_out(A.event_m, e0 + ca + my, em);
         }
+      }
+      if constexpr (kDefer) {  // without event masses the mark goes to the event's first pair mass
+        if (!A.event_m && want_pairs && my < nch && s_redo[my]) store_out(A.pair_m, q0 + ch[my].p, redo_mark());
       }
       __syncthreads();
       ca = cb;
@@ -701,6 +745,48 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORD
       for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
       if ((threadIdx.x & 63) == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
     }
+  }
+}
+
+// The FP32 compensated events k_event_reduce marked: their pair masses and
+// event mass again, with the FP64 redo of the pairs whose error bound asks for
+// it (counted in the fallback counter).  The totals stay as computed.  A
+// separate launch keeps FP64 code, and its registers, out of the tiled kernel;
+// without marks it only reads one value per event.
+template <typename T>
+__global__ __launch_bounds__(kBigBlock) void k_event_reduce_fix(FwdArgs<T, GLV_PTETAPHIM, GLV_COMPENSATED> A) {
+  __shared__ double red[16];
+  __shared__ int64_t list[kBigBlock];
+  __shared__ int count;
+  unsigned fb = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
+    const int64_t e = base + threadIdx.x;
+    bool marked = false;
+    if (e < A.ne) {
+      const int64_t n = A.off[e + 1] - A.off[e];
+      if (n >= 2 && n <= A.cap) {  // events of the tiled kernel that have pairs
+        if (A.event_m)
+          marked = is_redo_mark(A.event_m[e]);
+        else if (A.pair_m)
+          marked = is_redo_mark(A.pair_m[A.poff[e]]);
+      }
+    }
+    if (!__syncthreads_or(marked)) continue;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    if (marked) list[atomicAdd(&count, 1)] = e;
+    __syncthreads();
+    const int nfix = count;
+    for (int b = 0; b < nfix; ++b) {
+      const int64_t eb = list[b];
+      big_event<T, GLV_PTETAPHIM, GLV_COMPENSATED>(A, eb, A.off[eb], A.off[eb + 1], red, &fb, false);
+    }
+    __syncthreads();
+  }
+  if (A.fallback) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
+    if ((threadIdx.x & 63) == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
   }
 }
 
@@ -989,6 +1075,13 @@ hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_event_reduce_big<T, COORDS, MODE>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
+  if constexpr (MODE == GLV_COMPENSATED && sizeof(T) == 4) {
+    if (em || pm) {
+      err = hipGetLastError();
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL((k_event_reduce_fix<T>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -1054,8 +1147,9 @@ size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
   size_t cols = (mode == GLV_COMPENSATED) ? 10 : 4;
   size_t nwaves = (size_t)t.block / 64;
   size_t acc = (mode == GLV_COMPENSATED) ? nwaves * (size_t)t.events_per_tile * 8 : 0;
+  size_t redo = (mode == GLV_COMPENSATED && dt == GLV_F32) ? (size_t)t.events_per_tile * sizeof(int) : 0;
   return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + ((size_t)t.events_per_tile + 1) * sizeof(EvRec) +
-         kColexPairs * sizeof(unsigned short) + cols * (size_t)t.lds_particles * tsz;
+         ((kColexPairs + 1) & ~1) * sizeof(unsigned short) + redo + cols * (size_t)t.lds_particles * tsz;
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {

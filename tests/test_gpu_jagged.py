@@ -281,3 +281,37 @@ def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
             ref = np.max(np.abs(want_s), axis=0)
             r, i = worst(err, (base + 64 * u * kappa) * ref + 1e-300)
             assert r <= 1.0, (tiling, c_gpr is None, i, got[:, i], want_s[:, i])
+
+
+def test_event_reduce_compensated_fp64_redo():
+    """Heavy, slow particles (M ~ U[5, 20] GeV, pt ~ LogUniform[0.01, 10] GeV,
+    eta ~ U[-4, 4]): pairs at opposite large |eta| exceed the FP32 error bound,
+    so their events take the FP64 redo.  Masses against the accurate oracle, a
+    non-zero fallback count, and the same pair and event masses whichever of
+    them are requested (the redo marks an event through its mass, or through
+    its first pair mass when event masses are not wanted)."""
+    g = synth.rng(711)
+    counts = np.concatenate([np.minimum(g.poisson(6, 1500), 40), [0, 1, 2]]).astype(np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    n = int(off[-1])
+    p = (np.exp(g.uniform(np.log(0.01), np.log(10.0), n)), g.uniform(-4, 4, n), g.uniform(-np.pi, np.pi, n),
+         g.uniform(5.0, 20.0, n))
+    wp = widened(p, torch.float32)
+    _, em_or, pm_or, _ = oracle.event_reduce("PtEtaPhiM", off, wp, mode=oracle.ACCURATE)
+    gp, go = gpu(p, torch.float32), _off(off)
+    runs = {}
+    for want_e, want_p in ((True, True), (False, True), (True, False)):
+        fb = torch.zeros(1, dtype=torch.int64, device=DEV)
+        _, em, pm = glv.glv_event_reduce(gp, go, mode="compensated", want_event_m=want_e, want_pair_m=want_p,
+                                         fallback_count=fb)
+        assert 0 < int(fb.item()) < pm_or.size, (want_e, want_p, int(fb.item()))
+        if want_e:
+            r, i = worst(np.abs(host(em).astype(np.float64) - em_or), mass_tol_comp_f32(em_or))
+            assert r <= 1.0, ("event_m", want_p, i, host(em)[i], em_or[i])
+        if want_p:
+            r, i = worst(np.abs(host(pm).astype(np.float64) - pm_or), mass_tol_comp_f32(pm_or))
+            assert r <= 1.0, ("pair_m", want_e, i, host(pm)[i], pm_or[i])
+        runs[(want_e, want_p)] = (host(em) if want_e else None, host(pm) if want_p else None)
+    assert np.array_equal(runs[(True, True)][1], runs[(False, True)][1])
+    assert np.array_equal(runs[(True, True)][0], runs[(True, False)][0])
