@@ -341,7 +341,7 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
   }
 }
 
-// FP32 compensated pair with the redo left to k_event_reduce_fix: *redo is
+// FP32 compensated pair with the redo left to k_event_reduce_big: *redo is
 // set when the error bound asks for FP64.
 __device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC<float>& b, double* kout,
                                                 bool* redo) {
@@ -354,7 +354,7 @@ __device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC
 
 // Marks an event of the tiled FP32 compensated reduction that holds a pair
 // needing the FP64 redo: written to the event's mass (or, without event
-// masses, to its first pair mass) for k_event_reduce_fix to find.  A quiet NaN
+// masses, to its first pair mass) for k_event_reduce_big to find.  A quiet NaN
 // with a payload that arithmetic does not produce; should an input NaN carry
 // it, the event is merely recomputed.
 constexpr unsigned kRedoMarkBits = 0x7fd2e6b1u;
@@ -716,26 +716,43 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
 // workgroup scans the offsets for them and takes each one whole, from global
 // memory.  A separate launch, so that this rare path does not set the main
 // kernel's register budget; on collider-sized events it only reads the offsets.
+// In the FP32 compensated mode the same scan finds the events k_event_reduce
+// marked for the FP64 redo (a mark in the event mass, or in the first pair
+// mass without event masses) and recomputes their pair masses and event mass
+// with the redo, counting the redone pairs; their totals stay as computed.
 constexpr int kBigBlock = 256;
 
 template <typename T, int COORDS, int MODE>
 __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORDS, MODE> A) {
+  constexpr bool kDefer = (MODE == GLV_COMPENSATED) && (sizeof(T) == 4);
   __shared__ double red[16];
-  __shared__ int64_t list[kBigBlock];
+  __shared__ int64_t list[kBigBlock];  // event << 1 | (1: redo only)
   __shared__ int count;
   unsigned fb = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
     const int64_t e = base + threadIdx.x;
-    const bool big = e < A.ne && A.off[e + 1] - A.off[e] > A.cap;
-    if (!__syncthreads_or(big)) continue;
+    bool big = false, redo = false;
+    if (e < A.ne) {
+      const int64_t n = A.off[e + 1] - A.off[e];
+      big = n > A.cap;
+      if constexpr (kDefer) {
+        if (!big && n >= 2) {
+          if (A.event_m)
+            redo = is_redo_mark(A.event_m[e]);
+          else if (A.pair_m)
+            redo = is_redo_mark(A.pair_m[A.poff[e]]);
+        }
+      }
+    }
+    if (!__syncthreads_or(big || redo)) continue;
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
-    if (big) list[atomicAdd(&count, 1)] = e;
+    if (big || redo) list[atomicAdd(&count, 1)] = (e << 1) | (redo ? 1 : 0);
     __syncthreads();
     const int nbig = count;
     for (int b = 0; b < nbig; ++b) {
-      const int64_t eb = list[b];
-      big_event<T, COORDS, MODE>(A, eb, A.off[eb], A.off[eb + 1], red, &fb);
+      const int64_t eb = list[b] >> 1;
+      big_event<T, COORDS, MODE>(A, eb, A.off[eb], A.off[eb + 1], red, &fb, (list[b] & 1) == 0);
     }
     __syncthreads();
   }
@@ -745,48 +762,6 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORD
       for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
       if ((threadIdx.x & 63) == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
     }
-  }
-}
-
-// The FP32 compensated events k_event_reduce marked: their pair masses and
-// event mass again, with the FP64 redo of the pairs whose error bound asks for
-// it (counted in the fallback counter).  The totals stay as computed.  A
-// separate launch keeps FP64 code, and its registers, out of the tiled kernel;
-// without marks it only reads one value per event.
-template <typename T>
-__global__ __launch_bounds__(kBigBlock) void k_event_reduce_fix(FwdArgs<T, GLV_PTETAPHIM, GLV_COMPENSATED> A) {
-  __shared__ double red[16];
-  __shared__ int64_t list[kBigBlock];
-  __shared__ int count;
-  unsigned fb = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
-    const int64_t e = base + threadIdx.x;
-    bool marked = false;
-    if (e < A.ne) {
-      const int64_t n = A.off[e + 1] - A.off[e];
-      if (n >= 2 && n <= A.cap) {  // events of the tiled kernel that have pairs
-        if (A.event_m)
-          marked = is_redo_mark(A.event_m[e]);
-        else if (A.pair_m)
-          marked = is_redo_mark(A.pair_m[A.poff[e]]);
-      }
-    }
-    if (!__syncthreads_or(marked)) continue;
-    if (threadIdx.x == 0) count = 0;
-    __syncthreads();
-    if (marked) list[atomicAdd(&count, 1)] = e;
-    __syncthreads();
-    const int nfix = count;
-    for (int b = 0; b < nfix; ++b) {
-      const int64_t eb = list[b];
-      big_event<T, GLV_PTETAPHIM, GLV_COMPENSATED>(A, eb, A.off[eb], A.off[eb + 1], red, &fb, false);
-    }
-    __syncthreads();
-  }
-  if (A.fallback) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
-    if ((threadIdx.x & 63) == 0 && fb) atomicAdd(A.fallback, (unsigned long long)fb);
   }
 }
 
@@ -1075,13 +1050,6 @@ hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_event_reduce_big<T, COORDS, MODE>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
-  if constexpr (MODE == GLV_COMPENSATED && sizeof(T) == 4) {
-    if (em || pm) {
-      err = hipGetLastError();
-      if (err != hipSuccess) return err;
-      hipLaunchKernelGGL((k_event_reduce_fix<T>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
-    }
-  }
   return hipGetLastError();
 }
 
