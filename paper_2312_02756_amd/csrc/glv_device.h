@@ -106,8 +106,27 @@ __device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
 
 // ------------------------------------------------------------ conversion
 
+// sincos / sinhcosh of either precision.  kPin (FP64 only) materializes the
+// polynomial constants at their use: for conversions done once per particle
+// in a kernel whose hot loop is elsewhere, so that the constants are not
+// hoisted into registers held across that loop.
+template <bool kPin, typename T>
+__device__ __forceinline__ void sincos_t(T x, T* s, T* c) {
+  if constexpr (sizeof(T) == 8)
+    fast_sincos<kPin>(x, s, c);
+  else
+    fast_sincos(x, s, c);
+}
+template <bool kPin, typename T>
+__device__ __forceinline__ void sinhcosh_t(T x, T* sh, T* ch) {
+  if constexpr (sizeof(T) == 8)
+    fast_sinhcosh<kPin>(x, sh, ch);
+  else
+    fast_sinhcosh(x, sh, ch);
+}
+
 // Cartesian (px, py, pz, E) of one vector given in COORDS.
-template <int COORDS, typename T>
+template <int COORDS, typename T, bool kPin = false>
 __device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
   if constexpr (COORDS == GLV_PXPYPZE) {
     v[0] = c0;
@@ -116,8 +135,8 @@ __device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
     v[3] = c3;
   } else {
     T s, c, sh, ch;
-    fast_sincos(c2, &s, &c);
-    fast_sinhcosh(c1, &sh, &ch);
+    sincos_t<kPin>(c2, &s, &c);
+    sinhcosh_t<kPin>(c1, &sh, &ch);
     v[0] = c0 * c;
     v[1] = c0 * s;
     v[2] = c0 * sh;
@@ -137,7 +156,7 @@ struct LegJ {
   T cp, sp, sh, ch;  // cos phi, sin phi, sinh eta, cosh eta
 };
 
-template <int COORDS, typename T>
+template <int COORDS, typename T, bool kPin = false>
 __device__ __forceinline__ LegJ<T> to_cart_j(T c0, T c1, T c2, T c3) {
   LegJ<T> L;
   if constexpr (COORDS == GLV_PXPYPZE) {
@@ -147,8 +166,8 @@ __device__ __forceinline__ LegJ<T> to_cart_j(T c0, T c1, T c2, T c3) {
     L.v[3] = c3;
     L.cp = L.sp = L.sh = L.ch = T(0);
   } else {
-    fast_sincos(c2, &L.sp, &L.cp);
-    fast_sinhcosh(c1, &L.sh, &L.ch);
+    sincos_t<kPin>(c2, &L.sp, &L.cp);
+    sinhcosh_t<kPin>(c1, &L.sh, &L.ch);
     L.v[0] = c0 * L.cp;
     L.v[1] = c0 * L.sp;
     L.v[2] = c0 * L.sh;

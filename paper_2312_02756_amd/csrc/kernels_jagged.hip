@@ -927,7 +927,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
         const int idx = tid + r * (int)blockDim.x;
         if (idx < nq) s_g[idx] = gv[r];
       }
-      LegJ<T> L = to_cart_j<COORDS, T>(c[0], c[1], c[2], c[3]);
+      LegJ<T> L = to_cart_j<COORDS, T, true>(c[0], c[1], c[2], c[3]);
       if (mine) cart[tid] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
       __syncthreads();
 
