@@ -316,6 +316,34 @@ __device__ __forceinline__ T dphi_reduced(T a, T b) {
   return d;
 }
 
+// Square root and quotient of the compensated path.  In FP32 the hardware
+// square root (within 1 ulp) and a times the hardware reciprocal (within
+// 2 ulp), where the compiler's correctly rounded expansions take about ten
+// instructions each; the error bound below budgets for the difference.  In
+// FP64 the ordinary ones.
+template <typename T>
+__device__ __forceinline__ T sqrt_budgeted(T x) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_sqrtf(x);
+  else
+    return d_sqrt(x);
+}
+template <typename T>
+__device__ __forceinline__ T div_budgeted(T a, T b) {
+  if constexpr (sizeof(T) == 4)
+    return a * __builtin_amdgcn_rcpf(b);
+  else
+    return a / b;
+}
+
+// Rounding units granted in the compensated error bound to the
+// multiplicative factors of the pair terms, and (times |delta|) to each
+// leg's rapidity shift delta: 16 each for products and quotients of
+// accurately computed factors, plus 4 for the FP32 hardware square roots
+// (mT, E) and reciprocal (t3) that replace correctly rounded ones.
+constexpr float kFactorUnits = 20.0f;
+constexpr float kDeltaUnits = 20.0f;
+
 // Per-leg terms: pt, eta, phi, M^2, mT = sqrt(pt^2 + M^2) and
 // delta = y - eta = -asinh(M^2 sinh(eta) / (mT (pt cosh(eta) + E))).
 template <typename T>
@@ -332,26 +360,27 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   L.phi = phi;
   T mm = mass * mass;
   L.m2 = mm;
-  L.mt = d_sqrt(pt * pt + mm);
+  L.mt = sqrt_budgeted(pt * pt + mm);
   T sh, ch;
   if constexpr (sizeof(T) == 8)
     fast_sinhcosh<kCold>(eta, &sh, &ch);
   else
     fast_sinhcosh(eta, &sh, &ch);
   T pc = pt * ch;
-  T e = d_sqrt(pc * pc + mm);
+  T e = sqrt_budgeted(pc * pc + mm);
   T den = L.mt * (pc + e);
   L.delta = (den > T(0)) ? -small_asinh<kCold>(mm * sh / den) : T(0);
   return L;
 }
 
+
 // Pair m^2 = Ma^2 + Mb^2 + 2 (t1 + t2 + t3) (all terms >= 0); *k receives
 // t1 + t2 + t3 = E_a E_b - p_a.p_b.  If `bound` is not NULL it receives a
 // running bound on the relative error of m^2 in units of the rounding unit:
 // every term is a product/quotient of accurately computed positive factors
-// (16 units covers them) except the rapidity difference dy, whose absolute
-// error is a few units of |d1| + |d2| + |dy| plus that of the deltas; t1
-// moves with dy as 2 mTa mTb |sinh dy|.
+// (kFactorUnits covers them) except the rapidity difference dy, whose
+// absolute error is a few units of |d1| + |d2| + |dy| plus that of the
+// deltas; t1 moves with dy as 2 mTa mTb |sinh dy|.
 template <typename T, bool kCold = false>
 __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T* k, T* bound) {
   T d1 = a.eta - b.eta;
@@ -371,15 +400,15 @@ __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T*
   T t2 = T(2) * a.pt * b.pt * (s2 * s2);
   T num = a.pt * a.pt * b.m2 + b.pt * b.pt * a.m2 + a.m2 * b.m2;
   T den = a.mt * b.mt + a.pt * b.pt;
-  T t3 = (num == T(0)) ? T(0) : num / den;
+  T t3 = (num == T(0)) ? T(0) : div_budgeted(num, den);
   T kk = t1 + t2 + t3;
   T m2 = a.m2 + b.m2 + T(2) * kk;
   *k = kk;
   if (bound) {
-    T edy = (d_abs(d1) + d_abs(d2) + d_abs(dy)) + T(16) * (d_abs(a.delta) + d_abs(b.delta));
-    T c1 = d_sqrt(T(1) + s1 * s1);
+    T edy = (d_abs(d1) + d_abs(d2) + d_abs(dy)) + T(kDeltaUnits) * (d_abs(a.delta) + d_abs(b.delta));
+    T c1 = sqrt_budgeted(T(1) + s1 * s1);
     T sens = T(4) * a.mt * b.mt * d_abs(s1 * c1);  // 2 * d(t1)/d(dy)
-    *bound = (m2 > T(0)) ? (sens * edy + T(16) * m2) / m2 : T(0);
+    *bound = (m2 > T(0)) ? div_budgeted(sens * edy + T(kFactorUnits) * m2, m2) : T(0);
   }
   return m2;
 }

@@ -129,7 +129,7 @@ struct MassComp {
           out.v[e] = (T)sqrt(m2d);
           ++cnt;
         } else {
-          out.v[e] = d_sqrt(m2);
+          out.v[e] = sqrt_budgeted(m2);
         }
       } else {
         out.v[e] = d_sqrt(comp_pair_m2<T>(la, lb, &k, nullptr));

@@ -333,7 +333,7 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
       return (T)sqrt(m2d);
     }
     *kout = (double)k;
-    return d_sqrt(m2);
+    return sqrt_budgeted(m2);
   } else {
     T m2 = comp_pair_m2<T>(a, b, &k, nullptr);
     *kout = (double)k;
@@ -349,7 +349,7 @@ __device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC
   const float m2 = comp_pair_m2<float>(a, b, &k, &bound);
   *redo = !(bound <= kFallbackUnits);
   *kout = (double)k;
-  return d_sqrt(m2);
+  return sqrt_budgeted(m2);
 }
 
 // Marks an event of the tiled FP32 compensated reduction that holds a pair
