@@ -518,8 +518,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   const int epb = A.epb, cap = A.cap;
   const int nwaves = blockDim.x >> 6;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // LDS (cap is a multiple of 64, so every record array keeps the 32-byte
-  // alignment of the start):
+  // LDS (each record array holds cap records of a size that is a multiple of
+  // the next one's alignment, so all stay aligned for any cap):
   //   cart[cap] (4 T), legA[cap] (4 T), legB[cap] (2 T)   staged records
   //   s_off[epb+1], s_poff[epb+1]   int64, the tile's offsets
   //   red[16], acc[nwaves*epb]      double

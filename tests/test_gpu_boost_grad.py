@@ -191,3 +191,26 @@ def test_autograd_mass_of_boosted_pair():
     scale = (np.abs(x1[3]) + np.abs(x2[3])) ** 2 / m_unboosted / (1.0 - sum(b * b for b in beta)) ** 1.5
     for t in bt:
         assert np.all(np.abs(host(t.grad)) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE"])
+def test_autograd_gradcheck_event_reduce(coords):
+    """torch.autograd.gradcheck of the jagged reduction's wrapper: every
+    output (totals, event masses, pair masses) against central differences,
+    on events of 0 to 6 particles."""
+    counts = np.array([3, 0, 1, 2, 6, 4], dtype=np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    g = synth.rng(640)
+    p, _ = synth.pairs_generic(g, int(off[-1]))
+    if coords == "PxPyPzE":
+        p = oracle.to_cartesian("PtEtaPhiM", p)
+    cols = tuple(t.clone().requires_grad_(True) for t in gpu(p, torch.float64))
+    go = torch.from_numpy(off).to("cuda:0")
+    po = glv.glv_pair_offsets(go)
+
+    def f(*c):
+        total, em, pm = ag.event_reduce(c, go, po, coords=coords)
+        return (*total, em, pm)
+
+    assert torch.autograd.gradcheck(f, cols, eps=1e-6, atol=1e-6, rtol=1e-5)
