@@ -24,7 +24,7 @@ stream the kernels run on, inside the timed steps.
 cpu_baseline: the CPU oracle (test infrastructure) timed on the host cores on
 one step's workload, repeated until about 10 s have passed, in the same unit.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--calib-copy]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--calib-copy]
 """
 
 import argparse
@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32-compensated vs plain FP64 comparison (profiling runs: only the step's "
+                         "launches)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -72,7 +75,7 @@ def parse():
 
 
 TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-             "-d $R/gpurun_out/prof_trace -o bench -- python3 $R/bench.py --steps 20 --warmup 3 --no-cpu "
+             "-d $R/gpurun_out/prof_trace -o bench -- python3 $R/bench.py --steps 20 --warmup 3 --no-cpu --no-compare "
              "> $R/gpurun_out/trace_bench.json")
 
 
@@ -157,9 +160,9 @@ def summarize_pmc(fetch_csv, write_csv):
     lines = [f"# HBM traffic per launch: rocprofv3 FETCH_SIZE x {f_scale:.4f} + WRITE_SIZE x {w_scale:.4f}",
              "# (scales from a 1 GiB device copy in the same runs).  Commands, from the repository root R:",
              "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o fetch -- "
-             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --calib-copy",
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --no-compare --calib-copy",
              "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_write -o write -- "
-             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --calib-copy",
+             "python3 $R/bench.py --steps 2 --warmup 1 --no-cpu --no-compare --calib-copy",
              "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/fetch_counter_collection.csv "
              "gpurun_out/pmc_write/write_counter_collection.csv",
              "# sources = digest of the kernel's source file and the shared headers at measurement time"]
@@ -387,7 +390,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom)}
 
-    comparison = compare_precisions(lib, SA, SB, MC, FB, sp, args.warmup, K)
+    comparison = None if args.no_compare else compare_precisions(lib, SA, SB, MC, FB, sp, args.warmup, K)
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
