@@ -631,52 +631,98 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
         int ev = 0;
         EvRec cur{0, 0}, nxt{0, 0};
         bool located = false;
-        for (int it = lo; it < hi; it += 64) {
-          const int k = it + lane;  // chunk-relative pair index
-          const bool valid = k < hi;
-          double kd = 0.0;
-          if (valid) {
-            if (!located) {
-              ev = search_rec(ch, 0, nch, k);
-              cur = ch[ev];
-              nxt = ch[ev + 1];
-              located = true;
-            }
-            while (nxt.p <= k) {
-              cur = nxt;
-              nxt = ch[++ev + 1];
-            }
-            const int base = cur.o;
-            int i, j;
-            pair_of_rank(k - cur.p, nxt.o - base, colex, &i, &j);
-            const int si = base + i, sj = base + j;
-            T m;
-            if constexpr (MODE == GLV_COMPENSATED) {
-              T ma, mb;
-              LegC<T> a = staged_leg<T, MODE>(st, si, &ma), b = staged_leg<T, MODE>(st, sj, &mb);
-              if constexpr (kDefer) {
-                bool redo;
-                m = comp_pair_fp32(a, b, &kd, &redo);
-                if (redo) s_redo[ev] = 1;
-              } else {
-                m = comp_pair<T>(a, b, ma, mb, &kd, &fb);
+        if constexpr (MODE != GLV_COMPENSATED) {
+          // two pairs per lane and iteration, k and k + 64: their LDS reads and
+          // mass evaluations overlap (the second's event is stepped to from the
+          // first's)
+          for (int it = lo; it < hi; it += 128) {
+            const int k0 = it + lane, k1 = k0 + 64;
+            if (k0 < hi) {
+              if (!located) {
+                ev = search_rec(ch, 0, nch, k0);
+                cur = ch[ev];
+                nxt = ch[ev + 1];
+                located = true;
               }
-            } else {
-              const typename V4<T>::type va = st.cart[si], vb = st.cart[sj];
-              T w[4];
+              while (nxt.p <= k0) {
+                cur = nxt;
+                nxt = ch[++ev + 1];
+              }
+              int i, j;
+              pair_of_rank(k0 - cur.p, nxt.o - cur.o, colex, &i, &j);
+              const int si0 = cur.o + i, sj0 = cur.o + j;
+              const bool two = k1 < hi;
+              int si1 = si0, sj1 = sj0;
+              if (two) {
+                while (nxt.p <= k1) {
+                  cur = nxt;
+                  nxt = ch[++ev + 1];
+                }
+                pair_of_rank(k1 - cur.p, nxt.o - cur.o, colex, &i, &j);
+                si1 = cur.o + i;
+                sj1 = cur.o + j;
+              }
+              const typename V4<T>::type a0 = st.cart[si0], b0 = st.cart[sj0];
+              const typename V4<T>::type a1 = st.cart[si1], b1 = st.cart[sj1];
+              T w0[4], w1[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) w[c] = va[c] + vb[c];
-              m = mass_of(w);
+              for (int c = 0; c < 4; ++c) {
+                w0[c] = a0[c] + b0[c];
+                w1[c] = a1[c] + b1[c];
+              }
+              const T m0 = mass_of(w0), m1 = mass_of(w1);
+              store_out(A.pair_m, q0 + k0, m0);
+              if (two) store_out(A.pair_m, q0 + k1, m1);
             }
-            if (want_pairs) store_out(A.pair_m, q0 + k, m);
           }
-          if constexpr (MODE == GLV_COMPENSATED) {
-            if (want_k) {
-              // segmented inclusive scan of kd keyed by event (keys ascend with lane)
-              const int key = valid ? ev : 0x7fffffff;
-              kd = seg_scan_wave(kd, key);
-              const int knext = dpp_i32<kDppWaveShl1, 0xf>(key, -1);  // lane 63: -1
-              if (valid && knext != key) acc[wid * epb + ev] += kd;
+        } else {
+          for (int it = lo; it < hi; it += 64) {
+            const int k = it + lane;  // chunk-relative pair index
+            const bool valid = k < hi;
+            double kd = 0.0;
+            if (valid) {
+              if (!located) {
+                ev = search_rec(ch, 0, nch, k);
+                cur = ch[ev];
+                nxt = ch[ev + 1];
+                located = true;
+              }
+              while (nxt.p <= k) {
+                cur = nxt;
+                nxt = ch[++ev + 1];
+              }
+              const int base = cur.o;
+              int i, j;
+              pair_of_rank(k - cur.p, nxt.o - base, colex, &i, &j);
+              const int si = base + i, sj = base + j;
+              T m;
+              if constexpr (MODE == GLV_COMPENSATED) {
+                T ma, mb;
+                LegC<T> a = staged_leg<T, MODE>(st, si, &ma), b = staged_leg<T, MODE>(st, sj, &mb);
+                if constexpr (kDefer) {
+                  bool redo;
+                  m = comp_pair_fp32(a, b, &kd, &redo);
+                  if (redo) s_redo[ev] = 1;
+                } else {
+                  m = comp_pair<T>(a, b, ma, mb, &kd, &fb);
+                }
+              } else {
+                const typename V4<T>::type va = st.cart[si], vb = st.cart[sj];
+                T w[4];
+  #pragma unroll
+                for (int c = 0; c < 4; ++c) w[c] = va[c] + vb[c];
+                m = mass_of(w);
+              }
+              if (want_pairs) store_out(A.pair_m, q0 + k, m);
+            }
+            if constexpr (MODE == GLV_COMPENSATED) {
+              if (want_k) {
+                // segmented inclusive scan of kd keyed by event (keys ascend with lane)
+                const int key = valid ? ev : 0x7fffffff;
+                kd = seg_scan_wave(kd, key);
+                const int knext = dpp_i32<kDppWaveShl1, 0xf>(key, -1);  // lane 63: -1
+                if (valid && knext != key) acc[wid * epb + ev] += kd;
+              }
             }
           }
         }
