@@ -510,10 +510,30 @@ def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em
         if dt >= min_seconds or reps >= max_reps:
             break
     items = reps * (3 * N_ITEMS + 2 * N_EVENTS)
+    # one thread (the paper's CPU baseline form) on 1/32 of a step: 2^19 items, 2^15 events
+    n1, e1 = N_ITEMS // 32, N_EVENTS // 32
+    cut = lambda cols: tuple(c[:n1] for c in cols)  # noqa: E731
+    off1 = off[: e1 + 1]
+    np1, nq1 = int(off1[-1]), int(np.sum((np.diff(off1) * (np.diff(off1) - 1)) // 2))
+    p1, p32 = tuple(c[:np1] for c in parts), tuple(c[:np1] for c in parts32)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.mass_plain("PtEtaPhiM", cut(a), cut(b))
+    oracle.mass_vjp("PtEtaPhiM", cut(a), cut(b), gm[:n1])
+    oracle.boost(cut(x), cut(beta))
+    oracle.boost_vjp(cut(x), cut(beta), cut(gy))
+    oracle.mass_accurate(cut(sa), cut(sb))
+    oracle.event_reduce("PtEtaPhiM", off1, p1)
+    oracle.event_reduce("PtEtaPhiM", off1, p32, oracle.ACCURATE)
+    oracle.event_reduce_vjp("PtEtaPhiM", off1, p1, tuple(c[:e1] for c in g_tot), g_em[:e1], g_pair[:nq1])
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle",
             "sample": f"{reps} x one step's workload: 2^24 items through mass fwd+bwd, boost fwd+bwd and the "
                       f"accurate mass, 2^20 jagged events through the plain reduction and its VJP and the accurate "
-                      f"reduction (binary64 oracle); {dt:.2f} s wall on {used} threads"}
+                      f"reduction (binary64 oracle); {dt:.2f} s wall on {used} threads",
+            "single_thread": {"value": round((3 * n1 + 2 * e1) / dt1 / 1e9, 6), "unit": "Gevents/s",
+                              "sample": f"1/32 of a step (2^19 items, 2^15 events) on 1 thread, {dt1:.2f} s"}}
 
 
 if __name__ == "__main__":
