@@ -18,7 +18,8 @@
  *   Sec. 3.1   InvariantMasses: mass of the sum of two 4-vectors given in any
  *              4D coordinate system; ApplyBoost: a 4D Lorentz transformation
  *              held as a 4x4 matrix, applied to an array of vectors.
- *   Fig. 1/2   the pair-mass kernel: w = v1[id] + v2[id]; m[id] = w.mass().
+ *   Fig. 1/2   the pair-mass kernel: each work item adds the two vectors at
+ *              its index and stores the mass of that sum.
  * The reverse-mode derivatives, the cancellation-free pair mass and the
  * per-event (jagged) reduction are not in the paper; each function below says
  * what it is derived from.

@@ -2,7 +2,7 @@
 // bundles, streaming (non-temporal) 16-byte loads/stores, the coordinate
 // conversions of a 4D vector (GenVectorX Sec. 2.1: Cartesian and
 // pt/eta/phi systems, templated on the scalar type) and the mass of a
-// Cartesian vector (Fig. 1, `w.mass()`).
+// Cartesian vector (Fig. 1: the mass of the summed pair).
 #pragma once
 
 #include <hip/hip_runtime.h>
