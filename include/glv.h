@@ -98,9 +98,10 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  * built-in default).  A tiling whose workgroup would need more than 64 KiB of
  * LDS is rejected with GLV_EINVAL_TILING: per staged particle the forward
  * keeps 4 values (10 in the compensated mode) and the backward 8 values (its
- * vector and up to four pair gradients) plus 2 bytes; per event of a tile a
- * few tens of bytes more.  The backward stages at most one particle per
- * workgroup thread (lds_particles above block acts as block). */
+ * vector and up to four pair gradients) plus 2 bytes; per event of a tile
+ * about 40 bytes more (the backward: 5 values and 24 bytes).  The backward
+ * stages at most one particle per workgroup thread (lds_particles above block
+ * acts as block). */
 typedef struct glv_tiling {
   int32_t block;
   int32_t events_per_tile;

@@ -243,16 +243,21 @@ __device__ __forceinline__ float inv_sqrt(float a) {
   return fmaf(0.5f * y, fmaf(-a * y, y, 1.0f), y);
 }
 
-// u = g dm/d(px, py, pz, E) for the mass of w: (-P, E) g / |m| with
-// 1/|m| = 1/sqrt|q| taken directly (no square root, no division on the
-// gradient path); zero where q = 0 (m = 0).  The same expression for q as
-// mass_of.
+// g / |m| for the mass of w, with 1/|m| = 1/sqrt|q| taken directly (no
+// square root, no division on the gradient path); zero where q = 0 (m = 0).
+// The same expression for q as mass_of.
 template <typename T>
-__device__ __forceinline__ void dmass(const T w[4], T g, T u[4]) {
+__device__ __forceinline__ T pair_coef(const T w[4], T g) {
   const T q = w[3] * w[3] - w[0] * w[0] - w[1] * w[1] - w[2] * w[2];
   const T a = d_abs(q);
   const T r = inv_sqrt(a);  // evaluated for every lane: a select, not a branch
-  const T s = (a > T(0)) ? g * r : T(0);
+  return (a > T(0)) ? g * r : T(0);
+}
+
+// u = g dm/d(px, py, pz, E) for the mass of w: (-P, E) g / |m|.
+template <typename T>
+__device__ __forceinline__ void dmass(const T w[4], T g, T u[4]) {
+  const T s = pair_coef(w, g);
   u[0] = -w[0] * s;
   u[1] = -w[1] * s;
   u[2] = -w[2] * s;

@@ -899,12 +899,20 @@ __device__ __forceinline__ bool bwd_big(int64_t n, int cap, bool pairs) {
 //     pair gradients -- contiguous in grad_pair -- are copied to LDS, each
 //     thread issuing all of its loads before its stores; one lane per event
 //     records its particles' event (from the offsets: all one phase);
-//   * thread t then walks its event's particles in CSR order: it adds the
-//     pair terms g_ij dm(v_i + v_j)/dw of its partners (the same 4-vector for
-//     both legs of a pair), walking the pair indices incrementally, and sums
-//     the event total V on the way -- every particle of an event forms the
-//     same V in the same order -- then adds g_total + g_m dm(V)/dV and applies
-//     its own conversion Jacobian.
+//   * pair phase: each pair's gradient g_ij becomes c_ij = g_ij / |m_ij| in
+//     place, computed once, by one of its two legs: particle a of an event of
+//     n takes the partners a + 1, ..., a + d cyclically, d = (n - 1) / 2
+//     rounded down, plus a + n/2 when n is even and a < n/2 -- every pair
+//     once, about n/2 per particle, whatever the particle's place;
+//   * in the same phase one lane per event (spread over the wavefronts; its
+//     g_total and g_m were loaded with the chunk) sums the event's vectors V
+//     in CSR order and stages g_total + g_m dm(V)/dV, the upstream every
+//     particle of the event receives from the event outputs;
+//   * thread t then walks its event's particles in CSR order and adds the
+//     pair terms c_ij (v_i + v_j) = c_ij v_i + c_ij v_j of its partners
+//     (dm(w)/dw = (-P, E) / |m|, the same 4-vector for both legs of a pair),
+//     walking the pair indices incrementally, then the event's upstream, and
+//     applies its own conversion Jacobian.
 template <typename T, int COORDS>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(32) unsigned char lds[];
@@ -916,11 +924,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
   const bool want_v = A.gem != nullptr;
   const int qcap = pairs ? (int)bwd_pair_cap(cap) : 0;
   const int tid = (int)threadIdx.x;
-  // LDS: cart[cap] (R4), s_g[qcap] (T), s_off[epb+1], s_poff[epb+1] (int64),
-  //      ch[epb+1] (EvRec), ev_of[cap] (uint16)
+  const bool want_u = want_v || A.gt[0] != nullptr;
+  // LDS: cart[cap], s_ut[epb] (R4), s_g[qcap + 2] (T; qcap is even, one
+  //      slot of slack), s_gm[epb rounded up to even] (T), s_off[epb+1],
+  //      s_poff[epb+1] (int64), ch[epb+1] (EvRec), ev_of[cap] (uint16)
   R4* cart = reinterpret_cast<R4*>(lds);
-  T* s_g = reinterpret_cast<T*>(cart + cap);
-  int64_t* s_off = reinterpret_cast<int64_t*>(s_g + ((qcap + 1) & ~1));
+  R4* s_ut = cart + cap;
+  T* s_g = reinterpret_cast<T*>(s_ut + epb);
+  T* s_gm = s_g + qcap + 2;
+  int64_t* s_off = reinterpret_cast<int64_t*>(s_gm + ((epb + 1) & ~1));
+  // event lanes: event t of a chunk belongs to thread (t % nw) * 64 + t / nw,
+  // spread over the workgroup's nw wavefronts (the block is a power of two
+  // >= 64 and a chunk has at most epb <= block events)
+  const int nw = (int)blockDim.x >> 6;
+  const int tev = (tid & 63) * nw + (tid >> 6);
   int64_t* s_poff = s_off + (epb + 1);
   EvRec* ch = reinterpret_cast<EvRec*>(s_poff + (epb + 1));
   unsigned short* ev_of = reinterpret_cast<unsigned short*>(ch + (epb + 1));
@@ -962,6 +979,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
         const int idx = tid + r * (int)blockDim.x;
         gv[r] = (idx < nq) ? A.gpair[q0 + idx] : T(0);
       }
+      // the event lane's upstreams (g_total, g_m), staged with the rest
+      const bool evl = want_u && tev < nch;
+      T gtv[4] = {0, 0, 0, 0}, gmv = 0;
+      if (evl) {
+        const int64_t e = e0 + ca + tev;
+        if (A.gt[0]) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) gtv[k] = A.gt[k][e];
+        }
+        if (want_v) gmv = A.gem[e];
+      }
       for (int t = tid; t <= nch; t += blockDim.x)
         ch[t] = EvRec{(int)(s_off[ca + t] - pbase), pairs ? (int)(s_poff[ca + t] - q0) : 0};
       for (int t = tid; t < nch; t += blockDim.x) {
@@ -973,58 +1001,105 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
         const int idx = tid + r * (int)blockDim.x;
         if (idx < nq) s_g[idx] = gv[r];
       }
+      if (evl) {
+        s_ut[tev] = R4{gtv[0], gtv[1], gtv[2], gtv[3]};
+        s_gm[tev] = gmv;
+      }
       LegJ<T> L = to_cart_j<COORDS, T, true>(c[0], c[1], c[2], c[3]);
       if (mine) cart[tid] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
       __syncthreads();
 
-      if (mine) {
-        const int ev = ev_of[tid];
-        const EvRec rc = ch[ev];
-        const int n = ch[ev + 1].o - rc.o;
-        const int ai = tid - rc.o;
-        T u[4] = {0, 0, 0, 0};
-        Acc vt[4] = {0, 0, 0, 0};  // event total, CSR order
-        if (pairs || want_v) {
-          // Partners in ascending order.  Pair (bj, ai), bj < ai, sits at rank
-          // R(bj) + ai - bj - 1, which grows by n - bj - 2 with bj; pair
-          // (ai, bj), bj > ai, at R(ai) + bj - ai - 1, consecutive from R(ai).
-          int qlo = rc.p + ai - 1;
-          int qhi = rc.p + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
-          const int qlast = nq > 0 ? nq - 1 : 0;
-          for (int bj = 0; bj < n; ++bj) {
-            // both LDS reads first, so that one wait covers them
-            const bool below = bj < ai;
-            const T g = pairs ? s_g[min(below ? qlo : qhi, qlast)] : T(0);
-            const R4 vj = cart[rc.o + bj];
+      // one lane per event: the upstream every particle's 4-vector receives
+      // from the event outputs, g_total + g_m dm(V)/dV, with V summed in CSR
+      // order
+      if (evl && want_v) {
+        const int lo = ch[tev].o, hi = ch[tev + 1].o;
+        Acc vt[4] = {0, 0, 0, 0};
+        int i = lo;
+        for (; i + 1 < hi; i += 2) {  // both reads first
+          const R4 v0 = cart[i], v1 = cart[i + 1];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) vt[k] += (Acc)vj[k];  // unused without g_m
-            if (!pairs || bj == ai) continue;
-            T w[4], uw[4];
+          for (int k = 0; k < 4; ++k) vt[k] = (vt[k] + (Acc)v0[k]) + (Acc)v1[k];
+        }
+        if (i < hi) {
+          const R4 v0 = cart[i];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) vt[k] += (Acc)v0[k];
+        }
+        T tot[4], ud[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
+        dmass<T>(tot, s_gm[tev], ud);
+        const R4 gt4 = s_ut[tev];
+        s_ut[tev] = R4{ud[0] + gt4[0], ud[1] + gt4[1], ud[2] + gt4[2], ud[3] + gt4[3]};
+      }
+
+      // Pair ranks inside an event: pair (b, a), b < a, sits at
+      // R(b) + a - b - 1, which grows by n - b - 2 with b; pair (a, b), b > a,
+      // at R(a) + b - a - 1, consecutive from R(a) = a (2n - a - 1) / 2.
+      int ev = 0, n = 0, ai = 0;
+      EvRec rc{0, 0};
+      if (mine) {
+        ev = ev_of[tid];
+        rc = ch[ev];
+        n = ch[ev + 1].o - rc.o;
+        ai = tid - rc.o;
+      }
+      const int qrow = rc.p + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
+      if (pairs) {
+        if (mine) {
+          const int cnt = ((n - 1) >> 1) + ((n & 1) == 0 && 2 * ai < n ? 1 : 0);
+          int qlo = rc.p + ai - 1, qhi = qrow;
+          for (int t = 0, b = ai + 1; t < cnt; ++t, ++b) {
+            const bool wrap = b >= n;
+            const int bb = wrap ? b - n : b;
+            const int q = wrap ? qlo : qhi;
+            const T g = s_g[q];
+            const R4 vj = cart[rc.o + bb];
+            T w[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) w[k] = L.v[k] + vj[k];
-            dmass<T>(w, g, uw);
+            s_g[q] = pair_coef<T>(w, g);
+            if (wrap)
+              qlo += n - bb - 2;
+            else
+              ++qhi;
+          }
+        }
+      }
+      if (pairs || want_u) __syncthreads();  // s_g and s_ut complete
+
+      if (mine) {
+        T u[4] = {0, 0, 0, 0};
+        if (want_u) {
+          const R4 ut = s_ut[ev];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) u[k] += uw[k];
+          for (int k = 0; k < 4; ++k) u[k] = ut[k];
+        }
+        if (pairs && n > 1) {
+          // partners in ascending order: S = sum of c_ab v_b, C = sum of c_ab
+          T S[4] = {0, 0, 0, 0}, C = 0;
+          int qlo = rc.p + ai - 1, qhi = qrow;
+          for (int bj = 0; bj < n; ++bj) {
+            // both LDS reads first, so that one wait covers them; at bj == ai
+            // qhi is at most nq (the slack slot) and the value is not used
+            const bool below = bj < ai;
+            const T cab = s_g[below ? qlo : qhi];
+            const R4 vj = cart[rc.o + bj];
+            if (bj == ai) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S[k] += cab * vj[k];
+            C += cab;
             if (below)
               qlo += n - bj - 2;
             else
               ++qhi;
           }
-        }
-        const int64_t e = e0 + ca + ev;
-        T ut[4] = {0, 0, 0, 0};
-        if (want_v) {
-          T tot[4];
+          // sum of c_ab (v_a + v_b) = C v_a + S, with dm/dw = (-P, E) / |m|
 #pragma unroll
-          for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
-          dmass<T>(tot, A.gem[e], ut);
+          for (int k = 0; k < 3; ++k) u[k] -= C * L.v[k] + S[k];
+          u[3] += C * L.v[3] + S[3];
         }
-        if (A.gt[0]) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) ut[k] += A.gt[k][e];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = ut[k] + u[k];
         T g[4];
         chain_coords<COORDS, T>(L, c[0], c[3], u, g);
 #pragma unroll
@@ -1172,8 +1247,8 @@ size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
   const size_t tsz = (dt == GLV_F64) ? 8 : 4;
   const size_t cap = (size_t)bwd_cap(t), epb = (size_t)t.events_per_tile;
   const size_t qcap = (size_t)kBwdPairsPerParticle * cap;
-  return 4 * cap * tsz + ((qcap + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 + (epb + 1) * sizeof(EvRec) +
-         cap * sizeof(unsigned short);
+  return 4 * (cap + epb) * tsz + (qcap + 2) * tsz + ((epb + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 +
+         (epb + 1) * sizeof(EvRec) + cap * sizeof(unsigned short);
 }
 
 hipError_t launch_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, hipStream_t s) {
