@@ -277,7 +277,7 @@ __device__ __forceinline__ double fast_sinh(double x) {
 __device__ __forceinline__ float fast_sinh(float x) {
   if (fabsf(x) < 0.5f) return poly_sinh_f(x);
   float sh, ch;
-  fast_sinhcosh(x, &sh, &ch);
+  fast_sinhcosh_rcp(x, &sh, &ch);
   return sh;
 }
 
@@ -345,7 +345,9 @@ __device__ __forceinline__ T div_budgeted(T a, T b) {
 // multiplicative factors of the pair terms, and (times |delta|) to each
 // leg's rapidity shift delta: 16 each for products and quotients of
 // accurately computed factors, plus 4 for the FP32 hardware square roots
-// (mT, E) and reciprocal (t3) that replace correctly rounded ones.
+// (mT, E) and reciprocals (t3, e^-x in sinh and cosh) and the unreduced
+// sine of the half azimuth difference (1.7 ulp) that replace correctly
+// rounded ones.
 constexpr float kFactorUnits = 20.0f;
 constexpr float kDeltaUnits = 20.0f;
 
@@ -370,7 +372,7 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   if constexpr (sizeof(T) == 8)
     fast_sinhcosh<kCold>(eta, &sh, &ch);
   else
-    fast_sinhcosh(eta, &sh, &ch);
+    fast_sinhcosh_rcp(eta, &sh, &ch);
   T pc = pt * ch;
   T e = sqrt_budgeted(pc * pc + mm);
   T den = L.mt * (pc + e);
@@ -379,15 +381,38 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
 }
 
 
+// Relative-error bound (units of u32) above which an FP32 pair is redone in
+// FP64: 2^-18 / 2^-24 = 64.
+constexpr float kFallbackUnits = 64.0f;
+
+// sin^2 of half the azimuth difference d.  In FP32 the unreduced polynomial
+// while |d/2| <= pi/2 (always, for azimuths in [-pi, pi] after the seam
+// reduction), otherwise the reduced sine.
+template <typename T, bool kCold>
+__device__ __forceinline__ T sin2_half(T d) {
+  T s, c;
+  if constexpr (sizeof(T) == 8) {
+    fast_sincos<kCold>(T(0.5) * d, &s, &c);
+  } else {
+    const float h = 0.5f * d;
+    if (fabsf(h) <= 1.5707964f)
+      s = sin_half_range(h);
+    else
+      fast_sincos(h, &s, &c);
+  }
+  return s * s;
+}
+
 // Pair m^2 = Ma^2 + Mb^2 + 2 (t1 + t2 + t3) (all terms >= 0); *k receives
-// t1 + t2 + t3 = E_a E_b - p_a.p_b.  If `bound` is not NULL it receives a
-// running bound on the relative error of m^2 in units of the rounding unit:
+// t1 + t2 + t3 = E_a E_b - p_a.p_b.  If `redo` is not NULL it is set when a
+// bound on the relative error of m^2 exceeds kFallbackUnits rounding units:
 // every term is a product/quotient of accurately computed positive factors
 // (kFactorUnits covers them) except the rapidity difference dy, whose
 // absolute error is a few units of |d1| + |d2| + |dy| plus that of the
-// deltas; t1 moves with dy as 2 mTa mTb |sinh dy|.
+// deltas; t1 moves with dy as 2 mTa mTb |sinh dy| = 4 mTa mTb |s1| cosh(dy/2),
+// taken at most as 4 mTa mTb |s1| (1 + |s1|).  A NaN bound asks for the redo.
 template <typename T, bool kCold = false>
-__device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T* k, T* bound) {
+__device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T* k, bool* redo) {
   T d1 = a.eta - b.eta;
   T d2 = a.delta - b.delta;
   T dy = d1 + d2;
@@ -397,29 +422,21 @@ __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T*
   else
     s1 = fast_sinh(T(0.5) * dy);
   T t1 = T(2) * a.mt * b.mt * (s1 * s1);
-  T s2, c2;
-  if constexpr (sizeof(T) == 8)
-    fast_sincos<kCold>(T(0.5) * dphi_reduced(a.phi, b.phi), &s2, &c2);
-  else
-    fast_sincos(T(0.5) * dphi_reduced(a.phi, b.phi), &s2, &c2);
-  T t2 = T(2) * a.pt * b.pt * (s2 * s2);
+  T t2 = T(2) * a.pt * b.pt * sin2_half<T, kCold>(dphi_reduced(a.phi, b.phi));
   T num = a.pt * a.pt * b.m2 + b.pt * b.pt * a.m2 + a.m2 * b.m2;
   T den = a.mt * b.mt + a.pt * b.pt;
   T t3 = (num == T(0)) ? T(0) : div_budgeted(num, den);
   T kk = t1 + t2 + t3;
   T m2 = a.m2 + b.m2 + T(2) * kk;
   *k = kk;
-  if (bound) {
+  if (redo) {
     T edy = (d_abs(d1) + d_abs(d2) + d_abs(dy)) + T(kDeltaUnits) * (d_abs(a.delta) + d_abs(b.delta));
-    T c1 = sqrt_budgeted(T(1) + s1 * s1);
-    T sens = T(4) * a.mt * b.mt * d_abs(s1 * c1);  // 2 * d(t1)/d(dy)
-    *bound = (m2 > T(0)) ? div_budgeted(sens * edy + T(kFactorUnits) * m2, m2) : T(0);
+    const T as1 = d_abs(s1);
+    T sens = T(4) * a.mt * b.mt * (as1 * (T(1) + as1));  // >= 2 * d(t1)/d(dy)
+    // bound = sens edy / m2 + kFactorUnits > kFallbackUnits, for m2 > 0
+    *redo = (m2 > T(0)) && !(sens * edy <= T(kFallbackUnits - kFactorUnits) * m2);
   }
   return m2;
 }
-
-// Relative-error bound (units of u32) above which an FP32 pair is redone in
-// FP64: 2^-18 / 2^-24 = 64.
-constexpr float kFallbackUnits = 64.0f;
 
 }  // namespace glv

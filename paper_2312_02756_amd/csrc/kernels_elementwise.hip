@@ -119,9 +119,9 @@ struct MassComp {
       LegC<T> lb = comp_leg<T>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
       T k;
       if constexpr (sizeof(T) == 4) {
-        T bound;
-        T m2 = comp_pair_m2<T>(la, lb, &k, &bound);
-        if (!(bound <= kFallbackUnits)) {
+        bool redo;
+        T m2 = comp_pair_m2<T>(la, lb, &k, &redo);
+        if (redo) {
           LegC<double> da = comp_leg<double, true>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
           LegC<double> db = comp_leg<double, true>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
           double kd;

@@ -321,9 +321,9 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
                                        unsigned* fb) {
   T k;
   if constexpr (sizeof(T) == 4) {
-    T bound;
-    T m2 = comp_pair_m2<T>(a, b, &k, &bound);
-    if (!(bound <= kFallbackUnits)) {
+    bool redo;
+    T m2 = comp_pair_m2<T>(a, b, &k, &redo);
+    if (redo) {
       LegC<double> da = comp_leg<double, true>(a.pt, a.eta, a.phi, ma);
       LegC<double> db = comp_leg<double, true>(b.pt, b.eta, b.phi, mb);
       double kd;
@@ -345,9 +345,8 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
 // set when the error bound asks for FP64.
 __device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC<float>& b, double* kout,
                                                 bool* redo) {
-  float k, bound;
-  const float m2 = comp_pair_m2<float>(a, b, &k, &bound);
-  *redo = !(bound <= kFallbackUnits);
+  float k;
+  const float m2 = comp_pair_m2<float>(a, b, &k, redo);
   *kout = (double)k;
   return sqrt_budgeted(m2);
 }
