@@ -80,6 +80,9 @@ typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2 
  *   dy = (eta_a - eta_b) + (delta_a - delta_b),
  *   delta = y - eta = -asinh(M^2 sinh(eta) / (mT (pt cosh(eta) + E))).
  * Every term is >= 0, so light, nearly collinear pairs keep their digits.
+ * The azimuth difference is exact for azimuths in [-pi, pi] (the seam at
+ * +-pi is reduced with a two-part pi); other azimuths are accepted, but the
+ * rounding of their difference is not covered by the guarantee below.
  * In FP32 each item carries a running bound on the relative error of m^2;
  * an item whose bound exceeds 2^-18 is recomputed in FP64 from its widened
  * inputs and counted in *fallback_count.  In FP64 the same form is evaluated

@@ -125,6 +125,16 @@ __device__ __forceinline__ void sinhcosh_t(T x, T* sh, T* ch) {
     fast_sinhcosh(x, sh, ch);
 }
 
+// E = sqrt((pt cosh eta)^2 + M^2) from pc = pt cosh eta, with one explicit
+// fused multiply-add, so that every conversion forms it bitwise alike.
+template <typename T>
+__device__ __forceinline__ T energy_of(T pc, T m) {
+  if constexpr (sizeof(T) == 8)
+    return d_sqrt(fma(pc, pc, m * m));
+  else
+    return d_sqrt(fmaf(pc, pc, m * m));
+}
+
 // Cartesian (px, py, pz, E) of one vector given in COORDS.
 template <int COORDS, typename T, bool kPin = false>
 __device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
@@ -142,7 +152,7 @@ __device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
     v[2] = c0 * sh;
     if constexpr (COORDS == GLV_PTETAPHIM) {
       T pc = c0 * ch;
-      v[3] = d_sqrt(pc * pc + c3 * c3);
+      v[3] = energy_of(pc, c3);
     } else {
       v[3] = c3;
     }
@@ -173,7 +183,7 @@ __device__ __forceinline__ LegJ<T> to_cart_j(T c0, T c1, T c2, T c3) {
     L.v[2] = c0 * L.sh;
     if constexpr (COORDS == GLV_PTETAPHIM) {
       T pc = c0 * L.ch;
-      L.v[3] = d_sqrt(pc * pc + c3 * c3);
+      L.v[3] = energy_of(pc, c3);
     } else {
       L.v[3] = c3;
     }
@@ -358,6 +368,36 @@ struct LegC {
   T pt, eta, phi, m2, mt, delta;
 };
 
+// mT and delta of a leg from pt, M^2, sinh(eta), pt cosh(eta) and E.
+template <typename T, bool kCold = false>
+__device__ __forceinline__ void leg_shift(T pt, T mm, T sh, T pc, T e, T* mt, T* delta) {
+  *mt = sqrt_budgeted(pt * pt + mm);
+  const T den = *mt * (pc + e);
+  *delta = (den > T(0)) ? -small_asinh<kCold>(mm * sh / den) : T(0);
+}
+
+// Compensated leg terms together with the Cartesian vector of a
+// (pt, eta, phi, M) particle, sharing sinh, cosh and E with the conversion
+// (v is bitwise what to_cart gives).
+template <typename T>
+__device__ __forceinline__ LegC<T> comp_leg_cart(T pt, T eta, T phi, T mass, T v[4]) {
+  T sn, cs, sh, ch;
+  sincos_t<false>(phi, &sn, &cs);
+  sinhcosh_t<false>(eta, &sh, &ch);
+  const T pc = pt * ch;
+  v[0] = pt * cs;
+  v[1] = pt * sn;
+  v[2] = pt * sh;
+  v[3] = energy_of(pc, mass);
+  LegC<T> L;
+  L.pt = pt;
+  L.eta = eta;
+  L.phi = phi;
+  L.m2 = mass * mass;
+  leg_shift<T>(pt, L.m2, sh, pc, v[3], &L.mt, &L.delta);
+  return L;
+}
+
 // kCold: this evaluation is the rarely taken FP64 redo of an FP32 item.
 template <typename T, bool kCold = false>
 __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
@@ -367,7 +407,6 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   L.phi = phi;
   T mm = mass * mass;
   L.m2 = mm;
-  L.mt = sqrt_budgeted(pt * pt + mm);
   T sh, ch;
   if constexpr (sizeof(T) == 8)
     fast_sinhcosh<kCold>(eta, &sh, &ch);
@@ -375,8 +414,7 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
     fast_sinhcosh_rcp(eta, &sh, &ch);
   T pc = pt * ch;
   T e = sqrt_budgeted(pc * pc + mm);
-  T den = L.mt * (pc + e);
-  L.delta = (den > T(0)) ? -small_asinh<kCold>(mm * sh / den) : T(0);
+  leg_shift<T, kCold>(pt, mm, sh, pc, e, &L.mt, &L.delta);
   return L;
 }
 

@@ -268,13 +268,16 @@ template <typename T, int COORDS, int MODE>
 __device__ __forceinline__ void stage_particle(const Cols4<T>& p, int64_t gi, const Stage<T, MODE>& s,
                                                int slot) {
   T c0 = p.c[0][gi], c1 = p.c[1][gi], c2 = p.c[2][gi], c3 = p.c[3][gi];
-  T v[4];
-  to_cart<COORDS>(c0, c1, c2, c3, v);
-  s.cart[slot] = typename V4<T>::type{v[0], v[1], v[2], v[3]};
-  if constexpr (MODE == GLV_COMPENSATED) {
-    LegC<T> L = comp_leg<T>(c0, c1, c2, c3);
+  if constexpr (MODE == GLV_COMPENSATED) {  // (pt, eta, phi, M)
+    T v[4];
+    const LegC<T> L = comp_leg_cart<T>(c0, c1, c2, c3, v);
+    s.cart[slot] = typename V4<T>::type{v[0], v[1], v[2], v[3]};
     s.legA[slot] = typename V4<T>::type{c0, c1, c2, c3};
     s.legB[slot] = typename V2<T>::type{L.mt, L.delta};
+  } else {
+    T v[4];
+    to_cart<COORDS>(c0, c1, c2, c3, v);
+    s.cart[slot] = typename V4<T>::type{v[0], v[1], v[2], v[3]};
   }
 }
 
@@ -480,8 +483,9 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
       j += lo;
       T m;
       if constexpr (MODE == GLV_COMPENSATED) {
-        LegC<T> a = comp_leg<T>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i]);
-        LegC<T> b = comp_leg<T>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j]);
+        T va[4], vb[4];  // the conversions are not needed here
+        LegC<T> a = comp_leg_cart<T>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], va);
+        LegC<T> b = comp_leg_cart<T>(A.p.c[0][j], A.p.c[1][j], A.p.c[2][j], A.p.c[3][j], vb);
         double kd;
         m = comp_pair<T>(a, b, A.p.c[3][i], A.p.c[3][j], &kd, fb);
         ksum += kd;
@@ -579,11 +583,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       const int64_t q0 = (want_pairs || want_k) ? s_poff[ca] : 0;
       const int np = (int)(s_off[cb] - pbase);
       // chunk-relative offsets, so the pair loop works in 32-bit integers
-      for (int t = threadIdx.x; t <= nch; t += blockDim.x) {
+      for (int t = threadIdx.x; t <= nch; t += blockDim.x)
         ch[t] = EvRec{(int)(s_off[ca + t] - pbase), (want_pairs || want_k) ? (int)(s_poff[ca + t] - q0) : 0};
       if constexpr (kDefer) {
         for (int t = threadIdx.x; t < nch; t += blockDim.x) s_redo[t] = 0;
-      }
       }
       for (int t = threadIdx.x; t < np; t += blockDim.x) stage_particle<T, COORDS, MODE>(A.p, pbase + t, st, t);
       __syncthreads();

@@ -167,6 +167,27 @@ def test_compensated_seam_and_degenerate():
     assert m[3] == 0.0
 
 
+def test_compensated_azimuths_beyond_pi():
+    """Azimuths shifted by whole turns (|phi| up to 5 pi): the half azimuth
+    difference then leaves [-pi/2, pi/2] and the reduced sine takes over.
+    Pairs at least 0.3 rad apart in azimuth, where the FP32 rounding of the
+    shifted inputs' difference stays within the tolerance."""
+    g = synth.rng(713)
+    n = 4096
+    a, b = synth.pairs_generic(g, n)
+    ka, kb = g.integers(-2, 3, n), g.integers(-2, 3, n)
+    a = (a[0], a[1], a[2] + 2 * np.pi * ka, a[3])
+    b = (b[0], b[1], b[2] + 2 * np.pi * kb, b[3])
+    a, b = synth.as_dtype(a, np.float32), synth.as_dtype(b, np.float32)
+    d = np.angle(np.exp(1j * (a[2].astype(np.float64) - b[2].astype(np.float64))))
+    keep = np.abs(d) >= 0.3
+    assert np.count_nonzero(keep) > n // 2 and np.count_nonzero(np.abs(a[2] - b[2]) > np.pi) > n // 4
+    m = host(glv.glv_invariant_mass(gpu(a, torch.float32), gpu(b, torch.float32), mode="compensated"))
+    m_or = oracle.mass_accurate(widened(a, torch.float32), widened(b, torch.float32))
+    r, i = worst(np.abs(m[keep].astype(np.float64) - m_or[keep]), mass_tol_comp_f32(m_or[keep]))
+    assert r <= 1.0, (i, m[keep][i], m_or[keep][i])
+
+
 def test_compensated_full_size_sampled():
     n = 1 << 26
     a, b, mask = _stress(n, synth.STRESS)
