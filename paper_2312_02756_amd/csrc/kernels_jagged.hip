@@ -1083,19 +1083,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
           T S[4] = {0, 0, 0, 0}, C = 0;
           int qlo = rc.p + ai - 1, qhi = qrow;
           for (int bj = 0; bj < n; ++bj) {
-            // both LDS reads first, so that one wait covers them; at bj == ai
-            // qhi is at most nq (the slack slot) and the value is not used
+            // branch-free: at bj == ai the slot read (at most nq, the slack
+            // slot) is replaced by 0, which adds exact zeros
             const bool below = bj < ai;
-            const T cab = s_g[below ? qlo : qhi];
+            const T cs = s_g[below ? qlo : qhi];
             const R4 vj = cart[rc.o + bj];
-            if (bj == ai) continue;
+            const T cab = (bj == ai) ? T(0) : cs;
 #pragma unroll
             for (int k = 0; k < 4; ++k) S[k] += cab * vj[k];
             C += cab;
-            if (below)
-              qlo += n - bj - 2;
-            else
-              ++qhi;
+            qlo += below ? n - bj - 2 : 0;
+            qhi += bj > ai ? 1 : 0;
           }
           // sum of c_ab (v_a + v_b) = C v_a + S, with dm/dw = (-P, E) / |m|
 #pragma unroll
