@@ -365,12 +365,14 @@ __device__ __forceinline__ bool is_redo_mark(float x) { return __builtin_bit_cas
 
 // Cross-lane moves within a wavefront (GFX9 DPP controls): shift right by d
 // lanes within each row of 16 lanes, lane 15 of each row to the next row,
-// lane 31 to rows 2 and 3, and the whole wavefront left by one lane.  A lane
+// lane 31 to rows 2 and 3, and the whole wavefront left or right by one
+// lane.  A lane
 // whose source does not exist, or whose row is masked off, receives `old`.
 constexpr int kDppRowShr = 0x110;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
 constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_i32(int x, int old) {
@@ -678,53 +680,71 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
             }
           }
         } else {
-          for (int it = lo; it < hi; it += 64) {
-            const int k = it + lane;  // chunk-relative pair index
-            const bool valid = k < hi;
-            double kd = 0.0;
-            if (valid) {
+          // compensated: two consecutive pairs per lane and iteration,
+          // k0 = it + 2 lane and k1 = k0 + 1, usually of one event, so that
+          // the K scan runs once per 128 pairs.  A lane whose k1 opens another
+          // event holds a head (k0, the last pair of its event) and a tail
+          // (k1); tails are scanned by event, a head takes the previous
+          // lane's scanned tail when that lane's tail has its event.
+          auto pair_at = [&](int si, int sj, int e, double* kd) -> T {
+            T ma, mb;
+            const LegC<T> la = staged_leg<T, MODE>(st, si, &ma), lb = staged_leg<T, MODE>(st, sj, &mb);
+            if constexpr (kDefer) {
+              bool redo;
+              const T m = comp_pair_fp32(la, lb, kd, &redo);
+              if (redo) s_redo[e] = 1;
+              return m;
+            } else {
+              return comp_pair<T>(la, lb, ma, mb, kd, &fb);
+            }
+          };
+          for (int it = lo; it < hi; it += 128) {
+            const int k0 = it + 2 * lane, k1 = k0 + 1;
+            const bool v0 = k0 < hi, v1 = k1 < hi;
+            double kd0 = 0.0, kd1 = 0.0;
+            int ev0 = 0x7fffffff, ev1 = 0x7fffffff;  // past the slice: never an event
+            if (v0) {
               if (!located) {
-                ev = search_rec(ch, 0, nch, k);
+                ev = search_rec(ch, 0, nch, k0);
                 cur = ch[ev];
                 nxt = ch[ev + 1];
                 located = true;
               }
-              while (nxt.p <= k) {
+              while (nxt.p <= k0) {
                 cur = nxt;
                 nxt = ch[++ev + 1];
               }
-              const int base = cur.o;
               int i, j;
-              pair_of_rank(k - cur.p, nxt.o - base, colex, &i, &j);
-              const int si = base + i, sj = base + j;
-              T m;
-              if constexpr (MODE == GLV_COMPENSATED) {
-                T ma, mb;
-                LegC<T> a = staged_leg<T, MODE>(st, si, &ma), b = staged_leg<T, MODE>(st, sj, &mb);
-                if constexpr (kDefer) {
-                  bool redo;
-                  m = comp_pair_fp32(a, b, &kd, &redo);
-                  if (redo) s_redo[ev] = 1;
-                } else {
-                  m = comp_pair<T>(a, b, ma, mb, &kd, &fb);
+              pair_of_rank(k0 - cur.p, nxt.o - cur.o, colex, &i, &j);
+              ev0 = ev;
+              const T m0 = pair_at(cur.o + i, cur.o + j, ev, &kd0);
+              if (want_pairs) store_out(A.pair_m, q0 + k0, m0);
+              if (v1) {
+                if (nxt.p <= k1) {  // k0 closed its event: k1 is (0, 1) of the next with pairs
+                  do {
+                    cur = nxt;
+                    nxt = ch[++ev + 1];
+                  } while (nxt.p <= k1);
+                  i = 0;
+                  j = 1;
+                } else if (++j == nxt.o - cur.o) {  // lexicographic successor
+                  ++i;
+                  j = i + 1;
                 }
-              } else {
-                const typename V4<T>::type va = st.cart[si], vb = st.cart[sj];
-                T w[4];
-  #pragma unroll
-                for (int c = 0; c < 4; ++c) w[c] = va[c] + vb[c];
-                m = mass_of(w);
+                ev1 = ev;
+                const T m1 = pair_at(cur.o + i, cur.o + j, ev, &kd1);
+                if (want_pairs) store_out(A.pair_m, q0 + k1, m1);
               }
-              if (want_pairs) store_out(A.pair_m, q0 + k, m);
             }
-            if constexpr (MODE == GLV_COMPENSATED) {
-              if (want_k) {
-                // segmented inclusive scan of kd keyed by event (keys ascend with lane)
-                const int key = valid ? ev : 0x7fffffff;
-                kd = seg_scan_wave(kd, key);
-                const int knext = dpp_i32<kDppWaveShl1, 0xf>(key, -1);  // lane 63: -1
-                if (valid && knext != key) acc[wid * epb + ev] += kd;
-              }
+            if (want_k) {
+              const bool split = v1 && ev1 != ev0;
+              const int tkey = v1 ? ev1 : ev0;  // keys ascend with the lane
+              const double ts = seg_scan_wave(split ? kd1 : kd0 + kd1, tkey);
+              const double pts = dpp_f64<kDppWaveShr1, 0xf>(ts);        // lane 0: 0
+              const int pkey = dpp_i32<kDppWaveShr1, 0xf>(tkey, -1);     // lane 0: -1
+              const int nfirst = dpp_i32<kDppWaveShl1, 0xf>(ev0, -1);    // lane 63: -1
+              if (split) acc[wid * epb + ev0] += (pkey == ev0 ? pts : 0.0) + kd0;
+              if (v0 && nfirst != tkey) acc[wid * epb + tkey] += ts;
             }
           }
         }
