@@ -86,16 +86,16 @@ glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
   return t;
 }
 
-// The backward stages 8 columns per particle (vector and Jacobian pieces).
 // Backward: one staged particle per thread (the launch clamps lds_particles to
-// the workgroup size); 256 threads and 128 events per tile measured fastest on
-// collider-sized events.
+// the workgroup size); 128 threads and 64 events per tile measured fastest on
+// collider-sized events (2^20 Poisson(8) events in FP64, against 256 / 128 and
+// a sweep of 64 to 512 threads).
 glv::Tiling default_tiling_bwd(glv_dtype dt) {
   (void)dt;
   glv::Tiling t;
-  t.block = 256;
-  t.events_per_tile = 128;
-  t.lds_particles = 256;
+  t.block = 128;
+  t.events_per_tile = 64;
+  t.lds_particles = 128;
   return t;
 }
 

@@ -236,8 +236,10 @@ def test_event_reduce_bwd(coords, dtype):
 def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
     """Events of 40-50 particles against a tiling of 256 staged particles and
     1024 staged pair gradients: the pair cap, not the particle cap, ends the
-    chunks, and 50-particle events (1225 pairs) take the separate path.  Also
-    without pair upstreams (no pair offsets needed) and without any upstream."""
+    chunks, and 50-particle events (1225 pairs) take the separate path; with
+    128 staged particles (512 pair gradients) every event of 40 or more takes
+    it.  Also without pair upstreams (no pair offsets needed) and without any
+    upstream."""
     counts = np.array([40, 3, 50, 0, 45, 1, 2, 40, 41, 50, 7, 44] * 6, dtype=np.int64)
     off = np.zeros(counts.size + 1, dtype=np.int64)
     off[1:] = np.cumsum(counts)
@@ -267,7 +269,7 @@ def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
                                        None if c_gt is None else widened(c_gt, dtype),
                                        None if c_gem is None else widened([c_gem], dtype)[0],
                                        None if c_gpr is None else widened([c_gpr], dtype)[0])
-        for tiling in ((128, 16, 256), None):
+        for tiling in ((256, 128, 256), (128, 16, 256), None):
             got = glv.glv_event_reduce_bwd(
                 gpu(p, dtype), _off(off), grad_total=None if c_gt is None else gpu(c_gt, dtype),
                 grad_event_m=None if c_gem is None else gpu([c_gem], dtype)[0],
