@@ -13,16 +13,18 @@
 //     event mass of the plain mode);
 //   * the chunk's pairs -- contiguous in the output too -- are split into
 //     equal contiguous slices, one per wavefront; lanes take consecutive pair
-//     indices, locate their event (binary search once, then stepping forward
-//     over the staged per-event records), turn the in-event rank into (i, j)
-//     through a table of co-lexicographic pairs and store the pair mass
-//     (consecutive lanes write consecutive addresses);
+//     indices (two per lane and iteration: k and k + 64 in the plain mode,
+//     k and k + 1 in the compensated mode), locate their event (binary
+//     search once, then stepping forward over the staged per-event records),
+//     turn the in-event rank into (i, j) through a table of co-lexicographic
+//     pairs and store the pair mass (a wavefront's stores cover consecutive
+//     addresses);
 //   * in the compensated mode the event mass is
 //     m^2 = sum_i M_i^2 + 2 sum_{i<j} K_ij (all terms >= 0); each wavefront
-//     folds its lanes' K_ij by a segmented lane-move (DPP) scan keyed by event and
-//     adds the segment sums to a per-(wavefront, event) LDS slot, and the
-//     event lane adds the slots in wavefront order: the result depends on
-//     the tiling only, never on timing.
+//     folds its lanes' K_ij by a segmented lane-move (DPP) scan keyed by
+//     event and adds the segment sums to a per-(wavefront, event) LDS slot,
+//     and the event lane adds the slots in wavefront order: the result
+//     depends on the tiling only, never on timing.
 // An event with more particles than fit in LDS is left to a second, small
 // launch (k_event_reduce_big), where a whole workgroup takes it straight from
 // global memory (correct for any size, slower); on collider-sized events that
