@@ -700,9 +700,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
               return comp_pair<T>(la, lb, ma, mb, kd, &fb);
             }
           };
-          for (int it = lo; it < hi; it += 128) {
-            const int k0 = it + 2 * lane, k1 = k0 + 1;
-            const bool v0 = k0 < hi, v1 = k1 < hi;
+          // a lane's two masses go out as one store: the slots start where the
+          // global pair index q0 + k is even (lane 0 of the first iteration
+          // may then hold only the slice's first pair)
+          const int sh = (int)((q0 + lo) & 1);
+          for (int it = lo - sh; it < hi; it += 128) {
+            int k0 = it + 2 * lane;
+            bool v0 = k0 >= lo && k0 < hi, v1 = k0 + 1 < hi;
+            if (!v0 && v1) {
+              k0 += 1;
+              v0 = true;
+              v1 = false;
+            }
+            const int k1 = k0 + 1;
             double kd0 = 0.0, kd1 = 0.0;
             int ev0 = 0x7fffffff, ev1 = 0x7fffffff;  // past the slice: never an event
             if (v0) {
@@ -720,7 +730,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
               pair_of_rank(k0 - cur.p, nxt.o - cur.o, colex, &i, &j);
               ev0 = ev;
               const T m0 = pair_at(cur.o + i, cur.o + j, ev, &kd0);
-              if (want_pairs) store_out(A.pair_m, q0 + k0, m0);
+              T m1 = T(0);
               if (v1) {
                 if (nxt.p <= k1) {  // k0 closed its event: k1 is (0, 1) of the next with pairs
                   do {
@@ -734,8 +744,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
                   j = i + 1;
                 }
                 ev1 = ev;
-                const T m1 = pair_at(cur.o + i, cur.o + j, ev, &kd1);
-                if (want_pairs) store_out(A.pair_m, q0 + k1, m1);
+                m1 = pair_at(cur.o + i, cur.o + j, ev, &kd1);
+              }
+              if (want_pairs) {
+                T* out = A.pair_m + q0 + k0;
+                if (v1 && (reinterpret_cast<uintptr_t>(out) & (2 * sizeof(T) - 1)) == 0) {
+                  __builtin_nontemporal_store(typename V2<T>::type{m0, m1},
+                                              reinterpret_cast<typename V2<T>::type*>(out));
+                } else {
+                  __builtin_nontemporal_store(m0, out);
+                  if (v1) __builtin_nontemporal_store(m1, out + 1);
+                }
               }
             }
             if (want_k) {
