@@ -317,3 +317,32 @@ def test_event_reduce_compensated_fp64_redo():
         runs[(want_e, want_p)] = (host(em) if want_e else None, host(pm) if want_p else None)
     assert np.array_equal(runs[(True, True)][1], runs[(False, True)][1])
     assert np.array_equal(runs[(True, True)][0], runs[(True, False)][0])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_event_reduce_misaligned_pair_output(dtype):
+    """Pair masses written through the C-ABI to an address one element past an
+    aligned one (the compensated mode stores a lane's two masses at once where
+    the address allows): the same values as into an aligned buffer."""
+    from paper_2312_02756_amd import _lib
+    off, p = _events(3000, 717)
+    gp, go = gpu(p, dtype), _off(off)
+    po = glv.glv_pair_offsets(go)
+    npairs = int(po[-1].item())
+    lib = _lib.load()
+    stream = torch.cuda.current_stream().cuda_stream
+    dt = _lib.GLV_F32 if dtype == torch.float32 else _lib.GLV_F64
+    for mode in (_lib.GLV_PLAIN, _lib.GLV_COMPENSATED):
+        outs = []
+        for shift in (0, 1):
+            buf = torch.full((npairs + 2,), -1.0, dtype=dtype, device=DEV)
+            em = torch.empty(go.numel() - 1, dtype=dtype, device=DEV)
+            rc = lib.glv_event_reduce(dt, _lib.GLV_PTETAPHIM, mode, go.numel() - 1, go.data_ptr(), po.data_ptr(),
+                                      _lib.P4(*[c.data_ptr() for c in gp]), None, em.data_ptr(),
+                                      buf.data_ptr() + shift * buf.element_size(), None, None, stream)
+            assert rc == 0
+            b = host(buf)
+            assert np.all(b[:shift] == -1.0) and np.all(b[shift + npairs:] == -1.0), (mode, shift)
+            outs.append((b[shift:shift + npairs], host(em)))
+        assert np.array_equal(outs[0][0], outs[1][0]), mode
+        assert np.array_equal(outs[0][1], outs[1][1]), mode
