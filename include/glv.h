@@ -90,9 +90,12 @@ typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2 
 typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
 
 /* Work decomposition of glv_event_reduce / glv_event_reduce_bwd.  It changes
- * speed only: pair masses and totals are identical for every tiling; the
- * compensated event mass (a sum of per-pair terms) may differ in the last bit
- * between tilings but is reproducible for a given tiling.
+ * speed only: pair masses are identical for every tiling, and so are totals,
+ * plain event masses and gradients of every event that fits the tiling's LDS
+ * capacity; an event that does not fit goes to a separate launch, whose sums
+ * take another order (last-bit differences).  The compensated event mass (a
+ * sum of per-pair terms) may differ in the last bit between tilings but is
+ * reproducible for a given tiling.
  *   block            threads per workgroup: 64, 128, 256 or 512
  *   events_per_tile  events a workgroup takes at a time: 1 .. block
  *   lds_particles    particles staged in LDS at once: 64 .. 4096

@@ -601,7 +601,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       if (my < nch) {
         const int lo = ch[my].o, hi = ch[my + 1].o;
         T tot[4];
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (MODE == GLV_COMPENSATED) {
+          // totals and sum of M^2 in one pass, two particles per LDS wait
+          double d[4] = {0, 0, 0, 0};
+          int t = lo;
+          for (; t + 2 <= hi; t += 2) {
+            const typename V4<T>::type r0 = st.cart[t], r1 = st.cart[t + 1];
+            const double m0 = (double)st.legA[t][3], m1 = (double)st.legA[t + 1][3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] = (d[k] + (double)r0[k]) + (double)r1[k];
+            msum = (msum + m0 * m0) + m1 * m1;
+          }
+          if (t < hi) {
+            const typename V4<T>::type r0 = st.cart[t];
+            const double m0 = (double)st.legA[t][3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] += (double)r0[k];
+            msum += m0 * m0;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
+        } else if constexpr (sizeof(T) == 4) {
           double d[4] = {0, 0, 0, 0};
           sum_records(st.cart, lo, hi, d);
 #pragma unroll
@@ -610,12 +630,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
 #pragma unroll
           for (int k = 0; k < 4; ++k) tot[k] = T(0);
           sum_records(st.cart, lo, hi, tot);
-        }
-        if constexpr (MODE == GLV_COMPENSATED) {
-          for (int t = lo; t < hi; ++t) {
-            const double mt = (double)st.legA[t][3];
-            msum += mt * mt;
-          }
         }
         const int64_t e = e0 + ca + my;
         if (A.total[0]) {
