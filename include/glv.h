@@ -90,12 +90,15 @@ typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2 
 typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
 
 /* Work decomposition of glv_event_reduce / glv_event_reduce_bwd.  It changes
- * speed only: pair masses are identical for every tiling, and so are totals,
- * plain event masses and gradients of every event that fits the tiling's LDS
- * capacity; an event that does not fit goes to a separate launch, whose sums
- * take another order (last-bit differences).  The compensated event mass (a
- * sum of per-pair terms) may differ in the last bit between tilings but is
- * reproducible for a given tiling.
+ * speed only: pair masses, totals, event masses and gradients of every event
+ * that fits the tiling's LDS capacity are identical for every such tiling,
+ * except the compensated event mass (a sum of per-pair terms), which may
+ * differ in the last bit between tilings but is reproducible for a given
+ * tiling.  An event that does not fit goes to a separate launch: its plain
+ * pair masses are the same, its sums take another order, and a compensated
+ * pair mass may differ in the last bit (that launch fuses the arithmetic
+ * differently, which can also move a pair across the FP64-redo threshold);
+ * all stay within the stated accuracy. */
  *   block            threads per workgroup: 64, 128, 256 or 512
  *   events_per_tile  events a workgroup takes at a time: 1 .. block
  *   lds_particles    particles staged in LDS at once: 64 .. 4096

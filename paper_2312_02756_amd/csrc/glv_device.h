@@ -368,10 +368,14 @@ struct LegC {
   T pt, eta, phi, m2, mt, delta;
 };
 
-// mT and delta of a leg from pt, M^2, sinh(eta), pt cosh(eta) and E.
+// mT and delta of a leg from pt, M^2, sinh(eta), pt cosh(eta) and E (pt^2 + M^2
+// with one explicit fused multiply-add, so that every kernel forms mT alike).
 template <typename T, bool kCold = false>
 __device__ __forceinline__ void leg_shift(T pt, T mm, T sh, T pc, T e, T* mt, T* delta) {
-  *mt = sqrt_budgeted(pt * pt + mm);
+  if constexpr (sizeof(T) == 8)
+    *mt = sqrt_budgeted(fma(pt, pt, mm));
+  else
+    *mt = sqrt_budgeted(fmaf(pt, pt, mm));
   const T den = *mt * (pc + e);
   *delta = (den > T(0)) ? -small_asinh<kCold>(mm * sh / den) : T(0);
 }

@@ -346,3 +346,32 @@ def test_event_reduce_misaligned_pair_output(dtype):
             outs.append((b[shift:shift + npairs], host(em)))
         assert np.array_equal(outs[0][0], outs[1][0]), mode
         assert np.array_equal(outs[0][1], outs[1][1]), mode
+
+
+def test_large_event_pair_masses_match_across_paths():
+    """Events of 300 and 120 particles: under a 256-particle tiling the first
+    goes to the separate large-event launch, under a 1024-particle tiling both
+    are staged.  Plain FP64 pair masses are bitwise identical either way; in
+    the compensated FP32 mode the separate launch fuses the arithmetic
+    differently, so a few pair masses of the large event may differ (within
+    2^-18 relative, the FP64-redo threshold) and none of the staged event's.
+    Both runs are checked against the oracle."""
+    counts = np.array([3, 300, 5, 0, 120, 2, 1, 9], dtype=np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    p, _ = synth.pairs_generic(synth.rng(719), int(off[-1]))
+    go = _off(off)
+    for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
+        gp = gpu(p, dtype)
+        runs = [glv.glv_event_reduce(gp, go, mode=mode, tiling=t) for t in ((256, 64, 256), (512, 64, 1024))]
+        a, b = host(runs[0][2]).astype(np.float64), host(runs[1][2]).astype(np.float64)
+        if mode == "plain":
+            assert np.array_equal(a, b)
+        else:
+            po = oracle.pair_offsets(off)
+            diff = np.nonzero(a != b)[0]
+            assert diff.size <= a.size // 1000, diff.size
+            assert np.all((diff >= po[1]) & (diff < po[2])), "only the 300-particle event"
+            assert np.all(np.abs(a[diff] - b[diff]) <= 2.0 ** -18 * np.abs(b[diff]))
+        _check_forward(off, p, dtype, "PtEtaPhiM", mode, *runs[0], "large via separate launch")
+        _check_forward(off, p, dtype, "PtEtaPhiM", mode, *runs[1], "large staged")
