@@ -98,7 +98,7 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  * pair masses are the same, its sums take another order, and a compensated
  * pair mass may differ in the last bit (that launch fuses the arithmetic
  * differently, which can also move a pair across the FP64-redo threshold);
- * all stay within the stated accuracy. */
+ * all stay within the stated accuracy.
  *   block            threads per workgroup: 64, 128, 256 or 512
  *   events_per_tile  events a workgroup takes at a time: 1 .. block
  *   lds_particles    particles staged in LDS at once: 64 .. 4096

@@ -127,3 +127,20 @@ def test_current_tiling_default(lib):
     assert t.block in (64, 128, 256, 512) and 1 <= t.events_per_tile <= t.block
     assert 64 <= t.lds_particles <= 4096
     assert lib.glv_current_tiling(2, 0, 1, ctypes.byref(t)) == MODE
+
+
+@pytest.mark.parametrize("lang", ["c", "c++"])
+def test_header_compiles_standalone(lang, tmp_path):
+    """include/glv.h is a plain C header: it compiles on its own as C and as
+    C++ with warnings as errors (no torch or HIP types needed)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc" if lang == "c" else "g++")
+    if gcc is None:
+        pytest.skip("no host compiler")
+    header = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "glv.h")
+    src = tmp_path / ("use." + ("c" if lang == "c" else "cpp"))
+    src.write_text('#include "glv.h"\nint probe(void) { return (int)GLV_OK + (int)sizeof(glv_tiling); }\n')
+    r = subprocess.run([gcc, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", "-I", os.path.dirname(header),
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
