@@ -543,7 +543,13 @@ def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em
     oracle.event_reduce_vjp("PtEtaPhiM", off1, p1, tuple(c[:e1] for c in g_tot), g_em[:e1], g_pair[:nq1])
     dt1 = time.perf_counter() - t1
     oracle.set_threads(threads)
-    return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle",
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
+    return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle", "cpu": cpu,
             "sample": f"{reps} x one step's workload: 2^24 items through mass fwd+bwd, boost fwd+bwd and the "
                       f"accurate mass, 2^20 jagged events through the plain reduction and its VJP and the accurate "
                       f"reduction (binary64 oracle); {dt:.2f} s wall on {used} threads",
