@@ -111,8 +111,11 @@ def summarize_trace(trace_csv, bench_json):
     out = ["# Kernel trace: one benchmark step (2^24 items per element-wise kernel, 2^20 jagged events)", "",
            "Command (from the repository root `R` on one MI355X):", "", "```", TRACE_CMD, "```", "",
            f"Source: `bench_kernel_trace.csv`; per step kernel its last {bench['warmup']} warm-up + "
-           f"{bench['steps']} timed dispatches; jagged tiling {bench['config']['event_tiling']} (autotuned on "
-           "these events, its trial launches excluded).  Algorithmic bytes per launch as in `bench.py`.", "",
+           f"{bench['steps']} timed dispatches; jagged tilings (block, events per tile, LDS particles) "
+           f"{tuple(bench['config']['event_tiling'].values())} FP64, "
+           f"{tuple(bench['config'].get('event_tiling_fp32_comp', {}).values())} FP32 compensated, "
+           f"{tuple(bench['config'].get('event_tiling_bwd', {}).values())} backward (autotuned on "
+           "these events, the trial launches excluded).  Algorithmic bytes per launch as in `bench.py`.", "",
            "| kernel | calls | avg µs | min µs | share % | block, grid, LDS B | alg. bytes / launch | alg. GB/s (avg) "
            "| % of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|"]
     for tot, name, key, calls, avg, mn, extra, geo in sorted(rows, key=lambda r: -r[0]):
@@ -275,9 +278,11 @@ def main():
     GTOT = gpu(g_tot, torch.float64)
     GEM = gpu([g_em], torch.float64)[0]
     GPAIR = gpu([g_pair], torch.float64)[0]
-    # the jagged reductions run with the tilings the autotuner picks on these events
+    # the jagged reductions run with the tilings the autotuners pick on these events
     tiling = glv.glv_autotune_event_reduce(P, OFF, PO)
     tiling32c = glv.glv_autotune_event_reduce(P32, OFF, PO, mode="compensated")
+    tiling_bwd = glv.glv_autotune_event_reduce_bwd(P, OFF, PO, grad_total=GTOT, grad_event_m=GEM,
+                                                   grad_pair_m=GPAIR)
     # outputs preallocated once, reused every step
     M = torch.empty(N_ITEMS, dtype=torch.float64, device=dev)
     MC = torch.empty(N_ITEMS, dtype=torch.float32, device=dev)
@@ -416,6 +421,8 @@ def main():
             "event_tiling": {"block": tiling[0], "events_per_tile": tiling[1], "lds_particles": tiling[2]},
             "event_tiling_fp32_comp": {"block": tiling32c[0], "events_per_tile": tiling32c[1],
                                        "lds_particles": tiling32c[2]},
+            "event_tiling_bwd": {"block": tiling_bwd[0], "events_per_tile": tiling_bwd[1],
+                                 "lds_particles": tiling_bwd[2]},
             "parallelism": "single GPU", "input_gen_s": round(gen_s, 1),
         },
         "roofline": roofline,

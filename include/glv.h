@@ -18,7 +18,7 @@
  * ---------------------------------------
  * Memory.  Every data pointer is a DEVICE pointer owned by the caller.  The
  *   library never allocates, frees or copies between host and device, and
- *   never synchronises (except glv_autotune_event_reduce, which times kernels
+ *   never synchronises (except the glv_autotune_* calls, which time kernels
  *   and therefore waits for `stream`).  Each call validates its arguments on
  *   the host without reading device memory, enqueues its kernels on `stream`
  *   (a hipStream_t; NULL = the default stream) and returns.
@@ -103,8 +103,9 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  *   events_per_tile  events a workgroup takes at a time: 1 .. block
  *   lds_particles    particles staged in LDS at once: 64 .. 4096
  * Fields set to 0 take the library's current choice (the autotuned one if
- * glv_autotune_event_reduce ran for this device/dtype/coords/mode, otherwise a
- * built-in default).  A tiling whose workgroup would need more than 64 KiB of
+ * glv_autotune_event_reduce, or glv_autotune_event_reduce_bwd for the
+ * backward, ran for this device/dtype/coords/mode, otherwise a built-in
+ * default).  A tiling whose workgroup would need more than 64 KiB of
  * LDS is rejected with GLV_EINVAL_TILING: per staged particle the forward
  * keeps 4 values (10 in the compensated mode) and the backward 8 values (its
  * vector and up to four pair gradients) plus 2 bytes; per event of a tile
@@ -222,6 +223,22 @@ glv_status glv_autotune_event_reduce(glv_dtype dtype, glv_coords coords, glv_mod
 /* The tiling glv_event_reduce would use for these arguments (the autotuned
  * choice or the default), written to *out. */
 glv_status glv_current_tiling(glv_dtype dtype, glv_coords coords, glv_mode mode, glv_tiling* out);
+
+/* The same for glv_event_reduce_bwd: times its candidate tilings (64 to 512
+ * threads, 16 to 256 events per tile, one staged particle per thread) on the
+ * caller's data, with the arguments of glv_event_reduce_bwd (grad_p ends up
+ * holding a valid result), keeps the fastest as this process's backward
+ * choice for (current device, dtype, coords) and writes it to *best if not
+ * NULL.  Synchronises `stream`. */
+glv_status glv_autotune_event_reduce_bwd(glv_dtype dtype, glv_coords coords, int64_t n_events,
+                                         const int64_t* offsets, const int64_t* pair_offsets,
+                                         const void* const p[4], const void* const grad_total[4],
+                                         const void* grad_event_m, const void* grad_pair_m,
+                                         void* const grad_p[4], glv_tiling* best, void* stream);
+
+/* The tiling glv_event_reduce_bwd would use (the autotuned backward choice or
+ * the default), written to *out. */
+glv_status glv_current_tiling_bwd(glv_dtype dtype, glv_coords coords, glv_tiling* out);
 
 const char* glv_status_str(glv_status s);
 int glv_abi_version(void);

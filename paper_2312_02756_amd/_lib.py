@@ -26,7 +26,8 @@ GLV_PLAIN, GLV_COMPENSATED = 0, 1
 EXPORTS = (
     "glv_invariant_mass", "glv_invariant_mass_bwd", "glv_boost", "glv_boost_bwd", "glv_pair_offsets",
     "glv_event_reduce", "glv_event_reduce_bwd", "glv_validate_offsets", "glv_autotune_event_reduce",
-    "glv_current_tiling", "glv_status_str", "glv_abi_version", "glv_last_hip_error",
+    "glv_current_tiling", "glv_autotune_event_reduce_bwd", "glv_current_tiling_bwd", "glv_status_str",
+    "glv_abi_version", "glv_last_hip_error",
 )
 
 
@@ -53,6 +54,8 @@ _SIGS = {
     "glv_validate_offsets": [_i64, _vp, _i64, _vp, _vp],
     "glv_autotune_event_reduce": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_current_tiling": [_i, _i, _i, _vp],
+    "glv_autotune_event_reduce_bwd": [_i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "glv_current_tiling_bwd": [_i, _i, _vp],
     "glv_status_str": [_i],
     "glv_abi_version": [],
     "glv_last_hip_error": [],

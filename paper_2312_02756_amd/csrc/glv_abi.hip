@@ -73,7 +73,59 @@ struct TileKey {
   }
 };
 std::mutex g_tile_mu;
-std::map<TileKey, glv::Tiling> g_tiles;
+std::map<TileKey, glv::Tiling> g_tiles;  // autotuned choices
+constexpr int kBwdKey = -1;              // TileKey::mode of the backward's choice
+
+void remember_tiling(glv_dtype dt, glv_coords co, int mode_key, const glv::Tiling& t) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tiles[{dev, (int)dt, (int)co, mode_key}] = t;
+}
+
+void write_tiling(const glv::Tiling& t, glv_tiling* out) {
+  out->block = t.block;
+  out->events_per_tile = t.events_per_tile;
+  out->lds_particles = t.lds_particles;
+  out->reserved = 0;
+}
+
+// Times every candidate on `s` (one warm-up launch, then the best of three)
+// and sets *chosen to the fastest; `launch(t)` enqueues one launch.
+template <typename Launch>
+hipError_t pick_fastest(const std::vector<glv::Tiling>& cands, hipStream_t s, Launch launch, glv::Tiling* chosen) {
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return err;
+  }
+  float best_ms = 1e30f;
+  for (const glv::Tiling& t : cands) {
+    err = launch(t);
+    if (err != hipSuccess) break;
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+      err = hipEventRecord(e0, s);
+      if (err == hipSuccess) err = launch(t);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess) tmin = std::min(tmin, ms);
+    }
+    if (err != hipSuccess) break;
+    if (tmin < best_ms) {
+      best_ms = tmin;
+      *chosen = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return err;
+}
 
 glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
   glv::Tiling t;
@@ -107,11 +159,11 @@ bool block_ok(int b) { return (b == 64 || b == 128 || b == 256 || b == 512) && b
 glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,
                           glv::Tiling* out) {
   glv::Tiling base = bwd ? default_tiling_bwd(dt) : default_tiling(dt, mode);
-  if (!bwd) {
+  {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     std::lock_guard<std::mutex> lk(g_tile_mu);
-    auto it = g_tiles.find({dev, (int)dt, (int)co, (int)mode});
+    auto it = g_tiles.find({dev, (int)dt, (int)co, bwd ? kBwdKey : (int)mode});
     if (it != g_tiles.end()) base = it->second;
   }
   if (user) {
@@ -321,9 +373,9 @@ glv_status glv_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t 
       glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, fallback, t, (hipStream_t)stream));
 }
 
-glv_status glv_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off, const int64_t* poff,
-                                const void* const p[4], const void* const gt[4], const void* gem,
-                                const void* gpair, void* const gp[4], const glv_tiling* tiling, void* stream) {
+glv_status validate_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,
+                                     const int64_t* poff, const void* const p[4], const void* const gt[4],
+                                     const void* gem, const void* gpair, void* const gp[4]) {
   glv_status st = check_event_args(dt, co, GLV_PLAIN, ne, off, p);
   if (st != GLV_OK || ne == 0) return st;
   if (!nonnull<4>((const void* const*)gp)) return GLV_EINVAL_NULL;
@@ -335,6 +387,14 @@ glv_status glv_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const i
     if (gp[k] == gpair || gp[k] == gem || (gt && gp[k] == gt[0])) return GLV_EINVAL_ALIAS;
     if (overlap(rng(off, ne + 1, 8), rng(gp[k], 1, elem(dt)))) return GLV_EINVAL_ALIAS;
   }
+  return GLV_OK;
+}
+
+glv_status glv_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off, const int64_t* poff,
+                                const void* const p[4], const void* const gt[4], const void* gem,
+                                const void* gpair, void* const gp[4], const glv_tiling* tiling, void* stream) {
+  glv_status st = validate_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp);
+  if (st != GLV_OK || ne == 0) return st;
   glv::Tiling t;
   st = resolve_tiling(dt, co, GLV_PLAIN, tiling, true, &t);
   if (st != GLV_OK) return st;
@@ -352,10 +412,18 @@ glv_status glv_current_tiling(glv_dtype dt, glv_coords co, glv_mode mode, glv_ti
   glv::Tiling t;
   glv_status st = resolve_tiling(dt, co, mode, nullptr, false, &t);
   if (st != GLV_OK) return st;
-  out->block = t.block;
-  out->events_per_tile = t.events_per_tile;
-  out->lds_particles = t.lds_particles;
-  out->reserved = 0;
+  write_tiling(t, out);
+  return GLV_OK;
+}
+
+glv_status glv_current_tiling_bwd(glv_dtype dt, glv_coords co, glv_tiling* out) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  if (!out) return GLV_EINVAL_NULL;
+  glv::Tiling t;
+  glv_status st = resolve_tiling(dt, co, GLV_PLAIN, nullptr, true, &t);
+  if (st != GLV_OK) return st;
+  write_tiling(t, out);
   return GLV_OK;
 }
 
@@ -383,54 +451,51 @@ glv_status glv_autotune_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode,
       }
   glv::Tiling chosen = default_tiling(dt, mode);
   if (ne > 0 && (total || em || pm)) {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return hip_status(hipGetLastError());
-    if (hipEventCreate(&e1) != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      return hip_status(hipGetLastError());
-    }
-    float best_ms = 1e30f;
-    hipError_t err = hipSuccess;
-    for (const glv::Tiling& t : cands) {
-      // one warm-up, then the best of three
-      err = glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
-      if (err != hipSuccess) break;
-      float tmin = 1e30f;
-      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
-        err = hipEventRecord(e0, s);
-        if (err == hipSuccess) err = glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err == hipSuccess) tmin = std::min(tmin, ms);
-      }
-      if (err != hipSuccess) break;
-      if (tmin < best_ms) {
-        best_ms = tmin;
-        chosen = t;
-      }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (err != hipSuccess) return hip_status(err);
+    auto launch = [&](const glv::Tiling& t) {
+      return glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
+    };
+    hipError_t err = pick_fastest(cands, s, launch, &chosen);
     // leave the outputs holding the chosen tiling's result
-    err = glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, chosen, s);
+    if (err == hipSuccess) err = launch(chosen);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) return hip_status(err);
   }
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  {
-    std::lock_guard<std::mutex> lk(g_tile_mu);
-    g_tiles[{dev, (int)dt, (int)co, (int)mode}] = chosen;
+  remember_tiling(dt, co, (int)mode, chosen);
+  if (best) write_tiling(chosen, best);
+  return GLV_OK;
+}
+
+glv_status glv_autotune_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,
+                                         const int64_t* poff, const void* const p[4], const void* const gt[4],
+                                         const void* gem, const void* gpair, void* const gp[4], glv_tiling* best,
+                                         void* stream) {
+  glv_status st = validate_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp);
+  if (st != GLV_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // candidates: workgroup size x events per tile; the backward stages one
+  // particle per thread, so the LDS capacity is the workgroup size
+  std::vector<glv::Tiling> cands;
+  const int blocks[] = {64, 128, 256, 512};
+  const int epbs[] = {16, 32, 64, 128, 256};
+  for (int b : blocks)
+    for (int e : epbs) {
+      if (e > b) continue;
+      glv::Tiling t{b, e, b};
+      if (glv::event_reduce_bwd_lds_bytes(dt, t) > kMaxLds) continue;
+      cands.push_back(t);
+    }
+  glv::Tiling chosen = default_tiling_bwd(dt);
+  if (ne > 0) {
+    auto launch = [&](const glv::Tiling& t) {
+      return glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t, s);
+    };
+    hipError_t err = pick_fastest(cands, s, launch, &chosen);
+    if (err == hipSuccess) err = launch(chosen);  // gp holds the chosen tiling's result
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return hip_status(err);
   }
-  if (best) {
-    best->block = chosen.block;
-    best->events_per_tile = chosen.events_per_tile;
-    best->lds_particles = chosen.lds_particles;
-    best->reserved = 0;
-  }
+  remember_tiling(dt, co, kBwdKey, chosen);
+  if (best) write_tiling(chosen, best);
   return GLV_OK;
 }
 

@@ -263,5 +263,38 @@ def glv_current_tiling(dtype=torch.float64, coords="PtEtaPhiM", mode="plain"):
     return (t.block, t.events_per_tile, t.lds_particles)
 
 
+def glv_autotune_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None, grad_event_m=None,
+                                  grad_pair_m=None, coords="PtEtaPhiM"):
+    """Times the backward's candidate tilings on these inputs and upstreams,
+    keeps the fastest for this process (device, dtype, coords) and returns
+    it as (block, events_per_tile, lds_particles)."""
+    dev, dt = p[0].device, p[0].dtype
+    _check_device(p[0])
+    offsets = _offsets(offsets, dev)
+    ne = offsets.numel() - 1
+    n = p[0].numel()
+    p = _cols(p, n, dt, dev, "p")
+    if grad_pair_m is not None and pair_offsets is None:
+        pair_offsets = glv_pair_offsets(offsets)
+    gt = _cols(grad_total, ne, dt, dev, "grad_total") if grad_total is not None else None
+    gem = _cols([grad_event_m], ne, dt, dev, "grad_event_m")[0] if grad_event_m is not None else None
+    gpm = _cols([grad_pair_m], None, dt, dev, "grad_pair_m")[0] if grad_pair_m is not None else None
+    gp = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    best = glv_tiling()
+    check("glv_autotune_event_reduce_bwd",
+          _lib.load().glv_autotune_event_reduce_bwd(
+              _dtype_code(dt), _coords_code(coords), ne, _ptr(offsets), _ptr(pair_offsets),
+              P4(*[t.data_ptr() for t in p]), P4(*[t.data_ptr() for t in gt]) if gt else None, _ptr(gem),
+              _ptr(gpm), P4(*[t.data_ptr() for t in gp]), ctypes.byref(best), _stream(dev)))
+    return (best.block, best.events_per_tile, best.lds_particles)
+
+
+def glv_current_tiling_bwd(dtype=torch.float64, coords="PtEtaPhiM"):
+    t = glv_tiling()
+    check("glv_current_tiling_bwd", _lib.load().glv_current_tiling_bwd(_dtype_code(dtype), _coords_code(coords),
+                                                                       ctypes.byref(t)))
+    return (t.block, t.events_per_tile, t.lds_particles)
+
+
 def glv_abi_version():
     return _lib.load().glv_abi_version()

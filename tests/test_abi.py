@@ -129,6 +129,19 @@ def test_current_tiling_default(lib):
     assert lib.glv_current_tiling(2, 0, 1, ctypes.byref(t)) == MODE
 
 
+def test_current_tiling_bwd_default_and_autotune_validation(lib):
+    t = _lib.glv_tiling()
+    assert lib.glv_current_tiling_bwd(2, 1, ctypes.byref(t)) == OK
+    assert (t.block, t.events_per_tile, t.lds_particles) == (128, 64, 128)
+    assert lib.glv_current_tiling_bwd(3, 1, ctypes.byref(t)) == DTYPE
+    assert lib.glv_current_tiling_bwd(2, 1, None) == NULL
+    # host-side validation, before any device work: missing gradient outputs
+    P4 = _lib.P4
+    cols = P4(*[0x1000 * (k + 1) for k in range(4)])
+    assert lib.glv_autotune_event_reduce_bwd(2, 1, 10, 0x100, None, cols, None, None, None, None, None,
+                                             None) == NULL
+
+
 @pytest.mark.parametrize("lang", ["c", "c++"])
 def test_header_compiles_standalone(lang, tmp_path):
     """include/glv.h is a plain C header: it compiles on its own as C and as

@@ -375,3 +375,23 @@ def test_large_event_pair_masses_match_across_paths():
             assert np.all(np.abs(a[diff] - b[diff]) <= 2.0 ** -18 * np.abs(b[diff]))
         _check_forward(off, p, dtype, "PtEtaPhiM", mode, *runs[0], "large via separate launch")
         _check_forward(off, p, dtype, "PtEtaPhiM", mode, *runs[1], "large staged")
+
+
+def test_autotune_bwd_picks_a_valid_tiling():
+    """The backward's autotuner returns one of its candidates, makes it the
+    current backward tiling, and a launch with the default (now the tuned
+    one) equals a launch with that tiling given explicitly."""
+    off, p = _events(1 << 16, 721)
+    gp, go = gpu(p, torch.float64), _off(off)
+    g = synth.rng(722)
+    ne = off.size - 1
+    po = oracle.pair_offsets(off)
+    gt = gpu(synth.upstream(g, ne, 4), torch.float64)
+    gem = gpu([g.standard_normal(ne)], torch.float64)[0]
+    gpr = gpu([g.standard_normal(int(po[-1]))], torch.float64)[0]
+    best = glv.glv_autotune_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr)
+    assert best[0] in (64, 128, 256, 512) and 16 <= best[1] <= best[0] and best[2] == best[0], best
+    assert glv.glv_current_tiling_bwd(torch.float64, "PtEtaPhiM") == best
+    a = glv.glv_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr)
+    b = glv.glv_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr, tiling=best)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
