@@ -174,6 +174,33 @@ def test_event_reduce_full_size_sampled():
                        torch.from_numpy(pm[pair_idx]), f"full {mode}")
 
 
+def test_event_reduce_bwd_full_size_sampled():
+    """The reverse mode on 2^20 events with the benchmark's upstreams and launch
+    shape; the gradients of every particle of 5,000 sampled events checked
+    against the oracle's VJP of those events alone (an event's gradients
+    depend only on its own particles and upstreams)."""
+    off, p = _events(1 << 20, synth.JAGGED)
+    ne = off.size - 1
+    po_all = oracle.pair_offsets(off)
+    gj = synth.rng(synth.JAGGED_GRADS)
+    g_tot = synth.upstream(gj, ne, 4)
+    g_em = synth.upstream(gj, ne, 1)[0]
+    g_pair = synth.upstream(gj, int(po_all[-1]), 1)[0]
+    got = glv.glv_event_reduce_bwd(gpu(p, torch.float64), _off(off), grad_total=gpu(g_tot, torch.float64),
+                                   grad_event_m=gpu([g_em], torch.float64)[0],
+                                   grad_pair_m=gpu([g_pair], torch.float64)[0])
+    got = [host(c) for c in got]
+    sel = np.sort(np.random.default_rng(13).choice(ne, 5000, replace=False))
+    cnt = off[sel + 1] - off[sel]
+    soff = np.zeros(sel.size + 1, dtype=np.int64)
+    soff[1:] = np.cumsum(cnt)
+    pidx = np.concatenate([np.arange(off[e], off[e + 1]) for e in sel])
+    qidx = np.concatenate([np.arange(po_all[e], po_all[e + 1]) for e in sel])
+    sp = tuple(c[pidx] for c in p)
+    want = oracle.event_reduce_vjp("PtEtaPhiM", soff, sp, tuple(t[sel] for t in g_tot), g_em[sel], g_pair[qidx])
+    _check_bwd(soff, sp, torch.float64, "PtEtaPhiM", [c[pidx] for c in got], want, "full size")
+
+
 def test_autotune_picks_a_valid_tiling():
     off, p = _events(1 << 16, 706)
     gp, go = gpu(p, torch.float64), _off(off)
@@ -186,6 +213,30 @@ def test_autotune_picks_a_valid_tiling():
 
 
 # ---------------------------------------------------------------- backward
+
+def _check_bwd(off, wp, dtype, coords, got, want, label):
+    """Per particle: the largest error over its 4 gradient components against
+    (base + 64 u kappa) times the largest oracle component, with kappa the
+    worst conditioning S/m^2 of its event's mass and pair masses times n."""
+    ne = off.size - 1
+    po = oracle.pair_offsets(off)
+    S_abs, _ = event_abs_scale(oracle.to_cartesian(coords, wp), off)
+    u = U64 if dtype == torch.float64 else U32
+    base = 1e-12 if dtype == torch.float64 else 1e-5
+    cnt = np.diff(off)
+    ev = np.repeat(np.arange(ne), cnt)
+    _, em_or, pm_or, _ = oracle.event_reduce(coords, off, wp)
+    kappa_ev = S_abs / np.maximum(em_or ** 2, 1e-300)
+    _, s_pairs = _pairs_or(off, wp, coords)
+    kp = s_pairs / np.maximum(pm_or ** 2, 1e-300)
+    kappa_pair_ev = np.zeros(ne)
+    np.maximum.at(kappa_pair_ev, np.repeat(np.arange(ne), np.diff(po)), kp)
+    kappa = np.maximum(kappa_ev, kappa_pair_ev)[ev] * np.maximum(cnt[ev], 1)
+    err = np.max(np.abs(np.stack(got) - np.stack(want)), axis=0)
+    ref = np.max(np.abs(np.stack(want)), axis=0)
+    r, i = worst(err, (base + 64 * u * kappa) * ref + 1e-300)
+    assert r <= 1.0, (label, i, [c[i] for c in got], [c[i] for c in want])
+
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE"])
@@ -205,31 +256,11 @@ def test_event_reduce_bwd(coords, dtype):
     wp = widened(p, dtype)
     want = oracle.event_reduce_vjp(coords, off, wp, widened(gt, dtype), widened([gem], dtype)[0],
                                    widened([gpr], dtype)[0])
-    # scale: the same vjp with absolute upstreams and conditioning of the masses
-    S_abs, _ = event_abs_scale(oracle.to_cartesian(coords, wp), off)
-    u = U64 if dtype == torch.float64 else U32
-    base = 1e-12 if dtype == torch.float64 else 1e-5
     for tiling in (None, (128, 16, 128)):
         got = glv.glv_event_reduce_bwd(gpu(p, dtype), _off(off), grad_total=gpu(gt, dtype),
                                        grad_event_m=gpu([gem], dtype)[0], grad_pair_m=gpu([gpr], dtype)[0],
                                        coords=coords, tiling=tiling)
-        got = [host(c).astype(np.float64) for c in got]
-        # per particle: infinity norm over its 4 components, conditioning of its event
-        cnt = np.diff(off)
-        ev = np.repeat(np.arange(ne), cnt)
-        em_or = oracle.event_reduce(coords, off, wp)[1]
-        kappa_ev = S_abs / np.maximum(em_or ** 2, 1e-300)
-        _, s_pairs = _pairs_or(off, wp, coords)
-        pm_or = oracle.event_reduce(coords, off, wp)[2]
-        kp = s_pairs / np.maximum(pm_or ** 2, 1e-300)
-        kappa_pair_ev = np.zeros(ne)
-        pev = np.repeat(np.arange(ne), np.diff(po))
-        np.maximum.at(kappa_pair_ev, pev, kp)
-        kappa = np.maximum(kappa_ev, kappa_pair_ev)[ev] * np.maximum(cnt[ev], 1)
-        err = np.max(np.abs(np.stack(got) - np.stack(want)), axis=0)
-        ref = np.max(np.abs(np.stack(want)), axis=0)
-        r, i = worst(err, (base + 64 * u * kappa) * ref + 1e-300)
-        assert r <= 1.0, (tiling, i, [c[i] for c in got], [c[i] for c in want])
+        _check_bwd(off, wp, dtype, coords, [host(c).astype(np.float64) for c in got], want, tiling)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
