@@ -146,6 +146,29 @@ def test_boost_bwd_against_oracle(dtype):
         assert r <= 1.0, ("gbeta", k, i)
 
 
+def test_boost_bwd_full_size_sampled():
+    """The boost's reverse mode on 2^24 items with the benchmark's upstreams
+    (the same draws, in the same order) and launch shape; 65,536 sampled items
+    against the oracle."""
+    n = 1 << 24
+    x, beta = synth.boost_items(synth.rng(synth.LARGE), n)
+    gr = synth.rng(synth.GRADS)
+    synth.upstream(gr, n, 1)  # the mass upstream is drawn first
+    gy = synth.upstream(gr, n, 4)
+    gx, gbeta = glv.glv_boost_bwd(gpu(x, torch.float64), gpu(beta, torch.float64), gpu(gy, torch.float64))
+    gx, gbeta = host(gx), host(gbeta)
+    idx = np.sort(np.random.default_rng(10).choice(n, 65536, replace=False))
+    xs, bs, gs = (tuple(c[idx] for c in cols) for cols in (x, beta, gy))
+    ox, ob = oracle.boost_vjp(xs, bs, gs)
+    sx, sb = _boost_vjp_scale(xs, bs, gs)
+    for k in range(4):
+        r, i = worst(np.abs(gx[k][idx] - ox[k]), 1e-12 * sx[k])
+        assert r <= 1.0, ("gx", k, i)
+    for k in range(3):
+        r, i = worst(np.abs(gbeta[k][idx] - ob[k]), 1e-12 * sb[k])
+        assert r <= 1.0, ("gbeta", k, i)
+
+
 def test_boost_bwd_broadcast_grad_x_only():
     n = 5000
     x, beta = synth.boost_items(synth.rng(621), n)
