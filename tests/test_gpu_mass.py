@@ -200,3 +200,26 @@ def test_compensated_full_size_sampled():
     assert r <= 1.0, (idx[i], m[idx][i], m_or[i])
     assert np.all(np.isfinite(m))
     assert int(fb.item()) < n // 100
+
+
+def test_golden_pair_masses():
+    """The fixed cases of tests/golden/pair_masses.txt (generic, Z-like,
+    collinear, identical, zero leg, azimuth seam, large |eta|, heavy and slow,
+    high pt, back to back) against their stored binary128 masses: plain FP64
+    within its bound, the FP64 cancellation-free mode within 64 u64, and
+    identical massless legs exactly 0 in that mode."""
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_fixtures.py")
+    spec = importlib.util.spec_from_file_location("make_fixtures", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    labels, a, b, m_q, _ = mod.load()
+    _, s = oracle.mass_plain("PtEtaPhiM", a, b, scale=True)
+    m = host(glv.glv_invariant_mass(gpu(a, torch.float64), gpu(b, torch.float64)))
+    r, i = worst(np.abs(m - m_q), mass_tol_f64(m_q, s))
+    assert r <= 1.0, (labels[i], m[i], m_q[i])
+    mc = host(glv.glv_invariant_mass(gpu(a, torch.float64), gpu(b, torch.float64), mode="compensated"))
+    keep = np.array([lab != "identical_massless" for lab in labels])
+    assert np.all(np.abs(mc - m_q)[keep] <= 64 * U64 * m_q[keep]), [(l, x, y) for l, x, y in zip(labels, mc, m_q)]
+    assert mc[labels.index("identical_massless")] == 0.0

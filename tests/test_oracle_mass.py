@@ -7,6 +7,7 @@ identity of binary floating point, or an invariant.  Paper: Sec. 2.1
 """
 
 import math
+import os
 
 import mpmath
 import numpy as np
@@ -220,3 +221,36 @@ def test_scale_is_sum_of_squares_of_the_sum():
     cb = oracle.to_cartesian("PtEtaPhiM", b)
     w = [u + v for u, v in zip(ca, cb)]
     assert np.allclose(s, sum(c * c for c in w), rtol=1e-14, atol=0)
+
+
+def _golden():
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_fixtures.py")
+    spec = importlib.util.spec_from_file_location("make_fixtures", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_golden_pair_masses_reproduce_and_closed_forms():
+    """tests/golden/pair_masses.txt is exactly what the oracle writes today, and
+    its closed-form cases hold: identical massless legs give 0 in the
+    cancellation-free form (and a value at the binary128 rounding scale,
+    sqrt(u128) E, by the definition), a zero leg gives the other leg's M,
+    equal back-to-back massless legs give 2E, identical massive legs 2M."""
+    g = _golden()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pair_masses.txt")
+    assert open(path).read() == g.render()
+    labels, a, b, m_q, m_acc = g.load(path)
+    at = {lab: i for i, lab in enumerate(labels)}
+    i = at["identical_massless"]
+    assert m_acc[i] == 0.0
+    assert m_q[i] <= 16 * 2.0 ** -56.5 * 2 * a[0][i] * math.cosh(a[1][i])
+    assert m_q[at["zero_leg"]] == b[3][at["zero_leg"]]
+    i = at["back_to_back_equal"]
+    assert m_q[i] == 2.0 * a[0][i]
+    i = at["identical_massive"]
+    assert abs(m_q[i] - 2.0 * a[3][i]) <= 4 * U64 * m_q[i]
+    # elsewhere the cancellation-free form agrees with binary128 within its bound
+    keep = np.array([lab != "identical_massless" for lab in labels])
+    assert np.all(np.abs(m_acc - m_q)[keep] <= mass_tol_acc_f64(m_q[keep]))
