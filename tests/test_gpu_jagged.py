@@ -426,3 +426,48 @@ def test_autotune_bwd_picks_a_valid_tiling():
     a = glv.glv_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr)
     b = glv.glv_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr, tiling=best)
     assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("seed", [731, 732, 733, 734, 735, 736])
+def test_random_layouts_and_tilings(seed):
+    """Seeded random event layouts (runs of empty and one-particle events,
+    Poisson(8) events, now and then 60 to 300 particles) under a random valid
+    tiling: the plain FP64 and compensated FP32 forward and the FP64 reverse
+    mode against the oracle.  Chunk edges, the pair cap and the separate
+    large-event launch all occur."""
+    g = np.random.default_rng(seed)
+    ne = int(g.integers(200, 3000))
+    kind = g.random(ne)
+    counts = np.where(kind < 0.15, g.integers(0, 2, ne),
+                      np.where(kind < 0.97, np.minimum(g.poisson(8, ne), 64), g.integers(60, 301, ne)))
+    counts = counts.astype(np.int64)
+    off = np.zeros(ne + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    p, _ = synth.pairs_generic(synth.rng(seed), int(off[-1]))
+    block = int(g.choice([64, 128, 256, 512]))
+    tiling = (block, int(g.integers(1, block + 1)), int(g.choice([64, 128, 256, 512, 1024])))
+    go = _off(off)
+    for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
+        try:
+            out = glv.glv_event_reduce(gpu(p, dtype), go, mode=mode, tiling=tiling)
+        except RuntimeError as e:  # a tiling beyond the LDS limit is refused, never run
+            assert "GLV_EINVAL_TILING" in str(e), e
+            continue
+        _check_forward(off, p, dtype, "PtEtaPhiM", mode, *out, f"seed {seed} {mode} {tiling}")
+    po = oracle.pair_offsets(off)
+    gt = synth.upstream(g, ne, 4)
+    gem = g.standard_normal(ne)
+    gpr = g.standard_normal(int(po[-1]))
+    want = oracle.event_reduce_vjp("PtEtaPhiM", off, p, gt, gem, gpr)
+    bt = (block, tiling[1], block)
+    try:
+        got = glv.glv_event_reduce_bwd(gpu(p, torch.float64), go, grad_total=gpu(gt, torch.float64),
+                                       grad_event_m=gpu([gem], torch.float64)[0],
+                                       grad_pair_m=gpu([gpr], torch.float64)[0], tiling=bt)
+    except RuntimeError as e:
+        assert "GLV_EINVAL_TILING" in str(e), e
+        bt = (block, min(tiling[1], 64), block)
+        got = glv.glv_event_reduce_bwd(gpu(p, torch.float64), go, grad_total=gpu(gt, torch.float64),
+                                       grad_event_m=gpu([gem], torch.float64)[0],
+                                       grad_pair_m=gpu([gpr], torch.float64)[0], tiling=bt)
+    _check_bwd(off, p, torch.float64, "PtEtaPhiM", [host(c) for c in got], want, f"seed {seed} bwd {bt}")
