@@ -59,6 +59,24 @@ def test_plain_ragged_sizes_and_misaligned(n, dtype):
     _check_plain("PtEtaPhiM", tuple(c[1:] for c in a), tuple(c[1:] for c in b), dtype, m1)
 
 
+@pytest.mark.parametrize("n", [1, 3, 5, 63, 65, 257, 4097])
+def test_compensated_ragged_sizes_and_misaligned(n):
+    """The FP32 compensated mass on ragged sizes (four pairs per lane plus a
+    tail) and on views one element in (one pair per lane), against the
+    accurate oracle of the widened inputs; the two runs agree bitwise."""
+    a, b, _ = synth.pairs_stress(synth.rng(540 + n), n + 1)
+    a, b = synth.as_dtype(a, np.float32), synth.as_dtype(b, np.float32)
+    ga, gb = gpu(a, torch.float32), gpu(b, torch.float32)
+    m = host(glv.glv_invariant_mass(tuple(t[:n] for t in ga), tuple(t[:n] for t in gb), mode="compensated"))
+    m1 = host(glv.glv_invariant_mass(tuple(t[1:] for t in ga), tuple(t[1:] for t in gb), mode="compensated"))
+    for got, sl in ((m, slice(0, n)), (m1, slice(1, n + 1))):
+        wa, wb = widened(tuple(c[sl] for c in a), torch.float32), widened(tuple(c[sl] for c in b), torch.float32)
+        m_or = oracle.mass_accurate(wa, wb)
+        r, i = worst(np.abs(got.astype(np.float64) - m_or), mass_tol_comp_f32(m_or))
+        assert r <= 1.0, (n, i, got[i], m_or[i])
+    assert np.array_equal(m[1:], m1[:-1])
+
+
 def test_back_to_back_is_exactly_2E_and_swap_is_bitwise():
     x, _ = synth.boost_items(synth.rng(501), 10000)
     a = gpu(x, torch.float64)
