@@ -990,14 +990,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
   T* s_g = reinterpret_cast<T*>(s_ut + epb);
   T* s_gm = s_g + qcap + 2;
   int64_t* s_off = reinterpret_cast<int64_t*>(s_gm + ((epb + 1) & ~1));
-  // event lanes: event t of a chunk belongs to thread (t % nw) * 64 + t / nw,
-  // spread over the workgroup's nw wavefronts (the block is a power of two
-  // >= 64 and a chunk has at most epb <= block events)
-  const int nw = (int)blockDim.x >> 6;
-  const int tev = (tid & 63) * nw + (tid >> 6);
   int64_t* s_poff = s_off + (epb + 1);
   EvRec* ch = reinterpret_cast<EvRec*>(s_poff + (epb + 1));
   unsigned short* ev_of = reinterpret_cast<unsigned short*>(ch + (epb + 1));
+  // event lanes: event t of a chunk belongs to thread (t % nw) * 64 + t / nw,
+  // spread over the workgroup's nw wavefronts (the block is a power of two
+  // >= 64 and a chunk has at most epb <= block events); tev is the inverse
+  const int nw = (int)blockDim.x >> 6;
+  const int tev = (tid & 63) * nw + (tid >> 6);
   const int64_t ntiles = (A.ne + epb - 1) / epb;
 
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
