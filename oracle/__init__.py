@@ -65,6 +65,28 @@ def to_cartesian(coords, cols):
     return tuple(out)
 
 
+def convert(src, dst, cols):
+    """Coordinates in system ``dst`` of vectors given in ``src`` (through the
+    Cartesian components; src == dst copies)."""
+    c = [_f64(x) for x in cols]
+    n = c[0].size
+    out = [np.empty(n) for _ in range(4)]
+    _load().orc_convert(ctypes.c_int(_coords(src)), ctypes.c_int(_coords(dst)), ctypes.c_int64(n), *map(_p, c),
+                        *map(_p, out))
+    return tuple(out)
+
+
+def convert_vjp(src, dst, cols, g):
+    """(d convert / d cols)^T g for upstream gradients ``g`` of the 4 outputs."""
+    c = [_f64(x) for x in cols]
+    gg = [_f64(x) for x in g]
+    n = c[0].size
+    out = [np.empty(n) for _ in range(4)]
+    _load().orc_convert_vjp(ctypes.c_int(_coords(src)), ctypes.c_int(_coords(dst)), ctypes.c_int64(n),
+                            *map(_p, c), *map(_p, gg), *map(_p, out))
+    return tuple(out)
+
+
 def mass_plain(coords, a, b, scale=False):
     """Pair mass by the definition (binary64); optionally S = E^2 + |P|^2."""
     a = [_f64(x) for x in a]

@@ -321,6 +321,52 @@ void orc_boost_scale(int64_t n, const double* x0, const double* x1, const double
   }
 }
 
+/* ---------------------------------------------- conversion, either way */
+
+/* Coordinates `coords` of a Cartesian 4-vector v = (px, py, pz, E), the
+ * inverse of `cart` (Sec. 2.1: any system of a 4D vector): pt = hypot(px, py),
+ * eta = asinh(pz / pt), phi = atan2(py, px), and M = the mass of v with the
+ * pair mass's sign convention (-sqrt(-q) for a spacelike v), or E itself.
+ * On the beam axis (pt = 0) eta is +-inf by the sign of pz, 0 when pz = 0. */
+static void coords_of(int coords, const double v[4], double c[4]) {
+  if (coords == ORC_PXPYPZE) {
+    for (int k = 0; k < 4; ++k) c[k] = v[k];
+    return;
+  }
+  double pt = hypot(v[0], v[1]);
+  c[0] = pt;
+  if (pt > 0.0)
+    c[1] = asinh(v[2] / pt);
+  else
+    c[1] = (v[2] > 0.0) ? INFINITY : ((v[2] < 0.0) ? -INFINITY : 0.0);
+  c[2] = atan2(v[1], v[0]);
+  c[3] = (coords == ORC_PTETAPHIM) ? mass_of(v) : v[3];
+}
+
+/* Conversion of n vectors from system `from` to system `to`: through the
+ * Cartesian components, except that from == to copies. */
+void orc_convert(int from, int to, int64_t n, const double* i0, const double* i1, const double* i2,
+                 const double* i3, double* o0, double* o1, double* o2, double* o3) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double c[4];
+    if (from == to) {
+      c[0] = i0[i];
+      c[1] = i1[i];
+      c[2] = i2[i];
+      c[3] = i3[i];
+    } else {
+      double v[4];
+      cart(from, i0[i], i1[i], i2[i], i3[i], v);
+      coords_of(to, v, c);
+    }
+    o0[i] = c[0];
+    o1[i] = c[1];
+    o2[i] = c[2];
+    o3[i] = c[3];
+  }
+}
+
 /* ------------------------------------------------------------- gradients */
 
 /* d m / d (Cartesian sum) = (-Px, -Py, -Pz, E) / |m|, zero where m = 0.
@@ -365,6 +411,63 @@ static void chain_coords(int coords, double c0, double c1, double c2, double c3,
     g[1] = u[2] * pt * ch;
     g[2] = -u[0] * py + u[1] * px;
     g[3] = u[3];
+  }
+}
+
+/* Cartesian gradient u = (d c / d v)^T gc of c = coords_of(coords, v):
+ *   d pt  = (px, py, 0, 0) / pt
+ *   d eta = (-pz px / (pt^2 p), -pz py / (pt^2 p), 1 / p, 0),  p = |(px, py, pz)|
+ *          (eta = asinh(pz / pt) and d asinh(x) = dx / sqrt(1 + x^2))
+ *   d phi = (-py, px, 0, 0) / pt^2
+ *   d M   = (-px, -py, -pz, E) / |M|   (zero where M = 0), or d E = (0, 0, 0, 1).
+ * On the beam axis (pt = 0) the pt, eta and phi rows are taken as zero. */
+static void dcoords_dcart(int coords, const double v[4], const double gc[4], double u[4]) {
+  if (coords == ORC_PXPYPZE) {
+    for (int k = 0; k < 4; ++k) u[k] = gc[k];
+    return;
+  }
+  for (int k = 0; k < 4; ++k) u[k] = 0.0;
+  double pt = hypot(v[0], v[1]);
+  if (pt > 0.0) {
+    double p = sqrt(pt * pt + v[2] * v[2]);
+    u[0] += gc[0] * v[0] / pt;
+    u[1] += gc[0] * v[1] / pt;
+    u[0] += gc[1] * (-v[2] * v[0] / (pt * pt * p));
+    u[1] += gc[1] * (-v[2] * v[1] / (pt * pt * p));
+    u[2] += gc[1] / p;
+    u[0] += gc[2] * (-v[1] / (pt * pt));
+    u[1] += gc[2] * (v[0] / (pt * pt));
+  }
+  if (coords == ORC_PTETAPHIM) {
+    double dm[4];
+    dmass_dcart(v, mass_of(v), dm);
+    for (int k = 0; k < 4; ++k) u[k] += gc[3] * dm[k];
+  } else {
+    u[3] += gc[3];
+  }
+}
+
+/* Reverse-mode derivative of orc_convert: g_in = (d out / d in)^T g_out, the
+ * Cartesian gradient of the target coordinates chained back through the
+ * source conversion; from == to passes g_out through. */
+void orc_convert_vjp(int from, int to, int64_t n, const double* i0, const double* i1, const double* i2,
+                     const double* i3, const double* g0, const double* g1, const double* g2, const double* g3,
+                     double* r0, double* r1, double* r2, double* r3) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double gc[4] = {g0[i], g1[i], g2[i], g3[i]}, g[4];
+    if (from == to) {
+      for (int k = 0; k < 4; ++k) g[k] = gc[k];
+    } else {
+      double v[4], u[4];
+      cart(from, i0[i], i1[i], i2[i], i3[i], v);
+      dcoords_dcart(to, v, gc, u);
+      chain_coords(from, i0[i], i1[i], i2[i], i3[i], u, g);
+    }
+    r0[i] = g[0];
+    r1[i] = g[1];
+    r2[i] = g[2];
+    r3[i] = g[3];
   }
 }
 
