@@ -164,6 +164,32 @@ glv_status glv_boost_bwd(glv_dtype dtype, int64_t n, const void* const x[4],
                          const void* const grad_y[4], void* const grad_x[4],
                          void* const grad_beta[3], void* stream);
 
+/* Coordinate conversion (Sec. 2.1: a 4D vector in any of its systems):
+ * out = the `to` coordinates of the vectors in[] given in `from`, through
+ * their Cartesian components (from == to copies):
+ *   to PxPyPzE    the conversions above;
+ *   to PtEtaPhiM  pt = hypot(px, py), eta = asinh(pz / pt), phi = atan2(py, px)
+ *                 in [-pi, pi], M = the mass of the vector with the pair mass's
+ *                 sign convention (-sqrt(-q) when spacelike);
+ *   to PtEtaPhiE  the same with E.
+ * On the beam axis (pt = 0) eta is +inf or -inf by the sign of pz, 0 when
+ * pz = 0.  in and out are 4 columns of n elements; out may be in itself
+ * (column for column), otherwise no output overlaps an input or another
+ * output (GLV_EINVAL_ALIAS).  Errors: GLV_EINVAL_DTYPE, _COORDS, _SIZE (n <
+ * 0), _NULL. */
+glv_status glv_convert(glv_dtype dtype, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                       void* const out[4], void* stream);
+
+/* Reverse mode of glv_convert: grad_in = (d out / d in)^T grad_out per item
+ * (the Cartesian gradient of the target coordinates, chained through the
+ * source conversion's Jacobian; from == to copies).  On the beam axis the pt,
+ * eta and phi rows of the inverse are taken as zero; the M row is zero where
+ * M = 0.  grad_in may be grad_out itself (column for column); otherwise no
+ * output overlaps an input or another output. */
+glv_status glv_convert_bwd(glv_dtype dtype, glv_coords from, glv_coords to, int64_t n,
+                           const void* const in[4], const void* const grad_out[4], void* const grad_in[4],
+                           void* stream);
+
 /* Pair offsets of CSR events: pair_offsets[0] = 0,
  * pair_offsets[e+1] = pair_offsets[e] + c_e (c_e - 1) / 2 with
  * c_e = offsets[e+1] - offsets[e].  Both arrays hold n_events + 1 int64. */

@@ -27,7 +27,7 @@ EXPORTS = (
     "glv_invariant_mass", "glv_invariant_mass_bwd", "glv_boost", "glv_boost_bwd", "glv_pair_offsets",
     "glv_event_reduce", "glv_event_reduce_bwd", "glv_validate_offsets", "glv_autotune_event_reduce",
     "glv_current_tiling", "glv_autotune_event_reduce_bwd", "glv_current_tiling_bwd", "glv_status_str",
-    "glv_abi_version", "glv_last_hip_error",
+    "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd",
 )
 
 
@@ -55,6 +55,8 @@ _SIGS = {
     "glv_autotune_event_reduce": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_current_tiling": [_i, _i, _i, _vp],
     "glv_autotune_event_reduce_bwd": [_i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "glv_convert": [_i, _i, _i, _i64, _vp, _vp, _vp],
+    "glv_convert_bwd": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp],
     "glv_current_tiling_bwd": [_i, _i, _vp],
     "glv_status_str": [_i],
     "glv_abi_version": [],

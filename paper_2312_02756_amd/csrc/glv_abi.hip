@@ -321,6 +321,46 @@ glv_status glv_boost(glv_dtype dt, int64_t n, const void* const x[4], const void
   return hip_status(glv::launch_boost(dt, n, x, beta, beta_stride, y, (hipStream_t)stream));
 }
 
+glv_status glv_convert(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                       void* const out[4], void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(from) || !coords_ok(to)) return GLV_EINVAL_COORDS;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<4>(in) || !nonnull<4>((const void* const*)out)) return GLV_EINVAL_NULL;
+  size_t es = elem(dt);
+  bool inplace = true;
+  for (int k = 0; k < 4; ++k) inplace = inplace && (out[k] == in[k]);
+  std::vector<Range> outs, ins;
+  for (int k = 0; k < 4; ++k) {
+    outs.push_back(rng(out[k], n, es));
+    if (!inplace) ins.push_back(rng(in[k], n, es));
+  }
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;  // in place: column for column, columns disjoint
+  return hip_status(glv::launch_convert(dt, from, to, n, in, out, (hipStream_t)stream));
+}
+
+glv_status glv_convert_bwd(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                           const void* const grad_out[4], void* const grad_in[4], void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(from) || !coords_ok(to)) return GLV_EINVAL_COORDS;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<4>(in) || !nonnull<4>(grad_out) || !nonnull<4>((const void* const*)grad_in))
+    return GLV_EINVAL_NULL;
+  size_t es = elem(dt);
+  bool inplace = true;  // grad_in over grad_out, column for column
+  for (int k = 0; k < 4; ++k) inplace = inplace && (grad_in[k] == grad_out[k]);
+  std::vector<Range> outs, ins;
+  for (int k = 0; k < 4; ++k) {
+    outs.push_back(rng(grad_in[k], n, es));
+    ins.push_back(rng(in[k], n, es));
+    if (!inplace) ins.push_back(rng(grad_out[k], n, es));
+  }
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  return hip_status(glv::launch_convert_bwd(dt, from, to, n, in, grad_out, grad_in, (hipStream_t)stream));
+}
+
 glv_status glv_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4], const void* const beta[3],
                          int64_t beta_stride, const void* const gy[4], void* const gx[4], void* const gbeta[3],
                          void* stream) {

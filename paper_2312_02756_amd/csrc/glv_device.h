@@ -274,6 +274,71 @@ __device__ __forceinline__ void dmass(const T w[4], T g, T u[4]) {
   u[3] = w[3] * s;
 }
 
+// ------------------------------------------------- conversion, either way
+
+__device__ __forceinline__ double hypot_t(double x, double y) { return ::hypot(x, y); }
+__device__ __forceinline__ float hypot_t(float x, float y) { return ::hypotf(x, y); }
+__device__ __forceinline__ double atan2_t(double y, double x) { return ::atan2(y, x); }
+__device__ __forceinline__ float atan2_t(float y, float x) { return ::atan2f(y, x); }
+__device__ __forceinline__ double asinh_t(double x) { return fast_asinh<false>(x); }
+__device__ __forceinline__ float asinh_t(float x) { return ::asinhf(x); }
+
+// Coordinates TO of a Cartesian vector v = (px, py, pz, E), the inverse of
+// to_cart (Sec. 2.1: a 4D vector in any of its systems): pt = hypot(px, py),
+// eta = asinh(pz / pt), phi = atan2(py, px), and M = mass_of(v) (the pair
+// mass's sign convention) or E.  On the beam axis (pt = 0) eta is +-inf by
+// the sign of pz, 0 for pz = 0.
+template <int TO, typename T>
+__device__ __forceinline__ void from_cart(const T v[4], T c[4]) {
+  if constexpr (TO == GLV_PXPYPZE) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = v[k];
+  } else {
+    const T pt = hypot_t(v[0], v[1]);
+    c[0] = pt;
+    const T inf = __builtin_huge_val();
+    c[1] = (pt > T(0)) ? asinh_t(v[2] / pt) : ((v[2] > T(0)) ? inf : ((v[2] < T(0)) ? -inf : T(0)));
+    c[2] = atan2_t(v[1], v[0]);
+    if constexpr (TO == GLV_PTETAPHIM)
+      c[3] = mass_of(v);
+    else
+      c[3] = v[3];
+  }
+}
+
+// u = (d c / d v)^T gc for c = from_cart<TO>(v): d pt = (px, py, 0, 0)/pt,
+// d eta = (-pz px, -pz py, pt^2, 0)/(pt^2 p) with p = |(px, py, pz)|,
+// d phi = (-py, px, 0, 0)/pt^2, d M = (-P, E)/|M| (zero where M = 0) or
+// d E = (0, 0, 0, 1); on the beam axis the pt, eta and phi rows are zero.
+template <int TO, typename T>
+__device__ __forceinline__ void dcoords_dcart(const T v[4], const T gc[4], T u[4]) {
+  if constexpr (TO == GLV_PXPYPZE) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = gc[k];
+  } else {
+    const T pt = hypot_t(v[0], v[1]);
+    const T p = d_sqrt(pt * pt + v[2] * v[2]);
+    const bool off_axis = pt > T(0);
+    const T ipt = off_axis ? T(1) / pt : T(0);
+    const T ip = off_axis ? T(1) / p : T(0);
+    const T ipt2 = ipt * ipt;
+    const T a = gc[0] * ipt - gc[1] * v[2] * ipt2 * ip;  // common factor of px and py (pt and eta rows)
+    const T b = gc[2] * ipt2;                               // phi row
+    u[0] = a * v[0] - b * v[1];
+    u[1] = a * v[1] + b * v[0];
+    u[2] = gc[1] * ip;
+    if constexpr (TO == GLV_PTETAPHIM) {
+      const T s = pair_coef(v, gc[3]);  // gc[3] / |M|
+      u[0] -= s * v[0];
+      u[1] -= s * v[1];
+      u[2] -= s * v[2];
+      u[3] = s * v[3];
+    } else {
+      u[3] = gc[3];
+    }
+  }
+}
+
 // ------------------------------------------------- cancellation-free mass
 
 // sinh alone (small arguments by the odd polynomial, else from one exp).

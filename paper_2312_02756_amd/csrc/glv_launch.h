@@ -25,6 +25,12 @@ hipError_t launch_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4],
                             const void* const gy[4], void* const gx[4], void* const gbeta[3],
                             hipStream_t s);
 
+hipError_t launch_convert(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                          void* const out[4], hipStream_t s);
+
+hipError_t launch_convert_bwd(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                              const void* const gout[4], void* const gin[4], hipStream_t s);
+
 hipError_t launch_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* pair_offsets,
                                hipStream_t s);
 

@@ -180,6 +180,78 @@ struct MassBwd {
   }
 };
 
+// ------------------------------------------------------------ conversion
+
+// Coordinates TO of vectors given in FROM (through the Cartesian components;
+// FROM == TO copies).
+template <typename T, int FROM, int TO>
+struct Convert {
+  static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
+  Cols4<T> in;
+  OutCols4<T> out;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pc[4], po[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pc[k] = load_pack<T, V>(in.c[k], i);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      if constexpr (FROM == TO) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) po[k].v[e] = pc[k].v[e];
+      } else {
+        T v[4], c[4];
+        to_cart<FROM>(pc[0].v[e], pc[1].v[e], pc[2].v[e], pc[3].v[e], v);
+        from_cart<TO, T>(v, c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) po[k].v[e] = c[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_pack<T, V>(out.c[k], i, po[k]);
+    return 0;
+  }
+};
+
+// Reverse mode: the Cartesian gradient of the target coordinates, chained
+// back through the source conversion's Jacobian; FROM == TO passes through.
+template <typename T, int FROM, int TO>
+struct ConvertBwd {
+  static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
+  Cols4<T> in, gout;
+  OutCols4<T> gin;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pc[4], pg[4], po[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pg[k] = load_pack<T, V>(gout.c[k], i);
+      if constexpr (FROM != TO) pc[k] = load_pack<T, V>(in.c[k], i);
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      if constexpr (FROM == TO) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) po[k].v[e] = pg[k].v[e];
+      } else {
+        const LegJ<T> L = to_cart_j<FROM, T>(pc[0].v[e], pc[1].v[e], pc[2].v[e], pc[3].v[e]);
+        T gc[4], u[4], g[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gc[k] = pg[k].v[e];
+        dcoords_dcart<TO, T>(L.v, gc, u);
+        chain_coords<FROM, T>(L, pc[0].v[e], pc[3].v[e], u, g);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) po[k].v[e] = g[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_pack<T, V>(gin.c[k], i, po[k]);
+    return 0;
+  }
+};
+
 // ----------------------------------------------------------------- boost
 
 // gamma and kappa = gamma^2/(1 + gamma) from the velocity, formed in FP64
@@ -391,7 +463,76 @@ hipError_t boost_bwd_typed(int64_t n, const void* const x[4], const void* const 
                            nullptr, s);
 }
 
+template <typename T, int FROM>
+hipError_t convert_to(glv_coords to, int64_t n, const void* const in[4], void* const out[4], hipStream_t s) {
+  const bool al = all16<4>(in) && all16<4>((const void* const*)out);
+  const Cols4<T> ci = cols4<T>(in);
+  const OutCols4<T> co = out4<T>(out);
+  switch (to) {
+    case GLV_PXPYPZE:
+      return dispatch_width<T>(Convert<T, FROM, GLV_PXPYPZE>{ci, co}, al, n, nullptr, s);
+    case GLV_PTETAPHIM:
+      return dispatch_width<T>(Convert<T, FROM, GLV_PTETAPHIM>{ci, co}, al, n, nullptr, s);
+    default:
+      return dispatch_width<T>(Convert<T, FROM, GLV_PTETAPHIE>{ci, co}, al, n, nullptr, s);
+  }
+}
+
+template <typename T>
+hipError_t convert_typed(glv_coords from, glv_coords to, int64_t n, const void* const in[4], void* const out[4],
+                         hipStream_t s) {
+  switch (from) {
+    case GLV_PXPYPZE:
+      return convert_to<T, GLV_PXPYPZE>(to, n, in, out, s);
+    case GLV_PTETAPHIM:
+      return convert_to<T, GLV_PTETAPHIM>(to, n, in, out, s);
+    default:
+      return convert_to<T, GLV_PTETAPHIE>(to, n, in, out, s);
+  }
+}
+
+template <typename T, int FROM>
+hipError_t convert_bwd_to(glv_coords to, int64_t n, const void* const in[4], const void* const gout[4],
+                          void* const gin[4], hipStream_t s) {
+  const bool al = all16<4>(in) && all16<4>(gout) && all16<4>((const void* const*)gin);
+  const Cols4<T> ci = cols4<T>(in), cg = cols4<T>(gout);
+  const OutCols4<T> co = out4<T>(gin);
+  switch (to) {
+    case GLV_PXPYPZE:
+      return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PXPYPZE>{ci, cg, co}, al, n, nullptr, s);
+    case GLV_PTETAPHIM:
+      return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PTETAPHIM>{ci, cg, co}, al, n, nullptr, s);
+    default:
+      return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PTETAPHIE>{ci, cg, co}, al, n, nullptr, s);
+  }
+}
+
+template <typename T>
+hipError_t convert_bwd_typed(glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                             const void* const gout[4], void* const gin[4], hipStream_t s) {
+  switch (from) {
+    case GLV_PXPYPZE:
+      return convert_bwd_to<T, GLV_PXPYPZE>(to, n, in, gout, gin, s);
+    case GLV_PTETAPHIM:
+      return convert_bwd_to<T, GLV_PTETAPHIM>(to, n, in, gout, gin, s);
+    default:
+      return convert_bwd_to<T, GLV_PTETAPHIE>(to, n, in, gout, gin, s);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_convert(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                          void* const out[4], hipStream_t s) {
+  if (dt == GLV_F64) return convert_typed<double>(from, to, n, in, out, s);
+  return convert_typed<float>(from, to, n, in, out, s);
+}
+
+hipError_t launch_convert_bwd(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
+                              const void* const gout[4], void* const gin[4], hipStream_t s) {
+  if (dt == GLV_F64) return convert_bwd_typed<double>(from, to, n, in, gout, gin, s);
+  return convert_bwd_typed<float>(from, to, n, in, gout, gin, s);
+}
 
 hipError_t launch_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
                        const void* const b[4], void* m, unsigned long long* fb, hipStream_t s) {

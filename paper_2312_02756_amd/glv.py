@@ -145,6 +145,35 @@ def glv_boost_bwd(x, beta, grad_y, want_beta=True):
 
 # ------------------------------------------------------------ jagged events
 
+def glv_convert(cols, from_coords, to_coords, out=None):
+    """The ``to_coords`` coordinates of vectors given in ``from_coords`` (4
+    columns each).  ``out`` may be ``cols`` itself (in place)."""
+    dev, dt = cols[0].device, cols[0].dtype
+    _check_device(cols[0])
+    n = cols[0].numel()
+    cols = _cols(cols, n, dt, dev, "cols")
+    y = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4)) if out is None else _cols(out, n, dt, dev, "out")
+    check("glv_convert", _lib.load().glv_convert(_dtype_code(dt), _coords_code(from_coords), _coords_code(to_coords),
+                                                 n, P4(*[t.data_ptr() for t in cols]), P4(*[t.data_ptr() for t in y]),
+                                                 _stream(dev)))
+    return y
+
+
+def glv_convert_bwd(cols, grad_out, from_coords, to_coords):
+    """(d convert / d cols)^T grad_out, 4 columns."""
+    dev, dt = cols[0].device, cols[0].dtype
+    _check_device(cols[0])
+    n = cols[0].numel()
+    cols = _cols(cols, n, dt, dev, "cols")
+    grad_out = _cols(grad_out, n, dt, dev, "grad_out")
+    g = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    check("glv_convert_bwd",
+          _lib.load().glv_convert_bwd(_dtype_code(dt), _coords_code(from_coords), _coords_code(to_coords), n,
+                                      P4(*[t.data_ptr() for t in cols]), P4(*[t.data_ptr() for t in grad_out]),
+                                      P4(*[t.data_ptr() for t in g]), _stream(dev)))
+    return g
+
+
 def _offsets(offsets, dev):
     if offsets.dtype != torch.int64 or offsets.device != dev or not offsets.is_contiguous() or offsets.dim() != 1:
         raise ValueError("offsets must be a contiguous 1-D int64 tensor on the particles' device")

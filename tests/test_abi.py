@@ -96,6 +96,32 @@ def test_boost_validation(lib):
     assert g(2, 0, None, cols(BETA, 3), 0, cols(Y), cols(Y + 8 * GiB), None, None) == OK
 
 
+def test_convert_validation(lib):
+    f = lib.glv_convert
+    Y = 80 * GiB
+    assert f(7, 0, 1, N, cols(A), cols(Y), None) == DTYPE
+    assert f(2, 3, 1, N, cols(A), cols(Y), None) == COORDS
+    assert f(2, 0, -1, N, cols(A), cols(Y), None) == COORDS
+    assert f(2, 0, 1, -1, cols(A), cols(Y), None) == SIZE
+    bad = cols(Y)
+    bad[3] = None
+    assert f(2, 0, 1, N, cols(A), bad, None) == NULL
+    assert f(2, 0, 1, 0, None, None, None) == OK                                    # empty: nothing to do
+    y = cols(A)
+    y[0], y[1] = y[1], y[0]
+    assert f(1, 1, 0, N, cols(A), y, None) == ALIAS                                  # permuted in place
+    part = cols(Y)
+    part[2] = A + 2 * GiB
+    assert f(1, 1, 0, N, cols(A), part, None) == ALIAS                               # one column in place
+    assert f(2, 1, 0, N, cols(A), cols(A + 4 * (N - 1)), None) == ALIAS              # shifted overlap
+    g = lib.glv_convert_bwd
+    G = 64 * GiB
+    assert g(2, 1, 0, N, cols(A), cols(G), cols(A), None) == ALIAS                   # grad_in over the vectors
+    assert g(2, 1, 0, N, cols(A), cols(G), cols(G + 8), None) == ALIAS               # shifted over grad_out
+    assert g(2, 1, 0, N, cols(A), None, cols(Y), None) == NULL
+    assert g(2, 1, 9, N, cols(A), cols(G), cols(Y), None) == COORDS
+
+
 def test_jagged_validation(lib):
     OFF, PO, P, T, EM, PM = A, B, 100 * GiB, 140 * GiB, 180 * GiB, 190 * GiB
     f = lib.glv_event_reduce
