@@ -9,7 +9,7 @@ Thin ctypes wrapper around ``liborc.so`` (built from ``glv_oracle.c`` by
 float64 first (exactly), so every result is the exact-input result computed
 in binary64 (or binary128 for the ``*_q`` functions).
 
-Coordinate codes: 0 = PxPyPzE, 1 = PtEtaPhiM, 2 = PtEtaPhiE.
+Coordinate codes: 0 = PxPyPzE, 1 = PtEtaPhiM, 2 = PtEtaPhiE, 3 = PxPyPzM.
 """
 
 import ctypes
@@ -19,9 +19,9 @@ import numpy as np
 
 from . import build as _build
 
-PXPYPZE, PTETAPHIM, PTETAPHIE = 0, 1, 2
+PXPYPZE, PTETAPHIM, PTETAPHIE, PXPYPZM = 0, 1, 2, 3
 PLAIN, ACCURATE = 0, 1
-COORDS = {"PxPyPzE": PXPYPZE, "PtEtaPhiM": PTETAPHIM, "PtEtaPhiE": PTETAPHIE}
+COORDS = {"PxPyPzE": PXPYPZE, "PtEtaPhiM": PTETAPHIM, "PtEtaPhiE": PTETAPHIE, "PxPyPzM": PXPYPZM}
 
 _lib = None
 

@@ -44,7 +44,7 @@
 #include <omp.h>
 #endif
 
-enum { ORC_PXPYPZE = 0, ORC_PTETAPHIM = 1, ORC_PTETAPHIE = 2 };
+enum { ORC_PXPYPZE = 0, ORC_PTETAPHIM = 1, ORC_PTETAPHIE = 2, ORC_PXPYPZM = 3 };
 enum { ORC_PLAIN = 0, ORC_ACCURATE = 1 };
 
 typedef __float128 quad;
@@ -69,13 +69,14 @@ int orc_get_threads(void) {
 
 /* ------------------------------------------------------------- conversion */
 
-/* Cartesian (px, py, pz, E) of one vector given in `coords` (Sec. 2.1, 3.1). */
+/* Cartesian (px, py, pz, E) of one vector given in `coords` (Sec. 2.1, 3.1);
+ * PxPyPzM has E = sqrt(|p|^2 + M^2). */
 static void cart(int coords, double c0, double c1, double c2, double c3, double v[4]) {
-  if (coords == ORC_PXPYPZE) {
+  if (coords == ORC_PXPYPZE || coords == ORC_PXPYPZM) {
     v[0] = c0;
     v[1] = c1;
     v[2] = c2;
-    v[3] = c3;
+    v[3] = (coords == ORC_PXPYPZE) ? c3 : sqrt(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
     return;
   }
   double pt = c0, eta = c1, phi = c2;
@@ -91,11 +92,16 @@ static void cart(int coords, double c0, double c1, double c2, double c3, double 
 }
 
 static void cart_q(int coords, double c0, double c1, double c2, double c3, quad v[4]) {
-  if (coords == ORC_PXPYPZE) {
+  if (coords == ORC_PXPYPZE || coords == ORC_PXPYPZM) {
     v[0] = c0;
     v[1] = c1;
     v[2] = c2;
-    v[3] = c3;
+    if (coords == ORC_PXPYPZE) {
+      v[3] = c3;
+    } else {
+      quad x = c0, y = c1, z = c2, mm = c3;
+      v[3] = sqrtq(x * x + y * y + z * z + mm * mm);
+    }
     return;
   }
   quad pt = c0, eta = c1, phi = c2;
@@ -326,11 +332,13 @@ void orc_boost_scale(int64_t n, const double* x0, const double* x1, const double
 /* Coordinates `coords` of a Cartesian 4-vector v = (px, py, pz, E), the
  * inverse of `cart` (Sec. 2.1: any system of a 4D vector): pt = hypot(px, py),
  * eta = asinh(pz / pt), phi = atan2(py, px), and M = the mass of v with the
- * pair mass's sign convention (-sqrt(-q) for a spacelike v), or E itself.
+ * pair mass's sign convention (-sqrt(-q) for a spacelike v), or E itself;
+ * PxPyPzM keeps (px, py, pz) and takes that M.
  * On the beam axis (pt = 0) eta is +-inf by the sign of pz, 0 when pz = 0. */
 static void coords_of(int coords, const double v[4], double c[4]) {
-  if (coords == ORC_PXPYPZE) {
-    for (int k = 0; k < 4; ++k) c[k] = v[k];
+  if (coords == ORC_PXPYPZE || coords == ORC_PXPYPZM) {
+    for (int k = 0; k < 3; ++k) c[k] = v[k];
+    c[3] = (coords == ORC_PXPYPZE) ? v[3] : mass_of(v);
     return;
   }
   double pt = hypot(v[0], v[1]);
@@ -392,6 +400,16 @@ static void chain_coords(int coords, double c0, double c1, double c2, double c3,
     for (int k = 0; k < 4; ++k) g[k] = u[k];
     return;
   }
+  if (coords == ORC_PXPYPZM) {
+    /* E = sqrt(|p|^2 + M^2): dE/dp_k = p_k/E, dE/dM = M/E */
+    double e = sqrt(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
+    double ue = (e > 0.0) ? u[3] / e : 0.0;
+    g[0] = u[0] + ue * c0;
+    g[1] = u[1] + ue * c1;
+    g[2] = u[2] + ue * c2;
+    g[3] = ue * c3;
+    return;
+  }
   double pt = c0, eta = c1, phi = c2;
   double cp = cos(phi), sp = sin(phi), sh = sinh(eta), ch = cosh(eta);
   double px = pt * cp, py = pt * sp;
@@ -420,10 +438,17 @@ static void chain_coords(int coords, double c0, double c1, double c2, double c3,
  *          (eta = asinh(pz / pt) and d asinh(x) = dx / sqrt(1 + x^2))
  *   d phi = (-py, px, 0, 0) / pt^2
  *   d M   = (-px, -py, -pz, E) / |M|   (zero where M = 0), or d E = (0, 0, 0, 1).
- * On the beam axis (pt = 0) the pt, eta and phi rows are taken as zero. */
+ * On the beam axis (pt = 0) the pt, eta and phi rows are taken as zero.
+ * PxPyPzM: the identity rows of px, py, pz and the M row above. */
 static void dcoords_dcart(int coords, const double v[4], const double gc[4], double u[4]) {
   if (coords == ORC_PXPYPZE) {
     for (int k = 0; k < 4; ++k) u[k] = gc[k];
+    return;
+  }
+  if (coords == ORC_PXPYPZM) {
+    double dm[4];
+    dmass_dcart(v, mass_of(v), dm);
+    for (int k = 0; k < 4; ++k) u[k] = (k < 3 ? gc[k] : 0.0) + gc[3] * dm[k];
     return;
   }
   for (int k = 0; k < 4; ++k) u[k] = 0.0;
@@ -509,6 +534,15 @@ static void chain_coords_abs(int coords, double c0, double c1, double c2, double
                              double g[4]) {
   if (coords == ORC_PXPYPZE) {
     for (int k = 0; k < 4; ++k) g[k] = fabs(u[k]);
+    return;
+  }
+  if (coords == ORC_PXPYPZM) {
+    double e = sqrt(c0 * c0 + c1 * c1 + c2 * c2 + c3 * c3);
+    double ue = (e > 0.0) ? fabs(u[3]) / e : 0.0;
+    g[0] = fabs(u[0]) + ue * fabs(c0);
+    g[1] = fabs(u[1]) + ue * fabs(c1);
+    g[2] = fabs(u[2]) + ue * fabs(c2);
+    g[3] = ue * fabs(c3);
     return;
   }
   double pt = fabs(c0), eta = c1, phi = c2;

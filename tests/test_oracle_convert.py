@@ -1,5 +1,6 @@
 """Pins of the oracle's stand-alone coordinate conversion (Sec. 2.1: a 4D
-vector in any of its coordinate systems; PxPyPzE <-> PtEtaPhiM / PtEtaPhiE)
+vector in any of its coordinate systems; PxPyPzE, PtEtaPhiM, PtEtaPhiE and
+PxPyPzM)
 and of its reverse mode.  CPU only."""
 import math
 
@@ -10,7 +11,7 @@ import pytest
 import oracle
 import synth
 
-SYSTEMS = ["PxPyPzE", "PtEtaPhiM", "PtEtaPhiE"]
+SYSTEMS = ["PxPyPzE", "PtEtaPhiM", "PtEtaPhiE", "PxPyPzM"]
 U = 2.0 ** -53
 
 
@@ -39,6 +40,34 @@ def test_closed_values_and_beam_axis():
     assert s[3][0] == -3.0
     _, _, _, e = oracle.convert("PxPyPzE", "PtEtaPhiE", cols)
     assert np.array_equal(e, cols[3])
+
+
+def test_pxpypzm_closed_values():
+    """PxPyPzM: E = sqrt(|p|^2 + M^2) on Pythagorean quadruples, p = 0 (E = |M|),
+    M = 0 (E = |p|), only M^2 entering; back again the masses are exact."""
+    pm = tuple(np.array(v, dtype=np.float64) for v in
+               ([3.0, 1.0, 0.0, 0.0, 2.0, -6.0], [4.0, 2.0, 0.0, 0.0, 3.0, 0.0], [12.0, 2.0, 0.0, 0.0, 6.0, 0.0],
+                [0.0, 4.0, 5.0, -5.0, 0.0, 8.0]))
+    px, py, pz, e = oracle.convert("PxPyPzM", "PxPyPzE", pm)
+    assert e.tolist() == [13.0, 5.0, 5.0, 5.0, 7.0, 10.0]
+    assert all(np.array_equal(a, b) for a, b in zip((px, py, pz), pm[:3]))
+    back = oracle.convert("PxPyPzE", "PxPyPzM", (px, py, pz, e))
+    assert back[3].tolist() == [0.0, 4.0, 5.0, 5.0, 0.0, 8.0]  # |M|: the sign of M does not enter
+    s = oracle.convert("PxPyPzE", "PxPyPzM", tuple(np.array([x]) for x in (3.0, 4.0, 0.0, 4.0)))
+    assert s[3][0] == -3.0  # spacelike: -sqrt(-q)
+    pt, eta, phi, m = oracle.convert("PxPyPzM", "PtEtaPhiM", pm)
+    assert pt[0] == 5.0 and phi[0] == math.atan2(4.0, 3.0) and m[0] == 0.0 and m[1] == 4.0
+
+
+def test_pxpypzm_energy_against_mpmath():
+    px, py, pz, e = _cart_random(1000, 809, spacelike_frac=0.0)
+    m = synth.rng(810).uniform(-50, 50, 1000)
+    _, _, _, en = oracle.convert("PxPyPzM", "PxPyPzE", (px, py, pz, m))
+    mpmath.mp.dps = 50
+    for i in range(0, 1000, 3):
+        X, Y, Z, M = (mpmath.mpf(float(v[i])) for v in (px, py, pz, m))
+        E = float(mpmath.sqrt(X * X + Y * Y + Z * Z + M * M))
+        assert abs(en[i] - E) <= 3 * U * E
 
 
 @pytest.mark.parametrize("src", SYSTEMS)
@@ -98,12 +127,21 @@ def _fd_check(src, dst, cols, g, rel=1e-6):
         fu, fd = oracle.convert(src, dst, up), oracle.convert(src, dst, dn)
         return sum(gg * (u - d) for gg, u, d in zip(g, fu, fd)) / (2 * h)
 
+    # rounding of one evaluation of <g, convert(x)>: 8 u of each output, and for
+    # a mass output 8 u S / (2|M|) (E^2 - |p|^2 cancels; S = E^2 + |p|^2)
+    out = oracle.convert(src, dst, cols)
+    v = oracle.convert(src, "PxPyPzE", cols)
+    S = v[3] ** 2 + v[0] ** 2 + v[1] ** 2 + v[2] ** 2
+    eps = sum(np.abs(gg) * 8 * U * (np.abs(o) + 1) for gg, o in zip(g, out))
+    if dst in ("PtEtaPhiM", "PxPyPzM"):
+        eps = eps + np.abs(g[3]) * 8 * U * S / (2 * np.maximum(np.abs(out[3]), 1e-300))
     for k in range(4):
-        ang = src != "PxPyPzE" and k in (1, 2)  # eta, phi: absolute steps
+        ang = src.startswith("PtEtaPhi") and k in (1, 2)  # eta, phi: absolute steps
         h = np.full(cols[k].size, 1e-6) if ang else 1e-6 * np.maximum(1.0, np.abs(cols[k]))
         num = (4 * central(k, h / 2) - central(k, h)) / 3
         scale = np.max(np.abs(np.stack(an)), axis=0) + np.abs(num)
-        bad = np.abs(num - an[k]) > rel * scale + 1e-9
+        # Richardson of central differences: rounding noise at most 3 eps / h
+        bad = np.abs(num - an[k]) > rel * scale + 3 * eps / h + 1e-9
         assert not np.any(bad), (src, dst, k, np.nonzero(bad)[0][:5], num[bad][:3], an[k][bad][:3])
 
 
@@ -118,7 +156,8 @@ def test_vjp_against_finite_differences(src, dst):
 
 
 @pytest.mark.parametrize("src,dst", [("PtEtaPhiM", "PxPyPzE"), ("PtEtaPhiE", "PxPyPzE"),
-                                     ("PtEtaPhiM", "PtEtaPhiE"), ("PxPyPzE", "PtEtaPhiM")])
+                                     ("PtEtaPhiM", "PtEtaPhiE"), ("PxPyPzE", "PtEtaPhiM"),
+                                     ("PxPyPzM", "PxPyPzE"), ("PxPyPzM", "PtEtaPhiM"), ("PtEtaPhiE", "PxPyPzM")])
 def test_vjp_of_a_round_trip_is_the_identity(src, dst):
     """For y = convert(src, dst, x): J_{src->dst}(x)^T J_{dst->src}(y)^T g = g."""
     a, _ = synth.pairs_generic(synth.rng(807), 1000)

@@ -19,7 +19,7 @@ def _fd_mass(coords, a, b, step_rel, step_abs_angle):
     small step costs no accuracy.  Returns 8 arrays: d m / d a_k (k = 0..3)
     then d m / d b_k."""
     out = []
-    angle = {"PtEtaPhiM": (1, 2), "PtEtaPhiE": (1, 2), "PxPyPzE": ()}[coords]
+    angle = {"PtEtaPhiM": (1, 2), "PtEtaPhiE": (1, 2), "PxPyPzE": (), "PxPyPzM": ()}[coords]
     for leg in (0, 1):
         for k in range(4):
             x = (a, b)[leg][k]
@@ -35,7 +35,7 @@ def _fd_mass(coords, a, b, step_rel, step_abs_angle):
     return out
 
 
-@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PtEtaPhiE", "PxPyPzE"])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PtEtaPhiE", "PxPyPzE", "PxPyPzM"])
 def test_mass_vjp_matches_finite_differences(coords):
     g = synth.rng(300)
     n = 3000
@@ -46,6 +46,9 @@ def test_mass_vjp_matches_finite_differences(coords):
         if coords == "PtEtaPhiE":
             a = (a[0], a[1], a[2], ca[3])
             b = (b[0], b[1], b[2], cb[3])
+        elif coords == "PxPyPzM":
+            a = (ca[0], ca[1], ca[2], a[3] + 1.0)
+            b = (cb[0], cb[1], cb[2], b[3] + 1.0)
         else:
             a, b = ca, cb
     gm = g.standard_normal(n)
@@ -182,6 +185,11 @@ def test_mass_vjp_scale_bounds_the_vjp():
         for v, s in zip(va + vb, sa + sb):
             assert np.all(s >= np.abs(v) * (1 - 1e-14))
     ca, cb = oracle.to_cartesian("PtEtaPhiM", a), oracle.to_cartesian("PtEtaPhiM", b)
+    pa, pb = (ca[0], ca[1], ca[2], a[3] + 1.0), (cb[0], cb[1], cb[2], b[3] + 1.0)
+    va, vb = oracle.mass_vjp("PxPyPzM", pa, pb, gm)
+    sa, sb = oracle.mass_vjp_scale("PxPyPzM", pa, pb, gm)
+    for v, s in zip(va + vb, sa + sb):
+        assert np.all(s >= np.abs(v) * (1 - 1e-14))
     va, vb = oracle.mass_vjp("PxPyPzE", ca, cb, gm)
     sa, sb = oracle.mass_vjp_scale("PxPyPzE", ca, cb, gm)
     for v, s in zip(va + vb, sa + sb):

@@ -132,13 +132,15 @@ def _fd_event(coords, off, p, g_total, g_em, g_pair, h=1e-6):
     return out
 
 
-@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE"])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PxPyPzM"])
 def test_event_vjp_matches_finite_differences(coords):
     g = synth.rng(406)
     off = np.array([0, 2, 2, 3, 7, 13], dtype=np.int64)
     # Cartesian particles come from the heavy boost workload: a light particle
     # alone in its event has a mass too ill-conditioned for finite differences
     p = synth.pairs_generic(g, 13)[0] if coords == "PtEtaPhiM" else synth.boost_items(g, 13)[0]
+    if coords == "PxPyPzM":
+        p = oracle.convert("PxPyPzE", "PxPyPzM", p)
     ne = off.size - 1
     po = oracle.pair_offsets(off)
     gt = synth.upstream(g, ne, 4)

@@ -145,8 +145,30 @@ def test_zero_leg_gives_the_other_legs_mass():
 def test_swapped_legs_bitwise():
     g = synth.rng(105)
     a, b = synth.pairs_generic(g, 5000)
-    for c in ("PtEtaPhiM", "PxPyPzE", "PtEtaPhiE"):
+    for c in ("PtEtaPhiM", "PxPyPzE", "PtEtaPhiE", "PxPyPzM"):
         assert np.array_equal(oracle.mass_plain(c, a, b), oracle.mass_plain(c, b, a))
+
+
+def test_pxpypzm_pair_closed_forms():
+    """Legs at rest: m = M_a + M_b; back to back with |p| = 3, M = 4: m = 2E = 10;
+    a massless leg along x and one along -x: m = 2 sqrt(pa pb)."""
+    a = (np.array([0.0, 3.0, 2.0]), np.array([0.0, 0.0, 0.0]), np.array([0.0, 0.0, 0.0]), np.array([3.0, 4.0, 0.0]))
+    b = (np.array([0.0, -3.0, -8.0]), np.array([0.0, 0.0, 0.0]), np.array([0.0, 0.0, 0.0]), np.array([5.0, 4.0, 0.0]))
+    m = oracle.mass_plain("PxPyPzM", a, b)
+    assert m.tolist() == [8.0, 10.0, 8.0]
+    assert np.array_equal(oracle.mass_plain_q("PxPyPzM", a, b), m)
+
+
+def test_pxpypzm_agrees_with_ptetaphim():
+    """The same physical legs given as PxPyPzM and PtEtaPhiM give the same
+    binary128 mass within the rounding of the binary64 Cartesian inputs."""
+    g = synth.rng(107)
+    a, b = synth.pairs_generic(g, 3000)
+    a, b = (a[0], a[1], a[2], a[3] + 1.0), (b[0], b[1], b[2], b[3] + 1.0)
+    ca, cb = oracle.to_cartesian("PtEtaPhiM", a), oracle.to_cartesian("PtEtaPhiM", b)
+    m1, s = oracle.mass_plain("PtEtaPhiM", a, b, scale=True)
+    m2 = oracle.mass_plain_q("PxPyPzM", (ca[0], ca[1], ca[2], a[3]), (cb[0], cb[1], cb[2], b[3]))
+    assert np.all(np.abs(m1 - m2) <= 32 * U64 * s / m1)
 
 
 def test_spacelike_sum_has_negative_mass():
