@@ -24,7 +24,13 @@ stream the kernels run on, inside the timed steps.
 cpu_baseline: the CPU oracle (test infrastructure) timed on the host cores on
 one step's workload, repeated until about 10 s have passed, in the same unit.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--calib-copy]
+convert: the stand-alone coordinate conversions (Sec. 2.1), FP64 and FP32,
+forward (2 x 4 columns per vector) and reverse mode (3 x 4 columns), each
+timed on its own over 2^24 vectors after the step; they are not part of the
+step and not of `value`.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--no-convert]
+                       [--calib-copy]
 """
 
 import argparse
@@ -52,6 +58,17 @@ KERNEL_SYMBOL = {
     "event_reduce": "k_event_reduce<double, 1, 0>", "event_reduce32c": "k_event_reduce<float, 1, 1>",
     "event_reduce_bwd": "k_event_reduce_bwd<double, 1>",
 }
+# Coordinate conversions, measured after the step: (dtype, from, to, reverse mode) and kernel symbol.
+CONVERT_CASES = {
+    "convert_ptm_to_cart": ("f64", "PtEtaPhiM", "PxPyPzE", False, "Convert<double, 1, 0>"),
+    "convert_cart_to_ptm": ("f64", "PxPyPzE", "PtEtaPhiM", False, "Convert<double, 0, 1>"),
+    "convert_ptm_to_cart_bwd": ("f64", "PtEtaPhiM", "PxPyPzE", True, "ConvertBwd<double, 1, 0>"),
+    "convert_cart_to_ptm_bwd": ("f64", "PxPyPzE", "PtEtaPhiM", True, "ConvertBwd<double, 0, 1>"),
+    "convert_ptm_to_cart_f32": ("f32", "PtEtaPhiM", "PxPyPzE", False, "Convert<float, 1, 0>"),
+    "convert_cart_to_ptm_f32": ("f32", "PxPyPzE", "PtEtaPhiM", False, "Convert<float, 0, 1>"),
+    "convert_cart_to_ptm_bwd_f32": ("f32", "PxPyPzE", "PtEtaPhiM", True, "ConvertBwd<float, 0, 1>"),
+}
+ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()}}
 
 
 def parse():
@@ -63,6 +80,7 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32-compensated vs plain FP64 comparison (profiling runs: only the step's "
                          "launches)")
+    ap.add_argument("--no-convert", action="store_true", help="skip the coordinate-conversion measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -101,7 +119,7 @@ def summarize_trace(trace_csv, bench_json):
     for name, ds in per.items():
         ds.sort()
         short = re.sub(r"glv::\(anonymous namespace\)::", "", name)
-        key = next((k for k, sym in KERNEL_SYMBOL.items() if sym in short), None)
+        key = next((k for k, sym in ALL_SYMBOLS.items() if sym in short), None)
         extra = len(ds) - n_step if key else 0
         if key:
             ds = ds[-n_step:]
@@ -115,21 +133,22 @@ def summarize_trace(trace_csv, bench_json):
            f"{tuple(bench['config']['event_tiling'].values())} FP64, "
            f"{tuple(bench['config'].get('event_tiling_fp32_comp', {}).values())} FP32 compensated, "
            f"{tuple(bench['config'].get('event_tiling_bwd', {}).values())} backward (autotuned on "
-           "these events, the trial launches excluded).  Algorithmic bytes per launch as in `bench.py`.", "",
+           "these events, the trial launches excluded); the coordinate conversions run after the step, "
+           "each warm-up + steps times.  Algorithmic bytes per launch as in `bench.py`.", "",
            "| kernel | calls | avg µs | min µs | share % | block, grid, LDS B | alg. bytes / launch | alg. GB/s (avg) "
            "| % of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|"]
     for tot, name, key, calls, avg, mn, extra, geo in sorted(rows, key=lambda r: -r[0]):
         label = f"`{name[:100]}`" + (f" ({key})" if key else "")
         g = f"{geo[0]}, {geo[1]}, {geo[2]}"
-        if key:
-            ab = bench["kernels"][key]["alg_bytes"]
+        if key and key in {**bench["kernels"], **(bench.get("convert") or {})}:
+            ab = {**bench["kernels"], **(bench.get("convert") or {})}[key]["alg_bytes"]
             gbs = ab / (avg * 1e-6) / 1e9
             out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | {ab} | "
                        f"{gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
         else:
             out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | — | — | — |")
     out += ["", "The benchmark's own HIP-event averages in the same run (under the tracer):", ""]
-    for k, v in bench["kernels"].items():
+    for k, v in {**bench["kernels"], **(bench.get("convert") or {})}.items():
         out.append(f"* {k}: {v['avg_us']} µs, {v['alg_GBps']} GB/s ({100 * v['frac_hbm_peak']:.1f} % of peak)")
     path = os.path.join(ROOT, "profiles", "step_kernel_trace.md")
     with open(path, "w") as fh:
@@ -169,7 +188,7 @@ def summarize_pmc(fetch_csv, write_csv):
              "#   python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/fetch_counter_collection.csv "
              "gpurun_out/pmc_write/write_counter_collection.csv",
              "# sources = digest of the kernel's source file and the shared headers at measurement time"]
-    for key, sym in KERNEL_SYMBOL.items():
+    for key, sym in ALL_SYMBOLS.items():
         names = [k for k in fetch if sym in re.sub(r"glv::\(anonymous namespace\)::", "", k)]
         if not names:
             continue
@@ -398,6 +417,8 @@ def main():
     comparison = None if args.no_compare else compare_precisions(
         lib, SA, SB, MC, FB, torch.from_numpy(collinear).to(dev), sp, args.warmup, K)
 
+    convert = None if args.no_convert else measure_convert(lib, A, X, GY, SA, stream, args.warmup, K)
+
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
@@ -429,8 +450,65 @@ def main():
         "cpu_baseline": cpu,
         "kernels": per_kernel,
         "fp32_comp_vs_fp64_plain": comparison,
+        "convert": convert,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_convert(lib, A, X, GY, SA, stream, warmup, steps):
+    """Each coordinate conversion on its own, 2^24 vectors: PtEtaPhiM inputs
+    are the mass workload's first legs, PxPyPzE inputs the boost workload's
+    vectors (FP64) or the FP32 light legs converted once beforehand; the
+    reverse modes take the boost workload's upstream gradients.  HIP events on
+    the kernels' stream around each launch; algorithmic bytes = 4 columns in
+    and 4 out (forward), 8 in and 4 out (reverse mode)."""
+    import torch
+
+    from paper_2312_02756_amd import _lib
+
+    P4 = _lib.P4
+    sp = stream.cuda_stream
+    dev = A[0].device
+    code = {"PxPyPzE": _lib.GLV_PXPYPZE, "PtEtaPhiM": _lib.GLV_PTETAPHIM}
+    ptr4 = lambda cols: P4(*[t.data_ptr() for t in cols])  # noqa: E731
+    n = A[0].numel()
+    new = lambda dt: tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))  # noqa: E731
+    O64, O32, C32, G32 = new(torch.float64), new(torch.float32), new(torch.float32), new(torch.float32)
+    for k in range(4):
+        G32[k].copy_(GY[k])
+    rc = lib.glv_convert(_lib.GLV_F32, code["PtEtaPhiM"], code["PxPyPzE"], n, ptr4(SA), ptr4(C32), sp)
+    if rc != 0:
+        raise RuntimeError(f"glv_convert: status {rc}")
+    inputs = {("f64", "PtEtaPhiM"): A, ("f64", "PxPyPzE"): X, ("f32", "PtEtaPhiM"): SA, ("f32", "PxPyPzE"): C32}
+    out = {}
+    for key, (dt, src, dst, bwd, _) in CONVERT_CASES.items():
+        es = 8 if dt == "f64" else 4
+        dcode = _lib.GLV_F64 if dt == "f64" else _lib.GLV_F32
+        cin, cout = ptr4(inputs[(dt, src)]), ptr4(O64 if dt == "f64" else O32)
+        cg = ptr4(GY if dt == "f64" else G32)
+        if bwd:
+            call = lambda: lib.glv_convert_bwd(dcode, code[src], code[dst], n, cin, cg, cout, sp)  # noqa: E731
+        else:
+            call = lambda: lib.glv_convert(dcode, code[src], code[dst], n, cin, cout, sp)  # noqa: E731
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for _ in range(warmup):
+            call()
+        for e0, e1 in evs:
+            e0.record(stream)
+            rc = call()
+            e1.record(stream)
+            if rc != 0:
+                raise RuntimeError(f"{key}: status {rc}")
+        torch.cuda.synchronize()
+        ts = np.array([e0.elapsed_time(e1) for e0, e1 in evs]) * 1e-3
+        avg = float(ts.mean())
+        ab = (12 if bwd else 8) * es * n
+        gbs = ab / avg / 1e9
+        out[key] = {"avg_us": round(avg * 1e6, 2), "median_us": round(float(np.median(ts)) * 1e6, 2),
+                    "min_us": round(float(ts.min()) * 1e6, 2), "alg_bytes": ab, "alg_GBps": round(gbs, 1),
+                    "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "Gvectors_per_s": round(n / avg / 1e9, 3),
+                    "traffic": stored_traffic(key)}
+    return out
 
 
 def compare_precisions(lib, SA, SB, MC, FB, collinear, sp, warmup, steps):

@@ -27,7 +27,9 @@
  *     GLV_PXPYPZE   (px, py, pz, E)
  *     GLV_PTETAPHIM (pt, eta, phi, M)   E = sqrt((pt cosh eta)^2 + M^2)
  *     GLV_PTETAPHIE (pt, eta, phi, E)
- *   with px = pt cos(phi), py = pt sin(phi), pz = pt sinh(eta).
+ *     GLV_PXPYPZM   (px, py, pz, M)     E = sqrt(px^2 + py^2 + pz^2 + M^2)
+ *   with px = pt cos(phi), py = pt sin(phi), pz = pt sinh(eta) (Sec. 2.1:
+ *   the four 4D systems; only M^2 enters, so the sign of a given M does not).
  * Sums are formed in Cartesian components, never converted back.
  * Mass.  q = E^2 - |P|^2; m = sqrt(q), and m = -sqrt(-q) for a spacelike
  *   q < 0 (values are not validated: NaN in gives NaN out, |beta| >= 1 gives
@@ -69,7 +71,7 @@ typedef enum glv_status {
 
 typedef enum glv_dtype { GLV_F32 = 1, GLV_F64 = 2 } glv_dtype;
 
-typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2 } glv_coords;
+typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2, GLV_PXPYPZM = 3 } glv_coords;
 
 /* GLV_PLAIN: the definition (convert, add, E^2 - |P|^2).
  * GLV_COMPENSATED (PtEtaPhiM only): the cancellation-free form
@@ -171,7 +173,8 @@ glv_status glv_boost_bwd(glv_dtype dtype, int64_t n, const void* const x[4],
  *   to PtEtaPhiM  pt = hypot(px, py), eta = asinh(pz / pt), phi = atan2(py, px)
  *                 in [-pi, pi], M = the mass of the vector with the pair mass's
  *                 sign convention (-sqrt(-q) when spacelike);
- *   to PtEtaPhiE  the same with E.
+ *   to PtEtaPhiE  the same with E;
+ *   to PxPyPzM    px, py, pz and that M.
  * On the beam axis (pt = 0) eta is +inf or -inf by the sign of pz, 0 when
  * pz = 0.  in and out are 4 columns of n elements; out may be in itself
  * (column for column), otherwise no output overlaps an input or another

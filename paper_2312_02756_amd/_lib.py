@@ -19,7 +19,7 @@ STATUS_NAMES = {
     8: "GLV_EINVAL_OFFSETS", 9: "GLV_EINVAL_TILING", 10: "GLV_EHIP",
 }
 GLV_F32, GLV_F64 = 1, 2
-GLV_PXPYPZE, GLV_PTETAPHIM, GLV_PTETAPHIE = 0, 1, 2
+GLV_PXPYPZE, GLV_PTETAPHIM, GLV_PTETAPHIE, GLV_PXPYPZM = 0, 1, 2, 3
 GLV_PLAIN, GLV_COMPENSATED = 0, 1
 
 # Every symbol include/glv.h declares.

@@ -27,7 +27,9 @@ glv_status hip_status(hipError_t e) {
 }
 
 bool dtype_ok(glv_dtype d) { return d == GLV_F32 || d == GLV_F64; }
-bool coords_ok(glv_coords c) { return c == GLV_PXPYPZE || c == GLV_PTETAPHIM || c == GLV_PTETAPHIE; }
+bool coords_ok(glv_coords c) {
+  return c == GLV_PXPYPZE || c == GLV_PTETAPHIM || c == GLV_PTETAPHIE || c == GLV_PXPYPZM;
+}
 size_t elem(glv_dtype d) { return d == GLV_F64 ? 8 : 4; }
 
 glv_status mode_ok(glv_mode m, glv_coords c) {

@@ -135,14 +135,24 @@ __device__ __forceinline__ T energy_of(T pc, T m) {
     return d_sqrt(fmaf(pc, pc, m * m));
 }
 
+// E = sqrt(px^2 + py^2 + pz^2 + M^2) of a PxPyPzM vector, with explicit
+// fused multiply-adds, so that every kernel forms it bitwise alike.
+template <typename T>
+__device__ __forceinline__ T energy_cart(T px, T py, T pz, T m) {
+  if constexpr (sizeof(T) == 8)
+    return d_sqrt(fma(px, px, fma(py, py, fma(pz, pz, m * m))));
+  else
+    return d_sqrt(fmaf(px, px, fmaf(py, py, fmaf(pz, pz, m * m))));
+}
+
 // Cartesian (px, py, pz, E) of one vector given in COORDS.
 template <int COORDS, typename T, bool kPin = false>
 __device__ __forceinline__ void to_cart(T c0, T c1, T c2, T c3, T v[4]) {
-  if constexpr (COORDS == GLV_PXPYPZE) {
+  if constexpr (COORDS == GLV_PXPYPZE || COORDS == GLV_PXPYPZM) {
     v[0] = c0;
     v[1] = c1;
     v[2] = c2;
-    v[3] = c3;
+    v[3] = (COORDS == GLV_PXPYPZE) ? c3 : energy_cart(c0, c1, c2, c3);
   } else {
     T s, c, sh, ch;
     sincos_t<kPin>(c2, &s, &c);
@@ -169,11 +179,11 @@ struct LegJ {
 template <int COORDS, typename T, bool kPin = false>
 __device__ __forceinline__ LegJ<T> to_cart_j(T c0, T c1, T c2, T c3) {
   LegJ<T> L;
-  if constexpr (COORDS == GLV_PXPYPZE) {
+  if constexpr (COORDS == GLV_PXPYPZE || COORDS == GLV_PXPYPZM) {
     L.v[0] = c0;
     L.v[1] = c1;
     L.v[2] = c2;
-    L.v[3] = c3;
+    L.v[3] = (COORDS == GLV_PXPYPZE) ? c3 : energy_cart(c0, c1, c2, c3);
     L.cp = L.sp = L.sh = L.ch = T(0);
   } else {
     sincos_t<kPin>(c2, &L.sp, &L.cp);
@@ -197,6 +207,13 @@ __device__ __forceinline__ void chain_coords(const LegJ<T>& L, T c0, T c3, const
   if constexpr (COORDS == GLV_PXPYPZE) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = u[k];
+  } else if constexpr (COORDS == GLV_PXPYPZM) {
+    // E = sqrt(|p|^2 + M^2): dE/dp_k = p_k/E, dE/dM = M/E
+    const T e = L.v[3];
+    const T ue = (e > T(0)) ? u[3] / e : T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = u[k] + ue * L.v[k];
+    g[3] = ue * c3;
   } else {
     T pt = c0;
     T g0 = u[0] * L.cp + u[1] * L.sp + u[2] * L.sh;
@@ -286,13 +303,14 @@ __device__ __forceinline__ float asinh_t(float x) { return ::asinhf(x); }
 // Coordinates TO of a Cartesian vector v = (px, py, pz, E), the inverse of
 // to_cart (Sec. 2.1: a 4D vector in any of its systems): pt = hypot(px, py),
 // eta = asinh(pz / pt), phi = atan2(py, px), and M = mass_of(v) (the pair
-// mass's sign convention) or E.  On the beam axis (pt = 0) eta is +-inf by
-// the sign of pz, 0 for pz = 0.
+// mass's sign convention) or E; PxPyPzM keeps (px, py, pz) and takes that M.
+// On the beam axis (pt = 0) eta is +-inf by the sign of pz, 0 for pz = 0.
 template <int TO, typename T>
 __device__ __forceinline__ void from_cart(const T v[4], T c[4]) {
-  if constexpr (TO == GLV_PXPYPZE) {
+  if constexpr (TO == GLV_PXPYPZE || TO == GLV_PXPYPZM) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = v[k];
+    for (int k = 0; k < 3; ++k) c[k] = v[k];
+    c[3] = (TO == GLV_PXPYPZE) ? v[3] : mass_of(v);
   } else {
     const T pt = hypot_t(v[0], v[1]);
     c[0] = pt;
@@ -310,11 +328,17 @@ __device__ __forceinline__ void from_cart(const T v[4], T c[4]) {
 // d eta = (-pz px, -pz py, pt^2, 0)/(pt^2 p) with p = |(px, py, pz)|,
 // d phi = (-py, px, 0, 0)/pt^2, d M = (-P, E)/|M| (zero where M = 0) or
 // d E = (0, 0, 0, 1); on the beam axis the pt, eta and phi rows are zero.
+// PxPyPzM: the identity rows of px, py, pz and the d M row.
 template <int TO, typename T>
 __device__ __forceinline__ void dcoords_dcart(const T v[4], const T gc[4], T u[4]) {
   if constexpr (TO == GLV_PXPYPZE) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) u[k] = gc[k];
+  } else if constexpr (TO == GLV_PXPYPZM) {
+    const T s = pair_coef(v, gc[3]);  // gc[3] / |M|
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = gc[k] - s * v[k];
+    u[3] = s * v[3];
   } else {
     const T pt = hypot_t(v[0], v[1]);
     const T p = d_sqrt(pt * pt + v[2] * v[2]);

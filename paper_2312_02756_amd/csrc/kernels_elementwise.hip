@@ -411,6 +411,8 @@ hipError_t mass_typed(glv_coords co, glv_mode mode, int64_t n, const void* const
       return dispatch_width<T>(MassPlain<T, GLV_PXPYPZE>{ca, cb, (T*)m}, al, n, nullptr, s);
     case GLV_PTETAPHIM:
       return dispatch_width<T>(MassPlain<T, GLV_PTETAPHIM>{ca, cb, (T*)m}, al, n, nullptr, s);
+    case GLV_PXPYPZM:
+      return dispatch_width<T>(MassPlain<T, GLV_PXPYPZM>{ca, cb, (T*)m}, al, n, nullptr, s);
     default:
       return dispatch_width<T>(MassPlain<T, GLV_PTETAPHIE>{ca, cb, (T*)m}, al, n, nullptr, s);
   }
@@ -429,6 +431,8 @@ hipError_t mass_bwd_typed(glv_coords co, int64_t n, const void* const a[4], cons
       return dispatch_width<T>(MassBwd<T, GLV_PXPYPZE>{ca, cb, g, oa, ob}, al, n, nullptr, s);
     case GLV_PTETAPHIM:
       return dispatch_width<T>(MassBwd<T, GLV_PTETAPHIM>{ca, cb, g, oa, ob}, al, n, nullptr, s);
+    case GLV_PXPYPZM:
+      return dispatch_width<T>(MassBwd<T, GLV_PXPYPZM>{ca, cb, g, oa, ob}, al, n, nullptr, s);
     default:
       return dispatch_width<T>(MassBwd<T, GLV_PTETAPHIE>{ca, cb, g, oa, ob}, al, n, nullptr, s);
   }
@@ -473,6 +477,8 @@ hipError_t convert_to(glv_coords to, int64_t n, const void* const in[4], void* c
       return dispatch_width<T>(Convert<T, FROM, GLV_PXPYPZE>{ci, co}, al, n, nullptr, s);
     case GLV_PTETAPHIM:
       return dispatch_width<T>(Convert<T, FROM, GLV_PTETAPHIM>{ci, co}, al, n, nullptr, s);
+    case GLV_PXPYPZM:
+      return dispatch_width<T>(Convert<T, FROM, GLV_PXPYPZM>{ci, co}, al, n, nullptr, s);
     default:
       return dispatch_width<T>(Convert<T, FROM, GLV_PTETAPHIE>{ci, co}, al, n, nullptr, s);
   }
@@ -486,6 +492,8 @@ hipError_t convert_typed(glv_coords from, glv_coords to, int64_t n, const void* 
       return convert_to<T, GLV_PXPYPZE>(to, n, in, out, s);
     case GLV_PTETAPHIM:
       return convert_to<T, GLV_PTETAPHIM>(to, n, in, out, s);
+    case GLV_PXPYPZM:
+      return convert_to<T, GLV_PXPYPZM>(to, n, in, out, s);
     default:
       return convert_to<T, GLV_PTETAPHIE>(to, n, in, out, s);
   }
@@ -502,6 +510,8 @@ hipError_t convert_bwd_to(glv_coords to, int64_t n, const void* const in[4], con
       return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PXPYPZE>{ci, cg, co}, al, n, nullptr, s);
     case GLV_PTETAPHIM:
       return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PTETAPHIM>{ci, cg, co}, al, n, nullptr, s);
+    case GLV_PXPYPZM:
+      return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PXPYPZM>{ci, cg, co}, al, n, nullptr, s);
     default:
       return dispatch_width<T>(ConvertBwd<T, FROM, GLV_PTETAPHIE>{ci, cg, co}, al, n, nullptr, s);
   }
@@ -515,6 +525,8 @@ hipError_t convert_bwd_typed(glv_coords from, glv_coords to, int64_t n, const vo
       return convert_bwd_to<T, GLV_PXPYPZE>(to, n, in, gout, gin, s);
     case GLV_PTETAPHIM:
       return convert_bwd_to<T, GLV_PTETAPHIM>(to, n, in, gout, gin, s);
+    case GLV_PXPYPZM:
+      return convert_bwd_to<T, GLV_PXPYPZM>(to, n, in, gout, gin, s);
     default:
       return convert_bwd_to<T, GLV_PTETAPHIE>(to, n, in, gout, gin, s);
   }

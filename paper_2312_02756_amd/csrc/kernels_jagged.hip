@@ -1265,6 +1265,8 @@ hipError_t fwd_dt(glv_coords co, glv_mode mode, int64_t ne, const int64_t* off, 
       return fwd_typed<T, GLV_PXPYPZE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
     case GLV_PTETAPHIM:
       return fwd_typed<T, GLV_PTETAPHIM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+    case GLV_PXPYPZM:
+      return fwd_typed<T, GLV_PXPYPZM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
     default:
       return fwd_typed<T, GLV_PTETAPHIE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
   }
@@ -1279,6 +1281,8 @@ hipError_t bwd_dt(glv_coords co, int64_t ne, const int64_t* off, const int64_t* 
       return bwd_typed<T, GLV_PXPYPZE>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
     case GLV_PTETAPHIM:
       return bwd_typed<T, GLV_PTETAPHIM>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+    case GLV_PXPYPZM:
+      return bwd_typed<T, GLV_PXPYPZM>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
     default:
       return bwd_typed<T, GLV_PTETAPHIE>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
   }

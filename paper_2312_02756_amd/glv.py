@@ -5,7 +5,7 @@ with torch's current HIP stream; every step of the computation runs in the
 library's gfx950 kernels.  Outputs are allocated here with torch (the
 library itself never allocates).
 
-Coordinates are given as "PxPyPzE", "PtEtaPhiM" or "PtEtaPhiE"; modes as
+Coordinates are given as "PxPyPzE", "PtEtaPhiM", "PtEtaPhiE" or "PxPyPzM"; modes as
 "plain" or "compensated".
 """
 
@@ -16,7 +16,8 @@ import torch
 from . import _lib
 from ._lib import P3, P4, check, glv_tiling
 
-COORDS = {"PxPyPzE": _lib.GLV_PXPYPZE, "PtEtaPhiM": _lib.GLV_PTETAPHIM, "PtEtaPhiE": _lib.GLV_PTETAPHIE}
+COORDS = {"PxPyPzE": _lib.GLV_PXPYPZE, "PtEtaPhiM": _lib.GLV_PTETAPHIM, "PtEtaPhiE": _lib.GLV_PTETAPHIE,
+          "PxPyPzM": _lib.GLV_PXPYPZM}
 MODES = {"plain": _lib.GLV_PLAIN, "compensated": _lib.GLV_COMPENSATED}
 DTYPES = {torch.float32: _lib.GLV_F32, torch.float64: _lib.GLV_F64}
 

@@ -100,7 +100,7 @@ def test_convert_validation(lib):
     f = lib.glv_convert
     Y = 80 * GiB
     assert f(7, 0, 1, N, cols(A), cols(Y), None) == DTYPE
-    assert f(2, 3, 1, N, cols(A), cols(Y), None) == COORDS
+    assert f(2, 4, 1, N, cols(A), cols(Y), None) == COORDS
     assert f(2, 0, -1, N, cols(A), cols(Y), None) == COORDS
     assert f(2, 0, 1, -1, cols(A), cols(Y), None) == SIZE
     bad = cols(Y)

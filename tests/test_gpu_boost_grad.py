@@ -80,14 +80,19 @@ def _mass_vjp_tol(a, b, coords, dtype, g_or, gm):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PtEtaPhiE", "PxPyPzE"])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PtEtaPhiE", "PxPyPzE", "PxPyPzM"])
 def test_mass_bwd_against_oracle(coords, dtype):
     n = 65536 + 3
     g = synth.rng(610)
     a, b = synth.pairs_generic(g, n)
     if coords != "PtEtaPhiM":
         ca, cb = oracle.to_cartesian("PtEtaPhiM", a), oracle.to_cartesian("PtEtaPhiM", b)
-        a, b = (ca, cb) if coords == "PxPyPzE" else ((a[0], a[1], a[2], ca[3]), (b[0], b[1], b[2], cb[3]))
+        if coords == "PxPyPzE":
+            a, b = ca, cb
+        elif coords == "PxPyPzM":
+            a, b = (ca[0], ca[1], ca[2], a[3]), (cb[0], cb[1], cb[2], b[3])
+        else:
+            a, b = (a[0], a[1], a[2], ca[3]), (b[0], b[1], b[2], cb[3])
     gm = g.standard_normal(n)
     ga, gb = glv.glv_invariant_mass_bwd(gpu(a, dtype), gpu(b, dtype), gpu([gm], dtype)[0], coords=coords)
     ga, gb = host(ga), host(gb)

@@ -93,12 +93,12 @@ def test_validate_offsets():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PtEtaPhiE"])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PtEtaPhiE", "PxPyPzM"])
 def test_event_reduce_plain(coords, dtype):
     off, p = _events(3000, 702)
     if coords != "PtEtaPhiM":
         c = oracle.to_cartesian("PtEtaPhiM", p)
-        p = c if coords == "PxPyPzE" else (p[0], p[1], p[2], c[3])
+        p = {"PxPyPzE": c, "PtEtaPhiE": (p[0], p[1], p[2], c[3]), "PxPyPzM": (c[0], c[1], c[2], p[3])}[coords]
     total, em, pm = glv.glv_event_reduce(gpu(p, dtype), _off(off), coords=coords)
     _check_forward(off, p, dtype, coords, "plain", total, em, pm, f"{coords} {dtype}")
 
@@ -239,15 +239,16 @@ def _check_bwd(off, wp, dtype, coords, got, want, label):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE"])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PxPyPzM"])
 def test_event_reduce_bwd(coords, dtype):
     counts = np.concatenate([np.minimum(synth.rng(707).poisson(8, 2000), 64), [0, 1, 300, 2]]).astype(np.int64)
     off = np.zeros(counts.size + 1, dtype=np.int64)
     off[1:] = np.cumsum(counts)
     g = synth.rng(708)
     p, _ = synth.pairs_generic(g, int(off[-1]))
-    if coords == "PxPyPzE":
-        p = oracle.to_cartesian("PtEtaPhiM", p)
+    if coords != "PtEtaPhiM":
+        c = oracle.to_cartesian("PtEtaPhiM", p)
+        p = c if coords == "PxPyPzE" else (c[0], c[1], c[2], p[3])
     ne = counts.size
     po = oracle.pair_offsets(off)
     gt = synth.upstream(g, ne, 4)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 glv = pytest.importorskip("paper_2312_02756_amd.glv")
 
-COORDS = ["PtEtaPhiM", "PtEtaPhiE", "PxPyPzE"]
+COORDS = ["PtEtaPhiM", "PtEtaPhiE", "PxPyPzE", "PxPyPzM"]
 
 
 def _legs(coords, n, seed):
@@ -24,6 +24,8 @@ def _legs(coords, n, seed):
     ca, cb = oracle.to_cartesian("PtEtaPhiM", a), oracle.to_cartesian("PtEtaPhiM", b)
     if coords == "PxPyPzE":
         return ca, cb
+    if coords == "PxPyPzM":
+        return (ca[0], ca[1], ca[2], a[3]), (cb[0], cb[1], cb[2], b[3])
     return (a[0], a[1], a[2], ca[3]), (b[0], b[1], b[2], cb[3])
 
 
