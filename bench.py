@@ -24,7 +24,7 @@ stream the kernels run on, inside the timed steps.
 cpu_baseline: the CPU oracle (test infrastructure) timed on the host cores on
 one step's workload, repeated until about 10 s have passed, in the same unit.
 
-convert: the stand-alone coordinate conversions (Sec. 2.1), FP64 and FP32,
+convert: the stand-alone coordinate conversions (Sec. 3.1), FP64 and FP32,
 forward (2 x 4 columns per vector) and reverse mode (3 x 4 columns), each
 timed on its own over 2^24 vectors after the step; they are not part of the
 step and not of `value`.

@@ -5,9 +5,9 @@
  * The library computes, over millions of independent items held as
  * structure-of-arrays (SoA) columns in GPU memory,
  *   - the invariant mass of pairs of 4-vectors given in any of three 4D
- *     coordinate systems (GenVectorX, arXiv 2312.02756, Sec. 3.1 and Fig. 1:
- *     m[i] = mass(v1[i] + v2[i]); coordinate systems Sec. 2.1),
- *   - the Lorentz boost of Cartesian 4-vectors (Sec. 3.1, ApplyBoost: a 4D
+ *     coordinate systems (GenVectorX, arXiv 2312.02756, Sec. 4.1 and Fig. 1:
+ *     m[i] = mass(v1[i] + v2[i]); coordinate systems Sec. 3.1),
+ *   - the Lorentz boost of Cartesian 4-vectors (Sec. 4.1, ApplyBoost: a 4D
  *     Lorentz transformation held as a 4x4 matrix),
  *   - a per-event reduction over jagged (CSR) events: each event's total
  *     4-vector, its mass and the masses of all its particle pairs (the pair
@@ -28,8 +28,9 @@
  *     GLV_PTETAPHIM (pt, eta, phi, M)   E = sqrt((pt cosh eta)^2 + M^2)
  *     GLV_PTETAPHIE (pt, eta, phi, E)
  *     GLV_PXPYPZM   (px, py, pz, M)     E = sqrt(px^2 + py^2 + pz^2 + M^2)
- *   with px = pt cos(phi), py = pt sin(phi), pz = pt sinh(eta) (Sec. 2.1:
- *   the four 4D systems; only M^2 enters, so the sign of a given M does not).
+ *   with px = pt cos(phi), py = pt sin(phi), pz = pt sinh(eta).  (Sec. 3.1
+ *   leaves the coordinate system to the user; these are the four 4D systems
+ *   of GenVector.)  Only M^2 enters, so the sign of a given M does not.
  * Sums are formed in Cartesian components, never converted back.
  * Mass.  q = E^2 - |P|^2; m = sqrt(q), and m = -sqrt(-q) for a spacelike
  *   q < 0 (values are not validated: NaN in gives NaN out, |beta| >= 1 gives
@@ -121,7 +122,7 @@ typedef struct glv_tiling {
   int32_t reserved; /* must be 0 */
 } glv_tiling;
 
-/* Pair invariant mass (Sec. 3.1, Fig. 1): m[i] = mass(conv(a_i) + conv(b_i)),
+/* Pair invariant mass (Sec. 4.1, Fig. 1): m[i] = mass(conv(a_i) + conv(b_i)),
  * i in [0, n).
  *   a, b            4 column pointers each (component order of `coords`)
  *   m               n outputs; must not overlap any input
@@ -143,7 +144,7 @@ glv_status glv_invariant_mass_bwd(glv_dtype dtype, glv_coords coords, int64_t n,
                                   const void* grad_m, void* const grad_a[4], void* const grad_b[4],
                                   void* stream);
 
-/* Active Lorentz boost (Sec. 3.1, ApplyBoost) of Cartesian vectors x by
+/* Active Lorentz boost (Sec. 4.1, ApplyBoost) of Cartesian vectors x by
  * velocity beta: with g = 1/sqrt(1 - beta^2), k = g^2/(1 + g), s = beta.p,
  *   E' = g (E + s),   p' = p + (k s + g E) beta.
  *   x, y        4 columns (px, py, pz, E); y may equal x column for column
@@ -166,7 +167,7 @@ glv_status glv_boost_bwd(glv_dtype dtype, int64_t n, const void* const x[4],
                          const void* const grad_y[4], void* const grad_x[4],
                          void* const grad_beta[3], void* stream);
 
-/* Coordinate conversion (Sec. 2.1: a 4D vector in any of its systems):
+/* Coordinate conversion (Sec. 3.1: a 4D vector in any of its systems):
  * out = the `to` coordinates of the vectors in[] given in `from`, through
  * their Cartesian components (from == to copies):
  *   to PxPyPzE    the conversions above;

@@ -13,9 +13,9 @@
  * blocked, fused or reordered.
  *
  * Paper: GenVectorX (arXiv 2312.02756).
- *   Sec. 2.1   coordinate systems of a 4D vector (Cartesian, polar-like),
+ *   Sec. 3.1   coordinate systems of a 4D vector (Cartesian, polar-like),
  *              templated on the scalar type.
- *   Sec. 3.1   InvariantMasses: mass of the sum of two 4-vectors given in any
+ *   Sec. 4.1   InvariantMasses: mass of the sum of two 4-vectors given in any
  *              4D coordinate system; ApplyBoost: a 4D Lorentz transformation
  *              held as a 4x4 matrix, applied to an array of vectors.
  *   Fig. 1/2   the pair-mass kernel: each work item adds the two vectors at
@@ -69,7 +69,7 @@ int orc_get_threads(void) {
 
 /* ------------------------------------------------------------- conversion */
 
-/* Cartesian (px, py, pz, E) of one vector given in `coords` (Sec. 2.1, 3.1);
+/* Cartesian (px, py, pz, E) of one vector given in `coords` (Sec. 3.1, 4.1);
  * PxPyPzM has E = sqrt(|p|^2 + M^2). */
 static void cart(int coords, double c0, double c1, double c2, double c3, double v[4]) {
   if (coords == ORC_PXPYPZE || coords == ORC_PXPYPZM) {
@@ -145,7 +145,7 @@ static quad mass_of_q(const quad w[4]) {
   return q >= 0 ? sqrtq(q) : -sqrtq(-q);
 }
 
-/* Pair invariant mass, the definition (Sec. 3.1, Fig. 1): convert both legs,
+/* Pair invariant mass, the definition (Sec. 4.1, Fig. 1): convert both legs,
  * add them, take the mass of the sum.  If `scale` is not NULL it receives
  * S = E^2 + px^2 + py^2 + pz^2 of the sum, the size of the terms that cancel
  * in q (used by tests to state rounding tolerances). */
@@ -256,7 +256,7 @@ void orc_mass_accurate(int64_t n, const double* a0, const double* a1, const doub
 
 /* ----------------------------------------------------------------- boost */
 
-/* Active Lorentz boost by velocity beta (Sec. 3.1, ApplyBoost).  In (E, p)
+/* Active Lorentz boost by velocity beta (Sec. 4.1, ApplyBoost).  In (E, p)
  * order the matrix is [[g, g b^T], [g b, I + k b b^T]] with g = 1/sqrt(1-b^2)
  * and k = (g - 1)/b^2 = g^2/(1 + g):
  *   E' = g (E + b.p),   p' = p + (k (b.p) + g E) b.
@@ -330,7 +330,7 @@ void orc_boost_scale(int64_t n, const double* x0, const double* x1, const double
 /* ---------------------------------------------- conversion, either way */
 
 /* Coordinates `coords` of a Cartesian 4-vector v = (px, py, pz, E), the
- * inverse of `cart` (Sec. 2.1: any system of a 4D vector): pt = hypot(px, py),
+ * inverse of `cart` (Sec. 3.1: any system of a 4D vector): pt = hypot(px, py),
  * eta = asinh(pz / pt), phi = atan2(py, px), and M = the mass of v with the
  * pair mass's sign convention (-sqrt(-q) for a spacelike v), or E itself;
  * PxPyPzM keeps (px, py, pz) and takes that M.

@@ -1,6 +1,6 @@
 // Device-side building blocks shared by the gfx950 kernels: SoA column
 // bundles, streaming (non-temporal) 16-byte loads/stores, the coordinate
-// conversions of a 4D vector (GenVectorX Sec. 2.1: Cartesian and
+// conversions of a 4D vector (GenVectorX Sec. 3.1: Cartesian and
 // pt/eta/phi systems, templated on the scalar type) and the mass of a
 // Cartesian vector (Fig. 1: the mass of the summed pair).
 #pragma once
@@ -301,7 +301,7 @@ __device__ __forceinline__ double asinh_t(double x) { return fast_asinh<false>(x
 __device__ __forceinline__ float asinh_t(float x) { return ::asinhf(x); }
 
 // Coordinates TO of a Cartesian vector v = (px, py, pz, E), the inverse of
-// to_cart (Sec. 2.1: a 4D vector in any of its systems): pt = hypot(px, py),
+// to_cart (Sec. 3.1: a 4D vector in any of its systems): pt = hypot(px, py),
 // eta = asinh(pz / pt), phi = atan2(py, px), and M = mass_of(v) (the pair
 // mass's sign convention) or E; PxPyPzM keeps (px, py, pz) and takes that M.
 // On the beam axis (pt = 0) eta is +-inf by the sign of pz, 0 for pz = 0.

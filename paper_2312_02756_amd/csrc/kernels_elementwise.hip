@@ -1,6 +1,6 @@
 // Element-wise gfx950 kernels over SoA columns: pair invariant mass (plain
 // and cancellation-free), its reverse mode, and the Lorentz boost with its
-// reverse mode (GenVectorX Sec. 3.1: InvariantMasses and ApplyBoost, one
+// reverse mode (GenVectorX Sec. 4.1: InvariantMasses and ApplyBoost, one
 // independent result per item).
 //
 // Every op streams its columns exactly once, so the kernels are built for

@@ -1,5 +1,5 @@
 """Writes tests/golden/pair_masses.txt: hand-picked PtEtaPhiM pairs (the pair
-mass of GenVectorX Sec. 3.1 / Fig. 1) with their masses from the CPU oracle --
+mass of GenVectorX Sec. 4.1 / Fig. 1) with their masses from the CPU oracle --
 the definition evaluated in binary128 and rounded to binary64, and the
 cancellation-free form in binary64.  The paper prints no worked numerical
 example, so these are oracle values; the file guards them against drift and
@@ -41,7 +41,7 @@ def render():
     a, b = cols([c[1] for c in CASES]), cols([c[2] for c in CASES])
     m_q = oracle.mass_plain_q("PtEtaPhiM", a, b)
     m_acc = oracle.mass_accurate(a, b)
-    lines = ["# Pair masses of PtEtaPhiM legs (GenVectorX Sec. 3.1, Fig. 1: convert, add, mass of the sum).",
+    lines = ["# Pair masses of PtEtaPhiM legs (GenVectorX Sec. 4.1, Fig. 1: convert, add, mass of the sum).",
              "# No worked example is printed in the paper: m_binary128 is the oracle's definition in binary128",
              "# rounded to binary64, m_accurate its cancellation-free form in binary64.  Written by",
              "# tests/golden/make_fixtures.py; columns: label, pt_a eta_a phi_a M_a, pt_b eta_b phi_b M_b,",

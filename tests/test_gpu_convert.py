@@ -1,4 +1,4 @@
-"""GPU parity of the stand-alone coordinate conversion (Sec. 2.1) and its
+"""GPU parity of the stand-alone coordinate conversion (Sec. 3.1) and its
 reverse mode against the oracle, for every pair of systems."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Pins for the oracle's Lorentz boost (CPU only).  Paper: Sec. 3.1
+"""Pins for the oracle's Lorentz boost (CPU only).  Paper: Sec. 4.1
 (ApplyBoost: a 4D Lorentz transformation held as a 4x4 matrix).
 
 The boost is pinned by the rapidity form (a different formula for the same

@@ -1,4 +1,4 @@
-"""Pins of the oracle's stand-alone coordinate conversion (Sec. 2.1: a 4D
+"""Pins of the oracle's stand-alone coordinate conversion (Sec. 3.1: a 4D
 vector in any of its coordinate systems; PxPyPzE, PtEtaPhiM, PtEtaPhiE and
 PxPyPzM)
 and of its reverse mode.  CPU only."""

@@ -2,8 +2,8 @@
 
 Each check compares the oracle with something it does not share code with:
 an independent closed form evaluated in mpmath at 60 digits, an exact
-identity of binary floating point, or an invariant.  Paper: Sec. 2.1
-(coordinate systems), Sec. 3.1 and Fig. 1 (mass of the sum of two vectors).
+identity of binary floating point, or an invariant.  Paper: Sec. 3.1
+(coordinate systems), Sec. 4.1 and Fig. 1 (mass of the sum of two vectors).
 """
 
 import math
