@@ -240,3 +240,65 @@ def event_reduce_vjp(coords, offsets, p, g_total=None, g_em=None, g_pair=None):
     _load().orc_event_reduce_vjp(ctypes.c_int(_coords(coords)), ctypes.c_int64(ne), _p(offsets), _p(po),
                                  *map(_p, p), *map(_p, gt), _p(gem), _p(gpr), *map(_p, gp))
     return tuple(gp)
+
+
+# ------------------------------------------------- general transformations
+
+def _ptrs(cols):
+    arr = (ctypes.c_void_p * len(cols))(*[c.ctypes.data for c in cols])
+    return arr
+
+
+def _transform(fn, x, mats, stride, n_out=4):
+    x = [_f64(c) for c in x]
+    mats = [_f64(c) for c in mats]
+    n = x[0].size
+    y = [np.empty(n) for _ in range(n_out)]
+    fn(ctypes.c_int64(n), _ptrs(x), _ptrs(mats), ctypes.c_int64(int(stride)), _ptrs(y))
+    return tuple(y)
+
+
+def lorentz_transform(x, m, stride=1):
+    """y = L x per item; ``m`` = 16 row-major columns (stride 1) or 16 scalars /
+    one-element arrays (stride 0)."""
+    return _transform(_load().orc_lorentz_transform, x, m, stride)
+
+
+def lorentz_transform_vjp(x, m, gy, stride=1, want_gm=True):
+    x, m, gy = [_f64(c) for c in x], [_f64(c) for c in m], [_f64(c) for c in gy]
+    n = x[0].size
+    gx = [np.empty(n) for _ in range(4)]
+    gm = [np.empty(n) for _ in range(16)] if want_gm else None
+    _load().orc_lorentz_transform_vjp(ctypes.c_int64(n), _ptrs(x), _ptrs(m), ctypes.c_int64(int(stride)),
+                                      _ptrs(gy), _ptrs(gx), _ptrs(gm) if gm else None)
+    return tuple(gx), (tuple(gm) if gm else None)
+
+
+def rotate(x, r, stride=1):
+    """Rotation3D: 9 row-major columns (or scalars with stride 0) applied to
+    (px, py, pz); E passes through."""
+    return _transform(_load().orc_rotate, x, r, stride)
+
+
+def rotate_vjp(x, r, gy, stride=1, want_gr=True):
+    x, r, gy = [_f64(c) for c in x], [_f64(c) for c in r], [_f64(c) for c in gy]
+    n = x[0].size
+    gx = [np.empty(n) for _ in range(4)]
+    gr = [np.empty(n) for _ in range(9)] if want_gr else None
+    _load().orc_rotate_vjp(ctypes.c_int64(n), _ptrs(x), _ptrs(r), ctypes.c_int64(int(stride)), _ptrs(gy),
+                           _ptrs(gx), _ptrs(gr) if gr else None)
+    return tuple(gx), (tuple(gr) if gr else None)
+
+
+def rotate_axis_angle(x, aa, stride=1):
+    """AxisAngle: aa = (ax, ay, az, angle) columns (or scalars with stride 0)."""
+    return _transform(_load().orc_rotate_axis_angle, x, aa, stride)
+
+
+def rotate_axis_angle_vjp(aa, gy, stride=1):
+    aa, gy = [_f64(c) for c in aa], [_f64(c) for c in gy]
+    n = gy[0].size
+    gx = [np.empty(n) for _ in range(4)]
+    _load().orc_rotate_axis_angle_vjp(ctypes.c_int64(n), _ptrs(aa), ctypes.c_int64(int(stride)), _ptrs(gy),
+                                      _ptrs(gx))
+    return tuple(gx)

@@ -784,3 +784,128 @@ void orc_event_reduce_vjp(int coords, int64_t n_events, const int64_t* offsets,
     }
   }
 }
+
+/* ------------------------------------------------ general transformations */
+
+/* Lorentz transformation held as a 4x4 matrix (Sec. 3.1: Lorentz
+ * transformations; Sec. 4.1: ApplyBoost applies one held as a 4x4 matrix),
+ * acting on (px, py, pz, E), row-major: y_r = sum_c L[4r + c] x_c, summed
+ * left to right.  m[k] points at column k of the matrices; stride 1: one
+ * matrix per item (m[k][i]), 0: one matrix for all items (m[k][0]). */
+void orc_lorentz_transform(int64_t n, const double* const* x, const double* const* m, int64_t stride,
+                           double* const* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = i * stride;
+    double v[4] = {x[0][i], x[1][i], x[2][i], x[3][i]}, r[4];
+    for (int a = 0; a < 4; ++a) {
+      double s = 0.0;
+      for (int c = 0; c < 4; ++c) s += m[4 * a + c][j] * v[c];
+      r[a] = s;
+    }
+    for (int a = 0; a < 4; ++a) y[a][i] = r[a];
+  }
+}
+
+/* Reverse mode: grad_x = L^T grad_y; grad_m[4r + c] = grad_y_r x_c per item
+ * (stride 1 only; grad_m may be NULL). */
+void orc_lorentz_transform_vjp(int64_t n, const double* const* x, const double* const* m, int64_t stride,
+                               const double* const* gy, double* const* gx, double* const* gm) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = i * stride;
+    double g[4] = {gy[0][i], gy[1][i], gy[2][i], gy[3][i]};
+    for (int c = 0; c < 4; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < 4; ++a) s += m[4 * a + c][j] * g[a];
+      gx[c][i] = s;
+    }
+    if (gm)
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) gm[4 * a + c][i] = g[a] * x[c][i];
+  }
+}
+
+/* Rotation3D (Sec. 3.1: a rotation held as a 3x3 matrix) applied to the
+ * spatial part of 4-vectors (px, py, pz, E): p' = R p (row-major, left to
+ * right), E' = E.  Strides as for orc_lorentz_transform. */
+void orc_rotate(int64_t n, const double* const* x, const double* const* r, int64_t stride, double* const* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = i * stride;
+    double v[3] = {x[0][i], x[1][i], x[2][i]}, o[3];
+    for (int a = 0; a < 3; ++a) {
+      double s = 0.0;
+      for (int c = 0; c < 3; ++c) s += r[3 * a + c][j] * v[c];
+      o[a] = s;
+    }
+    for (int a = 0; a < 3; ++a) y[a][i] = o[a];
+    y[3][i] = x[3][i];
+  }
+}
+
+/* Reverse mode: grad_p = R^T grad_p', grad_E = grad_E'; grad_r[3a + c] =
+ * grad_p'_a p_c per item (stride 1 only; may be NULL). */
+void orc_rotate_vjp(int64_t n, const double* const* x, const double* const* r, int64_t stride,
+                    const double* const* gy, double* const* gx, double* const* gr) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = i * stride;
+    double g[3] = {gy[0][i], gy[1][i], gy[2][i]};
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) s += r[3 * a + c][j] * g[a];
+      gx[c][i] = s;
+    }
+    gx[3][i] = gy[3][i];
+    if (gr)
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) gr[3 * a + c][i] = g[a] * x[c][i];
+  }
+}
+
+/* AxisAngle (Sec. 3.1: the same rotation held as an axis and an angle)
+ * applied to the spatial part: with the unit axis u = a / |a| and angle t,
+ * Rodrigues' formula p' = p cos t + (u x p) sin t + u (u.p)(1 - cos t);
+ * E' = E.  A zero axis gives the identity.  aa[0..2] = axis, aa[3] = angle;
+ * strides as for orc_lorentz_transform. */
+static void axis_angle_apply(const double a[3], double t, const double p[3], double o[3]) {
+  double len = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  if (len == 0.0) {
+    for (int k = 0; k < 3; ++k) o[k] = p[k];
+    return;
+  }
+  double u[3] = {a[0] / len, a[1] / len, a[2] / len};
+  double c = cos(t), s = sin(t);
+  double cr[3] = {u[1] * p[2] - u[2] * p[1], u[2] * p[0] - u[0] * p[2], u[0] * p[1] - u[1] * p[0]};
+  double d = u[0] * p[0] + u[1] * p[1] + u[2] * p[2];
+  for (int k = 0; k < 3; ++k) o[k] = p[k] * c + cr[k] * s + u[k] * d * (1.0 - c);
+}
+
+void orc_rotate_axis_angle(int64_t n, const double* const* x, const double* const* aa, int64_t stride,
+                           double* const* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = i * stride;
+    double a[3] = {aa[0][j], aa[1][j], aa[2][j]};
+    double p[3] = {x[0][i], x[1][i], x[2][i]}, o[3];
+    axis_angle_apply(a, aa[3][j], p, o);
+    for (int k = 0; k < 3; ++k) y[k][i] = o[k];
+    y[3][i] = x[3][i];
+  }
+}
+
+/* Reverse mode w.r.t. the vectors: the rotation is orthogonal, so
+ * grad_p = R^T grad_p' is the rotation by the opposite angle; grad_E = grad_E'. */
+void orc_rotate_axis_angle_vjp(int64_t n, const double* const* aa, int64_t stride, const double* const* gy,
+                               double* const* gx) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = i * stride;
+    double a[3] = {aa[0][j], aa[1][j], aa[2][j]};
+    double g[3] = {gy[0][i], gy[1][i], gy[2][i]}, o[3];
+    axis_angle_apply(a, -aa[3][j], g, o);
+    for (int k = 0; k < 3; ++k) gx[k][i] = o[k];
+    gx[3][i] = gy[3][i];
+  }
+}
