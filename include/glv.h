@@ -194,6 +194,55 @@ glv_status glv_convert_bwd(glv_dtype dtype, glv_coords from, glv_coords to, int6
                            const void* const in[4], const void* const grad_out[4], void* const grad_in[4],
                            void* stream);
 
+/* General Lorentz transformation (Sec. 3.1: Lorentz transformations, such
+ * as LorentzRotation, held as a 4x4 matrix; Sec. 4.1: ApplyBoost applies
+ * one): y = L x per item on Cartesian vectors x = (px, py, pz, E), with
+ * y_r = sum_c L[4r + c] x_c.  L holds 16 column pointers in row-major order:
+ * L_stride 1 = one matrix per item (each column n elements), 0 = one matrix
+ * for all items (each pointer at one element).  L is not checked to be a
+ * Lorentz transformation: any 4x4 matrix is applied.  y may be x itself
+ * (column for column); otherwise no output overlaps an input or another
+ * output (GLV_EINVAL_ALIAS).  Errors: GLV_EINVAL_DTYPE, _SIZE, _STRIDE
+ * (L_stride not 0 or 1), _NULL. */
+glv_status glv_lorentz_transform(glv_dtype dtype, int64_t n, const void* const x[4], const void* const L[16],
+                                 int64_t L_stride, void* const y[4], void* stream);
+
+/* Reverse mode: grad_x = L^T grad_y; grad_L (NULL = not wanted) receives the
+ * per-item gradient grad_L[4r + c] = grad_y_r x_c and needs L_stride 1
+ * (GLV_EINVAL_STRIDE otherwise) and x; x may be NULL without grad_L.  No
+ * output overlaps an input or another output. */
+glv_status glv_lorentz_transform_bwd(glv_dtype dtype, int64_t n, const void* const x[4], const void* const L[16],
+                                     int64_t L_stride, const void* const grad_y[4], void* const grad_x[4],
+                                     void* const grad_L[16], void* stream);
+
+/* Rotation3D (Sec. 3.1: a rotation held as a 3x3 matrix) applied to the
+ * spatial part of Cartesian vectors: (px, py, pz)' = R (px, py, pz), E' = E,
+ * R in 9 row-major column pointers with R_stride as L_stride above (R is not
+ * checked to be orthogonal).  Aliasing and errors as glv_lorentz_transform. */
+glv_status glv_rotate(glv_dtype dtype, int64_t n, const void* const x[4], const void* const R[9], int64_t R_stride,
+                      void* const y[4], void* stream);
+
+/* Reverse mode: grad_p = R^T grad_p', grad_E = grad_E'; grad_R (NULL = not
+ * wanted; R_stride 1 and x needed) receives grad_R[3r + c] = grad_p'_r p_c. */
+glv_status glv_rotate_bwd(glv_dtype dtype, int64_t n, const void* const x[4], const void* const R[9],
+                          int64_t R_stride, const void* const grad_y[4], void* const grad_x[4],
+                          void* const grad_R[9], void* stream);
+
+/* AxisAngle (Sec. 3.1: the same rotation held as an axis and an angle):
+ * axis_angle = (ax, ay, az, angle in radians) columns, per item (stride 1)
+ * or one for all (stride 0).  The axis is normalised, u = a/|a|, and the
+ * spatial part rotated by Rodrigues' formula
+ * R = cos(t) I + sin(t) [u]x + (1 - cos(t)) u u^T; a zero axis gives the
+ * identity; E' = E.  Aliasing and errors as glv_lorentz_transform. */
+glv_status glv_rotate_axis_angle(glv_dtype dtype, int64_t n, const void* const x[4],
+                                 const void* const axis_angle[4], int64_t stride, void* const y[4], void* stream);
+
+/* Reverse mode with respect to the vectors: grad_p = R^T grad_p' (the
+ * rotation by the opposite angle), grad_E = grad_E'.  The gradient with
+ * respect to the axis and angle is not provided.  grad_x overlaps no input. */
+glv_status glv_rotate_axis_angle_bwd(glv_dtype dtype, int64_t n, const void* const axis_angle[4], int64_t stride,
+                                     const void* const grad_y[4], void* const grad_x[4], void* stream);
+
 /* Pair offsets of CSR events: pair_offsets[0] = 0,
  * pair_offsets[e+1] = pair_offsets[e] + c_e (c_e - 1) / 2 with
  * c_e = offsets[e+1] - offsets[e].  Both arrays hold n_events + 1 int64. */

@@ -27,7 +27,9 @@ EXPORTS = (
     "glv_invariant_mass", "glv_invariant_mass_bwd", "glv_boost", "glv_boost_bwd", "glv_pair_offsets",
     "glv_event_reduce", "glv_event_reduce_bwd", "glv_validate_offsets", "glv_autotune_event_reduce",
     "glv_current_tiling", "glv_autotune_event_reduce_bwd", "glv_current_tiling_bwd", "glv_status_str",
-    "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd",
+    "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd", "glv_lorentz_transform",
+    "glv_lorentz_transform_bwd", "glv_rotate", "glv_rotate_bwd", "glv_rotate_axis_angle",
+    "glv_rotate_axis_angle_bwd",
 )
 
 
@@ -38,6 +40,8 @@ class glv_tiling(ctypes.Structure):
 
 P4 = ctypes.c_void_p * 4
 P3 = ctypes.c_void_p * 3
+P9 = ctypes.c_void_p * 9
+P16 = ctypes.c_void_p * 16
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _i64 = ctypes.c_int64
@@ -57,6 +61,12 @@ _SIGS = {
     "glv_autotune_event_reduce_bwd": [_i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_convert": [_i, _i, _i, _i64, _vp, _vp, _vp],
     "glv_convert_bwd": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp],
+    "glv_lorentz_transform": [_i, _i64, _vp, _vp, _i64, _vp, _vp],
+    "glv_lorentz_transform_bwd": [_i, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
+    "glv_rotate": [_i, _i64, _vp, _vp, _i64, _vp, _vp],
+    "glv_rotate_bwd": [_i, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
+    "glv_rotate_axis_angle": [_i, _i64, _vp, _vp, _i64, _vp, _vp],
+    "glv_rotate_axis_angle_bwd": [_i, _i64, _vp, _i64, _vp, _vp, _vp],
     "glv_current_tiling_bwd": [_i, _i, _vp],
     "glv_status_str": [_i],
     "glv_abi_version": [],

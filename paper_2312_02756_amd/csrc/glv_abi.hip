@@ -232,6 +232,64 @@ glv_status validate_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int
 
 }  // namespace
 
+namespace {
+
+// Arguments of a forward transformation x[4] -> y[4] with K parameter
+// columns m (n values each at stride 1, one value at stride 0).  y may be x
+// itself, column for column.
+template <int K>
+glv_status transform_args(glv_dtype dt, int64_t n, const void* const x[4], const void* const* m, int64_t ms,
+                          void* const y[4]) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (ms != 0 && ms != 1) return GLV_EINVAL_STRIDE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<4>(x) || !nonnull<K>(m) || !nonnull<4>((const void* const*)y)) return GLV_EINVAL_NULL;
+  const size_t es = elem(dt);
+  bool inplace = true;
+  for (int k = 0; k < 4; ++k) inplace = inplace && (y[k] == x[k]);
+  std::vector<Range> outs, ins;
+  for (int k = 0; k < 4; ++k) outs.push_back(rng(y[k], n, es));
+  for (int k = 0; k < K; ++k) ins.push_back(rng(m[k], ms ? n : 1, es));
+  if (!inplace)
+    for (int k = 0; k < 4; ++k) ins.push_back(rng(x[k], n, es));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  if (inplace)
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        if (overlap(rng(x[i], n, es), rng(x[j], n, es))) return GLV_EINVAL_ALIAS;
+  return GLV_OK;
+}
+
+// Arguments of a reverse mode: grad_y[4] -> grad_x[4], and with gm (NN
+// columns, stride 1 only) the per-item parameter gradient, which needs x.
+// No output overlaps an input or another output.
+template <int K, int NN>
+glv_status transform_bwd_args(glv_dtype dt, int64_t n, const void* const x[4], const void* const* m, int64_t ms,
+                              const void* const gy[4], void* const gx[4], void* const* gm) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (ms != 0 && ms != 1) return GLV_EINVAL_STRIDE;
+  if (gm && ms != 1) return GLV_EINVAL_STRIDE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<K>(m) || !nonnull<4>(gy) || !nonnull<4>((const void* const*)gx)) return GLV_EINVAL_NULL;
+  if (gm && (!nonnull<NN>((const void* const*)gm) || !nonnull<4>(x))) return GLV_EINVAL_NULL;
+  const size_t es = elem(dt);
+  std::vector<Range> outs, ins;
+  for (int k = 0; k < 4; ++k) {
+    outs.push_back(rng(gx[k], n, es));
+    ins.push_back(rng(gy[k], n, es));
+    if (gm) ins.push_back(rng(x[k], n, es));
+  }
+  for (int k = 0; k < K; ++k) ins.push_back(rng(m[k], ms ? n : 1, es));
+  if (gm)
+    for (int k = 0; k < NN; ++k) outs.push_back(rng(gm[k], n, es));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  return GLV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int glv_abi_version(void) { return GLV_ABI_VERSION; }
@@ -386,6 +444,55 @@ glv_status glv_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4], const 
   }
   if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
   return hip_status(glv::launch_boost_bwd(dt, n, x, beta, beta_stride, gy, gx, gbeta, (hipStream_t)stream));
+}
+
+// ---------------------------------------------- general transformations
+
+glv_status glv_lorentz_transform(glv_dtype dt, int64_t n, const void* const x[4], const void* const L[16],
+                                 int64_t L_stride, void* const y[4], void* stream) {
+  const glv_status st = transform_args<16>(dt, n, x, L, L_stride, y);
+  if (st != GLV_OK || n == 0) return st;
+  return hip_status(glv::launch_transform(dt, glv::kTfLorentz, n, x, L, L_stride, y, (hipStream_t)stream));
+}
+
+glv_status glv_lorentz_transform_bwd(glv_dtype dt, int64_t n, const void* const x[4], const void* const L[16],
+                                     int64_t L_stride, const void* const grad_y[4], void* const grad_x[4],
+                                     void* const grad_L[16], void* stream) {
+  const glv_status st = transform_bwd_args<16, 16>(dt, n, x, L, L_stride, grad_y, grad_x, grad_L);
+  if (st != GLV_OK || n == 0) return st;
+  return hip_status(glv::launch_transform_bwd(dt, glv::kTfLorentz, n, x, L, L_stride, grad_y, grad_x, grad_L,
+                                              (hipStream_t)stream));
+}
+
+glv_status glv_rotate(glv_dtype dt, int64_t n, const void* const x[4], const void* const R[9], int64_t R_stride,
+                      void* const y[4], void* stream) {
+  const glv_status st = transform_args<9>(dt, n, x, R, R_stride, y);
+  if (st != GLV_OK || n == 0) return st;
+  return hip_status(glv::launch_transform(dt, glv::kTfRot3, n, x, R, R_stride, y, (hipStream_t)stream));
+}
+
+glv_status glv_rotate_bwd(glv_dtype dt, int64_t n, const void* const x[4], const void* const R[9],
+                          int64_t R_stride, const void* const grad_y[4], void* const grad_x[4],
+                          void* const grad_R[9], void* stream) {
+  const glv_status st = transform_bwd_args<9, 9>(dt, n, x, R, R_stride, grad_y, grad_x, grad_R);
+  if (st != GLV_OK || n == 0) return st;
+  return hip_status(glv::launch_transform_bwd(dt, glv::kTfRot3, n, x, R, R_stride, grad_y, grad_x, grad_R,
+                                              (hipStream_t)stream));
+}
+
+glv_status glv_rotate_axis_angle(glv_dtype dt, int64_t n, const void* const x[4], const void* const axis_angle[4],
+                                 int64_t stride, void* const y[4], void* stream) {
+  const glv_status st = transform_args<4>(dt, n, x, axis_angle, stride, y);
+  if (st != GLV_OK || n == 0) return st;
+  return hip_status(glv::launch_transform(dt, glv::kTfAxisAngle, n, x, axis_angle, stride, y, (hipStream_t)stream));
+}
+
+glv_status glv_rotate_axis_angle_bwd(glv_dtype dt, int64_t n, const void* const axis_angle[4], int64_t stride,
+                                     const void* const grad_y[4], void* const grad_x[4], void* stream) {
+  const glv_status st = transform_bwd_args<4, 9>(dt, n, nullptr, axis_angle, stride, grad_y, grad_x, nullptr);
+  if (st != GLV_OK || n == 0) return st;
+  return hip_status(glv::launch_transform_bwd(dt, glv::kTfAxisAngle, n, nullptr, axis_angle, stride, grad_y,
+                                              grad_x, nullptr, (hipStream_t)stream));
 }
 
 glv_status glv_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, void* stream) {

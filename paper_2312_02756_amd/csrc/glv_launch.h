@@ -31,6 +31,19 @@ hipError_t launch_convert(glv_dtype dt, glv_coords from, glv_coords to, int64_t 
 hipError_t launch_convert_bwd(glv_dtype dt, glv_coords from, glv_coords to, int64_t n, const void* const in[4],
                               const void* const gout[4], void* const gin[4], hipStream_t s);
 
+// General transformations: a 4x4 Lorentz matrix (16 parameter columns), a
+// 3x3 rotation matrix (9) or an axis and an angle (4), per item (stride 1)
+// or one for all items (stride 0).  The reverse mode's matrix gradient (gm,
+// NULL = not wanted) exists for the two matrix kinds at stride 1.
+enum { kTfLorentz = 0, kTfRot3 = 1, kTfAxisAngle = 2 };
+
+hipError_t launch_transform(glv_dtype dt, int kind, int64_t n, const void* const x[4], const void* const* m,
+                            int64_t m_stride, void* const y[4], hipStream_t s);
+
+hipError_t launch_transform_bwd(glv_dtype dt, int kind, int64_t n, const void* const x[4], const void* const* m,
+                                int64_t m_stride, const void* const gy[4], void* const gx[4], void* const* gm,
+                                hipStream_t s);
+
 hipError_t launch_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* pair_offsets,
                                hipStream_t s);
 

@@ -1,7 +1,8 @@
 // Element-wise gfx950 kernels over SoA columns: pair invariant mass (plain
 // and cancellation-free), its reverse mode, and the Lorentz boost with its
 // reverse mode (GenVectorX Sec. 4.1: InvariantMasses and ApplyBoost, one
-// independent result per item).
+// independent result per item), coordinate conversion, and general Lorentz
+// transformations and rotations (Sec. 3.1) with their reverse modes.
 //
 // Every op streams its columns exactly once, so the kernels are built for
 // HBM bandwidth: each lane moves 16 bytes per column per step (2 doubles or
@@ -375,6 +376,165 @@ struct BoostBwd {
   }
 };
 
+// ------------------------------------------------ general transformations
+
+// Parameters per item of each kind: a 4x4 Lorentz matrix, a 3x3 rotation
+// matrix, or an axis and an angle (all row-major columns).
+template <int KIND>
+struct TfParams {
+  static constexpr int K = KIND == kTfLorentz ? 16 : (KIND == kTfRot3 ? 9 : 4);
+  static constexpr int N = KIND == kTfLorentz ? 4 : 3;  // order of the matrix
+};
+
+template <typename T, int K>
+struct ColsK {
+  const T* c[K];
+};
+template <typename T, int K>
+struct OutColsK {
+  T* c[K];
+};
+
+// Rotation matrix of an axis a and an angle t by Rodrigues' formula,
+// R = cos t I + sin t [u]x + (1 - cos t) u u^T with u = a/|a|; a zero axis
+// gives the identity.
+template <typename T>
+__device__ __forceinline__ void axis_angle_matrix(T ax, T ay, T az, T t, T r[9]) {
+  const T l2 = ax * ax + ay * ay + az * az;
+  const bool axis = l2 > T(0);
+  const T il = axis ? inv_sqrt(l2) : T(0);
+  const T u0 = ax * il, u1 = ay * il, u2 = az * il;
+  T sn, cs;
+  sincos_t<false>(t, &sn, &cs);
+  sn = axis ? sn : T(0);
+  cs = axis ? cs : T(1);
+  const T w = T(1) - cs;
+  r[0] = cs + u0 * u0 * w;
+  r[1] = u0 * u1 * w - u2 * sn;
+  r[2] = u0 * u2 * w + u1 * sn;
+  r[3] = u1 * u0 * w + u2 * sn;
+  r[4] = cs + u1 * u1 * w;
+  r[5] = u1 * u2 * w - u0 * sn;
+  r[6] = u2 * u0 * w - u1 * sn;
+  r[7] = u2 * u1 * w + u0 * sn;
+  r[8] = cs + u2 * u2 * w;
+}
+
+// Fused multiply-add in the element type.
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Parameter packs: per item (STRIDE 1) or one value for all items (STRIDE 0).
+template <typename T, int V, int STRIDE, int K>
+__device__ __forceinline__ void load_params(const ColsK<T, K>& m, int64_t i, Pack<T, V> (&p)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if constexpr (STRIDE == 1) {
+      p[k] = load_pack<T, V>(m.c[k], i);
+    } else {
+      const T v = m.c[k][0];
+#pragma unroll
+      for (int e = 0; e < V; ++e) p[k].v[e] = v;
+    }
+  }
+}
+
+// The N x N matrix of element e.
+template <typename T, int KIND, int V, int K>
+__device__ __forceinline__ void matrix_of(const Pack<T, V> (&p)[K], int e, T mat[TfParams<KIND>::N * TfParams<KIND>::N]) {
+  if constexpr (KIND == kTfAxisAngle) {
+    axis_angle_matrix<T>(p[0].v[e], p[1].v[e], p[2].v[e], p[3].v[e], mat);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) mat[k] = p[k].v[e];
+  }
+}
+
+// y = L x (Lorentz: all four components) or p' = R p, E' = E (rotations).
+template <typename T, int KIND, int STRIDE>
+struct TransformFwd {
+  static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
+  static constexpr int K = TfParams<KIND>::K, N = TfParams<KIND>::N;
+  Cols4<T> x;
+  ColsK<T, K> m;
+  OutCols4<T> y;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> px[4], pm[K], out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) px[k] = load_pack<T, V>(x.c[k], i);
+    load_params<T, V, STRIDE, K>(m, i, pm);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T mat[N * N];
+      matrix_of<T, KIND, V, K>(pm, e, mat);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T acc = mat[N * a] * px[0].v[e];
+#pragma unroll
+        for (int c = 1; c < N; ++c) acc = fma_t(mat[N * a + c], px[c].v[e], acc);
+        out[a].v[e] = acc;
+      }
+      if constexpr (N == 3) out[3].v[e] = px[3].v[e];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_pack<T, V>(y.c[k], i, out[k]);
+    return 0;
+  }
+};
+
+// Reverse mode: grad_x = M^T grad_y (E passes through a rotation); with
+// WANT_GM the per-item matrix gradient grad_M[N a + c] = grad_y_a x_c.
+template <typename T, int KIND, int STRIDE, bool WANT_GM>
+struct TransformBwd {
+  static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockStream;
+  static constexpr int K = TfParams<KIND>::K, N = TfParams<KIND>::N;
+  Cols4<T> x, gy;
+  ColsK<T, K> m;
+  OutCols4<T> gx;
+  OutColsK<T, N * N> gm;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pg[4], px[4], pm[K], ox[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pg[k] = load_pack<T, V>(gy.c[k], i);
+      if constexpr (WANT_GM) px[k] = load_pack<T, V>(x.c[k], i);
+    }
+    load_params<T, V, STRIDE, K>(m, i, pm);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T mat[N * N];
+      matrix_of<T, KIND, V, K>(pm, e, mat);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T acc = mat[c] * pg[0].v[e];
+#pragma unroll
+        for (int a = 1; a < N; ++a) acc = fma_t(mat[N * a + c], pg[a].v[e], acc);
+        ox[c].v[e] = acc;
+      }
+      if constexpr (N == 3) ox[3].v[e] = pg[3].v[e];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_pack<T, V>(gx.c[k], i, ox[k]);
+    if constexpr (WANT_GM) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          Pack<T, V> o;
+#pragma unroll
+          for (int e = 0; e < V; ++e) o.v[e] = pg[a].v[e] * px[c].v[e];
+          store_pack<T, V>(gm.c[N * a + c], i, o);
+        }
+      }
+    }
+    return 0;
+  }
+};
+
 template <typename T>
 Cols4<T> cols4(const void* const p[4]) {
   return {{(const T*)p[0], (const T*)p[1], (const T*)p[2], (const T*)p[3]}};
@@ -465,6 +625,52 @@ hipError_t boost_bwd_typed(int64_t n, const void* const x[4], const void* const 
                              n, nullptr, s);
   return dispatch_width<T>(BoostBwd<T, 0, false>{cx, cbeta, cols4<T>(gy), out4<T>(gx), out3<T>(nullptr)}, al, n,
                            nullptr, s);
+}
+
+template <typename T, int K>
+ColsK<T, K> colsk(const void* const* p) {
+  ColsK<T, K> r;
+#pragma unroll
+  for (int k = 0; k < K; ++k) r.c[k] = p ? (const T*)p[k] : nullptr;
+  return r;
+}
+template <typename T, int K>
+OutColsK<T, K> outk(void* const* p) {
+  OutColsK<T, K> r;
+#pragma unroll
+  for (int k = 0; k < K; ++k) r.c[k] = p ? (T*)p[k] : nullptr;
+  return r;
+}
+
+template <typename T, int KIND>
+hipError_t transform_typed(int64_t n, const void* const x[4], const void* const* m, int64_t ms, void* const y[4],
+                           hipStream_t s) {
+  constexpr int K = TfParams<KIND>::K;
+  const bool al = all16<4>(x) && all16<4>((const void* const*)y) && (ms == 0 || all16<K>(m));
+  const ColsK<T, K> cm = colsk<T, K>(m);
+  if (ms == 1) return dispatch_width<T>(TransformFwd<T, KIND, 1>{cols4<T>(x), cm, out4<T>(y)}, al, n, nullptr, s);
+  return dispatch_width<T>(TransformFwd<T, KIND, 0>{cols4<T>(x), cm, out4<T>(y)}, al, n, nullptr, s);
+}
+
+template <typename T, int KIND>
+hipError_t transform_bwd_typed(int64_t n, const void* const x[4], const void* const* m, int64_t ms,
+                               const void* const gy[4], void* const gx[4], void* const* gm, hipStream_t s) {
+  constexpr int K = TfParams<KIND>::K, NN = TfParams<KIND>::N * TfParams<KIND>::N;
+  const bool want = gm != nullptr;
+  const bool al = all16<4>(gy) && all16<4>((const void* const*)gx) && (ms == 0 || all16<K>(m)) &&
+                  (!want || (all16<4>(x) && all16<NN>((const void* const*)gm)));
+  const Cols4<T> cx = want ? cols4<T>(x) : Cols4<T>{{nullptr, nullptr, nullptr, nullptr}};
+  const ColsK<T, K> cm = colsk<T, K>(m);
+  if constexpr (KIND != kTfAxisAngle) {
+    if (want)  // per-item matrix gradients: stride 1 only (checked by the caller)
+      return dispatch_width<T>(TransformBwd<T, KIND, 1, true>{cx, cols4<T>(gy), cm, out4<T>(gx), outk<T, NN>(gm)},
+                               al, n, nullptr, s);
+  }
+  if (ms == 1)
+    return dispatch_width<T>(TransformBwd<T, KIND, 1, false>{cx, cols4<T>(gy), cm, out4<T>(gx), outk<T, NN>(nullptr)},
+                             al, n, nullptr, s);
+  return dispatch_width<T>(TransformBwd<T, KIND, 0, false>{cx, cols4<T>(gy), cm, out4<T>(gx), outk<T, NN>(nullptr)},
+                           al, n, nullptr, s);
 }
 
 template <typename T, int FROM>
@@ -570,6 +776,39 @@ hipError_t launch_boost_bwd(glv_dtype dt, int64_t n, const void* const x[4],
                             void* const gx[4], void* const gb[3], hipStream_t s) {
   if (dt == GLV_F64) return boost_bwd_typed<double>(n, x, beta, bs, gy, gx, gb, s);
   return boost_bwd_typed<float>(n, x, beta, bs, gy, gx, gb, s);
+}
+
+hipError_t launch_transform(glv_dtype dt, int kind, int64_t n, const void* const x[4], const void* const* m,
+                            int64_t ms, void* const y[4], hipStream_t s) {
+  const bool f64 = dt == GLV_F64;
+  switch (kind) {
+    case kTfLorentz:
+      return f64 ? transform_typed<double, kTfLorentz>(n, x, m, ms, y, s)
+                 : transform_typed<float, kTfLorentz>(n, x, m, ms, y, s);
+    case kTfRot3:
+      return f64 ? transform_typed<double, kTfRot3>(n, x, m, ms, y, s)
+                 : transform_typed<float, kTfRot3>(n, x, m, ms, y, s);
+    default:
+      return f64 ? transform_typed<double, kTfAxisAngle>(n, x, m, ms, y, s)
+                 : transform_typed<float, kTfAxisAngle>(n, x, m, ms, y, s);
+  }
+}
+
+hipError_t launch_transform_bwd(glv_dtype dt, int kind, int64_t n, const void* const x[4], const void* const* m,
+                                int64_t ms, const void* const gy[4], void* const gx[4], void* const* gm,
+                                hipStream_t s) {
+  const bool f64 = dt == GLV_F64;
+  switch (kind) {
+    case kTfLorentz:
+      return f64 ? transform_bwd_typed<double, kTfLorentz>(n, x, m, ms, gy, gx, gm, s)
+                 : transform_bwd_typed<float, kTfLorentz>(n, x, m, ms, gy, gx, gm, s);
+    case kTfRot3:
+      return f64 ? transform_bwd_typed<double, kTfRot3>(n, x, m, ms, gy, gx, gm, s)
+                 : transform_bwd_typed<float, kTfRot3>(n, x, m, ms, gy, gx, gm, s);
+    default:
+      return f64 ? transform_bwd_typed<double, kTfAxisAngle>(n, x, m, ms, gy, gx, nullptr, s)
+                 : transform_bwd_typed<float, kTfAxisAngle>(n, x, m, ms, gy, gx, nullptr, s);
+  }
 }
 
 }  // namespace glv

@@ -144,6 +144,91 @@ def glv_boost_bwd(x, beta, grad_y, want_beta=True):
     return gx, gbeta
 
 
+# ---------------------------------------------------- general transformations
+
+_TF = {"lorentz": ("glv_lorentz_transform", 16, 16), "rotate": ("glv_rotate", 9, 9),
+       "axis_angle": ("glv_rotate_axis_angle", 4, None)}
+
+
+def _params(m, n, k, dt, dev, name):
+    if len(m) != k:
+        raise ValueError(f"{name}: expected {k} columns, got {len(m)}")
+    stride = 1 if m[0].numel() == n else 0
+    return _cols(m, n if stride else 1, dt, dev, name), stride
+
+
+def _transform(kind, x, m, out):
+    fn, k, _ = _TF[kind]
+    dev, dt = x[0].device, x[0].dtype
+    _check_device(x[0])
+    n = x[0].numel()
+    x = _cols(x, n, dt, dev, "x")
+    m, stride = _params(m, n, k, dt, dev, "matrix" if k > 4 else "axis_angle")
+    y = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4)) if out is None else _cols(out, n, dt, dev, "out")
+    arr = ctypes.c_void_p * k
+    check(fn, getattr(_lib.load(), fn)(_dtype_code(dt), n, P4(*[t.data_ptr() for t in x]),
+                                       arr(*[t.data_ptr() for t in m]), stride, P4(*[t.data_ptr() for t in y]),
+                                       _stream(dev)))
+    return y
+
+
+def glv_lorentz_transform(x, L, out=None):
+    """y = L x for Cartesian (px, py, pz, E) columns; L = 16 row-major columns
+    of n items, or of 1 element = one matrix for all.  ``out`` may be ``x``."""
+    return _transform("lorentz", x, L, out)
+
+
+def glv_rotate(x, R, out=None):
+    """Rotation3D: R = 9 row-major columns (n items or 1 element) applied to
+    (px, py, pz); E passes through."""
+    return _transform("rotate", x, R, out)
+
+
+def glv_rotate_axis_angle(x, axis_angle, out=None):
+    """AxisAngle: axis_angle = (ax, ay, az, angle) columns (n items or 1 element)."""
+    return _transform("axis_angle", x, axis_angle, out)
+
+
+def _transform_bwd(kind, x, m, grad_y, want_matrix):
+    fn, k, nn = _TF[kind]
+    dev, dt = grad_y[0].device, grad_y[0].dtype
+    _check_device(grad_y[0])
+    n = grad_y[0].numel()
+    gy = _cols(grad_y, n, dt, dev, "grad_y")
+    m, stride = _params(m, n, k, dt, dev, "matrix" if k > 4 else "axis_angle")
+    gx = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    lib = _lib.load()
+    arr = ctypes.c_void_p * k
+    if kind == "axis_angle":
+        check(fn + "_bwd", lib.glv_rotate_axis_angle_bwd(_dtype_code(dt), n, arr(*[t.data_ptr() for t in m]), stride,
+                                                        P4(*[t.data_ptr() for t in gy]),
+                                                        P4(*[t.data_ptr() for t in gx]), _stream(dev)))
+        return gx
+    gm = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(nn)) if want_matrix else None
+    xp = P4(*[t.data_ptr() for t in _cols(x, n, dt, dev, "x")]) if x is not None else None
+    gm_arg = (ctypes.c_void_p * nn)(*[t.data_ptr() for t in gm]) if gm else None
+    check(fn + "_bwd", getattr(lib, fn + "_bwd")(_dtype_code(dt), n, xp, arr(*[t.data_ptr() for t in m]), stride,
+                                                 P4(*[t.data_ptr() for t in gy]), P4(*[t.data_ptr() for t in gx]),
+                                                 gm_arg, _stream(dev)))
+    return gx, gm
+
+
+def glv_lorentz_transform_bwd(x, L, grad_y, want_matrix=True):
+    """(grad_x, grad_L): L^T grad_y and the per-item grad_y x^T (16 columns;
+    needs one matrix per item)."""
+    return _transform_bwd("lorentz", x, L, grad_y, want_matrix)
+
+
+def glv_rotate_bwd(x, R, grad_y, want_matrix=True):
+    """(grad_x, grad_R) of glv_rotate."""
+    return _transform_bwd("rotate", x, R, grad_y, want_matrix)
+
+
+def glv_rotate_axis_angle_bwd(axis_angle, grad_y):
+    """grad_x of glv_rotate_axis_angle (the rotation by the opposite angle)."""
+    return _transform_bwd("axis_angle", None, axis_angle, grad_y, False)
+
+
 # ------------------------------------------------------------ jagged events
 
 def glv_convert(cols, from_coords, to_coords, out=None):

@@ -122,6 +122,48 @@ def test_convert_validation(lib):
     assert g(2, 1, 9, N, cols(A), cols(G), cols(Y), None) == COORDS
 
 
+def test_transform_validation(lib):
+    X, L, Y, G = A, 40 * GiB, 80 * GiB, 100 * GiB
+    P16, P9 = _lib.P16, _lib.P9
+
+    def mat(base, k):
+        return (P16 if k == 16 else (P9 if k == 9 else _lib.P4))(*[base + i * GiB for i in range(k)])
+
+    f = lib.glv_lorentz_transform
+    assert f(7, N, cols(X), mat(L, 16), 1, cols(Y), None) == DTYPE
+    assert f(2, -1, cols(X), mat(L, 16), 1, cols(Y), None) == SIZE
+    assert f(2, N, cols(X), mat(L, 16), 2, cols(Y), None) == STRIDE
+    assert f(2, 0, None, None, 0, None, None) == OK                                   # empty
+    m = mat(L, 16)
+    m[11] = None
+    assert f(2, N, cols(X), m, 1, cols(Y), None) == NULL
+    assert f(2, N, cols(X), mat(L, 16), 1, None, None) == NULL
+    assert f(2, N, cols(X), mat(L, 16), 1, cols(L + 3 * GiB), None) == ALIAS         # y over the matrix
+    assert f(2, N, cols(X), mat(L, 16), 0, cols(L + 15 * GiB - 4 * 8), None) == ALIAS  # over a broadcast entry
+    y = cols(X)
+    y[2], y[3] = y[3], y[2]
+    assert f(1, N, cols(X), mat(L, 16), 1, y, None) == ALIAS                        # permuted in place
+    g = lib.glv_lorentz_transform_bwd
+    assert g(2, N, cols(X), mat(L, 16), 0, cols(G), cols(Y), mat(Y + 8 * GiB, 16), None) == STRIDE  # grad_L: per item
+    assert g(2, N, None, mat(L, 16), 1, cols(G), cols(Y), mat(Y + 8 * GiB, 16), None) == NULL      # grad_L needs x
+    assert g(2, N, cols(X), mat(L, 16), 1, cols(G), cols(G), None, None) == ALIAS                 # grad_x over grad_y
+    assert g(2, N, cols(X), mat(L, 16), 1, cols(G), cols(Y), mat(X, 16), None) == ALIAS           # grad_L over x
+    r = lib.glv_rotate
+    assert r(2, N, cols(X), mat(L, 9), 3, cols(Y), None) == STRIDE
+    assert r(2, N, cols(X), None, 1, cols(Y), None) == NULL
+    assert r(2, N, cols(X), mat(L, 9), 1, cols(L + 8 * GiB), None) == ALIAS
+    rb = lib.glv_rotate_bwd
+    assert rb(2, N, cols(X), mat(L, 9), 0, cols(G), cols(Y), mat(Y + 8 * GiB, 9), None) == STRIDE
+    assert rb(9, N, cols(X), mat(L, 9), 1, cols(G), cols(Y), None, None) == DTYPE
+    a = lib.glv_rotate_axis_angle
+    assert a(2, N, cols(X), mat(L, 4), -1, cols(Y), None) == STRIDE
+    assert a(2, N, cols(X), mat(L, 4), 1, cols(L), None) == ALIAS
+    ab = lib.glv_rotate_axis_angle_bwd
+    assert ab(2, N, mat(L, 4), 1, cols(G), cols(L + 2 * GiB), None) == ALIAS             # grad_x over the angles
+    assert ab(2, N, mat(L, 4), 1, None, cols(Y), None) == NULL
+    assert ab(2, 0, None, 0, None, None, None) == OK
+
+
 def test_jagged_validation(lib):
     OFF, PO, P, T, EM, PM = A, B, 100 * GiB, 140 * GiB, 180 * GiB, 190 * GiB
     f = lib.glv_event_reduce
