@@ -29,8 +29,12 @@ forward (2 x 4 columns per vector) and reverse mode (3 x 4 columns), each
 timed on its own over 2^24 vectors after the step; they are not part of the
 step and not of `value`.
 
+transform: general Lorentz transformations (4x4) and rotations (3x3 matrix,
+axis and angle), one for all vectors or one per vector, and the per-item
+reverse mode with the matrix gradient, timed the same way.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--no-convert]
-                       [--calib-copy]
+                       [--no-transform] [--calib-copy]
 """
 
 import argparse
@@ -68,7 +72,17 @@ CONVERT_CASES = {
     "convert_cart_to_ptm_f32": ("f32", "PxPyPzE", "PtEtaPhiM", False, "Convert<float, 0, 1>"),
     "convert_cart_to_ptm_bwd_f32": ("f32", "PxPyPzE", "PtEtaPhiM", True, "ConvertBwd<float, 0, 1>"),
 }
-ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()}}
+# General transformations, measured after the step: kernel symbol and algorithmic bytes per vector.
+TRANSFORM_CASES = {
+    "lorentz_broadcast": ("TransformFwd<double, 0, 0>", 64),
+    "lorentz_per_item": ("TransformFwd<double, 0, 1>", 192),
+    "lorentz_per_item_bwd": ("TransformBwd<double, 0, 1, true>", 352),
+    "rotate_broadcast": ("TransformFwd<double, 1, 0>", 64),
+    "axis_angle_per_item": ("TransformFwd<double, 2, 1>", 96),
+    "lorentz_broadcast_f32": ("TransformFwd<float, 0, 0>", 32),
+}
+ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()},
+               **{k: v[0] for k, v in TRANSFORM_CASES.items()}}
 
 
 def parse():
@@ -81,6 +95,7 @@ def parse():
                     help="skip the FP32-compensated vs plain FP64 comparison (profiling runs: only the step's "
                          "launches)")
     ap.add_argument("--no-convert", action="store_true", help="skip the coordinate-conversion measurements")
+    ap.add_argument("--no-transform", action="store_true", help="skip the general-transformation measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -133,22 +148,23 @@ def summarize_trace(trace_csv, bench_json):
            f"{tuple(bench['config']['event_tiling'].values())} FP64, "
            f"{tuple(bench['config'].get('event_tiling_fp32_comp', {}).values())} FP32 compensated, "
            f"{tuple(bench['config'].get('event_tiling_bwd', {}).values())} backward (autotuned on "
-           "these events, the trial launches excluded); the coordinate conversions run after the step, "
-           "each warm-up + steps times.  Algorithmic bytes per launch as in `bench.py`.", "",
+           "these events, the trial launches excluded); the coordinate conversions and general "
+           "transformations run after the step, each warm-up + steps times.  Algorithmic bytes per launch as in `bench.py`.", "",
            "| kernel | calls | avg µs | min µs | share % | block, grid, LDS B | alg. bytes / launch | alg. GB/s (avg) "
            "| % of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|"]
     for tot, name, key, calls, avg, mn, extra, geo in sorted(rows, key=lambda r: -r[0]):
         label = f"`{name[:100]}`" + (f" ({key})" if key else "")
         g = f"{geo[0]}, {geo[1]}, {geo[2]}"
-        if key and key in {**bench["kernels"], **(bench.get("convert") or {})}:
-            ab = {**bench["kernels"], **(bench.get("convert") or {})}[key]["alg_bytes"]
+        measured = {**bench["kernels"], **(bench.get("convert") or {}), **(bench.get("transform") or {})}
+        if key and key in measured:
+            ab = measured[key]["alg_bytes"]
             gbs = ab / (avg * 1e-6) / 1e9
             out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | {ab} | "
                        f"{gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
         else:
             out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | — | — | — |")
     out += ["", "The benchmark's own HIP-event averages in the same run (under the tracer):", ""]
-    for k, v in {**bench["kernels"], **(bench.get("convert") or {})}.items():
+    for k, v in {**bench["kernels"], **(bench.get("convert") or {}), **(bench.get("transform") or {})}.items():
         out.append(f"* {k}: {v['avg_us']} µs, {v['alg_GBps']} GB/s ({100 * v['frac_hbm_peak']:.1f} % of peak)")
     path = os.path.join(ROOT, "profiles", "step_kernel_trace.md")
     with open(path, "w") as fh:
@@ -418,6 +434,8 @@ def main():
         lib, SA, SB, MC, FB, torch.from_numpy(collinear).to(dev), sp, args.warmup, K)
 
     convert = None if args.no_convert else measure_convert(lib, A, X, GY, SA, stream, args.warmup, K)
+    transform = None if args.no_transform else measure_transform(lib, A, B, GA, GB, X, GY, BETA, GM, stream,
+                                                                 args.warmup, K)
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -451,8 +469,81 @@ def main():
         "kernels": per_kernel,
         "fp32_comp_vs_fp64_plain": comparison,
         "convert": convert,
+        "transform": transform,
     }
     print(json.dumps(out), flush=True)
+
+
+def time_launches(key, call, stream, warmup, steps, n, alg_bytes):
+    """HIP events on the kernels' stream around each of `steps` launches of
+    `call` (after `warmup` untimed ones): times, achieved GB/s from the
+    algorithmic bytes, and the stored traffic."""
+    import torch
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for _ in range(warmup):
+        call()
+    for e0, e1 in evs:
+        e0.record(stream)
+        rc = call()
+        e1.record(stream)
+        if rc != 0:
+            raise RuntimeError(f"{key}: status {rc}")
+    torch.cuda.synchronize()
+    ts = np.array([e0.elapsed_time(e1) for e0, e1 in evs]) * 1e-3
+    avg = float(ts.mean())
+    gbs = alg_bytes / avg / 1e9
+    return {"avg_us": round(avg * 1e6, 2), "median_us": round(float(np.median(ts)) * 1e6, 2),
+            "min_us": round(float(ts.min()) * 1e6, 2), "alg_bytes": int(alg_bytes), "alg_GBps": round(gbs, 1),
+            "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "Gvectors_per_s": round(n / avg / 1e9, 3),
+            "traffic": stored_traffic(key)}
+
+
+def measure_transform(lib, A, B, GA, GB, X, GY, BETA, GM, stream, warmup, steps):
+    """Each general transformation on its own over the boost workload's 2^24
+    vectors.  Per-vector matrices take 16 resident columns as entries (the
+    mass legs and the mass gradients of the step: the arithmetic does not
+    depend on the values), none of them the vectors or upstreams themselves,
+    so that every column is a separate HBM stream; axis and angle are the
+    boost velocities and the mass upstream; broadcast matrices are a
+    rotation-boost product."""
+    import torch
+
+    from paper_2312_02756_amd import _lib
+
+    sp = stream.cuda_stream
+    dev = X[0].device
+    n = X[0].numel()
+    P4, P9, P16 = _lib.P4, _lib.P9, _lib.P16
+    ptr = lambda arr, cols: arr(*[t.data_ptr() for t in cols])  # noqa: E731
+    per_item = list(A) + list(B) + list(GA) + list(GB)
+    aa = list(BETA) + [GM]
+    th, b = 0.3, 0.6  # rotation about z by 0.3 rad, then a boost along x with beta 0.6
+    g = 1.0 / np.sqrt(1.0 - b * b)
+    rz = np.array([[np.cos(th), -np.sin(th), 0, 0], [np.sin(th), np.cos(th), 0, 0], [0, 0, 1, 0], [0, 0, 0, 1]])
+    bx = np.array([[g, 0, 0, g * b], [0, 1, 0, 0], [0, 0, 1, 0], [g * b, 0, 0, g]])
+    lb = bx @ rz
+    one64 = [torch.tensor([v], dtype=torch.float64, device=dev) for v in lb.ravel()]
+    one32 = [t.to(torch.float32) for t in one64]
+    rot = [torch.tensor([v], dtype=torch.float64, device=dev) for v in rz[:3, :3].ravel()]
+    Y64 = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4))
+    GL = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(16))
+    X32 = tuple(t.to(torch.float32) for t in X)
+    Y32 = tuple(torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4))
+    F64, F32 = _lib.GLV_F64, _lib.GLV_F32
+    cX, cY, cX32, cY32 = ptr(P4, X), ptr(P4, Y64), ptr(P4, X32), ptr(P4, Y32)
+    cL1, cLn, cR1, cAA = ptr(P16, one64), ptr(P16, per_item), ptr(P9, rot), ptr(P4, aa)
+    cL32, cGY, cGL = ptr(P16, one32), ptr(P4, GY), ptr(P16, GL)
+    calls = {
+        "lorentz_broadcast": lambda: lib.glv_lorentz_transform(F64, n, cX, cL1, 0, cY, sp),
+        "lorentz_per_item": lambda: lib.glv_lorentz_transform(F64, n, cX, cLn, 1, cY, sp),
+        "lorentz_per_item_bwd": lambda: lib.glv_lorentz_transform_bwd(F64, n, cX, cLn, 1, cGY, cY, cGL, sp),
+        "rotate_broadcast": lambda: lib.glv_rotate(F64, n, cX, cR1, 0, cY, sp),
+        "axis_angle_per_item": lambda: lib.glv_rotate_axis_angle(F64, n, cX, cAA, 1, cY, sp),
+        "lorentz_broadcast_f32": lambda: lib.glv_lorentz_transform(F32, n, cX32, cL32, 0, cY32, sp),
+    }
+    return {key: time_launches(key, calls[key], stream, warmup, steps, n, TRANSFORM_CASES[key][1] * n)
+            for key in TRANSFORM_CASES}
 
 
 def measure_convert(lib, A, X, GY, SA, stream, warmup, steps):
@@ -482,7 +573,6 @@ def measure_convert(lib, A, X, GY, SA, stream, warmup, steps):
     inputs = {("f64", "PtEtaPhiM"): A, ("f64", "PxPyPzE"): X, ("f32", "PtEtaPhiM"): SA, ("f32", "PxPyPzE"): C32}
     out = {}
     for key, (dt, src, dst, bwd, _) in CONVERT_CASES.items():
-        es = 8 if dt == "f64" else 4
         dcode = _lib.GLV_F64 if dt == "f64" else _lib.GLV_F32
         cin, cout = ptr4(inputs[(dt, src)]), ptr4(O64 if dt == "f64" else O32)
         cg = ptr4(GY if dt == "f64" else G32)
@@ -490,24 +580,8 @@ def measure_convert(lib, A, X, GY, SA, stream, warmup, steps):
             call = lambda: lib.glv_convert_bwd(dcode, code[src], code[dst], n, cin, cg, cout, sp)  # noqa: E731
         else:
             call = lambda: lib.glv_convert(dcode, code[src], code[dst], n, cin, cout, sp)  # noqa: E731
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for _ in range(warmup):
-            call()
-        for e0, e1 in evs:
-            e0.record(stream)
-            rc = call()
-            e1.record(stream)
-            if rc != 0:
-                raise RuntimeError(f"{key}: status {rc}")
-        torch.cuda.synchronize()
-        ts = np.array([e0.elapsed_time(e1) for e0, e1 in evs]) * 1e-3
-        avg = float(ts.mean())
-        ab = (12 if bwd else 8) * es * n
-        gbs = ab / avg / 1e9
-        out[key] = {"avg_us": round(avg * 1e6, 2), "median_us": round(float(np.median(ts)) * 1e6, 2),
-                    "min_us": round(float(ts.min()) * 1e6, 2), "alg_bytes": ab, "alg_GBps": round(gbs, 1),
-                    "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4), "Gvectors_per_s": round(n / avg / 1e9, 3),
-                    "traffic": stored_traffic(key)}
+        es = 8 if dt == "f64" else 4
+        out[key] = time_launches(key, call, stream, warmup, steps, n, (12 if bwd else 8) * es * n)
     return out
 
 
