@@ -302,3 +302,26 @@ def rotate_axis_angle_vjp(aa, gy, stride=1):
     _load().orc_rotate_axis_angle_vjp(ctypes.c_int64(n), _ptrs(aa), ctypes.c_int64(int(stride)), _ptrs(gy),
                                       _ptrs(gx))
     return tuple(gx)
+
+
+# ------------------------------------------------------------ analysis step
+
+def histogram(v, lo, hi, n_bins):
+    """Counts of n_bins equal bins of [lo, hi) with an underflow bin first and
+    an overflow bin last (n_bins + 2 uint64)."""
+    v = _f64(v)
+    counts = np.zeros(int(n_bins) + 2, dtype=np.uint64)
+    _load().orc_histogram(ctypes.c_int64(v.size), _p(v), ctypes.c_double(lo), ctypes.c_double(hi),
+                          ctypes.c_int64(int(n_bins)), _p(counts))
+    return counts
+
+
+def best_pair(pair_offsets, pm, target):
+    """(rank, mass) per event of its pair closest to ``target``."""
+    po = np.ascontiguousarray(pair_offsets, dtype=np.int64)
+    pm = _f64(pm)
+    ne = po.size - 1
+    rank = np.empty(ne, dtype=np.int64)
+    bm = np.empty(ne)
+    _load().orc_best_pair(ctypes.c_int64(ne), _p(po), _p(pm), ctypes.c_double(target), _p(rank), _p(bm))
+    return rank, bm

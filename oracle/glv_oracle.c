@@ -909,3 +909,53 @@ void orc_rotate_axis_angle_vjp(int64_t n, const double* const* aa, int64_t strid
     gx[3][i] = gy[3][i];
   }
 }
+
+/* ------------------------------------------------------- analysis step */
+
+/* Histogram of n values (masses) over n_bins equal bins of [lo, hi) -- the
+ * analysis step that follows the mass (not in the paper; Sec. 6 places
+ * GenVector inside ROOT, which analyses and visualises such data).
+ * counts[0] receives v < lo, counts[n_bins + 1] receives v >= hi, and v in
+ * [lo, hi) goes to counts[1 + b] with b = floor((v - lo) * s), s = n_bins /
+ * (hi - lo), both evaluated in binary64, b clamped to n_bins - 1.  NaN is not
+ * counted.  The counts are added to what `counts` holds. */
+void orc_histogram(int64_t n, const double* v, double lo, double hi, int64_t n_bins, uint64_t* counts) {
+  double s = (double)n_bins / (hi - lo);
+  for (int64_t i = 0; i < n; ++i) {
+    double x = v[i];
+    if (x != x) continue;
+    if (x < lo) {
+      counts[0] += 1;
+    } else if (x >= hi) {
+      counts[n_bins + 1] += 1;
+    } else {
+      int64_t b = (int64_t)floor((x - lo) * s);
+      if (b > n_bins - 1) b = n_bins - 1;
+      counts[1 + b] += 1;
+    }
+  }
+}
+
+/* Per event, its pair (lexicographic rank among i < j, as the pair masses of
+ * the jagged reduction are laid out) whose mass lies closest to `target`:
+ * the smallest |m - target| in binary64, the lowest rank among equal
+ * distances; a NaN mass is never chosen.  An event without a chosen pair
+ * gets rank -1 and mass NaN. */
+void orc_best_pair(int64_t ne, const int64_t* pair_offsets, const double* pm, double target, int64_t* rank,
+                   double* best_m) {
+  for (int64_t e = 0; e < ne; ++e) {
+    int64_t r = -1;
+    double best = 0.0, bm = NAN;
+    for (int64_t k = pair_offsets[e]; k < pair_offsets[e + 1]; ++k) {
+      double d = fabs(pm[k] - target);
+      if (d != d) continue;
+      if (r < 0 || d < best) {
+        r = k - pair_offsets[e];
+        best = d;
+        bm = pm[k];
+      }
+    }
+    rank[e] = r;
+    best_m[e] = bm;
+  }
+}
