@@ -243,6 +243,32 @@ glv_status glv_rotate_axis_angle(glv_dtype dtype, int64_t n, const void* const x
 glv_status glv_rotate_axis_angle_bwd(glv_dtype dtype, int64_t n, const void* const axis_angle[4], int64_t stride,
                                      const void* const grad_y[4], void* const grad_x[4], void* stream);
 
+/* Histogram of masses (the analysis step after the mass; not in the paper,
+ * whose Sec. 6 places GenVector inside ROOT, which analyses such data):
+ * n values m (dtype) into n_bins equal bins of [lo, hi).  counts holds
+ * n_bins + 2 uint64 and the call ADDS to it (clear it first for one
+ * histogram): counts[0] = values below lo, counts[n_bins + 1] = values at or
+ * above hi, counts[1 + b] with b = floor((v - lo) * (n_bins / (hi - lo)))
+ * evaluated in binary64 (b clamped to n_bins - 1); NaN is not counted.
+ * Errors: GLV_EINVAL_DTYPE; _SIZE (n < 0, n_bins < 1, lo or hi not finite,
+ * lo >= hi, or n_bins / (hi - lo) not finite); _NULL; _ALIAS (counts
+ * overlaps m). */
+glv_status glv_mass_histogram(glv_dtype dtype, int64_t n, const void* m, double lo, double hi, int64_t n_bins,
+                              unsigned long long* counts, void* stream);
+
+/* Per CSR event, its pair whose mass lies closest to `target` (the analysis
+ * step after the jagged reduction; not in the paper): pair_offsets from
+ * glv_pair_offsets and pair_m as glv_event_reduce writes them (lexicographic
+ * i < j within each event; trusted, like the offsets there).  best_rank[e]
+ * (int64) = the rank within the event of the pair with the smallest
+ * |m - target| in binary64, the lowest rank among equal distances, NaN
+ * masses never chosen; -1 and a NaN best_m[e] (dtype) for an event without
+ * such a pair.  The outputs overlap neither each other nor pair_offsets
+ * (GLV_EINVAL_ALIAS) nor, unchecked, pair_m.  Errors: GLV_EINVAL_DTYPE,
+ * _SIZE (n_events < 0), _NULL. */
+glv_status glv_event_best_pair(glv_dtype dtype, int64_t n_events, const int64_t* pair_offsets, const void* pair_m,
+                               double target, int64_t* best_rank, void* best_m, void* stream);
+
 /* Pair offsets of CSR events: pair_offsets[0] = 0,
  * pair_offsets[e+1] = pair_offsets[e] + c_e (c_e - 1) / 2 with
  * c_e = offsets[e+1] - offsets[e].  Both arrays hold n_events + 1 int64. */

@@ -29,7 +29,7 @@ EXPORTS = (
     "glv_current_tiling", "glv_autotune_event_reduce_bwd", "glv_current_tiling_bwd", "glv_status_str",
     "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd", "glv_lorentz_transform",
     "glv_lorentz_transform_bwd", "glv_rotate", "glv_rotate_bwd", "glv_rotate_axis_angle",
-    "glv_rotate_axis_angle_bwd",
+    "glv_rotate_axis_angle_bwd", "glv_mass_histogram", "glv_event_best_pair",
 )
 
 
@@ -67,6 +67,8 @@ _SIGS = {
     "glv_rotate_bwd": [_i, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
     "glv_rotate_axis_angle": [_i, _i64, _vp, _vp, _i64, _vp, _vp],
     "glv_rotate_axis_angle_bwd": [_i, _i64, _vp, _i64, _vp, _vp, _vp],
+    "glv_mass_histogram": [_i, _i64, _vp, ctypes.c_double, ctypes.c_double, _i64, _vp, _vp],
+    "glv_event_best_pair": [_i, _i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
     "glv_current_tiling_bwd": [_i, _i, _vp],
     "glv_status_str": [_i],
     "glv_abi_version": [],

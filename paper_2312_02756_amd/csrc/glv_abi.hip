@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -493,6 +494,32 @@ glv_status glv_rotate_axis_angle_bwd(glv_dtype dt, int64_t n, const void* const 
   if (st != GLV_OK || n == 0) return st;
   return hip_status(glv::launch_transform_bwd(dt, glv::kTfAxisAngle, n, nullptr, axis_angle, stride, grad_y,
                                               grad_x, nullptr, (hipStream_t)stream));
+}
+
+glv_status glv_mass_histogram(glv_dtype dt, int64_t n, const void* m, double lo, double hi, int64_t n_bins,
+                              unsigned long long* counts, void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (n < 0 || n_bins < 1) return GLV_EINVAL_SIZE;
+  const double scale = (double)n_bins / (hi - lo);
+  if (!(std::isfinite(lo) && std::isfinite(hi) && lo < hi && std::isfinite(scale) && scale > 0.0))
+    return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
+  if (!m || !counts) return GLV_EINVAL_NULL;
+  if (overlap(rng(counts, n_bins + 2, 8), rng(m, n, elem(dt)))) return GLV_EINVAL_ALIAS;
+  return hip_status(glv::launch_histogram(dt, n, m, lo, hi, n_bins, counts, (hipStream_t)stream));
+}
+
+glv_status glv_event_best_pair(glv_dtype dt, int64_t ne, const int64_t* pair_offsets, const void* pair_m,
+                               double target, int64_t* best_rank, void* best_m, void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (ne < 0) return GLV_EINVAL_SIZE;
+  if (ne == 0) return GLV_OK;
+  if (!pair_offsets || !pair_m || !best_rank || !best_m) return GLV_EINVAL_NULL;
+  std::vector<Range> outs{rng(best_rank, ne, 8), rng(best_m, ne, elem(dt))};
+  std::vector<Range> ins{rng(pair_offsets, ne + 1, 8)};
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  return hip_status(glv::launch_best_pair(dt, ne, pair_offsets, pair_m, target, best_rank, best_m,
+                                          (hipStream_t)stream));
 }
 
 glv_status glv_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, void* stream) {

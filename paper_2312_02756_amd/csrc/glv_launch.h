@@ -44,6 +44,15 @@ hipError_t launch_transform_bwd(glv_dtype dt, int kind, int64_t n, const void* c
                                 int64_t m_stride, const void* const gy[4], void* const gx[4], void* const* gm,
                                 hipStream_t s);
 
+// Histogram of n masses into n_bins equal bins of [lo, hi) plus under- and
+// overflow, added to counts[n_bins + 2].
+hipError_t launch_histogram(glv_dtype dt, int64_t n, const void* m, double lo, double hi, int64_t n_bins,
+                            unsigned long long* counts, hipStream_t s);
+
+// Per event, the rank and mass of its pair closest to target.
+hipError_t launch_best_pair(glv_dtype dt, int64_t n_events, const int64_t* pair_offsets, const void* pair_m,
+                            double target, int64_t* rank, void* best_m, hipStream_t s);
+
 hipError_t launch_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* pair_offsets,
                                hipStream_t s);
 

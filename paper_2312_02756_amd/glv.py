@@ -260,6 +260,36 @@ def glv_convert_bwd(cols, grad_out, from_coords, to_coords):
     return g
 
 
+def glv_mass_histogram(m, lo, hi, n_bins, counts=None):
+    """Counts (n_bins + 2 uint64 as int64: underflow, the bins, overflow) of the
+    masses ``m`` in n_bins equal bins of [lo, hi).  ``counts``, if given, is
+    added to (accumulate several batches)."""
+    dev, dt = m.device, m.dtype
+    _check_device(m)
+    (m,) = _cols((m,), m.numel(), dt, dev, "m")
+    if counts is None:
+        counts = torch.zeros(int(n_bins) + 2, dtype=torch.int64, device=dev)
+    elif counts.dtype != torch.int64 or counts.numel() != int(n_bins) + 2 or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous int64 tensor of n_bins + 2 elements")
+    check("glv_mass_histogram", _lib.load().glv_mass_histogram(_dtype_code(dt), m.numel(), _ptr(m), float(lo),
+                                                               float(hi), int(n_bins), _ptr(counts), _stream(dev)))
+    return counts
+
+
+def glv_event_best_pair(pair_offsets, pair_m, target):
+    """(rank, mass) per event of its pair closest to ``target`` (rank -1 and
+    NaN for an event without one)."""
+    _check_device(pair_m)
+    dev, dt = pair_m.device, pair_m.dtype
+    po = _offsets(pair_offsets, dev)
+    ne = po.numel() - 1
+    rank = torch.empty(ne, dtype=torch.int64, device=dev)
+    bm = torch.empty(ne, dtype=dt, device=dev)
+    check("glv_event_best_pair", _lib.load().glv_event_best_pair(_dtype_code(dt), ne, _ptr(po), _ptr(pair_m),
+                                                                 float(target), _ptr(rank), _ptr(bm), _stream(dev)))
+    return rank, bm
+
+
 def _offsets(offsets, dev):
     if offsets.dtype != torch.int64 or offsets.device != dev or not offsets.is_contiguous() or offsets.dim() != 1:
         raise ValueError("offsets must be a contiguous 1-D int64 tensor on the particles' device")

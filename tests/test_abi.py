@@ -164,6 +164,31 @@ def test_transform_validation(lib):
     assert ab(2, 0, None, 0, None, None, None) == OK
 
 
+def test_analysis_validation(lib):
+    C, R, BM = 40 * GiB, 60 * GiB, 70 * GiB
+    h = lib.glv_mass_histogram
+    assert h(7, N, A, 0.0, 1.0, 10, C, None) == DTYPE
+    assert h(2, -1, A, 0.0, 1.0, 10, C, None) == SIZE
+    assert h(2, N, A, 0.0, 1.0, 0, C, None) == SIZE                       # no bins
+    assert h(2, N, A, 1.0, 1.0, 10, C, None) == SIZE                      # empty range
+    assert h(2, N, A, 2.0, 1.0, 10, C, None) == SIZE                      # reversed
+    assert h(2, N, A, float("nan"), 1.0, 10, C, None) == SIZE
+    assert h(2, N, A, -1e308, 1e308, 10, C, None) == SIZE                 # hi - lo overflows
+    assert h(2, N, A, 0.0, 1e-320, 1 << 40, C, None) == SIZE              # n_bins / (hi - lo) overflows
+    assert h(2, N, None, 0.0, 1.0, 10, C, None) == NULL
+    assert h(2, N, A, 0.0, 1.0, 10, None, None) == NULL
+    assert h(2, N, A, 0.0, 1.0, 10, A + 8 * (N - 1), None) == ALIAS         # counts over the masses
+    assert h(2, 0, None, 0.0, 1.0, 10, None, None) == OK                    # empty
+    b = lib.glv_event_best_pair
+    assert b(5, N, B, M, 91.0, R, BM, None) == DTYPE
+    assert b(2, -2, B, M, 91.0, R, BM, None) == SIZE
+    assert b(2, N, None, M, 91.0, R, BM, None) == NULL
+    assert b(2, N, B, M, 91.0, R, None, None) == NULL
+    assert b(2, N, B, M, 91.0, R, R + 8, None) == ALIAS                    # the two outputs overlap
+    assert b(2, N, B, M, 91.0, B + 8 * N, BM, None) == ALIAS               # rank over the offsets' last entry
+    assert b(2, 0, None, None, 91.0, None, None, None) == OK
+
+
 def test_jagged_validation(lib):
     OFF, PO, P, T, EM, PM = A, B, 100 * GiB, 140 * GiB, 180 * GiB, 190 * GiB
     f = lib.glv_event_reduce
