@@ -33,8 +33,12 @@ transform: general Lorentz transformations (4x4) and rotations (3x3 matrix,
 axis and angle), one for all vectors or one per vector, and the per-item
 reverse mode with the matrix gradient, timed the same way.
 
+analysis: a 1000-bin histogram of the step's 2^24 FP64 pair masses and the
+per-event pair closest to 91.1876 GeV over the jagged events' pair masses,
+timed the same way.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--no-convert]
-                       [--no-transform] [--calib-copy]
+                       [--no-transform] [--no-analysis] [--calib-copy]
 """
 
 import argparse
@@ -81,8 +85,10 @@ TRANSFORM_CASES = {
     "axis_angle_per_item": ("TransformFwd<double, 2, 1>", 96),
     "lorentz_broadcast_f32": ("TransformFwd<float, 0, 0>", 32),
 }
+# The analysis step, measured after the step: kernel symbols.
+ANALYSIS_SYMBOL = {"mass_histogram": "k_hist_lds<double, 2>", "event_best_pair": "k_best_pair<double>"}
 ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()},
-               **{k: v[0] for k, v in TRANSFORM_CASES.items()}}
+               **{k: v[0] for k, v in TRANSFORM_CASES.items()}, **ANALYSIS_SYMBOL}
 
 
 def parse():
@@ -96,6 +102,7 @@ def parse():
                          "launches)")
     ap.add_argument("--no-convert", action="store_true", help="skip the coordinate-conversion measurements")
     ap.add_argument("--no-transform", action="store_true", help="skip the general-transformation measurements")
+    ap.add_argument("--no-analysis", action="store_true", help="skip the histogram and best-pair measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -148,14 +155,15 @@ def summarize_trace(trace_csv, bench_json):
            f"{tuple(bench['config']['event_tiling'].values())} FP64, "
            f"{tuple(bench['config'].get('event_tiling_fp32_comp', {}).values())} FP32 compensated, "
            f"{tuple(bench['config'].get('event_tiling_bwd', {}).values())} backward (autotuned on "
-           "these events, the trial launches excluded); the coordinate conversions and general "
-           "transformations run after the step, each warm-up + steps times.  Algorithmic bytes per launch as in `bench.py`.", "",
+           "these events, the trial launches excluded); the coordinate conversions, general "
+           "transformations and the analysis step run after the step, each warm-up + steps times.  Algorithmic bytes per launch as in `bench.py`.", "",
            "| kernel | calls | avg µs | min µs | share % | block, grid, LDS B | alg. bytes / launch | alg. GB/s (avg) "
            "| % of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|"]
     for tot, name, key, calls, avg, mn, extra, geo in sorted(rows, key=lambda r: -r[0]):
         label = f"`{name[:100]}`" + (f" ({key})" if key else "")
         g = f"{geo[0]}, {geo[1]}, {geo[2]}"
-        measured = {**bench["kernels"], **(bench.get("convert") or {}), **(bench.get("transform") or {})}
+        measured = {**bench["kernels"], **(bench.get("convert") or {}), **(bench.get("transform") or {}),
+                    **(bench.get("analysis") or {})}
         if key and key in measured:
             ab = measured[key]["alg_bytes"]
             gbs = ab / (avg * 1e-6) / 1e9
@@ -164,7 +172,8 @@ def summarize_trace(trace_csv, bench_json):
         else:
             out.append(f"| {label} | {calls} | {avg:.1f} | {mn:.1f} | {100 * tot / total:.2f} | {g} | — | — | — |")
     out += ["", "The benchmark's own HIP-event averages in the same run (under the tracer):", ""]
-    for k, v in {**bench["kernels"], **(bench.get("convert") or {}), **(bench.get("transform") or {})}.items():
+    for k, v in {**bench["kernels"], **(bench.get("convert") or {}), **(bench.get("transform") or {}),
+                 **(bench.get("analysis") or {})}.items():
         out.append(f"* {k}: {v['avg_us']} µs, {v['alg_GBps']} GB/s ({100 * v['frac_hbm_peak']:.1f} % of peak)")
     path = os.path.join(ROOT, "profiles", "step_kernel_trace.md")
     with open(path, "w") as fh:
@@ -222,6 +231,7 @@ def summarize_pmc(fetch_csv, write_csv):
 # Sources that define each kernel and its launch configuration.
 KERNEL_SOURCES = {k: ["kernels_jagged.hip", "glv_abi.hip"] for k in ("event_reduce", "event_reduce32c",
                                                                        "event_reduce_bwd")}
+KERNEL_SOURCES.update({k: ["kernels_analysis.hip"] for k in ("mass_histogram", "event_best_pair")})
 SHARED_SOURCES = ["glv_device.h", "glv_math.h", "glv_launch.h"]
 
 
@@ -436,6 +446,23 @@ def main():
     convert = None if args.no_convert else measure_convert(lib, A, X, GY, SA, stream, args.warmup, K)
     transform = None if args.no_transform else measure_transform(lib, A, B, GA, GB, X, GY, BETA, GM, stream,
                                                                  args.warmup, K)
+    analysis = None
+    if not args.no_analysis:
+        counts = torch.zeros(1002, dtype=torch.int64, device=dev)
+        rank = torch.empty(N_EVENTS, dtype=torch.int64, device=dev)
+        best = torch.empty(N_EVENTS, dtype=torch.float64, device=dev)
+        analysis = {
+            "mass_histogram": time_launches(
+                "mass_histogram", lambda: lib.glv_mass_histogram(F64, N_ITEMS, M.data_ptr(), 0.0, 200.0, 1000,
+                                                                 counts.data_ptr(), sp),
+                stream, args.warmup, K, N_ITEMS, 8 * N_ITEMS),
+            "event_best_pair": time_launches(
+                "event_best_pair", lambda: lib.glv_event_best_pair(F64, N_EVENTS, PO.data_ptr(), PM.data_ptr(),
+                                                                   91.1876, rank.data_ptr(), best.data_ptr(), sp),
+                stream, args.warmup, K, N_EVENTS, 8 * n_pairs + 8 * (N_EVENTS + 1) + 16 * N_EVENTS),
+        }
+        analysis["mass_histogram"]["bins"] = 1000
+        analysis["event_best_pair"]["pairs"] = n_pairs
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -470,6 +497,7 @@ def main():
         "fp32_comp_vs_fp64_plain": comparison,
         "convert": convert,
         "transform": transform,
+        "analysis": analysis,
     }
     print(json.dumps(out), flush=True)
 

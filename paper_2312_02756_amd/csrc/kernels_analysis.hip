@@ -13,7 +13,9 @@ constexpr int kHistLdsSlots = 8192;
 // Workgroups of the LDS path (two per CU): each merges its counters into the
 // global ones once, so fewer, longer-lived workgroups mean fewer global atomics.
 constexpr int64_t kHistGrid = 512;
-constexpr int kBestBlock = 256;
+constexpr int kBestLanes = 8;    // lanes per event in the best-pair kernel
+constexpr int kBestBlock = 256;  // 32 events per workgroup
+constexpr int kBestUnroll = 4;   // pair loads in flight per lane
 
 struct HistSpec {
   double lo, hi, s;  // s = n_bins / (hi - lo), formed on the host
@@ -98,30 +100,65 @@ hipError_t hist_typed(int64_t n, const void* m, double lo, double hi, int64_t nb
   return hipGetLastError();
 }
 
-// One lane per event: its pairs in rank order, the smallest |m - target| in
-// binary64, the first rank among equal distances; NaN is never chosen.
+// kBestLanes lanes per event: each lane walks every kBestLanes-th pair of
+// its event (a lane group reads consecutive pairs together) keeping the
+// smallest (distance, rank); a butterfly over the group then takes the
+// lexicographic minimum, so the lowest rank wins among equal distances; the
+// mass travels with it, so no dependent read follows.
+// The distance's bits order as unsigned integers (it is not negative);
+// ~0 marks "none" (above every distance, +inf included), and NaN distances
+// never enter.
 template <typename T>
 __global__ __launch_bounds__(kBestBlock) void k_best_pair(int64_t ne, const int64_t* __restrict__ po,
                                                           const T* __restrict__ pm, double target,
                                                           int64_t* __restrict__ rank, T* __restrict__ best_m) {
-  const int64_t e = (int64_t)blockIdx.x * kBestBlock + threadIdx.x;
-  if (e >= ne) return;
-  const int64_t lo = po[e], hi = po[e + 1];
-  int64_t r = -1;
-  double best = 0.0;
-  T bm = (T)__builtin_nan("");
-  for (int64_t k = lo; k < hi; ++k) {
-    const T m = pm[k];
-    const double d = fabs((double)m - target);
-    if (d != d) continue;
-    if (r < 0 || d < best) {
-      r = k - lo;
-      best = d;
-      bm = m;
+  const int64_t e = ((int64_t)blockIdx.x * kBestBlock + threadIdx.x) / kBestLanes;
+  const int sub = threadIdx.x % kBestLanes;
+  const bool live = e < ne;  // lanes past the last event still join the butterfly
+  int64_t lo = 0, hi = 0;
+  if (live) {
+    lo = po[e];
+    hi = po[e + 1];
+  }
+  unsigned long long bd = ~0ull;
+  int64_t br = 0;
+  T bm = T(0);
+  // kBestUnroll loads in flight per lane before their comparisons; positions
+  // past the event read as NaN and drop out like NaN masses
+  for (int64_t k = lo + sub; k < hi; k += kBestUnroll * kBestLanes) {
+    T m[kBestUnroll];
+#pragma unroll
+    for (int u = 0; u < kBestUnroll; ++u) {
+      const int64_t kk = k + u * kBestLanes;
+      m[u] = kk < hi ? pm[kk] : (T)__builtin_nan("");
+    }
+#pragma unroll
+    for (int u = 0; u < kBestUnroll; ++u) {
+      const double d = fabs((double)m[u] - target);
+      const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+      if (d == d && b < bd) {  // a lane's ranks only grow, so a tie keeps its earlier rank
+        bd = b;
+        br = k + u * kBestLanes - lo;
+        bm = m[u];
+      }
     }
   }
-  rank[e] = r;
-  best_m[e] = bm;
+#pragma unroll
+  for (int off = kBestLanes / 2; off > 0; off >>= 1) {
+    const unsigned long long od = __shfl_xor(bd, off, kBestLanes);
+    const int64_t orr = __shfl_xor(br, off, kBestLanes);
+    const T om = __shfl_xor(bm, off, kBestLanes);
+    if (od < bd || (od == bd && orr < br)) {
+      bd = od;
+      br = orr;
+      bm = om;
+    }
+  }
+  if (live && sub == 0) {
+    const bool found = bd != ~0ull;
+    rank[e] = found ? br : -1;
+    best_m[e] = found ? bm : (T)__builtin_nan("");
+  }
 }
 
 }  // namespace
@@ -136,7 +173,8 @@ hipError_t launch_histogram(glv_dtype dt, int64_t n, const void* m, double lo, d
 hipError_t launch_best_pair(glv_dtype dt, int64_t n_events, const int64_t* pair_offsets, const void* pair_m,
                             double target, int64_t* rank, void* best_m, hipStream_t s) {
   if (n_events <= 0) return hipSuccess;
-  const int64_t blocks = (n_events + kBestBlock - 1) / kBestBlock;
+  constexpr int64_t kEventsPerBlock = kBestBlock / kBestLanes;
+  const int64_t blocks = (n_events + kEventsPerBlock - 1) / kEventsPerBlock;
   if (dt == GLV_F64)
     hipLaunchKernelGGL((k_best_pair<double>), dim3((unsigned)blocks), dim3(kBestBlock), 0, s, n_events, pair_offsets,
                        (const double*)pair_m, target, rank, (double*)best_m);
