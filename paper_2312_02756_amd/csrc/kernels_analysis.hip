@@ -7,12 +7,13 @@
 namespace glv {
 namespace {
 
-constexpr int kHistBlock = 256;
+constexpr int kHistBlock = 1024;
 // Counters (bins plus under- and overflow) a workgroup keeps in LDS: 32 KiB.
 constexpr int kHistLdsSlots = 8192;
-// Workgroups of the LDS path (two per CU): each merges its counters into the
-// global ones once, so fewer, longer-lived workgroups mean fewer global atomics.
-constexpr int64_t kHistGrid = 512;
+// Workgroups of the LDS path (one per CU, 16 wavefronts each): each merges
+// its counters into the global ones once, so fewer, larger workgroups mean
+// fewer global atomics on each bin.
+constexpr int64_t kHistGrid = 256;
 constexpr int kBestLanes = 8;    // lanes per event in the best-pair kernel
 constexpr int kBestBlock = 256;  // 32 events per workgroup
 constexpr int kBestUnroll = 4;   // pair loads in flight per lane
