@@ -79,3 +79,78 @@ def event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM"):
         pair_offsets = glv.glv_pair_offsets(offsets)
     out = EventReduce.apply(offsets, pair_offsets, coords, *p)
     return tuple(out[:4]), out[4], out[5]
+
+
+def _grads(gy, like):
+    return tuple(g.contiguous() if g is not None else torch.zeros_like(like) for g in gy)
+
+
+class Convert(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, src, dst, *cols):
+        ctx.src, ctx.dst = src, dst
+        ctx.save_for_backward(*cols)
+        return glv.glv_convert(cols, src, dst)
+
+    @staticmethod
+    def backward(ctx, *gy):
+        cols = ctx.saved_tensors
+        return (None, None) + tuple(glv.glv_convert_bwd(cols, _grads(gy, cols[0]), ctx.src, ctx.dst))
+
+
+class LorentzTransform(torch.autograd.Function):
+    """y = L x (or a Rotation3D); differentiable w.r.t. x and, for one matrix
+    per item, the matrix (a broadcast matrix gets no gradient)."""
+
+    @staticmethod
+    def forward(ctx, kind, *cols):
+        x, m = cols[:4], cols[4:]
+        ctx.kind = kind
+        ctx.save_for_backward(*cols)
+        fn = glv.glv_lorentz_transform if kind == "lorentz" else glv.glv_rotate
+        return fn(x, m)
+
+    @staticmethod
+    def backward(ctx, *gy):
+        cols = ctx.saved_tensors
+        x, m = cols[:4], cols[4:]
+        per_item = m[0].numel() == x[0].numel()
+        fn = glv.glv_lorentz_transform_bwd if ctx.kind == "lorentz" else glv.glv_rotate_bwd
+        gx, gm = fn(x, m, _grads(gy, x[0]), want_matrix=per_item and any(ctx.needs_input_grad[5:]))
+        return (None,) + tuple(gx) + (tuple(gm) if gm is not None else (None,) * len(m))
+
+
+class RotateAxisAngle(torch.autograd.Function):
+    """Differentiable w.r.t. the vectors only (not the axis and angle)."""
+
+    @staticmethod
+    def forward(ctx, *cols):
+        x, aa = cols[:4], cols[4:]
+        ctx.save_for_backward(x[0], *aa)
+        return glv.glv_rotate_axis_angle(x, aa)
+
+    @staticmethod
+    def backward(ctx, *gy):
+        x0, *aa = ctx.saved_tensors
+        return tuple(glv.glv_rotate_axis_angle_bwd(aa, _grads(gy, x0))) + (None,) * 4
+
+
+def convert(cols, src, dst):
+    """Differentiable coordinate conversion of 4 columns from ``src`` to ``dst``."""
+    return Convert.apply(src, dst, *cols)
+
+
+def lorentz_transform(x, L):
+    """Differentiable y = L x (L: 16 row-major columns, per item or broadcast)."""
+    return LorentzTransform.apply("lorentz", *x, *L)
+
+
+def rotate(x, R):
+    """Differentiable Rotation3D of (px, py, pz) (R: 9 row-major columns)."""
+    return LorentzTransform.apply("rotate", *x, *R)
+
+
+def rotate_axis_angle(x, axis_angle):
+    """AxisAngle rotation, differentiable w.r.t. x (the axis and angle are
+    treated as constants)."""
+    return RotateAxisAngle.apply(*x, *axis_angle)
