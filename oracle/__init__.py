@@ -325,3 +325,14 @@ def best_pair(pair_offsets, pm, target):
     bm = np.empty(ne)
     _load().orc_best_pair(ctypes.c_int64(ne), _p(po), _p(pm), ctypes.c_double(target), _p(rank), _p(bm))
     return rank, bm
+
+
+def mass_vjp_q(a, b, gm):
+    """Pair-mass VJP of PtEtaPhiM legs by the chain rule in binary128."""
+    a, b = [_f64(c) for c in a], [_f64(c) for c in b]
+    gm = _f64(gm)
+    n = a[0].size
+    ga = [np.empty(n) for _ in range(4)]
+    gb = [np.empty(n) for _ in range(4)]
+    _load().orc_mass_vjp_q(ctypes.c_int64(n), _ptrs(a), _ptrs(b), _p(gm), _ptrs(ga), _ptrs(gb))
+    return tuple(ga), tuple(gb)

@@ -959,3 +959,45 @@ void orc_best_pair(int64_t ne, const int64_t* pair_offsets, const double* pm, do
     best_m[e] = bm;
   }
 }
+
+/* -------------------------------------------- the pair-mass VJP, binary128 */
+
+/* The chain rule of orc_mass_vjp for PtEtaPhiM legs carried out in binary128
+ * (the Cartesian legs, their sum, (-P, E)/|m|, and the Jacobian of each leg's
+ * conversion), each result rounded once to binary64.  The cancellation of
+ * E dE - P.dp that costs the binary64 form its digits for nearly collinear
+ * light pairs is then far below binary64 rounding: this is the reference for
+ * a cancellation-free reverse mode. */
+static void chain_ptetaphim_q(double c0, double c1, double c2, double c3, const quad u[4], quad g[4]) {
+  quad pt = c0, eta = c1, phi = c2, mm = c3;
+  quad cp = cosq(phi), sp = sinq(phi), sh = sinhq(eta), ch = coshq(eta);
+  quad pc = pt * ch;
+  quad e = sqrtq(pc * pc + mm * mm);
+  quad ue = (e > 0) ? u[3] / e : 0;
+  g[0] = u[0] * cp + u[1] * sp + u[2] * sh + ue * pt * ch * ch;
+  g[1] = u[2] * pt * ch + ue * pt * pt * sh * ch;
+  g[2] = -u[0] * pt * sp + u[1] * pt * cp;
+  g[3] = ue * mm;
+}
+
+void orc_mass_vjp_q(int64_t n, const double* const* a, const double* const* b, const double* gm,
+                    double* const* ga, double* const* gb) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    quad va[4], vb[4], w[4], u[4], g[4];
+    cart_q(ORC_PTETAPHIM, a[0][i], a[1][i], a[2][i], a[3][i], va);
+    cart_q(ORC_PTETAPHIM, b[0][i], b[1][i], b[2][i], b[3][i], vb);
+    for (int k = 0; k < 4; ++k) w[k] = va[k] + vb[k];
+    quad q = w[3] * w[3] - w[0] * w[0] - w[1] * w[1] - w[2] * w[2];
+    quad am = sqrtq(fabsq(q));
+    quad s = (am > 0) ? (quad)gm[i] / am : 0;
+    u[0] = -w[0] * s;
+    u[1] = -w[1] * s;
+    u[2] = -w[2] * s;
+    u[3] = w[3] * s;
+    chain_ptetaphim_q(a[0][i], a[1][i], a[2][i], a[3][i], u, g);
+    for (int k = 0; k < 4; ++k) ga[k][i] = (double)g[k];
+    chain_ptetaphim_q(b[0][i], b[1][i], b[2][i], b[3][i], u, g);
+    for (int k = 0; k < 4; ++k) gb[k][i] = (double)g[k];
+  }
+}

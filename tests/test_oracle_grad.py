@@ -194,3 +194,30 @@ def test_mass_vjp_scale_bounds_the_vjp():
     sa, sb = oracle.mass_vjp_scale("PxPyPzE", ca, cb, gm)
     for v, s in zip(va + vb, sa + sb):
         assert np.array_equal(s, np.abs(v))
+
+
+def test_mass_vjp_q_pins():
+    """The binary128 VJP: equal to the binary64 one on generic pairs; on the
+    collinear light stress pairs equal to central differences of the binary128
+    forward (where binary64 loses its digits); phi rotation of both legs
+    leaves m unchanged (the two phi components cancel); Euler homogeneity."""
+    g = synth.rng(310)
+    a, b = synth.pairs_generic(g, 2000)
+    gm = g.standard_normal(2000)
+    qa, qb = oracle.mass_vjp_q(a, b, gm)
+    da, db = oracle.mass_vjp("PtEtaPhiM", a, b, gm)
+    ref = np.max(np.abs(np.stack(qa + qb)), axis=0)
+    assert np.all(np.abs(np.stack(qa + qb) - np.stack(da + db)) <= 1e-9 * ref)
+    sa, sb, _ = synth.pairs_stress(synth.rng(311), 600, collinear_frac=1.0)
+    one = np.ones(600)
+    qa, qb = oracle.mass_vjp_q(sa, sb, one)
+    an = np.stack(list(qa) + list(qb))
+    fd = np.stack(_fd_mass("PtEtaPhiM", sa, sb, 1e-12, 1e-12))
+    ref = np.max(np.abs(an), axis=0)
+    assert np.all(np.abs(fd - an) <= 1e-9 * ref)
+    da, db = oracle.mass_vjp("PtEtaPhiM", sa, sb, one)
+    assert np.max(np.abs(np.stack(list(da) + list(db)) - an) / ref) > 1e-8  # binary64 loses ~10 digits here
+    assert np.all(np.abs(qa[2] + qb[2]) <= 4 * 2.0 ** -53 * np.abs(qa[2]) + 1e-300)
+    m = oracle.mass_plain_q("PtEtaPhiM", sa, sb)
+    terms = np.stack([sa[0] * qa[0], sa[3] * qa[3], sb[0] * qb[0], sb[3] * qb[3]])
+    assert np.all(np.abs(terms.sum(axis=0) - m) <= 8 * 2.0 ** -53 * np.abs(terms).sum(axis=0))
