@@ -144,6 +144,23 @@ glv_status glv_invariant_mass_bwd(glv_dtype dtype, glv_coords coords, int64_t n,
                                   const void* grad_m, void* const grad_a[4], void* const grad_b[4],
                                   void* stream);
 
+/* Reverse mode of the cancellation-free pair mass (the GLV_COMPENSATED form,
+ * PtEtaPhiM legs only; not in the paper): the same gradients as
+ * glv_invariant_mass_bwd, computed from K = E_a E_b - p_a.p_b written as
+ * mTa mTb cosh(dy) - pta ptb cos(dphi) and its derivatives, so that nearly
+ * collinear light pairs keep their digits in FP32 (the plain form subtracts
+ * E dE from P.dp).  m dm = Ma dMa + Mb dMb + dK with, for leg a (leg b with
+ * dy and dphi negated), dK/dpta = (pta mTb/mTa) 2 sinh^2(dy/2) + ptb 2
+ * sin^2(dphi/2) + (pta^2 Mb^2 - ptb^2 Ma^2)/((pta mTb + ptb mTa) mTa) + mTa
+ * mTb sinh(dy) dya/dpta, dK/detaa = mTa mTb sinh(dy) pta cosh(etaa)/Ea,
+ * dK/dphia = pta ptb sin(dphi), dK/dMa = (Ma/mTa) mTb cosh(dy) + mTa mTb
+ * sinh(dy) dya/dMa.  No FP64 redo.  Zero where m = 0; a leg with pt = M = 0
+ * gets zero rows.  Arguments, aliasing and errors as glv_invariant_mass_bwd
+ * (no coords argument). */
+glv_status glv_invariant_mass_comp_bwd(glv_dtype dtype, int64_t n, const void* const a[4], const void* const b[4],
+                                       const void* grad_m, void* const grad_a[4], void* const grad_b[4],
+                                       void* stream);
+
 /* Active Lorentz boost (Sec. 4.1, ApplyBoost) of Cartesian vectors x by
  * velocity beta: with g = 1/sqrt(1 - beta^2), k = g^2/(1 + g), s = beta.p,
  *   E' = g (E + s),   p' = p + (k s + g E) beta.

@@ -29,7 +29,7 @@ EXPORTS = (
     "glv_current_tiling", "glv_autotune_event_reduce_bwd", "glv_current_tiling_bwd", "glv_status_str",
     "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd", "glv_lorentz_transform",
     "glv_lorentz_transform_bwd", "glv_rotate", "glv_rotate_bwd", "glv_rotate_axis_angle",
-    "glv_rotate_axis_angle_bwd", "glv_mass_histogram", "glv_event_best_pair",
+    "glv_rotate_axis_angle_bwd", "glv_mass_histogram", "glv_event_best_pair", "glv_invariant_mass_comp_bwd",
 )
 
 
@@ -50,6 +50,7 @@ _i64 = ctypes.c_int64
 _SIGS = {
     "glv_invariant_mass": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp],
     "glv_invariant_mass_bwd": [_i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
+    "glv_invariant_mass_comp_bwd": [_i, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_boost": [_i, _i64, _vp, _vp, _i64, _vp, _vp],
     "glv_boost_bwd": [_i, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
     "glv_pair_offsets": [_i64, _vp, _vp, _vp],

@@ -12,14 +12,17 @@ class InvariantMass(torch.autograd.Function):
     @staticmethod
     def forward(ctx, coords, mode, *cols):
         a, b = cols[:4], cols[4:]
-        ctx.coords = coords
+        ctx.coords, ctx.mode = coords, mode
         ctx.save_for_backward(*cols)
         return glv.glv_invariant_mass(a, b, coords=coords, mode=mode)
 
     @staticmethod
     def backward(ctx, gm):
         cols = ctx.saved_tensors
-        ga, gb = glv.glv_invariant_mass_bwd(cols[:4], cols[4:], gm.contiguous(), coords=ctx.coords)
+        if ctx.mode == "compensated":  # the reverse mode of the cancellation-free form
+            ga, gb = glv.glv_invariant_mass_comp_bwd(cols[:4], cols[4:], gm.contiguous())
+        else:
+            ga, gb = glv.glv_invariant_mass_bwd(cols[:4], cols[4:], gm.contiguous(), coords=ctx.coords)
         return (None, None) + tuple(ga) + tuple(gb)
 
 

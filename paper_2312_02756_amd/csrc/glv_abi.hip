@@ -334,13 +334,11 @@ glv_status glv_invariant_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_
   return hip_status(glv::launch_mass(dt, co, mode, n, a, b, m, fallback, (hipStream_t)stream));
 }
 
-glv_status glv_invariant_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* const a[4],
-                                  const void* const b[4], const void* gm, void* const ga[4], void* const gb[4],
-                                  void* stream) {
-  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
-  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
-  if (n < 0) return GLV_EINVAL_SIZE;
-  if (n == 0) return GLV_OK;
+namespace {
+
+// Arguments of a pair-mass reverse mode (validated before any launch).
+glv_status mass_bwd_args(glv_dtype dt, int64_t n, const void* const a[4], const void* const b[4], const void* gm,
+                         void* const ga[4], void* const gb[4]) {
   if (!nonnull<4>(a) || !nonnull<4>(b) || !gm || !nonnull<4>((const void* const*)ga) ||
       !nonnull<4>((const void* const*)gb))
     return GLV_EINVAL_NULL;
@@ -353,7 +351,30 @@ glv_status glv_invariant_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const 
     outs.push_back(rng(gb[k], n, es));
   }
   ins.push_back(rng(gm, n, es));
-  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  return any_overlap(outs, ins) ? GLV_EINVAL_ALIAS : GLV_OK;
+}
+
+}  // namespace
+
+glv_status glv_invariant_mass_comp_bwd(glv_dtype dt, int64_t n, const void* const a[4], const void* const b[4],
+                                       const void* gm, void* const ga[4], void* const gb[4], void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
+  const glv_status st = mass_bwd_args(dt, n, a, b, gm, ga, gb);
+  if (st != GLV_OK) return st;
+  return hip_status(glv::launch_mass_comp_bwd(dt, n, a, b, gm, ga, gb, (hipStream_t)stream));
+}
+
+glv_status glv_invariant_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* const a[4],
+                                  const void* const b[4], const void* gm, void* const ga[4], void* const gb[4],
+                                  void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  if (n < 0) return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
+  const glv_status st = mass_bwd_args(dt, n, a, b, gm, ga, gb);
+  if (st != GLV_OK) return st;
   return hip_status(glv::launch_mass_bwd(dt, co, n, a, b, gm, ga, gb, (hipStream_t)stream));
 }
 

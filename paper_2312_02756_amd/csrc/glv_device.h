@@ -570,4 +570,98 @@ __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T*
   return m2;
 }
 
+// ------------------------------------- reverse mode of the cancellation-free mass
+
+// A leg of the compensated form with the pieces its reverse mode needs.
+template <typename T>
+struct LegCJ {
+  LegC<T> c;
+  T mass, sh, ch, e;  // M as given, sinh(eta), cosh(eta), E
+};
+
+template <typename T>
+__device__ __forceinline__ LegCJ<T> comp_leg_j(T pt, T eta, T phi, T mass) {
+  LegCJ<T> L;
+  L.c.pt = pt;
+  L.c.eta = eta;
+  L.c.phi = phi;
+  L.mass = mass;
+  const T mm = mass * mass;
+  L.c.m2 = mm;
+  if constexpr (sizeof(T) == 8)
+    fast_sinhcosh<false>(eta, &L.sh, &L.ch);
+  else
+    fast_sinhcosh_rcp(eta, &L.sh, &L.ch);
+  const T pc = pt * L.ch;
+  L.e = sqrt_budgeted(pc * pc + mm);
+  leg_shift<T, false>(pt, mm, L.sh, pc, L.e, &L.c.mt, &L.c.delta);
+  return L;
+}
+
+// m dm/d(pt, eta, phi, M) of leg a with partner b, from K = E_a E_b - p_a.p_b
+// = mTa mTb cosh(dy) - pta ptb cos(dphi) and m dm = Ma dMa + Mb dMb + dK:
+//   dK/dpta  = (pta mTb / mTa) 2 sinh^2(dy/2) + ptb 2 sin^2(dphi/2)
+//              + (pta^2 Mb^2 - ptb^2 Ma^2) / ((pta mTb + ptb mTa) mTa)
+//              + mTa mTb sinh(dy) dya/dpta
+//   dK/detaa = mTa mTb sinh(dy) pta cosh(etaa) / Ea
+//   dK/dphia = pta ptb sin(dphi)
+//   dK/dMa   = (Ma / mTa) mTb cosh(dy) + mTa mTb sinh(dy) dya/dMa
+// with dy/dpt = sinh(eta) M^2 / (mT^2 E) and dy/dM = -pt sinh(eta) M / (mT^2 E)
+// at fixed eta (from sinh y = pt sinh(eta) / mT).  The first row regroups
+// mTb pta/mTa cosh(dy) - ptb cos(dphi), which cancels for nearly collinear
+// pairs, into terms of the forward form; only its third term is a signed
+// difference, of two squares products.  shdy = sinh(dy), sdphi = sin(dphi)
+// as seen from leg a.  Legs with mT = 0 (pt = M = 0) get zero rows.
+template <typename T>
+__device__ __forceinline__ void comp_leg_rows(const LegCJ<T>& a, const LegCJ<T>& b, T sh2, T chdy, T shdy, T cf1,
+                                              T sdphi, T g[4]) {
+  const T imt = (a.c.mt > T(0)) ? T(1) / a.c.mt : T(0);
+  const T ie = (a.e > T(0)) ? T(1) / a.e : T(0);
+  const T pp = a.c.mt * b.c.mt;
+  const T w = pp * shdy * ie * imt * imt;  // mTa mTb sinh(dy) / (mTa^2 Ea)
+  const T sden = (a.c.pt * b.c.mt + b.c.pt * a.c.mt) * a.c.mt;
+  const T diff = (sden > T(0)) ? (a.c.pt * a.c.pt * b.c.m2 - b.c.pt * b.c.pt * a.c.m2) / sden : T(0);
+  g[0] = a.c.pt * b.c.mt * imt * sh2 + b.c.pt * cf1 + diff + w * a.sh * a.c.m2;
+  g[1] = pp * shdy * a.c.pt * a.ch * ie;
+  g[2] = a.c.pt * b.c.pt * sdphi;
+  g[3] = a.mass + a.mass * imt * b.c.mt * chdy - w * a.c.pt * a.sh * a.mass;
+}
+
+// Both legs' gradients of the cancellation-free pair mass times gm.
+template <typename T>
+__device__ __forceinline__ void comp_pair_vjp(const LegCJ<T>& a, const LegCJ<T>& b, T gm, T ga[4], T gb[4]) {
+  const T dy = (a.c.eta - b.c.eta) + (a.c.delta - b.c.delta);
+  T s1;
+  if constexpr (sizeof(T) == 8)
+    s1 = fast_sinh<false>(T(0.5) * dy);
+  else
+    s1 = fast_sinh(T(0.5) * dy);
+  const T c1 = d_sqrt(T(1) + s1 * s1);
+  const T sh2 = T(2) * s1 * s1;  // cosh(dy) - 1
+  const T shdy = T(2) * s1 * c1;
+  const T chdy = T(1) + sh2;
+  const T h = T(0.5) * dphi_reduced(a.c.phi, b.c.phi);
+  // sine and cosine of the half difference from the reduced sincos: its
+  // reduction by pi/2 keeps cos(h) accurate next to |h| = pi/2, where
+  // sqrt(1 - sin^2) would cancel (sin(dphi) of nearly back-to-back legs)
+  T hs, hc;
+  if constexpr (sizeof(T) == 8)
+    fast_sincos<false>(h, &hs, &hc);
+  else
+    fast_sincos(h, &hs, &hc);
+  const T cf1 = T(2) * hs * hs;  // 1 - cos(dphi)
+  const T sdphi = T(2) * hs * hc;
+  T k;
+  const T m2 = comp_pair_m2<T>(a.c, b.c, &k, nullptr);
+  const T s = (m2 > T(0)) ? gm * inv_sqrt(m2) : T(0);
+  T ra[4], rb[4];
+  comp_leg_rows<T>(a, b, sh2, chdy, shdy, cf1, sdphi, ra);
+  comp_leg_rows<T>(b, a, sh2, chdy, -shdy, cf1, -sdphi, rb);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    ga[k2] = s * ra[k2];
+    gb[k2] = s * rb[k2];
+  }
+}
+
 }  // namespace glv

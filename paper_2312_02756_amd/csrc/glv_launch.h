@@ -17,6 +17,10 @@ hipError_t launch_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* c
                            const void* const b[4], const void* gm, void* const ga[4],
                            void* const gb[4], hipStream_t s);
 
+// Reverse mode of the cancellation-free (compensated) pair mass, PtEtaPhiM legs.
+hipError_t launch_mass_comp_bwd(glv_dtype dt, int64_t n, const void* const a[4], const void* const b[4],
+                                const void* gm, void* const ga[4], void* const gb[4], hipStream_t s);
+
 hipError_t launch_boost(glv_dtype dt, int64_t n, const void* const x[4], const void* const beta[3],
                         int64_t beta_stride, void* const y[4], hipStream_t s);
 

@@ -181,6 +181,45 @@ struct MassBwd {
   }
 };
 
+// Reverse mode of the cancellation-free pair mass (PtEtaPhiM legs): the
+// gradient rows built from the forward form's own terms.
+template <typename T>
+struct MassCompBwd {
+  static constexpr bool kCounts = false;
+  static constexpr int kBlock = kBlockAlu;
+  Cols4<T> a, b;
+  const T* gm;
+  OutCols4<T> ga, gb;
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> pa[4], pb[4], pg, oa[4], ob[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pa[k] = load_pack<T, V>(a.c[k], i);
+      pb[k] = load_pack<T, V>(b.c[k], i);
+    }
+    pg = load_pack<T, V>(gm, i);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const LegCJ<T> la = comp_leg_j<T>(pa[0].v[e], pa[1].v[e], pa[2].v[e], pa[3].v[e]);
+      const LegCJ<T> lb = comp_leg_j<T>(pb[0].v[e], pb[1].v[e], pb[2].v[e], pb[3].v[e]);
+      T ra[4], rb[4];
+      comp_pair_vjp<T>(la, lb, pg.v[e], ra, rb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        oa[k].v[e] = ra[k];
+        ob[k].v[e] = rb[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      store_pack<T, V>(ga.c[k], i, oa[k]);
+      store_pack<T, V>(gb.c[k], i, ob[k]);
+    }
+    return 0;
+  }
+};
+
 // ------------------------------------------------------------ conversion
 
 // Coordinates TO of vectors given in FROM (through the Cartesian components;
@@ -756,6 +795,19 @@ hipError_t launch_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, co
                        const void* const b[4], void* m, unsigned long long* fb, hipStream_t s) {
   if (dt == GLV_F64) return mass_typed<double>(co, mode, n, a, b, m, nullptr, s);
   return mass_typed<float>(co, mode, n, a, b, m, fb, s);
+}
+
+hipError_t launch_mass_comp_bwd(glv_dtype dt, int64_t n, const void* const a[4], const void* const b[4],
+                                const void* gm, void* const ga[4], void* const gb[4], hipStream_t s) {
+  const bool al = all16<4>(a) && all16<4>(b) && aligned16(gm) && all16<4>((const void* const*)ga) &&
+                  all16<4>((const void* const*)gb);
+  if (dt == GLV_F64)
+    return dispatch_width<double>(MassCompBwd<double>{cols4<double>(a), cols4<double>(b), (const double*)gm,
+                                                      out4<double>(ga), out4<double>(gb)},
+                                  al, n, nullptr, s);
+  return dispatch_width<float>(MassCompBwd<float>{cols4<float>(a), cols4<float>(b), (const float*)gm,
+                                                  out4<float>(ga), out4<float>(gb)},
+                               al, n, nullptr, s);
 }
 
 hipError_t launch_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* const a[4],

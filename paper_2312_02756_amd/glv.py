@@ -88,6 +88,25 @@ def glv_invariant_mass(a, b, coords="PtEtaPhiM", mode="plain", out=None, fallbac
     return m
 
 
+def glv_invariant_mass_comp_bwd(a, b, grad_m):
+    """Gradients of the cancellation-free pair mass of PtEtaPhiM legs (the
+    reverse mode that keeps its digits for nearly collinear light pairs)."""
+    dev, dt = a[0].device, a[0].dtype
+    _check_device(a[0])
+    n = a[0].numel()
+    a = _cols(a, n, dt, dev, "a")
+    b = _cols(b, n, dt, dev, "b")
+    (grad_m,) = _cols([grad_m], n, dt, dev, "grad_m")
+    ga = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    gb = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    check("glv_invariant_mass_comp_bwd",
+          _lib.load().glv_invariant_mass_comp_bwd(_dtype_code(dt), n, P4(*[t.data_ptr() for t in a]),
+                                                  P4(*[t.data_ptr() for t in b]), _ptr(grad_m),
+                                                  P4(*[t.data_ptr() for t in ga]), P4(*[t.data_ptr() for t in gb]),
+                                                  _stream(dev)))
+    return ga, gb
+
+
 def glv_invariant_mass_bwd(a, b, grad_m, coords="PtEtaPhiM"):
     dev, dt = a[0].device, a[0].dtype
     _check_device(a[0])
