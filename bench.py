@@ -35,7 +35,8 @@ reverse mode with the matrix gradient, timed the same way.
 
 analysis: a 1000-bin histogram of the step's 2^24 FP64 pair masses and the
 per-event pair closest to 91.1876 GeV over the jagged events' pair masses,
-timed the same way.
+and the reverse mode of the cancellation-free mass on the 2^24 FP32 stress
+pairs (68 B/pair), timed the same way.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--no-convert]
                        [--no-transform] [--no-analysis] [--calib-copy]
@@ -86,7 +87,8 @@ TRANSFORM_CASES = {
     "lorentz_broadcast_f32": ("TransformFwd<float, 0, 0>", 32),
 }
 # The analysis step, measured after the step: kernel symbols.
-ANALYSIS_SYMBOL = {"mass_histogram": "k_hist_lds<double, 2>", "event_best_pair": "k_best_pair<double>"}
+ANALYSIS_SYMBOL = {"mass_histogram": "k_hist_lds<double, 2>", "event_best_pair": "k_best_pair<double>",
+                   "mass_comp32_bwd": "MassCompBwd<float>"}
 ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()},
                **{k: v[0] for k, v in TRANSFORM_CASES.items()}, **ANALYSIS_SYMBOL}
 
@@ -461,6 +463,14 @@ def main():
                                                                    91.1876, rank.data_ptr(), best.data_ptr(), sp),
                 stream, args.warmup, K, N_EVENTS, 8 * n_pairs + 8 * (N_EVENTS + 1) + 16 * N_EVENTS),
         }
+        GM32 = GM.to(torch.float32)
+        GA32 = tuple(torch.empty(N_ITEMS, dtype=torch.float32, device=dev) for _ in range(4))
+        GB32 = tuple(torch.empty(N_ITEMS, dtype=torch.float32, device=dev) for _ in range(4))
+        cGA32, cGB32 = ptr4(GA32), ptr4(GB32)
+        analysis["mass_comp32_bwd"] = time_launches(
+            "mass_comp32_bwd", lambda: lib.glv_invariant_mass_comp_bwd(F32, N_ITEMS, cSA, cSB, GM32.data_ptr(), cGA32,
+                                                                       cGB32, sp),
+            stream, args.warmup, K, N_ITEMS, 68 * N_ITEMS)
         analysis["mass_histogram"]["bins"] = 1000
         analysis["event_best_pair"]["pairs"] = n_pairs
 
