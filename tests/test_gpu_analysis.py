@@ -83,3 +83,21 @@ def test_best_pair_full_size():
     wr, wm = oracle.best_pair(po, pm, 91.1876)
     assert np.array_equal(host(rank), wr)
     assert np.array_equal(host(bm), wm, equal_nan=True)
+
+
+def test_edge_cases_empty_and_giant_event():
+    """Empty inputs launch nothing; one event of 2,000 particles (1,999,000
+    pairs) among small ones is walked by its lane group to the end."""
+    e64 = torch.empty(0, dtype=torch.float64, device=DEV)
+    c = glv.glv_mass_histogram(e64, 0.0, 1.0, 5)
+    assert host(c).tolist() == [0] * 7
+    r, m = glv.glv_event_best_pair(torch.zeros(1, dtype=torch.int64, device=DEV), e64, 91.0)
+    assert r.numel() == 0 and m.numel() == 0
+    counts = np.array([3, 2000, 0, 5], dtype=np.int64)
+    po = oracle.pair_offsets(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+    pm = synth.rng(962).uniform(0.0, 200.0, int(po[-1]))
+    pm[int(po[1]) + 1_500_000] = 91.0  # the closest pair deep inside the large event
+    rank, bm = glv.glv_event_best_pair(torch.from_numpy(po).to(DEV), torch.from_numpy(pm).to(DEV), 91.0)
+    wr, wm = oracle.best_pair(po, pm, 91.0)
+    assert np.array_equal(host(rank), wr) and wr[1] == 1_500_000
+    assert np.array_equal(host(bm), wm, equal_nan=True)

@@ -149,3 +149,12 @@ def test_lorentz_full_size_sampled():
     for k in range(16):
         r, _ = worst(np.abs(rgm[k][idx] - wgm[k]), U64 * np.abs(wgm[k]) + 1e-300)
         assert r <= 1.0
+
+
+def test_empty_inputs():
+    e = tuple(torch.empty(0, dtype=torch.float64, device="cuda:0") for _ in range(4))
+    one = lambda k: tuple(torch.ones(1, dtype=torch.float64, device="cuda:0") for _ in range(k))  # noqa: E731
+    assert all(t.numel() == 0 for t in glv.glv_lorentz_transform(e, one(16)))
+    assert all(t.numel() == 0 for t in glv.glv_rotate(e, one(9)))
+    assert all(t.numel() == 0 for t in glv.glv_rotate_axis_angle(e, one(4)))
+    assert all(t.numel() == 0 for t in glv.glv_convert(e, "PxPyPzE", "PtEtaPhiM"))
