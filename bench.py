@@ -3,26 +3,34 @@
 One step is one pass of every kernel of the path over one batch of synthetic,
 collider-shaped input already resident in HBM:
 
-  mass_fwd     FP64 pair mass, PtEtaPhiM, 2^24 pairs           (72 B/pair)
-  mass_bwd     FP64 reverse mode of the same pairs              (136 B/pair)
-  boost_fwd    FP64 boost, per-item beta, 2^24 vectors          (88 B/vector)
-  boost_bwd    FP64 reverse mode of the boost                   (144 B/vector)
-  mass_comp32  FP32 compensated pair mass, 2^24 light pairs     (36 B/pair)
+  mass_fwd / mass_fwd32     pair mass, PtEtaPhiM, 2^24 pairs     (72 / 36 B/pair)
+  mass_bwd / mass_bwd32     reverse mode of the same pairs        (136 / 68 B/pair)
+  boost_fwd / boost_fwd32   boost, per-item beta, 2^24 vectors    (88 / 44 B/vector)
+  boost_bwd / boost_bwd32   reverse mode of the boost             (144 / 72 B/vector)
+                            (FP64, then the same inputs rounded to FP32)
+  mass_comp32  FP32 compensated pair mass, 2^26 light pairs with
+               10 % nearly collinear (the precision-stress workload) (36 B/pair)
   event_reduce FP64 jagged reduction, 2^20 Poisson(8) events:
                totals, event mass and all pair masses           (~568 B/event)
   event_reduce32c  the same events in FP32, compensated mode     (~292 B/event)
   event_reduce_bwd FP64 reverse mode of the jagged reduction     (~824 B/event)
 
-value = items processed per second, in Gevents/s, where an item is a pair
-(through forward and backward), a vector (forward and backward), a
-compensated pair, a collider event (FP64 forward and backward) or a collider
-event in the FP32 compensated mode; every kernel is also reported
-separately with its algorithmic bytes, achieved GB/s and fraction of the
-8 TB/s HBM peak.  Per-kernel times come from HIP events recorded on the
-stream the kernels run on, inside the timed steps.
+value = kernel-items processed per second, in Gevents/s: every kernel of the
+step counts the items it processes (a pair, a vector or a collider event), so
+a pair through the FP64 forward and backward counts twice.  Every kernel is
+also reported separately with its algorithmic bytes, achieved GB/s and
+fraction of the 8 TB/s HBM peak.  Per-kernel times come from HIP events
+recorded on the stream the kernels run on, inside the timed steps.
 
 cpu_baseline: the CPU oracle (test infrastructure) timed on the host cores on
 one step's workload, repeated until about 10 s have passed, in the same unit.
+Its accurate (cancellation-free, binary64) masses of the 2^26 stress pairs
+are kept as the reference of the precision comparison below.
+
+fp32_comp_vs_fp64_plain: the FP32 compensated, plain FP64 and plain FP32
+masses of the 2^26 stress pairs, each launch timed and each result compared,
+pair by pair, with that oracle reference (max and 99.9th percentile, in GeV
+and relative, collinear and generic pairs apart, and the FP64 redo count).
 
 convert: the stand-alone coordinate conversions (Sec. 3.1), FP64 and FP32,
 forward (2 x 4 columns per vector) and reverse mode (3 x 4 columns), each
@@ -33,13 +41,13 @@ transform: general Lorentz transformations (4x4) and rotations (3x3 matrix,
 axis and angle), one for all vectors or one per vector, and the per-item
 reverse mode with the matrix gradient, timed the same way.
 
-analysis: a 1000-bin histogram of the step's 2^24 FP64 pair masses and the
-per-event pair closest to 91.1876 GeV over the jagged events' pair masses,
-and the reverse mode of the cancellation-free mass on the 2^24 FP32 stress
-pairs (68 B/pair), timed the same way.
+analysis: a 1000-bin histogram of 2^26 FP64 pair masses (512 MiB, twice the
+last-level cache) and the per-event pair closest to 91.1876 GeV over the
+jagged events' pair masses, and the reverse mode of the cancellation-free mass
+on 2^24 FP32 stress pairs (68 B/pair), timed the same way.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-compare] [--no-convert]
-                       [--no-transform] [--no-analysis] [--calib-copy]
+                       [--no-transform] [--no-analysis] [--calib-copy] [--kernels a,b,...]
 """
 
 import argparse
@@ -58,12 +66,14 @@ if ROOT not in sys.path:
 METRIC = "Gevents/s & HBM GB/s (% of peak): mass/boost fwd+bwd, FP32-comp vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
 N_ITEMS = 1 << 24
+N_STRESS = 1 << 26
 N_EVENTS = 1 << 20
-KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_comp32", "event_reduce", "event_reduce32c",
-           "event_reduce_bwd"]
+KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_fwd32", "mass_bwd32", "boost_fwd32",
+           "boost_bwd32", "mass_comp32", "event_reduce", "event_reduce32c", "event_reduce_bwd"]
 KERNEL_SYMBOL = {
     "mass_fwd": "MassPlain<double, 1>", "mass_bwd": "MassBwd<double, 1>", "boost_fwd": "BoostFwd<double, 1>",
-    "boost_bwd": "BoostBwd<double, 1, true>", "mass_comp32": "MassComp<float>",
+    "boost_bwd": "BoostBwd<double, 1, true>", "mass_fwd32": "MassPlain<float, 1>", "mass_bwd32": "MassBwd<float, 1>",
+    "boost_fwd32": "BoostFwd<float, 1>", "boost_bwd32": "BoostBwd<float, 1, true>", "mass_comp32": "MassComp<float>",
     "event_reduce": "k_event_reduce<double, 1, 0>", "event_reduce32c": "k_event_reduce<float, 1, 1>",
     "event_reduce_bwd": "k_event_reduce_bwd<double, 1>",
 }
@@ -105,6 +115,8 @@ def parse():
     ap.add_argument("--no-convert", action="store_true", help="skip the coordinate-conversion measurements")
     ap.add_argument("--no-transform", action="store_true", help="skip the general-transformation measurements")
     ap.add_argument("--no-analysis", action="store_true", help="skip the histogram and best-pair measurements")
+    ap.add_argument("--kernels", default=None,
+                    help="comma-separated subset of the step's kernels to run (profiling runs); default all")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -154,9 +166,9 @@ def summarize_trace(trace_csv, bench_json):
            "Command (from the repository root `R` on one MI355X):", "", "```", TRACE_CMD, "```", "",
            f"Source: `bench_kernel_trace.csv`; per step kernel its last {bench['warmup']} warm-up + "
            f"{bench['steps']} timed dispatches; jagged tilings (block, events per tile, LDS particles) "
-           f"{tuple(bench['config']['event_tiling'].values())} FP64, "
-           f"{tuple(bench['config'].get('event_tiling_fp32_comp', {}).values())} FP32 compensated, "
-           f"{tuple(bench['config'].get('event_tiling_bwd', {}).values())} backward (autotuned on "
+           f"{tuple((bench['config'].get('event_tiling') or {}).values())} FP64, "
+           f"{tuple((bench['config'].get('event_tiling_fp32_comp') or {}).values())} FP32 compensated, "
+           f"{tuple((bench['config'].get('event_tiling_bwd') or {}).values())} backward (autotuned on "
            "these events, the trial launches excluded); the coordinate conversions, general "
            "transformations and the analysis step run after the step, each warm-up + steps times.  Algorithmic bytes per launch as in `bench.py`.", "",
            "| kernel | calls | avg µs | min µs | share % | block, grid, LDS B | alg. bytes / launch | alg. GB/s (avg) "
@@ -298,7 +310,7 @@ def main():
     gr = synth.rng(synth.GRADS)
     gm = synth.upstream(gr, N_ITEMS, 1)[0]
     gy = synth.upstream(gr, N_ITEMS, 4)
-    sa, sb, collinear = synth.pairs_stress(synth.rng(synth.STRESS), N_ITEMS)
+    sa, sb, collinear = synth.pairs_stress(synth.rng(synth.STRESS), N_STRESS)
     sa, sb = synth.as_dtype(sa, np.float32), synth.as_dtype(sb, np.float32)
     off, parts = synth.jagged_events(synth.rng(synth.JAGGED), N_EVENTS)
     parts32 = synth.as_dtype(parts, np.float32)
@@ -314,6 +326,9 @@ def main():
     GM = gpu([gm], torch.float64)[0]
     X, BETA = gpu(x, torch.float64), gpu(beta, torch.float64)
     GY = gpu(gy, torch.float64)
+    # the FP32 rows take the same inputs rounded to FP32
+    to32 = lambda cols: tuple(t.to(torch.float32) for t in cols)  # noqa: E731
+    A32, B32, GM32, X32, BETA32, GY32 = to32(A), to32(B), GM.to(torch.float32), to32(X), to32(BETA), to32(GY)
     SA, SB = gpu(sa, torch.float32), gpu(sb, torch.float32)
     P = gpu(parts, torch.float64)
     P32 = gpu(parts32, torch.float32)
@@ -325,16 +340,30 @@ def main():
     GTOT = gpu(g_tot, torch.float64)
     GEM = gpu([g_em], torch.float64)[0]
     GPAIR = gpu([g_pair], torch.float64)[0]
+    run = KERNELS if not args.kernels else [k for k in KERNELS if k in args.kernels.split(",")]
     # the jagged reductions run with the tilings the autotuners pick on these events
-    tiling = glv.glv_autotune_event_reduce(P, OFF, PO)
-    tiling32c = glv.glv_autotune_event_reduce(P32, OFF, PO, mode="compensated")
-    tiling_bwd = glv.glv_autotune_event_reduce_bwd(P, OFF, PO, grad_total=GTOT, grad_event_m=GEM,
-                                                   grad_pair_m=GPAIR)
+    tiling = glv.glv_autotune_event_reduce(P, OFF, PO) if "event_reduce" in run else None
+    tiling32c = (glv.glv_autotune_event_reduce(P32, OFF, PO, mode="compensated") if "event_reduce32c" in run
+                 else None)
+    tiling_bwd = (glv.glv_autotune_event_reduce_bwd(P, OFF, PO, grad_total=GTOT, grad_event_m=GEM,
+                                                    grad_pair_m=GPAIR) if "event_reduce_bwd" in run else None)
     # outputs preallocated once, reused every step
-    M = torch.empty(N_ITEMS, dtype=torch.float64, device=dev)
-    MC = torch.empty(N_ITEMS, dtype=torch.float32, device=dev)
+    new = lambda n, dt, k: tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(k))  # noqa: E731
+    (M,) = new(N_ITEMS, torch.float64, 1)
+    (M32,) = new(N_ITEMS, torch.float32, 1)
+    (MC,) = new(N_STRESS, torch.float32, 1)
     FB = torch.zeros(1, dtype=torch.int64, device=dev)
-    Y = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
+    Y, GA, GB, GX = new(N_ITEMS, torch.float64, 4), new(N_ITEMS, torch.float64, 4), new(N_ITEMS, torch.float64, 4), \
+        new(N_ITEMS, torch.float64, 4)
+    GBETA = new(N_ITEMS, torch.float64, 3)
+    Y32, GA32, GB32, GX32 = new(N_ITEMS, torch.float32, 4), new(N_ITEMS, torch.float32, 4), \
+        new(N_ITEMS, torch.float32, 4), new(N_ITEMS, torch.float32, 4)
+    GBETA32 = new(N_ITEMS, torch.float32, 3)
+    TOT, (EM,), (PM,) = new(N_EVENTS, torch.float64, 4), new(N_EVENTS, torch.float64, 1), new(n_pairs, torch.float64, 1)
+    TOT32, (EM32,), (PM32,) = new(N_EVENTS, torch.float32, 4), new(N_EVENTS, torch.float32, 1), \
+        new(n_pairs, torch.float32, 1)
+    FBJ = torch.zeros(1, dtype=torch.int64, device=dev)
+    GP = new(n_part, torch.float64, 4)
     torch.cuda.synchronize()
 
     from paper_2312_02756_amd import _lib
@@ -344,22 +373,12 @@ def main():
     sp = stream.cuda_stream
     ptr4 = lambda cols: P4(*[t.data_ptr() for t in cols])  # noqa: E731
     ptr3 = lambda cols: P3(*[t.data_ptr() for t in cols])  # noqa: E731
-    GA = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
-    GB = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
-    GX = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(4))
-    GBETA = tuple(torch.empty(N_ITEMS, dtype=torch.float64, device=dev) for _ in range(3))
-    TOT = tuple(torch.empty(N_EVENTS, dtype=torch.float64, device=dev) for _ in range(4))
-    EM = torch.empty(N_EVENTS, dtype=torch.float64, device=dev)
-    PM = torch.empty(n_pairs, dtype=torch.float64, device=dev)
-    TOT32 = tuple(torch.empty(N_EVENTS, dtype=torch.float32, device=dev) for _ in range(4))
-    EM32 = torch.empty(N_EVENTS, dtype=torch.float32, device=dev)
-    PM32 = torch.empty(n_pairs, dtype=torch.float32, device=dev)
-    FBJ = torch.zeros(1, dtype=torch.int64, device=dev)
-    GP = tuple(torch.empty(n_part, dtype=torch.float64, device=dev) for _ in range(4))
 
     # C-ABI calls with pointers marshalled once
     cA, cB, cX, cBETA, cGY = ptr4(A), ptr4(B), ptr4(X), ptr3(BETA), ptr4(GY)
     cGA, cGB, cY, cGX, cGBETA = ptr4(GA), ptr4(GB), ptr4(Y), ptr4(GX), ptr3(GBETA)
+    cA32, cB32, cX32, cBETA32, cGY32 = ptr4(A32), ptr4(B32), ptr4(X32), ptr3(BETA32), ptr4(GY32)
+    cGA32, cGB32, cY32, cGX32, cGBETA32 = ptr4(GA32), ptr4(GB32), ptr4(Y32), ptr4(GX32), ptr3(GBETA32)
     cSA, cSB, cP, cTOT = ptr4(SA), ptr4(SB), ptr4(P), ptr4(TOT)
     cP32, cTOT32, cGTOT, cGP = ptr4(P32), ptr4(TOT32), ptr4(GTOT), ptr4(GP)
     F32, F64, PTM, CART = _lib.GLV_F32, _lib.GLV_F64, _lib.GLV_PTETAPHIM, _lib.GLV_PXPYPZE
@@ -370,7 +389,12 @@ def main():
         "mass_bwd": lambda: lib.glv_invariant_mass_bwd(F64, PTM, N_ITEMS, cA, cB, GM.data_ptr(), cGA, cGB, sp),
         "boost_fwd": lambda: lib.glv_boost(F64, N_ITEMS, cX, cBETA, 1, cY, sp),
         "boost_bwd": lambda: lib.glv_boost_bwd(F64, N_ITEMS, cX, cBETA, 1, cGY, cGX, cGBETA, sp),
-        "mass_comp32": lambda: lib.glv_invariant_mass(F32, PTM, COMP, N_ITEMS, cSA, cSB, MC.data_ptr(),
+        "mass_fwd32": lambda: lib.glv_invariant_mass(F32, PTM, PLAIN, N_ITEMS, cA32, cB32, M32.data_ptr(), None, sp),
+        "mass_bwd32": lambda: lib.glv_invariant_mass_bwd(F32, PTM, N_ITEMS, cA32, cB32, GM32.data_ptr(), cGA32,
+                                                         cGB32, sp),
+        "boost_fwd32": lambda: lib.glv_boost(F32, N_ITEMS, cX32, cBETA32, 1, cY32, sp),
+        "boost_bwd32": lambda: lib.glv_boost_bwd(F32, N_ITEMS, cX32, cBETA32, 1, cGY32, cGX32, cGBETA32, sp),
+        "mass_comp32": lambda: lib.glv_invariant_mass(F32, PTM, COMP, N_STRESS, cSA, cSB, MC.data_ptr(),
                                                       FB.data_ptr(), sp),
         "event_reduce": lambda: lib.glv_event_reduce(F64, PTM, PLAIN, N_EVENTS, OFF.data_ptr(), PO.data_ptr(), cP,
                                                      cTOT, EM.data_ptr(), PM.data_ptr(), None, None, sp),
@@ -384,18 +408,18 @@ def main():
     # algorithmic bytes per launch: what each kernel must read and write once
     alg_bytes = {
         "mass_fwd": 72 * N_ITEMS, "mass_bwd": 136 * N_ITEMS, "boost_fwd": 88 * N_ITEMS,
-        "boost_bwd": 144 * N_ITEMS, "mass_comp32": 36 * N_ITEMS,
+        "boost_bwd": 144 * N_ITEMS, "mass_fwd32": 36 * N_ITEMS, "mass_bwd32": 68 * N_ITEMS,
+        "boost_fwd32": 44 * N_ITEMS, "boost_bwd32": 72 * N_ITEMS, "mass_comp32": 36 * N_STRESS,
         "event_reduce": 32 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
         "event_reduce32c": 16 * n_part + 16 * (N_EVENTS + 1) + 20 * N_EVENTS + 4 * n_pairs,
         "event_reduce_bwd": 64 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
     }
-    units = {"mass_fwd": 0, "mass_bwd": N_ITEMS, "boost_fwd": 0, "boost_bwd": N_ITEMS, "mass_comp32": N_ITEMS,
-             "event_reduce": 0, "event_reduce32c": N_EVENTS, "event_reduce_bwd": N_EVENTS}
-    # a pair / vector / FP64 event counts once for its forward + backward pass
-    items_per_step = sum(units.values())
+    units = {k: (N_EVENTS if k.startswith("event_reduce") else N_STRESS if k == "mass_comp32" else N_ITEMS)
+             for k in KERNELS}
+    items_per_step = sum(units[k] for k in run)
 
     def step(evs=None):
-        for k in KERNELS:
+        for k in run:
             if evs is not None:
                 evs[k][0].record(stream)
             rc = calls[k]()
@@ -409,7 +433,7 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in KERNELS}
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in run}
            for _ in range(K)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -419,7 +443,7 @@ def main():
     elapsed = time.perf_counter() - t_start
 
     per_kernel = {}
-    for k in KERNELS:
+    for k in run:
         ts = np.array([e[k][0].elapsed_time(e[k][1]) for e in evs]) * 1e-3  # seconds
         avg = float(ts.mean())
         gbs = alg_bytes[k] / avg / 1e9
@@ -427,25 +451,38 @@ def main():
             "avg_us": round(avg * 1e6, 2), "median_us": round(float(np.median(ts)) * 1e6, 2),
             "min_us": round(float(ts.min()) * 1e6, 2),
             "alg_bytes": int(alg_bytes[k]), "alg_GBps": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "units": N_EVENTS if k.startswith("event_reduce") else N_ITEMS,
-            "Gunits_per_s": round((N_EVENTS if k.startswith("event_reduce") else N_ITEMS) / avg / 1e9, 3),
+            "units": units[k], "Gunits_per_s": round(units[k] / avg / 1e9, 3),
+            "traffic": stored_traffic(k),
         }
-    per_kernel["event_reduce"]["pairs"] = n_pairs
-    per_kernel["event_reduce"]["particles"] = n_part
-    per_kernel["mass_comp32"]["fp64_redo_per_launch"] = int(FB.item()) // max(1, args.warmup + K)
-    per_kernel["event_reduce32c"]["fp64_redo_per_launch"] = int(FBJ.item()) // max(1, args.warmup + K)
+    if "event_reduce" in per_kernel:
+        per_kernel["event_reduce"]["pairs"] = n_pairs
+        per_kernel["event_reduce"]["particles"] = n_part
+    if "mass_comp32" in per_kernel:
+        per_kernel["mass_comp32"]["fp64_redo_per_launch"] = int(FB.item()) // max(1, args.warmup + K)
+    if "event_reduce32c" in per_kernel:
+        per_kernel["event_reduce32c"]["fp64_redo_per_launch"] = int(FBJ.item()) // max(1, args.warmup + K)
 
     ms_per_step = elapsed / K * 1e3
     value = items_per_step / (elapsed / K) / 1e9
-    dom = max(KERNELS, key=lambda k: per_kernel[k]["avg_us"])
+    dom = max(run, key=lambda k: per_kernel[k]["avg_us"])
     ach = per_kernel[dom]["alg_GBps"]
     roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom)}
+    step_bytes = sum(alg_bytes[k] for k in run)
 
+    # the oracle on the host cores (its accurate masses of the stress pairs are
+    # the reference of the precision comparison)
+    cpu, ref_host = None, None
+    if not args.no_cpu:
+        cpu, ref_host = cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em, g_pair)
+
+    SA64 = SB64 = None
+    if not (args.no_compare and args.no_analysis):
+        SA64, SB64 = tuple(t.to(torch.float64) for t in SA), tuple(t.to(torch.float64) for t in SB)
     comparison = None if args.no_compare else compare_precisions(
-        lib, SA, SB, MC, FB, torch.from_numpy(collinear).to(dev), sp, args.warmup, K)
+        lib, SA, SB, SA64, SB64, MC, FB, torch.from_numpy(collinear).to(dev), ref_host, sp, args.warmup, K)
 
-    convert = None if args.no_convert else measure_convert(lib, A, X, GY, SA, stream, args.warmup, K)
+    convert = None if args.no_convert else measure_convert(lib, A, X, GY, A32, stream, args.warmup, K)
     transform = None if args.no_transform else measure_transform(lib, A, B, GA, GB, X, GY, BETA, GM, stream,
                                                                  args.warmup, K)
     analysis = None
@@ -453,23 +490,33 @@ def main():
         counts = torch.zeros(1002, dtype=torch.int64, device=dev)
         rank = torch.empty(N_EVENTS, dtype=torch.int64, device=dev)
         best = torch.empty(N_EVENTS, dtype=torch.float64, device=dev)
+        # 2^26 FP64 masses (512 MiB, twice the last-level cache): the plain
+        # FP64 masses of the widened stress pairs
+        MH = torch.empty(N_STRESS, dtype=torch.float64, device=dev)
+        rc = lib.glv_invariant_mass(F64, PTM, PLAIN, N_STRESS, ptr4(SA64), ptr4(SB64), MH.data_ptr(), None, sp)
+        if rc != 0:
+            raise RuntimeError(f"histogram input: status {rc}")
+        if "event_reduce" not in run:
+            rc = calls["event_reduce"]()
+            if rc != 0:
+                raise RuntimeError(f"best-pair input: status {rc}")
         analysis = {
             "mass_histogram": time_launches(
-                "mass_histogram", lambda: lib.glv_mass_histogram(F64, N_ITEMS, M.data_ptr(), 0.0, 200.0, 1000,
+                "mass_histogram", lambda: lib.glv_mass_histogram(F64, N_STRESS, MH.data_ptr(), 0.0, 200.0, 1000,
                                                                  counts.data_ptr(), sp),
-                stream, args.warmup, K, N_ITEMS, 8 * N_ITEMS),
+                stream, args.warmup, K, N_STRESS, 8 * N_STRESS),
             "event_best_pair": time_launches(
                 "event_best_pair", lambda: lib.glv_event_best_pair(F64, N_EVENTS, PO.data_ptr(), PM.data_ptr(),
                                                                    91.1876, rank.data_ptr(), best.data_ptr(), sp),
                 stream, args.warmup, K, N_EVENTS, 8 * n_pairs + 8 * (N_EVENTS + 1) + 16 * N_EVENTS),
         }
-        GM32 = GM.to(torch.float32)
-        GA32 = tuple(torch.empty(N_ITEMS, dtype=torch.float32, device=dev) for _ in range(4))
-        GB32 = tuple(torch.empty(N_ITEMS, dtype=torch.float32, device=dev) for _ in range(4))
-        cGA32, cGB32 = ptr4(GA32), ptr4(GB32)
+        GMS = GM32  # 2^24 FP32 upstreams for the first 2^24 stress pairs
+        GAS, GBS = new(N_ITEMS, torch.float32, 4), new(N_ITEMS, torch.float32, 4)
+        cSA24, cSB24 = ptr4(tuple(t[:N_ITEMS] for t in SA)), ptr4(tuple(t[:N_ITEMS] for t in SB))
+        cGAS, cGBS = ptr4(GAS), ptr4(GBS)
         analysis["mass_comp32_bwd"] = time_launches(
-            "mass_comp32_bwd", lambda: lib.glv_invariant_mass_comp_bwd(F32, N_ITEMS, cSA, cSB, GM32.data_ptr(), cGA32,
-                                                                       cGB32, sp),
+            "mass_comp32_bwd", lambda: lib.glv_invariant_mass_comp_bwd(F32, N_ITEMS, cSA24, cSB24, GMS.data_ptr(),
+                                                                       cGAS, cGBS, sp),
             stream, args.warmup, K, N_ITEMS, 68 * N_ITEMS)
         analysis["mass_histogram"]["bins"] = 1000
         analysis["event_best_pair"]["pairs"] = n_pairs
@@ -480,25 +527,26 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em, g_pair)
-
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gevents/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {
-            "workload": "2^24 FP64 PtEtaPhiM pairs (mass fwd+bwd) + 2^24 FP64 PxPyPzE vectors with per-item beta "
-                        "(boost fwd+bwd) + 2^24 FP32 light/collinear pairs (compensated mass) + 2^20 jagged "
-                        "events, Poisson(8) particles (totals, event mass, all pair masses; FP64 fwd+bwd and "
-                        "FP32 compensated fwd) per step",
-            "items_per_step": items_per_step, "pairs_in_events": n_pairs, "particles": n_part,
-            "event_tiling": {"block": tiling[0], "events_per_tile": tiling[1], "lds_particles": tiling[2]},
-            "event_tiling_fp32_comp": {"block": tiling32c[0], "events_per_tile": tiling32c[1],
-                                       "lds_particles": tiling32c[2]},
-            "event_tiling_bwd": {"block": tiling_bwd[0], "events_per_tile": tiling_bwd[1],
-                                 "lds_particles": tiling_bwd[2]},
+            "workload": "per step: 2^24 PtEtaPhiM pairs (mass fwd+bwd) and 2^24 PxPyPzE vectors with per-item "
+                        "beta (boost fwd+bwd), each in FP64 and in FP32; 2^26 FP32 light pairs, 10% nearly "
+                        "collinear (compensated mass); 2^20 jagged events, Poisson(8) particles (totals, event "
+                        "mass, all pair masses; FP64 fwd+bwd and FP32 compensated fwd)",
+            "kernels": run, "items_per_step": items_per_step,
+            "item": "one pair, vector or collider event through one kernel of the step",
+            "step_alg_bytes": step_bytes,
+            "step_alg_GBps": round(step_bytes / (elapsed / K) / 1e9, 1),
+            "pairs_in_events": n_pairs, "particles": n_part,
+            "event_tiling": None if tiling is None else dict(zip(("block", "events_per_tile", "lds_particles"),
+                                                                 tiling)),
+            "event_tiling_fp32_comp": None if tiling32c is None else dict(
+                zip(("block", "events_per_tile", "lds_particles"), tiling32c)),
+            "event_tiling_bwd": None if tiling_bwd is None else dict(
+                zip(("block", "events_per_tile", "lds_particles"), tiling_bwd)),
             "parallelism": "single GPU", "input_gen_s": round(gen_s, 1),
         },
         "roofline": roofline,
@@ -586,8 +634,9 @@ def measure_transform(lib, A, B, GA, GB, X, GY, BETA, GM, stream, warmup, steps)
 
 def measure_convert(lib, A, X, GY, SA, stream, warmup, steps):
     """Each coordinate conversion on its own, 2^24 vectors: PtEtaPhiM inputs
-    are the mass workload's first legs, PxPyPzE inputs the boost workload's
-    vectors (FP64) or the FP32 light legs converted once beforehand; the
+    are the mass workload's first legs (FP64, or rounded to FP32), PxPyPzE
+    inputs the boost workload's vectors (FP64) or the FP32 legs converted once
+    beforehand; the
     reverse modes take the boost workload's upstream gradients.  HIP events on
     the kernels' stream around each launch; algorithmic bytes = 4 columns in
     and 4 out (forward), 8 in and 4 out (reverse mode)."""
@@ -623,26 +672,25 @@ def measure_convert(lib, A, X, GY, SA, stream, warmup, steps):
     return out
 
 
-def compare_precisions(lib, SA, SB, MC, FB, collinear, sp, warmup, steps):
+def compare_precisions(lib, SA, SB, SA64, SB64, MC, FB, collinear, ref_host, sp, warmup, steps):
     """The FP32 compensated mass against plain FP64 and plain FP32 on the same
-    2^24 stress pairs (light legs, 10 % nearly collinear): time per launch and
-    the error, relative and in GeV, each against the FP64 cancellation-free
-    mass of the widened inputs (the library's FP64 compensated mode, within
-    64 u64 of binary128 in the tests): the largest and the 99.9th percentile,
-    over all pairs and over the collinear and the generic pairs apart, and the
-    compensated launch's FP64 redo count.  Outside the timed step."""
+    2^26 stress pairs (light legs, 10 % nearly collinear): time per launch and
+    the error, relative and in GeV, each against the oracle's accurate
+    (cancellation-free, binary64) mass of the same FP32 inputs, computed by the
+    CPU-baseline leg (``ref_host``; without it the errors are not reported):
+    the largest and the 99.9th percentile, over all pairs and over the
+    collinear and the generic pairs apart, and the compensated launch's FP64
+    redo count.  Outside the timed step."""
     import torch
 
     from paper_2312_02756_amd import _lib
 
     n = SA[0].numel()
-    SA64 = tuple(t.to(torch.float64) for t in SA)
-    SB64 = tuple(t.to(torch.float64) for t in SB)
     P4 = _lib.P4
     ptr4 = lambda cols: P4(*[t.data_ptr() for t in cols])  # noqa: E731
-    ref = torch.empty(n, dtype=torch.float64, device=SA[0].device)
-    m64 = torch.empty_like(ref)
-    m32 = torch.empty(n, dtype=torch.float32, device=SA[0].device)
+    dev = SA[0].device
+    m64 = torch.empty(n, dtype=torch.float64, device=dev)
+    m32 = torch.empty(n, dtype=torch.float32, device=dev)
     F32, F64, PTM = _lib.GLV_F32, _lib.GLV_F64, _lib.GLV_PTETAPHIM
     PLAIN, COMP = _lib.GLV_PLAIN, _lib.GLV_COMPENSATED
     # pointers marshalled once: host work between the events and the launch would be timed
@@ -654,10 +702,8 @@ def compare_precisions(lib, SA, SB, MC, FB, collinear, sp, warmup, steps):
         "fp32_plain": (lambda: lib.glv_invariant_mass(F32, PTM, PLAIN, n, cSA, cSB, p32, None, sp), m32, 36),
     }
     stream = torch.cuda.current_stream()
-    out = {"pairs": n, "reference": "FP64 compensated (cancellation-free) mass of the same, widened inputs"}
-    rc = lib.glv_invariant_mass(F64, PTM, COMP, n, cSA64, cSB64, ref.data_ptr(), None, sp)
-    if rc != 0:
-        raise RuntimeError(f"reference mass: status {rc}")
+    out = {"pairs": n, "reference": None if ref_host is None else
+           "oracle: accurate (cancellation-free) binary64 mass of the same FP32 inputs, host cores"}
     # the three variants in rotation, as kernels run within a step: the same
     # launch repeated back to back measures slower on this GPU than interleaved
     torch.cuda.synchronize()
@@ -676,6 +722,7 @@ def compare_precisions(lib, SA, SB, MC, FB, collinear, sp, warmup, steps):
             evs[name].append((e0, e1))
     torch.cuda.synchronize()
     out["fp32_comp_fp64_redo_per_launch"] = (int(FB.item()) - fb0) / (warmup + steps)
+    ref = None if ref_host is None else torch.from_numpy(ref_host).to(dev)
 
     def p999(x):  # the 99.9th percentile: smallest of the largest 0.1 %
         k = max(1, x.numel() - int(np.ceil(0.999 * x.numel())) + 1)
@@ -683,37 +730,50 @@ def compare_precisions(lib, SA, SB, MC, FB, collinear, sp, warmup, steps):
 
     for name, (call, res, bytes_per_pair) in runs.items():
         us = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs[name]])) * 1e3
+        out[name] = {"avg_us": round(us, 2), "alg_GBps": round(bytes_per_pair * n / us / 1e3, 1)}
+        if ref is None:
+            continue
         err = (res.to(torch.float64) - ref).abs()
         rel = err / ref.abs().clamp_min(1e-300)
-        out[name] = {"avg_us": round(us, 2), "alg_GBps": round(bytes_per_pair * n / us / 1e3, 1),
-                     "max_rel_err": float(rel.max()), "max_abs_err_GeV": float(err.max()),
-                     "pairs_over_1e-5_rel": int((rel > 1e-5).sum())}
+        out[name].update({"max_rel_err": float(rel.max()), "max_abs_err_GeV": float(err.max()),
+                          "pairs_over_1e-5_rel": int((rel > 1e-5).sum()),
+                          "pairs_over_tolerance": int((err > 4e-6 * ref.abs() + 1e-6).sum())})
         for sub_name, sel in (("collinear", collinear), ("generic", ~collinear)):
             r, a = rel[sel], err[sel]
             out[name][sub_name] = {"pairs": int(sel.sum()), "max_rel_err": float(r.max()),
                                    "p999_rel_err": p999(r), "max_abs_err_GeV": float(a.max()),
                                    "p999_abs_err_GeV": p999(a)}
+        del err, rel
     return out
 
 
 def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em, g_pair, min_seconds=10.0,
                  max_reps=20):
     """The oracle on the host cores over one step's workload (2^24 items per
-    element-wise kernel, 2^20 events), repeated until at least `min_seconds`
-    have passed, in the benchmark's unit."""
+    element-wise kernel in FP64 and in FP32, 2^26 stress pairs, 2^20 events),
+    repeated until at least `min_seconds` have passed, in the benchmark's
+    unit.  Returns the summary and the oracle's accurate masses of the stress
+    pairs (the reference of the precision comparison)."""
     import oracle
 
     threads = len(os.sched_getaffinity(0))
     oracle.set_threads(threads)
     used = oracle.get_threads()
+    r32 = lambda cols: tuple(np.asarray(c, dtype=np.float32) for c in cols)  # noqa: E731
+    a32, b32, x32, beta32, gy32 = r32(a), r32(b), r32(x), r32(beta), r32(gy)
+    gm32 = np.asarray(gm, dtype=np.float32)
     reps = 0
+    ref = None
     t = time.perf_counter()
     while True:
-        oracle.mass_plain("PtEtaPhiM", a, b)
-        oracle.mass_vjp("PtEtaPhiM", a, b, gm)
-        oracle.boost(x, beta)
-        oracle.boost_vjp(x, beta, gy)
-        oracle.mass_accurate(sa, sb)
+        for xa, xb, xg, xx, xbeta, xgy in ((a, b, gm, x, beta, gy), (a32, b32, gm32, x32, beta32, gy32)):
+            oracle.mass_plain("PtEtaPhiM", xa, xb)
+            oracle.mass_vjp("PtEtaPhiM", xa, xb, xg)
+            oracle.boost(xx, xbeta)
+            oracle.boost_vjp(xx, xbeta, xgy)
+        m_acc = oracle.mass_accurate(sa, sb)
+        if ref is None:
+            ref = m_acc
         oracle.event_reduce("PtEtaPhiM", off, parts)
         oracle.event_reduce("PtEtaPhiM", off, parts32, oracle.ACCURATE)
         oracle.event_reduce_vjp("PtEtaPhiM", off, parts, g_tot, g_em, g_pair)
@@ -721,20 +781,21 @@ def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em
         dt = time.perf_counter() - t
         if dt >= min_seconds or reps >= max_reps:
             break
-    items = reps * (3 * N_ITEMS + 2 * N_EVENTS)
-    # one thread (the paper's CPU baseline form) on 1/32 of a step: 2^19 items, 2^15 events
-    n1, e1 = N_ITEMS // 32, N_EVENTS // 32
-    cut = lambda cols: tuple(c[:n1] for c in cols)  # noqa: E731
+    items = reps * (8 * N_ITEMS + N_STRESS + 3 * N_EVENTS)
+    # one thread (the paper's CPU baseline form) on 1/32 of a step: 2^19 items, 2^21 stress pairs, 2^15 events
+    n1, s1, e1 = N_ITEMS // 32, N_STRESS // 32, N_EVENTS // 32
+    cut = lambda cols, k=n1: tuple(c[:k] for c in cols)  # noqa: E731
     off1 = off[: e1 + 1]
     np1, nq1 = int(off1[-1]), int(np.sum((np.diff(off1) * (np.diff(off1) - 1)) // 2))
     p1, p32 = tuple(c[:np1] for c in parts), tuple(c[:np1] for c in parts32)
     oracle.set_threads(1)
     t1 = time.perf_counter()
-    oracle.mass_plain("PtEtaPhiM", cut(a), cut(b))
-    oracle.mass_vjp("PtEtaPhiM", cut(a), cut(b), gm[:n1])
-    oracle.boost(cut(x), cut(beta))
-    oracle.boost_vjp(cut(x), cut(beta), cut(gy))
-    oracle.mass_accurate(cut(sa), cut(sb))
+    for xa, xb, xg, xx, xbeta, xgy in ((a, b, gm, x, beta, gy), (a32, b32, gm32, x32, beta32, gy32)):
+        oracle.mass_plain("PtEtaPhiM", cut(xa), cut(xb))
+        oracle.mass_vjp("PtEtaPhiM", cut(xa), cut(xb), xg[:n1])
+        oracle.boost(cut(xx), cut(xbeta))
+        oracle.boost_vjp(cut(xx), cut(xbeta), cut(xgy))
+    oracle.mass_accurate(cut(sa, s1), cut(sb, s1))
     oracle.event_reduce("PtEtaPhiM", off1, p1)
     oracle.event_reduce("PtEtaPhiM", off1, p32, oracle.ACCURATE)
     oracle.event_reduce_vjp("PtEtaPhiM", off1, p1, tuple(c[:e1] for c in g_tot), g_em[:e1], g_pair[:nq1])
@@ -747,11 +808,12 @@ def cpu_baseline(a, b, gm, x, beta, gy, sa, sb, off, parts, parts32, g_tot, g_em
     except OSError:
         pass
     return {"value": round(items / dt / 1e9, 5), "unit": "Gevents/s", "cores": used, "kind": "oracle", "cpu": cpu,
-            "sample": f"{reps} x one step's workload: 2^24 items through mass fwd+bwd, boost fwd+bwd and the "
-                      f"accurate mass, 2^20 jagged events through the plain reduction and its VJP and the accurate "
-                      f"reduction (binary64 oracle); {dt:.2f} s wall on {used} threads",
-            "single_thread": {"value": round((3 * n1 + 2 * e1) / dt1 / 1e9, 6), "unit": "Gevents/s",
-                              "sample": f"1/32 of a step (2^19 items, 2^15 events) on 1 thread, {dt1:.2f} s"}}
+            "sample": f"{reps} x one step's workload: 2^24 pairs through mass fwd+bwd and 2^24 vectors through "
+                      f"boost fwd+bwd, each on FP64 and on FP32 inputs, the accurate mass of 2^26 stress pairs, "
+                      f"2^20 jagged events through the plain reduction, its VJP and the accurate reduction "
+                      f"(binary64 oracle); {dt:.2f} s wall on {used} threads",
+            "single_thread": {"value": round((8 * n1 + s1 + 3 * e1) / dt1 / 1e9, 6), "unit": "Gevents/s",
+                              "sample": f"1/32 of a step on 1 thread, {dt1:.2f} s"}}, ref
 
 
 if __name__ == "__main__":

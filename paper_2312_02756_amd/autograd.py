@@ -73,7 +73,15 @@ def invariant_mass(a, b, coords="PtEtaPhiM", mode="plain"):
 
 
 def boost(x, beta):
-    """Differentiable boost of (px, py, pz, E) columns by beta columns."""
+    """Differentiable boost of (px, py, pz, E) columns by beta columns.
+
+    beta holds one velocity per vector or one for all (single-element
+    columns).  A broadcast beta gets no gradient (it would be a sum over all
+    items, a reduction rather than an element-wise step), so a broadcast beta
+    that requires one is rejected with ValueError."""
+    if beta[0].numel() != x[0].numel() and any(b.requires_grad for b in beta):
+        raise ValueError("boost: a broadcast beta (one velocity for all vectors) has no gradient; "
+                         "pass one velocity per vector or detach beta")
     return Boost.apply(*x, *beta)
 
 

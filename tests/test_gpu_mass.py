@@ -161,6 +161,47 @@ def test_compensated_fp32_stress_workload():
     assert np.max(np.abs(mp - m_or) / m_or) > 1e-3
 
 
+def _heavy_slow_pairs(n, seed):
+    """Heavy, slow legs (M ~ U[5, 20] GeV, pt ~ LogUniform[0.01, 10] GeV,
+    eta ~ U[-4, 4]): pairs at opposite large |eta| exceed the FP32 error
+    bound of the compensated form (its rapidity shifts are large there)."""
+    g = synth.rng(seed)
+
+    def leg():
+        return (np.exp(g.uniform(np.log(0.01), np.log(10.0), n)), g.uniform(-4.0, 4.0, n),
+                g.uniform(-np.pi, np.pi, n), g.uniform(5.0, 20.0, n))
+
+    a = leg()
+    b = leg()
+    return synth.as_dtype(a, np.float32), synth.as_dtype(b, np.float32)
+
+
+@pytest.mark.parametrize("n", [4097, 1 << 16])
+def test_compensated_fp64_redo_elementwise(n):
+    """Pairs that force the FP64 redo of the element-wise FP32 compensated
+    mass: some but not all items are recomputed, every element lies within
+    4e-6 m + 1e-6 GeV of the accurate oracle, and the aligned launch (four
+    pairs per lane) and the launch on views one element in (one pair per lane)
+    agree bitwise, redo count included."""
+    a, b = _heavy_slow_pairs(n + 1, 760)
+    ga, gb = gpu(a, torch.float32), gpu(b, torch.float32)
+    fb = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    fb1 = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    m = host(glv.glv_invariant_mass(tuple(t[1:] for t in ga), tuple(t[1:] for t in gb), mode="compensated",
+                                    fallback_count=fb1))
+    ca, cb = tuple(t[1:].clone() for t in ga), tuple(t[1:].clone() for t in gb)
+    assert all(t.data_ptr() % 16 == 0 for t in ca + cb)
+    mal = host(glv.glv_invariant_mass(ca, cb, mode="compensated", fallback_count=fb))
+    nfb, nfb1 = int(fb.item()), int(fb1.item())
+    assert 0 < nfb < n, nfb
+    assert nfb == nfb1
+    assert np.array_equal(m.view(np.uint32), mal.view(np.uint32))
+    wa, wb = widened(tuple(c[1:] for c in a), torch.float32), widened(tuple(c[1:] for c in b), torch.float32)
+    m_or = oracle.mass_accurate(wa, wb)
+    r, i = worst(np.abs(m.astype(np.float64) - m_or), mass_tol_comp_f32(m_or))
+    assert r <= 1.0, (i, m[i], m_or[i])
+
+
 def test_compensated_fp64_is_accurate():
     n = 1 << 18
     a, b, _ = synth.pairs_stress(synth.rng(503), n)
