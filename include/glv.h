@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define GLV_ABI_VERSION 1
+#define GLV_ABI_VERSION 2
 
 typedef enum glv_status {
   GLV_OK = 0,
@@ -93,33 +93,44 @@ typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2,
 typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
 
 /* Work decomposition of glv_event_reduce / glv_event_reduce_bwd.  It changes
- * speed only: pair masses, totals, event masses and gradients of every event
- * that fits the tiling's LDS capacity are identical for every such tiling,
- * except the compensated event mass (a sum of per-pair terms), which may
- * differ in the last bit between tilings but is reproducible for a given
- * tiling.  An event that does not fit goes to a separate launch: its plain
- * pair masses are the same, its sums take another order, and a compensated
- * pair mass may differ in the last bit (that launch fuses the arithmetic
- * differently, which can also move a pair across the FP64-redo threshold);
- * all stay within the stated accuracy.
+ * speed only: pair masses, totals and gradients of every event that fits the
+ * tiling's staging capacity, and plain event masses, are identical for every
+ * such tiling; the compensated event mass (a sum of per-pair terms, summed in
+ * an order that follows the tiling) may differ in the last bit between
+ * tilings but is reproducible for a given tiling.  An event that does not fit
+ * goes to a second launch of the same call: its plain pair masses are the
+ * same, its sums take another order, and a compensated pair mass may differ
+ * in the last bit (that launch fuses the arithmetic differently, which can
+ * also move a pair across the FP64-redo threshold); all stay within the
+ * stated accuracy.
+ * Forward (glv_event_reduce): every wavefront (64 threads) of a workgroup
+ * works alone on its own tile of consecutive events.
  *   block            threads per workgroup: 64, 128, 256 or 512
- *   events_per_tile  events a workgroup takes at a time: 1 .. block
- *   lds_particles    particles staged in LDS at once: 64 .. 4096
+ *   events_per_tile  events of one wavefront's tile: 1 .. 64
+ *   lds_particles    particles a wavefront stages at once: 64 .. 4096
+ *                    (larger events go to the second launch)
+ *   pairs_per_round  pairs a wavefront evaluates per round, a multiple of 64
+ *                    in 64 .. 4096 (pairs_per_round / 64 consecutive pairs
+ *                    per lane)
+ * Backward (glv_event_reduce_bwd): the same wavefront tiles.
+ *   block, events_per_tile, lds_particles   as for the forward
+ *   pairs_per_round  pair upstreams a wavefront stages at once, a multiple of
+ *                    64 in 64 .. 4096 (events with more pairs, or more
+ *                    particles than lds_particles, go to the second launch)
  * Fields set to 0 take the library's current choice (the autotuned one if
  * glv_autotune_event_reduce, or glv_autotune_event_reduce_bwd for the
  * backward, ran for this device/dtype/coords/mode, otherwise a built-in
- * default).  A tiling whose workgroup would need more than 64 KiB of
- * LDS is rejected with GLV_EINVAL_TILING: per staged particle the forward
- * keeps 4 values (10 in the compensated mode) and the backward 8 values (its
- * vector and up to four pair gradients) plus 2 bytes; per event of a tile
- * about 40 bytes more (the backward: 5 values and 24 bytes).  The backward
- * stages at most one particle per workgroup thread (lds_particles above block
- * acts as block). */
+ * default).  A tiling whose workgroup would need more than 64 KiB of LDS is
+ * rejected with GLV_EINVAL_TILING: per wavefront the forward keeps 4 values
+ * per staged particle (10 in the compensated mode), one value per pair of a
+ * round (plus 8 bytes in the compensated mode) and 12 bytes per event of the
+ * tile; the backward 10 values and 4 bytes per staged particle, one value per
+ * staged pair upstream and 4 values and 24 bytes per event of the tile. */
 typedef struct glv_tiling {
   int32_t block;
   int32_t events_per_tile;
   int32_t lds_particles;
-  int32_t reserved; /* must be 0 */
+  int32_t pairs_per_round;
 } glv_tiling;
 
 /* Pair invariant mass (Sec. 4.1, Fig. 1): m[i] = mass(conv(a_i) + conv(b_i)),

@@ -35,7 +35,7 @@ EXPORTS = (
 
 class glv_tiling(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("events_per_tile", ctypes.c_int32),
-                ("lds_particles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_particles", ctypes.c_int32), ("pairs_per_round", ctypes.c_int32)]
 
 
 P4 = ctypes.c_void_p * 4

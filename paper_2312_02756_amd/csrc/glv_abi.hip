@@ -90,7 +90,7 @@ void write_tiling(const glv::Tiling& t, glv_tiling* out) {
   out->block = t.block;
   out->events_per_tile = t.events_per_tile;
   out->lds_particles = t.lds_particles;
-  out->reserved = 0;
+  out->pairs_per_round = t.pairs_per_round;
 }
 
 // Times every candidate on `s` (one warm-up launch, then the best of three)
@@ -130,27 +130,29 @@ hipError_t pick_fastest(const std::vector<glv::Tiling>& cands, hipStream_t s, La
   return err;
 }
 
+// Forward: four independent wavefronts per workgroup, each taking tiles of 32
+// events, staging up to 128 particles and evaluating 512 pairs (8 per lane)
+// per round.
 glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
+  (void)dt;
+  (void)mode;
   glv::Tiling t;
   t.block = 256;
-  t.events_per_tile = 128;
-  // staged bytes per particle: 4 or 10 columns of the dtype; keep <= 40 KiB
-  size_t per = (mode == GLV_COMPENSATED ? 10 : 4) * elem(dt);
-  t.lds_particles = (int)std::min<size_t>(2048, (40 * 1024) / per);
-  t.lds_particles = std::max(64, t.lds_particles & ~63);
+  t.events_per_tile = 32;
+  t.lds_particles = 128;
+  t.pairs_per_round = 512;
   return t;
 }
 
-// Backward: one staged particle per thread (the launch clamps lds_particles to
-// the workgroup size); 128 threads and 64 events per tile measured fastest on
-// collider-sized events (2^20 Poisson(8) events in FP64, against 256 / 128 and
-// a sweep of 64 to 512 threads).
+// Backward: two independent wavefronts per workgroup, each taking tiles of 32
+// events and staging up to 128 particles and 512 pair upstreams.
 glv::Tiling default_tiling_bwd(glv_dtype dt) {
   (void)dt;
   glv::Tiling t;
   t.block = 128;
-  t.events_per_tile = 64;
+  t.events_per_tile = 32;
   t.lds_particles = 128;
+  t.pairs_per_round = 512;
   return t;
 }
 
@@ -170,14 +172,16 @@ glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_
     if (it != g_tiles.end()) base = it->second;
   }
   if (user) {
-    if (user->reserved != 0) return GLV_EINVAL_TILING;
     if (user->block) base.block = user->block;
     if (user->events_per_tile) base.events_per_tile = user->events_per_tile;
     if (user->lds_particles) base.lds_particles = user->lds_particles;
+    if (user->pairs_per_round) base.pairs_per_round = user->pairs_per_round;
   }
   if (!block_ok(base.block)) return GLV_EINVAL_TILING;
-  if (base.events_per_tile < 1 || base.events_per_tile > base.block) return GLV_EINVAL_TILING;
+  if (base.events_per_tile < 1 || base.events_per_tile > 64) return GLV_EINVAL_TILING;
   if (base.lds_particles < 64 || base.lds_particles > 4096) return GLV_EINVAL_TILING;
+  if (base.pairs_per_round < 64 || base.pairs_per_round > 4096 || base.pairs_per_round % 64 != 0)
+    return GLV_EINVAL_TILING;
   size_t lds = bwd ? glv::event_reduce_bwd_lds_bytes(dt, base) : glv::event_reduce_lds_bytes(dt, mode, base);
   if (lds > kMaxLds) return GLV_EINVAL_TILING;
   *out = base;
@@ -632,20 +636,18 @@ glv_status glv_autotune_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode,
   hipStream_t s = (hipStream_t)stream;
   // candidates: workgroup size x events per tile x LDS capacity
   std::vector<glv::Tiling> cands;
-  const int blocks[] = {128, 256, 512};
-  const int epbs[] = {32, 64, 128, 256, 512};
-  const int caps[] = {256, 512, 1024, 2048};
+  const int blocks[] = {64, 256};
+  const int epbs[] = {16, 32, 64};
+  const int caps[] = {64, 128, 256, 512};
+  const int qcaps[] = {256, 512, 1024};
   for (int b : blocks)
     for (int e : epbs)
-      for (int c : caps) {
-        if (e > b) continue;
-        glv::Tiling t{b, e, c};
-        if (glv::event_reduce_lds_bytes(dt, mode, t) > kMaxLds) continue;
-        // a tile's expected particles (8 per event on collider data) should
-        // fit the capacity at least once
-        if (c < e) continue;
-        cands.push_back(t);
-      }
+      for (int c : caps)
+        for (int q : qcaps) {
+          glv::Tiling t{b, e, c, q};
+          if (glv::event_reduce_lds_bytes(dt, mode, t) > kMaxLds) continue;
+          cands.push_back(t);
+        }
   glv::Tiling chosen = default_tiling(dt, mode);
   if (ne > 0 && (total || em || pm)) {
     auto launch = [&](const glv::Tiling& t) {
@@ -669,18 +671,20 @@ glv_status glv_autotune_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne
   glv_status st = validate_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp);
   if (st != GLV_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  // candidates: workgroup size x events per tile; the backward stages one
-  // particle per thread, so the LDS capacity is the workgroup size
+  // candidates: workgroup size x events per tile x staged particles x staged pairs
   std::vector<glv::Tiling> cands;
-  const int blocks[] = {64, 128, 256, 512};
-  const int epbs[] = {16, 32, 64, 128, 256};
+  const int blocks[] = {64, 128};
+  const int epbs[] = {16, 32, 64};
+  const int caps[] = {64, 128, 256};
+  const int qcaps[] = {256, 512, 1024};
   for (int b : blocks)
-    for (int e : epbs) {
-      if (e > b) continue;
-      glv::Tiling t{b, e, b};
-      if (glv::event_reduce_bwd_lds_bytes(dt, t) > kMaxLds) continue;
-      cands.push_back(t);
-    }
+    for (int e : epbs)
+      for (int c : caps)
+        for (int q : qcaps) {
+          glv::Tiling t{b, e, c, q};
+          if (glv::event_reduce_bwd_lds_bytes(dt, t) > kMaxLds) continue;
+          cands.push_back(t);
+        }
   glv::Tiling chosen = default_tiling_bwd(dt);
   if (ne > 0) {
     auto launch = [&](const glv::Tiling& t) {

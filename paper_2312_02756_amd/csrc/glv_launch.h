@@ -72,6 +72,7 @@ struct Tiling {
   int block;
   int events_per_tile;
   int lds_particles;
+  int pairs_per_round;  // forward: pairs a wavefront evaluates per round (the backward ignores it)
 };
 
 // LDS bytes one workgroup of the forward reduction needs for a tiling.

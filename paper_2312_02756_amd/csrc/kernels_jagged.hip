@@ -449,8 +449,10 @@ struct FwdArgs {
   T* pair_m;
   unsigned long long* fallback;
   int64_t ne;
-  int epb;  // events per tile
-  int cap;  // particles staged per chunk
+  int epb;         // events per wavefront tile
+  int cap;         // particles staged per chunk (per wavefront)
+  int qcap;        // pairs evaluated per round (per wavefront)
+  int wave_bytes;  // LDS bytes per wavefront
 };
 
 // One event too large for LDS: the whole workgroup, from global memory.
@@ -519,294 +521,340 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
   __syncthreads();
 }
 
+// Orders the LDS accesses of the lanes of one wavefront.  The waves of a
+// workgroup work independently, so the forward reduction needs no workgroup
+// barrier: LDS operations of one wavefront are performed in program order, and
+// the fences keep the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The value of x held by lane `lane` (uniform), for a 64-bit x.
+__device__ __forceinline__ int64_t readlane64(int64_t x, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(uint64_t)x, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)((uint64_t)x >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Last c in [lo, hi) with a[c] <= key (a non-decreasing, a[lo] <= key).
+__device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= key)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// LDS of one wavefront of the forward reduction (cap particles, qcap pairs):
+//   cart[cap]  (px, py, pz, E)             staged Cartesian records
+//   legA[cap]  (pt, eta, phi, M)           compensated mode
+//   legB[cap]  (mT, delta)                 compensated mode
+//   pm[qcap]   pair masses of a round      (stored from here, coalesced)
+//   kp[qcap]   partial sums of K per lane  (compensated event mass)
+//   eo, en, ep [epb + 1] int               the chunk's events with pairs:
+//              first particle, size, first pair (chunk-relative), then a
+//              sentinel (np, 0, nq)
+template <typename T, int MODE>
+struct WaveLds {
+  typename V4<T>::type* cart;
+  typename V4<T>::type* legA;
+  typename V2<T>::type* legB;
+  T* pm;
+  double* kp;
+  int* eo;
+  int* en;
+  int* ep;
+};
+
+template <typename T, int MODE>
+__host__ __device__ __forceinline__ size_t wave_lds_bytes(int cap, int qcap, int epb) {
+  size_t b = (size_t)cap * 4 * sizeof(T);
+  if (MODE == GLV_COMPENSATED) b += (size_t)cap * 6 * sizeof(T) + (size_t)qcap * sizeof(double);
+  b += (size_t)qcap * sizeof(T) + 3 * (size_t)(epb + 1) * sizeof(int);
+  return (b + 31) & ~(size_t)31;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int cap, int qcap, int epb) {
+  WaveLds<T, MODE> w;
+  w.cart = reinterpret_cast<typename V4<T>::type*>(p);
+  p += (size_t)cap * 4 * sizeof(T);
+  if constexpr (MODE == GLV_COMPENSATED) {
+    w.legA = reinterpret_cast<typename V4<T>::type*>(p);
+    p += (size_t)cap * 4 * sizeof(T);
+    w.legB = reinterpret_cast<typename V2<T>::type*>(p);
+    p += (size_t)cap * 2 * sizeof(T);
+    w.kp = reinterpret_cast<double*>(p);
+    p += (size_t)qcap * sizeof(double);
+  } else {
+    w.legA = nullptr;
+    w.legB = nullptr;
+    w.kp = nullptr;
+  }
+  w.pm = reinterpret_cast<T*>(p);
+  p += (size_t)qcap * sizeof(T);
+  w.eo = reinterpret_cast<int*>(p);
+  w.en = w.eo + (epb + 1);
+  w.ep = w.en + (epb + 1);
+  return w;
+}
+
+// The forward reduction.  Each wavefront of a workgroup independently takes a
+// tile of epb consecutive events (one per lane for their offsets) and walks it
+// in chunks of consecutive events holding at most cap particles:
+//   1. stage: the chunk's particles (contiguous in the columns) are loaded
+//      coalesced, converted once and written to the wave's LDS;
+//   2. totals: the lane of each event sums its particles in CSR order (the
+//      plain event mass from that total; in the compensated mode also the
+//      sum of M^2);
+//   3. pairs, in rounds of qcap pairs: lane L takes the contiguous pairs
+//      [L m, (L + 1) m) of the round (m = qcap / 64, made odd), locates the
+//      first by a binary search over the chunk's events with pairs and the
+//      square-root decode of its rank, then steps to the lexicographic
+//      successor -- every lane the same number of pairs whatever the event
+//      sizes, and a handful of integer operations per step.  Masses go to the
+//      wave's LDS and from there to pair_m with coalesced stores; in the
+//      compensated mode each lane also sums K = E_i E_j - p_i.p_j of its pairs
+//      per event and leaves the partial sum at the slot of its last pair in
+//      that event, and the event's lane adds those partials (the lanes in
+//      order, then the rounds in order): deterministic for a tiling.
+// Events with more than cap particles are left to k_event_reduce_big.  In
+// the FP32 compensated mode a pair whose error bound asks for FP64 makes its
+// K a NaN; the event's lane then writes a marker -- a quiet NaN with a fixed
+// payload -- into the event mass (or, without event masses, into the event's
+// first pair mass), and k_event_reduce_big recomputes the event.
 template <typename T, int COORDS, int MODE>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
   extern __shared__ __align__(32) unsigned char lds[];
-  const int epb = A.epb, cap = A.cap;
+  constexpr bool kComp = MODE == GLV_COMPENSATED;
+  constexpr bool kDefer = kComp && (sizeof(T) == 4);
+  using R4 = typename V4<T>::type;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nwaves = blockDim.x >> 6;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // LDS (each record array holds cap records of a size that is a multiple of
-  // the next one's alignment, so all stay aligned for any cap):
-  //   cart[cap] (4 T), legA[cap] (4 T), legB[cap] (2 T)   staged records
-  //   s_off[epb+1], s_poff[epb+1]   int64, the tile's offsets
-  //   red[16], acc[nwaves*epb]      double
-  //   ch[epb+1]                     EvRec, offsets relative to the chunk
-  //   colex[kColexPairs]            uint16, the pair table
-  //   s_redo[epb]                   int, FP32 compensated only
+  const int epb = A.epb, cap = A.cap, qcap = A.qcap;
+  const WaveLds<T, MODE> W = carve_wave_lds<T, MODE>(lds + (size_t)wid * A.wave_bytes, cap, qcap, epb);
   Stage<T, MODE> st;
-  st.cart = reinterpret_cast<typename V4<T>::type*>(lds);
-  unsigned char* after = lds + (size_t)cap * 4 * sizeof(T);
-  if constexpr (MODE == GLV_COMPENSATED) {
-    st.legA = reinterpret_cast<typename V4<T>::type*>(after);
-    st.legB = reinterpret_cast<typename V2<T>::type*>(after + (size_t)cap * 4 * sizeof(T));
-    after += (size_t)cap * 6 * sizeof(T);
-  }
-  int64_t* s_off = reinterpret_cast<int64_t*>(after);
-  int64_t* s_poff = s_off + (epb + 1);
-  double* red = reinterpret_cast<double*>(s_poff + (epb + 1));
-  double* acc = red + 16;
-  EvRec* ch = reinterpret_cast<EvRec*>(acc + ((MODE == GLV_COMPENSATED) ? nwaves * epb : 0));
-  unsigned short* colex = reinterpret_cast<unsigned short*>(ch + (epb + 1));
-  // FP32 compensated: events of the chunk with a pair needing the FP64 redo
-  int* s_redo = reinterpret_cast<int*>(colex + ((kColexPairs + 1) & ~1));
-  constexpr bool kDefer = (MODE == GLV_COMPENSATED) && (sizeof(T) == 4);
-  // a wave's share of a chunk's pairs is a shift: nwaves is a power of two
-  const int lg_waves = __builtin_ctz(nwaves);
-  const int wid_s = __builtin_amdgcn_readfirstlane(wid);
+  st.cart = W.cart;
+  st.legA = W.legA;
+  st.legB = W.legB;
 
+  const int64_t e0 = ((int64_t)blockIdx.x * nwaves + wid) * epb;
+  if (e0 >= A.ne) return;  // the whole wavefront: no workgroup barrier follows
+  const int nev = (int)min((int64_t)epb, A.ne - e0);
   const bool want_pairs = A.pair_m != nullptr;
-  const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m != nullptr;
-  unsigned fb = 0;
-  const int64_t ntiles = (A.ne + epb - 1) / epb;
+  // FP32 compensated: K is summed whenever pairs are evaluated (a NaN sum marks the redo)
+  const bool want_k = kComp && (A.event_m != nullptr || (kDefer && want_pairs));
+  const bool need_po = want_pairs || want_k;
 
-  if constexpr (MODE == GLV_COMPENSATED) {
-    for (int i = threadIdx.x; i < nwaves * epb; i += blockDim.x) acc[i] = 0.0;
-  }
-  if (want_pairs || want_k) {
-    for (int r = threadIdx.x; r < kColexPairs; r += blockDim.x) colex[r] = colex_entry(r);
-  }
-
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t e0 = tile * epb;
-    const int nev = (int)min((int64_t)epb, A.ne - e0);
-    for (int i = threadIdx.x; i <= nev; i += blockDim.x) {
-      s_off[i] = A.off[e0 + i];
-      if (want_pairs || want_k) s_poff[i] = A.poff[e0 + i];
+  // this lane's event of the tile
+  const bool mine = lane < nev;
+  int64_t olo = 0, ohi = 0, plo = 0, phi = 0;
+  if (mine) {
+    olo = A.off[e0 + lane];
+    ohi = A.off[e0 + lane + 1];
+    if (need_po) {
+      plo = A.poff[e0 + lane];
+      phi = A.poff[e0 + lane + 1];
     }
-    __syncthreads();
-    int ca = 0;
-    while (ca < nev) {
-      if (s_off[ca + 1] - s_off[ca] > cap) {  // k_event_reduce_big's event
-        ++ca;
-        continue;
-      }
-      // largest cb with s_off[cb] - s_off[ca] <= cap (cb > ca)
-      const int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
-      const int nch = cb - ca;
-      const int64_t pbase = s_off[ca];
-      const int64_t q0 = (want_pairs || want_k) ? s_poff[ca] : 0;
-      const int np = (int)(s_off[cb] - pbase);
-      // chunk-relative offsets, so the pair loop works in 32-bit integers
-      for (int t = threadIdx.x; t <= nch; t += blockDim.x)
-        ch[t] = EvRec{(int)(s_off[ca + t] - pbase), (want_pairs || want_k) ? (int)(s_poff[ca + t] - q0) : 0};
-      if constexpr (kDefer) {
-        for (int t = threadIdx.x; t < nch; t += blockDim.x) s_redo[t] = 0;
-      }
-      for (int t = threadIdx.x; t < np; t += blockDim.x) stage_particle<T, COORDS, MODE>(A.p, pbase + t, st, t);
-      __syncthreads();
+  }
+  const uint64_t valid = (nev >= 64) ? ~0ull : ((1ull << nev) - 1);
+  unsigned fb = 0;
 
-      // one lane per event: totals in CSR order, plain event mass
-      double msum = 0.0;
-      const int my = (int)threadIdx.x;  // event ca + my of the tile
-      if (my < nch) {
-        const int lo = ch[my].o, hi = ch[my + 1].o;
-        T tot[4];
-        if constexpr (MODE == GLV_COMPENSATED) {
-          // totals and sum of M^2 in one pass, two particles per LDS wait
-          double d[4] = {0, 0, 0, 0};
-          int t = lo;
-          for (; t + 2 <= hi; t += 2) {
-            const typename V4<T>::type r0 = st.cart[t], r1 = st.cart[t + 1];
-            const double m0 = (double)st.legA[t][3], m1 = (double)st.legA[t + 1][3];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) d[k] = (d[k] + (double)r0[k]) + (double)r1[k];
-            msum = (msum + m0 * m0) + m1 * m1;
-          }
-          if (t < hi) {
-            const typename V4<T>::type r0 = st.cart[t];
-            const double m0 = (double)st.legA[t][3];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) d[k] += (double)r0[k];
-            msum += m0 * m0;
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
-        } else if constexpr (sizeof(T) == 4) {
-          double d[4] = {0, 0, 0, 0};
-          sum_records(st.cart, lo, hi, d);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) tot[k] = T(0);
-          sum_records(st.cart, lo, hi, tot);
-        }
-        const int64_t e = e0 + ca + my;
-        if (A.total[0]) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) store_out(A.total[k], e, tot[k]);
-        }
-        if constexpr (MODE != GLV_COMPENSATED) {
-          if (A.event_m) store_out(A.event_m, e, mass_of(tot));
-        }
-      }
+  int ca = 0;
+  while (ca < nev) {
+    // chunk [ca, cb): consecutive events ending within cap particles of event ca's start
+    const int64_t base = readlane64(olo, ca);
+    const uint64_t ge = valid & (~0ull << ca);
+    const uint64_t fits = __ballot(mine && (ohi - base <= (int64_t)cap)) & ge;
+    const uint64_t stop = ge & ~fits;
+    const int cb = stop ? (int)__builtin_ctzll(stop) : nev;
+    if (cb == ca) {  // event ca exceeds the staging capacity: k_event_reduce_big's
+      ++ca;
+      continue;
+    }
+    const int np = (int)(readlane64(ohi, cb - 1) - base);
+    const int64_t q0 = need_po ? readlane64(plo, ca) : 0;
+    const int nq = need_po ? (int)(readlane64(phi, cb - 1) - q0) : 0;
+    const bool in_chunk = lane >= ca && lane < cb;
+    const int lo_rel = (int)(olo - base), n_e = (int)(ohi - olo);
 
-      // pairs: one contiguous slice of the chunk's pairs per wavefront
-      if (want_pairs || want_k) {
-        const int q = __builtin_amdgcn_readfirstlane(ch[nch].p);  // < 2^22: cap <= 2048
-        const int lo = (q * wid_s) >> lg_waves, hi = (q * (wid_s + 1)) >> lg_waves;
-        // A lane's pair index grows by 64 per iteration, so its event is found
-        // once by binary search and afterwards by stepping forward (a few
-        // events at most per iteration on collider-sized events).
-        int ev = 0;
-        EvRec cur{0, 0}, nxt{0, 0};
-        bool located = false;
-        if constexpr (MODE != GLV_COMPENSATED) {
-          // two pairs per lane and iteration, k and k + 64: their LDS reads and
-          // mass evaluations overlap (the second's event is stepped to from the
-          // first's)
-          for (int it = lo; it < hi; it += 128) {
-            const int k0 = it + lane, k1 = k0 + 64;
-            if (k0 < hi) {
-              if (!located) {
-                ev = search_rec(ch, 0, nch, k0);
-                cur = ch[ev];
-                nxt = ch[ev + 1];
-                located = true;
-              }
-              while (nxt.p <= k0) {
-                cur = nxt;
-                nxt = ch[++ev + 1];
-              }
-              int i, j;
-              pair_of_rank(k0 - cur.p, nxt.o - cur.o, colex, &i, &j);
-              const int si0 = cur.o + i, sj0 = cur.o + j;
-              const bool two = k1 < hi;
-              int si1 = si0, sj1 = sj0;
-              if (two) {
-                while (nxt.p <= k1) {
-                  cur = nxt;
-                  nxt = ch[++ev + 1];
-                }
-                pair_of_rank(k1 - cur.p, nxt.o - cur.o, colex, &i, &j);
-                si1 = cur.o + i;
-                sj1 = cur.o + j;
-              }
-              const typename V4<T>::type a0 = st.cart[si0], b0 = st.cart[sj0];
-              const typename V4<T>::type a1 = st.cart[si1], b1 = st.cart[sj1];
-              T w0[4], w1[4];
+    // the chunk's events with pairs, compacted, then the sentinel
+    const bool has_pairs = in_chunk && n_e >= 2;
+    const uint64_t hp = __ballot(has_pairs);
+    const int ncp = __builtin_popcountll(hp);
+    if (need_po) {
+      if (has_pairs) {
+        const int c = __builtin_popcountll(hp & ((1ull << lane) - 1));
+        W.eo[c] = lo_rel;
+        W.en[c] = n_e;
+        W.ep[c] = (int)(plo - q0);
+      }
+      if (lane == 0) {
+        W.eo[ncp] = np;
+        W.en[ncp] = 0;
+        W.ep[ncp] = nq;
+      }
+    }
+
+    // 1. stage the chunk's particles
+    for (int t = lane; t < np; t += 64) stage_particle<T, COORDS, MODE>(A.p, base + t, st, t);
+    wave_sync();
+
+    // 2. one lane per event: totals in CSR order, plain event mass
+    double msum = 0.0;
+    if (in_chunk) {
+      const int lo = lo_rel, hi = lo_rel + n_e;
+      T tot[4];
+      if constexpr (kComp) {
+        // totals and sum of M^2 in one pass, two particles per LDS wait
+        double d[4] = {0, 0, 0, 0};
+        int t = lo;
+        for (; t + 2 <= hi; t += 2) {
+          const R4 r0 = st.cart[t], r1 = st.cart[t + 1];
+          const double m0 = (double)st.legA[t][3], m1 = (double)st.legA[t + 1][3];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                w0[c] = a0[c] + b0[c];
-                w1[c] = a1[c] + b1[c];
+          for (int k = 0; k < 4; ++k) d[k] = (d[k] + (double)r0[k]) + (double)r1[k];
+          msum = (msum + m0 * m0) + m1 * m1;
+        }
+        if (t < hi) {
+          const R4 r0 = st.cart[t];
+          const double m0 = (double)st.legA[t][3];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) d[k] += (double)r0[k];
+          msum += m0 * m0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
+      } else if constexpr (sizeof(T) == 4) {
+        double d[4] = {0, 0, 0, 0};
+        sum_records(st.cart, lo, hi, d);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot[k] = T(0);
+        sum_records(st.cart, lo, hi, tot);
+      }
+      const int64_t e = e0 + lane;
+      if (A.total[0]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store_out(A.total[k], e, tot[k]);
+      }
+      if constexpr (!kComp) {
+        if (A.event_m) store_out(A.event_m, e, mass_of(tot));
+      }
+    }
+
+    // 3. pairs, in rounds of qcap
+    double ks = 0.0;  // the event lane's sum of K (compensated)
+    if (want_pairs || want_k) {
+      for (int r0 = 0; r0 < nq; r0 += qcap) {
+        const int qn = min(qcap, nq - r0);
+        const int m = ((qn + 63) >> 6) | 1;  // pairs per lane, odd: the LDS stores spread over the banks
+        int k = r0 + lane * m;
+        const int kend = min(k + m, r0 + qn);
+        if (k < kend) {
+          int c = search_le32(W.ep, 0, ncp, k);
+          int o = W.eo[c], n = W.en[c];
+          int i, j;
+          decode_pair_small(k - W.ep[c], n, &i, &j);
+          int cn = c + 1;
+          int on = W.eo[cn], nn = W.en[cn];  // the next event with pairs (or the sentinel)
+          double kacc = 0.0;
+          for (; k < kend; ++k) {
+            T mk;
+            if constexpr (kComp) {
+              T ma, mb;
+              const LegC<T> la = staged_leg<T, MODE>(st, o + i, &ma), lb = staged_leg<T, MODE>(st, o + j, &mb);
+              double kd;
+              if constexpr (kDefer) {
+                bool redo;
+                mk = comp_pair_fp32(la, lb, &kd, &redo);
+                if (redo) kd = __builtin_nan("");
+              } else {
+                mk = comp_pair<T>(la, lb, ma, mb, &kd, &fb);
               }
-              const T m0 = mass_of(w0), m1 = mass_of(w1);
-              store_out(A.pair_m, q0 + k0, m0);
-              if (two) store_out(A.pair_m, q0 + k1, m1);
-            }
-          }
-        } else {
-          // compensated: two consecutive pairs per lane and iteration,
-          // k0 = it + 2 lane and k1 = k0 + 1, usually of one event, so that
-          // the K scan runs once per 128 pairs.  A lane whose k1 opens another
-          // event holds a head (k0, the last pair of its event) and a tail
-          // (k1); tails are scanned by event, a head takes the previous
-          // lane's scanned tail when that lane's tail has its event.
-          auto pair_at = [&](int si, int sj, int e, double* kd) -> T {
-            T ma, mb;
-            const LegC<T> la = staged_leg<T, MODE>(st, si, &ma), lb = staged_leg<T, MODE>(st, sj, &mb);
-            if constexpr (kDefer) {
-              bool redo;
-              const T m = comp_pair_fp32(la, lb, kd, &redo);
-              if (redo) s_redo[e] = 1;
-              return m;
+              kacc += kd;
             } else {
-              return comp_pair<T>(la, lb, ma, mb, kd, &fb);
+              const R4 a = st.cart[o + i], b = st.cart[o + j];
+              T w[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) w[q] = a[q] + b[q];
+              mk = mass_of(w);
             }
-          };
-          // a lane's two masses go out as one store: the slots start where the
-          // global pair index q0 + k is even (lane 0 of the first iteration
-          // may then hold only the slice's first pair)
-          const int sh = (int)((q0 + lo) & 1);
-          for (int it = lo - sh; it < hi; it += 128) {
-            int k0 = it + 2 * lane;
-            bool v0 = k0 >= lo && k0 < hi, v1 = k0 + 1 < hi;
-            if (!v0 && v1) {
-              k0 += 1;
-              v0 = true;
-              v1 = false;
+            W.pm[k - r0] = mk;
+            // lexicographic successor within the chunk
+            bool fin = false;
+            if (++j == n) {
+              if (++i == n - 1) {
+                fin = true;
+                o = on;
+                n = nn;
+                i = 0;
+                cn = min(cn + 1, ncp);
+                on = W.eo[cn];
+                nn = W.en[cn];
+              }
+              j = i + 1;
             }
-            const int k1 = k0 + 1;
-            double kd0 = 0.0, kd1 = 0.0;
-            int ev0 = 0x7fffffff, ev1 = 0x7fffffff;  // past the slice: never an event
-            if (v0) {
-              if (!located) {
-                ev = search_rec(ch, 0, nch, k0);
-                cur = ch[ev];
-                nxt = ch[ev + 1];
-                located = true;
+            if constexpr (kComp) {
+              if (fin || k + 1 == kend) {  // leave the partial at the lane's last pair of the event
+                W.kp[k - r0] = kacc;
+                kacc = 0.0;
               }
-              while (nxt.p <= k0) {
-                cur = nxt;
-                nxt = ch[++ev + 1];
-              }
-              int i, j;
-              pair_of_rank(k0 - cur.p, nxt.o - cur.o, colex, &i, &j);
-              ev0 = ev;
-              const T m0 = pair_at(cur.o + i, cur.o + j, ev, &kd0);
-              T m1 = T(0);
-              if (v1) {
-                if (nxt.p <= k1) {  // k0 closed its event: k1 is (0, 1) of the next with pairs
-                  do {
-                    cur = nxt;
-                    nxt = ch[++ev + 1];
-                  } while (nxt.p <= k1);
-                  i = 0;
-                  j = 1;
-                } else if (++j == nxt.o - cur.o) {  // lexicographic successor
-                  ++i;
-                  j = i + 1;
-                }
-                ev1 = ev;
-                m1 = pair_at(cur.o + i, cur.o + j, ev, &kd1);
-              }
-              if (want_pairs) {
-                T* out = A.pair_m + q0 + k0;
-                if (v1 && (reinterpret_cast<uintptr_t>(out) & (2 * sizeof(T) - 1)) == 0) {
-                  __builtin_nontemporal_store(typename V2<T>::type{m0, m1},
-                                              reinterpret_cast<typename V2<T>::type*>(out));
-                } else {
-                  __builtin_nontemporal_store(m0, out);
-                  if (v1) __builtin_nontemporal_store(m1, out + 1);
-                }
-              }
-            }
-            if (want_k) {
-              const bool split = v1 && ev1 != ev0;
-              const int tkey = v1 ? ev1 : ev0;  // keys ascend with the lane
-              const double ts = seg_scan_wave(split ? kd1 : kd0 + kd1, tkey);
-              const double pts = dpp_f64<kDppWaveShr1, 0xf>(ts);        // lane 0: 0
-              const int pkey = dpp_i32<kDppWaveShr1, 0xf>(tkey, -1);     // lane 0: -1
-              const int nfirst = dpp_i32<kDppWaveShl1, 0xf>(ev0, -1);    // lane 63: -1
-              if (split) acc[wid * epb + ev0] += (pkey == ev0 ? pts : 0.0) + kd0;
-              if (v0 && nfirst != tkey) acc[wid * epb + tkey] += ts;
             }
           }
         }
-      }
-      __syncthreads();
-      if constexpr (MODE == GLV_COMPENSATED) {
-        if (want_k && my < nch) {
-          double ks = 0.0;
-          for (int w = 0; w < nwaves; ++w) {
-            ks += acc[w * epb + my];
-            acc[w * epb + my] = 0.0;
+        wave_sync();
+        if (want_pairs) {
+          T* out = A.pair_m + q0 + r0;
+          for (int t = lane; t < qn; t += 64) store_out(out, t, W.pm[t]);
+        }
+        if constexpr (kComp) {
+          // the event lane adds the partial sums of the lanes that covered
+          // its pairs of this round, in lane order
+          if (want_k && in_chunk && n_e >= 2) {
+            const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
+            const int lo = max(plo_rel, r0) - r0, hi = min(phi_rel, r0 + qn) - r0;
+            if (lo < hi) {
+              for (int seg = lo / m; seg * m < hi; ++seg) ks += W.kp[min((seg + 1) * m, hi) - 1];
+            }
           }
+        }
+        wave_sync();
+      }
+    }
+    if constexpr (kComp) {
+      if (want_k && in_chunk) {
+        const bool marked = kDefer && (ks != ks) && n_e >= 2;  // a pair asked for the FP64 redo
+        if (A.event_m) {
           T em = (T)sqrt(msum + 2.0 * ks);
           if constexpr (kDefer) {
-            if (s_redo[my]) em = redo_mark();
+            if (marked) em = redo_mark();
           }
-          store_out(A.event_m, e0 + ca + my, em);
+          store_out(A.event_m, e0 + lane, em);
+        } else {
+          if constexpr (kDefer) {
+            // without event masses the mark goes to the event's first pair
+            // mass, after this wavefront's own stores of the chunk's masses
+            if (__ballot(marked)) {
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+              if (marked) store_out(A.pair_m, plo, redo_mark());
+            }
+          }
         }
       }
-      if constexpr (kDefer) {  // without event masses the mark goes to the event's first pair mass
-        if (!A.event_m && want_pairs && my < nch && s_redo[my]) store_out(A.pair_m, q0 + ch[my].p, redo_mark());
-      }
-      __syncthreads();
-      ca = cb;
     }
+    wave_sync();
+    ca = cb;
   }
-  if constexpr (MODE == GLV_COMPENSATED && sizeof(T) == 4) {
+  if constexpr (kComp && sizeof(T) == 4) {
     if (A.fallback) {
 #pragma unroll
       for (int d = 32; d > 0; d >>= 1) fb += __shfl_xor(fb, d);
@@ -880,8 +928,10 @@ struct BwdArgs {
   const T* gpair;
   T* gp[4];
   int64_t ne;
-  int epb;
-  int cap;
+  int epb;         // events per wavefront tile
+  int cap;         // particles staged per chunk (per wavefront)
+  int qcap;        // pair upstreams staged per chunk (per wavefront)
+  int wave_bytes;  // LDS bytes per wavefront
 };
 
 // Cartesian gradient of particle i from its partners (global memory path).
@@ -936,233 +986,282 @@ __device__ void big_event_bwd(const BwdArgs<T, COORDS>& A, int64_t e, int64_t lo
   __syncthreads();
 }
 
-// Pairs staged per chunk of the backward: at most this many per particle of
-// the chunk capacity (a chunk also ends where its pairs would exceed it).
-constexpr int kBwdPairsPerParticle = 4;
-
-__device__ __forceinline__ int64_t bwd_pair_cap(int cap) { return (int64_t)kBwdPairsPerParticle * cap; }
-
-// An event the tiled backward leaves to k_event_reduce_bwd_big.
-__device__ __forceinline__ bool bwd_big(int64_t n, int cap, bool pairs) {
-  return n > cap || (pairs && npairs(n) > bwd_pair_cap(cap));
+// An event the tiled backward leaves to k_event_reduce_bwd_big: more than
+// cap particles or, with pair upstreams, more than qcap pairs.
+__device__ __forceinline__ bool bwd_big(int64_t n, int cap, int qcap, bool pairs) {
+  return n > cap || (pairs && npairs(n) > (int64_t)qcap);
 }
 
-// LDS-staged backward.  A chunk holds at most one particle per thread (cap <=
-// block; the launch clamps the staging capacity to the workgroup) and, when
-// pair gradients are given, kBwdPairsPerParticle * cap pairs:
-//   * thread t converts particle t of the chunk once, keeps its Cartesian
-//     vector and Jacobian pieces (cos phi, sin phi, sinh eta, cosh eta) in
-//     registers and stages the vector in LDS for its partners; the chunk's
-//     pair gradients -- contiguous in grad_pair -- are copied to LDS, each
-//     thread issuing all of its loads before its stores; one lane per event
-//     records its particles' event (from the offsets: all one phase);
-//   * pair phase: each pair's gradient g_ij becomes c_ij = g_ij / |m_ij| in
-//     place, computed once, by one of its two legs: particle a of an event of
-//     n takes the partners a + 1, ..., a + d cyclically, d = (n - 1) / 2
-//     rounded down, plus a + n/2 when n is even and a < n/2 -- every pair
-//     once, about n/2 per particle, whatever the particle's place;
-//   * in the same phase one lane per event (spread over the wavefronts; its
-//     g_total and g_m were loaded with the chunk) sums the event's vectors V
-//     in CSR order and stages g_total + g_m dm(V)/dV, the upstream every
-//     particle of the event receives from the event outputs;
-//   * thread t then walks its event's particles in CSR order and adds the
-//     pair terms c_ij (v_i + v_j) = c_ij v_i + c_ij v_j of its partners
-//     (dm(w)/dw = (-P, E) / |m|, the same 4-vector for both legs of a pair),
-//     walking the pair indices incrementally, then the event's upstream, and
-//     applies its own conversion Jacobian.
+template <int COORDS>
+constexpr bool polar_coords() {
+  return COORDS == GLV_PTETAPHIM || COORDS == GLV_PTETAPHIE;
+}
+
+// LDS of one wavefront of the backward (cap particles, qcap pairs, epb events):
+//   cart[cap]   (px, py, pz, E) of the staged particles
+//   jac[cap]    (cos phi, sin phi, sinh eta, cosh eta)     pt/eta/phi systems
+//   raw[cap]    (first, last coordinate): pt or px, and M or E
+//   ut[epb]     per chunk event: g_total + g_m dm(V)/dV
+//   gq[qcap+2]  the chunk's pair upstreams, then c = g/|m| in place (two
+//               slots of slack, read and discarded by the partner walk)
+//   pev[cap]    chunk-relative event of each staged particle
+//   ceo, cen, cep [epb]  per chunk event: first particle, size, first pair
+//   eo, en, ep [epb+1]   the chunk's events with pairs (compacted) + sentinel
+template <typename T>
+__host__ __device__ __forceinline__ size_t wave_lds_bytes_bwd(int cap, int qcap, int epb) {
+  size_t b = (size_t)cap * 10 * sizeof(T) + (size_t)epb * 4 * sizeof(T) + (size_t)(qcap + 2) * sizeof(T);
+  b += (size_t)cap * sizeof(int) + 3 * (size_t)epb * sizeof(int) + 3 * (size_t)(epb + 1) * sizeof(int);
+  return (b + 31) & ~(size_t)31;
+}
+
+// The backward.  Like the forward, every wavefront works alone on a tile of
+// epb consecutive events, in chunks of consecutive events holding at most
+// cap particles and (with pair upstreams) qcap pairs:
+//   1. stage: the chunk's particles are loaded coalesced and converted once
+//      with their Jacobian pieces (all kept in LDS), the chunk's pair
+//      upstreams -- contiguous in grad_pair -- copied to LDS;
+//   2. the lane of each event sums its particles' vectors V in CSR order and
+//      stages g_total + g_m dm(V)/dV, the upstream every particle of the
+//      event receives from the event outputs;
+//   3. pair phase: lane L takes the contiguous pairs [L m, (L + 1) m) of the
+//      chunk (as the forward does) and turns each upstream g into
+//      c = g / |m| in place, computed once per pair (dm(w)/dw = (-P, E)/|m|
+//      is the same for both legs);
+//   4. particle phase: particle t of the chunk (lane t mod 64) walks its
+//      event's particles in CSR order, stepping the lexicographic pair index
+//      incrementally, sums C = sum c_ab and S = sum c_ab v_b, forms
+//      (-1, -1, -1, 1) (C v_a + S) plus the event upstream and applies its
+//      own conversion Jacobian; gradients are stored coalesced.
+// Every sum has a fixed order and no atomics are needed.
 template <typename T, int COORDS>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   using R4 = typename V4<T>::type;
+  using R2 = typename V2<T>::type;
   // event totals of FP32 data are summed in FP64
   using Acc = typename std::conditional<sizeof(T) == 4, double, T>::type;
-  const int epb = A.epb, cap = A.cap;  // cap <= blockDim.x
+  constexpr bool kPolar = polar_coords<COORDS>();
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nwaves = blockDim.x >> 6;
+  const int epb = A.epb, cap = A.cap, qcap = A.qcap;
+  unsigned char* wl = lds + (size_t)wid * A.wave_bytes;
+  R4* cart = reinterpret_cast<R4*>(wl);
+  R4* jac = cart + cap;
+  R2* raw = reinterpret_cast<R2*>(jac + cap);
+  R4* ut = reinterpret_cast<R4*>(raw + cap);
+  T* gq = reinterpret_cast<T*>(ut + epb);
+  int* pev = reinterpret_cast<int*>(gq + qcap + 2);
+  int* ceo = pev + cap;
+  int* cen = ceo + epb;
+  int* cep = cen + epb;
+  int* eo = cep + epb;
+  int* en = eo + (epb + 1);
+  int* ep = en + (epb + 1);
+
+  const int64_t e0 = ((int64_t)blockIdx.x * nwaves + wid) * epb;
+  if (e0 >= A.ne) return;  // the whole wavefront: no workgroup barrier follows
+  const int nev = (int)min((int64_t)epb, A.ne - e0);
   const bool pairs = A.gpair != nullptr;
   const bool want_v = A.gem != nullptr;
-  const int qcap = pairs ? (int)bwd_pair_cap(cap) : 0;
-  const int tid = (int)threadIdx.x;
-  const bool want_u = want_v || A.gt[0] != nullptr;
-  // LDS: cart[cap], s_ut[epb] (R4), s_g[qcap + 2] (T; qcap is even, one
-  //      slot of slack), s_gm[epb rounded up to even] (T), s_off[epb+1],
-  //      s_poff[epb+1] (int64), ch[epb+1] (EvRec), ev_of[cap] (uint16)
-  R4* cart = reinterpret_cast<R4*>(lds);
-  R4* s_ut = cart + cap;
-  T* s_g = reinterpret_cast<T*>(s_ut + epb);
-  T* s_gm = s_g + qcap + 2;
-  int64_t* s_off = reinterpret_cast<int64_t*>(s_gm + ((epb + 1) & ~1));
-  int64_t* s_poff = s_off + (epb + 1);
-  EvRec* ch = reinterpret_cast<EvRec*>(s_poff + (epb + 1));
-  unsigned short* ev_of = reinterpret_cast<unsigned short*>(ch + (epb + 1));
-  // event lanes: event t of a chunk belongs to thread (t % nw) * 64 + t / nw,
-  // spread over the workgroup's nw wavefronts (the block is a power of two
-  // >= 64 and a chunk has at most epb <= block events); tev is the inverse
-  const int nw = (int)blockDim.x >> 6;
-  const int tev = (tid & 63) * nw + (tid >> 6);
-  const int64_t ntiles = (A.ne + epb - 1) / epb;
+  const bool want_t = A.gt[0] != nullptr;
+  const bool want_u = want_v || want_t;
 
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t e0 = tile * epb;
-    const int nev = (int)min((int64_t)epb, A.ne - e0);
-    for (int i = tid; i <= nev; i += blockDim.x) {
-      s_off[i] = A.off[e0 + i];
-      if (pairs) s_poff[i] = A.poff[e0 + i];
+  // this lane's event of the tile and its upstreams
+  const bool mine = lane < nev;
+  int64_t olo = 0, ohi = 0, plo = 0, phi = 0;
+  T gtv[4] = {0, 0, 0, 0}, gmv = 0;
+  if (mine) {
+    olo = A.off[e0 + lane];
+    ohi = A.off[e0 + lane + 1];
+    if (pairs) {
+      plo = A.poff[e0 + lane];
+      phi = A.poff[e0 + lane + 1];
     }
-    __syncthreads();
-    int ca = 0;
-    while (ca < nev) {
-      if (bwd_big(s_off[ca + 1] - s_off[ca], cap, pairs)) {  // k_event_reduce_bwd_big's event
-        ++ca;
-        continue;
-      }
-      // largest cb with at most cap particles (and qcap pairs) from ca
-      int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
-      if (pairs) cb = min(cb, search_le(s_poff, ca + 1, nev + 1, s_poff[ca] + qcap));
-      const int nch = cb - ca;
-      const int64_t pbase = s_off[ca];
-      const int64_t q0 = pairs ? s_poff[ca] : 0;
-      const int np = (int)(s_off[cb] - pbase);
-      const int nq = pairs ? (int)(s_poff[cb] - q0) : 0;
-      const bool mine = tid < np;
-      const int64_t gi = pbase + tid;
-      // loads first: own particle, up to kBwdPairsPerParticle pair gradients
-      T c[4] = {0, 0, 0, 0};
-      if (mine) {
+    if (want_t) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = A.p.c[k][gi];
-      }
-      T gv[kBwdPairsPerParticle];
-#pragma unroll
-      for (int r = 0; r < kBwdPairsPerParticle; ++r) {
-        const int idx = tid + r * (int)blockDim.x;
-        gv[r] = (idx < nq) ? A.gpair[q0 + idx] : T(0);
-      }
-      // the event lane's upstreams (g_total, g_m), staged with the rest
-      const bool evl = want_u && tev < nch;
-      T gtv[4] = {0, 0, 0, 0}, gmv = 0;
-      if (evl) {
-        const int64_t e = e0 + ca + tev;
-        if (A.gt[0]) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) gtv[k] = A.gt[k][e];
-        }
-        if (want_v) gmv = A.gem[e];
-      }
-      for (int t = tid; t <= nch; t += blockDim.x)
-        ch[t] = EvRec{(int)(s_off[ca + t] - pbase), pairs ? (int)(s_poff[ca + t] - q0) : 0};
-      for (int t = tid; t < nch; t += blockDim.x) {
-        const int lo = (int)(s_off[ca + t] - pbase), hi = (int)(s_off[ca + t + 1] - pbase);
-        for (int i = lo; i < hi; ++i) ev_of[i] = (unsigned short)t;
-      }
-#pragma unroll
-      for (int r = 0; r < kBwdPairsPerParticle; ++r) {
-        const int idx = tid + r * (int)blockDim.x;
-        if (idx < nq) s_g[idx] = gv[r];
-      }
-      if (evl) {
-        s_ut[tev] = R4{gtv[0], gtv[1], gtv[2], gtv[3]};
-        s_gm[tev] = gmv;
-      }
-      LegJ<T> L = to_cart_j<COORDS, T, true>(c[0], c[1], c[2], c[3]);
-      if (mine) cart[tid] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
-      __syncthreads();
+      for (int k = 0; k < 4; ++k) gtv[k] = A.gt[k][e0 + lane];
+    }
+    if (want_v) gmv = A.gem[e0 + lane];
+  }
+  const uint64_t valid = (nev >= 64) ? ~0ull : ((1ull << nev) - 1);
 
-      // one lane per event: the upstream every particle's 4-vector receives
-      // from the event outputs, g_total + g_m dm(V)/dV, with V summed in CSR
-      // order
-      if (evl && want_v) {
-        const int lo = ch[tev].o, hi = ch[tev + 1].o;
-        Acc vt[4] = {0, 0, 0, 0};
-        int i = lo;
-        for (; i + 1 < hi; i += 2) {  // both reads first
+  int ca = 0;
+  while (ca < nev) {
+    const int64_t base = readlane64(olo, ca);
+    const int64_t q0 = pairs ? readlane64(plo, ca) : 0;
+    const uint64_t ge = valid & (~0ull << ca);
+    const bool fit = mine && (ohi - base <= (int64_t)cap) && (!pairs || phi - q0 <= (int64_t)qcap);
+    const uint64_t fits = __ballot(fit) & ge;
+    const uint64_t stop = ge & ~fits;
+    const int cb = stop ? (int)__builtin_ctzll(stop) : nev;
+    if (cb == ca) {  // k_event_reduce_bwd_big's event
+      ++ca;
+      continue;
+    }
+    const int np = (int)(readlane64(ohi, cb - 1) - base);
+    const int nq = pairs ? (int)(readlane64(phi, cb - 1) - q0) : 0;
+    const bool in_chunk = lane >= ca && lane < cb;
+    const int ce = lane - ca;
+    const int lo_rel = (int)(olo - base), n_e = (int)(ohi - olo);
+    const bool has_pairs = pairs && in_chunk && n_e >= 2;
+    const uint64_t hp = __ballot(has_pairs);
+    const int ncp = __builtin_popcountll(hp);
+    if (in_chunk) {
+      ceo[ce] = lo_rel;
+      cen[ce] = n_e;
+      cep[ce] = (int)(plo - q0);
+    }
+    if (has_pairs) {
+      const int c = __builtin_popcountll(hp & ((1ull << lane) - 1));
+      eo[c] = lo_rel;
+      en[c] = n_e;
+      ep[c] = (int)(plo - q0);
+    }
+    if (pairs && lane == 0) {
+      eo[ncp] = np;
+      en[ncp] = 0;
+      ep[ncp] = nq;
+    }
+
+    // 1. stage: particles with their Jacobian pieces, the pair upstreams
+    for (int t = lane; t < np; t += 64) {
+      const int64_t gi = base + t;
+      const T c0 = A.p.c[0][gi], c1 = A.p.c[1][gi], c2 = A.p.c[2][gi], c3 = A.p.c[3][gi];
+      const LegJ<T> L = to_cart_j<COORDS, T, true>(c0, c1, c2, c3);
+      cart[t] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
+      if constexpr (kPolar) jac[t] = R4{L.cp, L.sp, L.sh, L.ch};
+      raw[t] = R2{c0, c3};
+    }
+    if (pairs) {
+      for (int t = lane; t < nq; t += 64) gq[t] = A.gpair[q0 + t];
+    }
+    wave_sync();
+
+    // 2. one lane per event: the event upstream, and the particles' event
+    if (in_chunk) {
+      Acc vt[4] = {0, 0, 0, 0};
+      const int hi = lo_rel + n_e;
+      int i = lo_rel;
+      for (; i + 1 < hi; i += 2) {  // both reads first
+        pev[i] = ce;
+        pev[i + 1] = ce;
+        if (want_v) {
           const R4 v0 = cart[i], v1 = cart[i + 1];
 #pragma unroll
           for (int k = 0; k < 4; ++k) vt[k] = (vt[k] + (Acc)v0[k]) + (Acc)v1[k];
         }
-        if (i < hi) {
+      }
+      if (i < hi) {
+        pev[i] = ce;
+        if (want_v) {
           const R4 v0 = cart[i];
 #pragma unroll
           for (int k = 0; k < 4; ++k) vt[k] += (Acc)v0[k];
         }
-        T tot[4], ud[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
-        dmass<T>(tot, s_gm[tev], ud);
-        const R4 gt4 = s_ut[tev];
-        s_ut[tev] = R4{ud[0] + gt4[0], ud[1] + gt4[1], ud[2] + gt4[2], ud[3] + gt4[3]};
       }
-
-      // Pair ranks inside an event: pair (b, a), b < a, sits at
-      // R(b) + a - b - 1, which grows by n - b - 2 with b; pair (a, b), b > a,
-      // at R(a) + b - a - 1, consecutive from R(a) = a (2n - a - 1) / 2.
-      int ev = 0, n = 0, ai = 0;
-      EvRec rc{0, 0};
-      if (mine) {
-        ev = ev_of[tid];
-        rc = ch[ev];
-        n = ch[ev + 1].o - rc.o;
-        ai = tid - rc.o;
-      }
-      const int qrow = rc.p + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
-      if (pairs) {
-        if (mine) {
-          const int cnt = ((n - 1) >> 1) + ((n & 1) == 0 && 2 * ai < n ? 1 : 0);
-          int qlo = rc.p + ai - 1, qhi = qrow;
-          for (int t = 0, b = ai + 1; t < cnt; ++t, ++b) {
-            const bool wrap = b >= n;
-            const int bb = wrap ? b - n : b;
-            const int q = wrap ? qlo : qhi;
-            const T g = s_g[q];
-            const R4 vj = cart[rc.o + bb];
-            T w[4];
+      if (want_u) {
+        T ud[4] = {0, 0, 0, 0};
+        if (want_v) {
+          T tot[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w[k] = L.v[k] + vj[k];
-            s_g[q] = pair_coef<T>(w, g);
-            if (wrap)
-              qlo += n - bb - 2;
-            else
-              ++qhi;
-          }
+          for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
+          dmass<T>(tot, gmv, ud);
         }
+        ut[ce] = R4{ud[0] + gtv[0], ud[1] + gtv[1], ud[2] + gtv[2], ud[3] + gtv[3]};
       }
-      if (pairs || want_u) __syncthreads();  // s_g and s_ut complete
-
-      if (mine) {
-        T u[4] = {0, 0, 0, 0};
-        if (want_u) {
-          const R4 ut = s_ut[ev];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) u[k] = ut[k];
-        }
-        if (pairs && n > 1) {
-          // partners in ascending order: S = sum of c_ab v_b, C = sum of c_ab
-          T S[4] = {0, 0, 0, 0}, C = 0;
-          int qlo = rc.p + ai - 1, qhi = qrow;
-          for (int bj = 0; bj < n; ++bj) {
-            // branch-free: at bj == ai the slot read (at most nq, the slack
-            // slot) is replaced by 0, which adds exact zeros
-            const bool below = bj < ai;
-            const T cs = s_g[below ? qlo : qhi];
-            const R4 vj = cart[rc.o + bj];
-            const T cab = (bj == ai) ? T(0) : cs;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) S[k] += cab * vj[k];
-            C += cab;
-            qlo += below ? n - bj - 2 : 0;
-            qhi += bj > ai ? 1 : 0;
-          }
-          // sum of c_ab (v_a + v_b) = C v_a + S, with dm/dw = (-P, E) / |m|
-#pragma unroll
-          for (int k = 0; k < 3; ++k) u[k] -= C * L.v[k] + S[k];
-          u[3] += C * L.v[3] + S[3];
-        }
-        T g[4];
-        chain_coords<COORDS, T>(L, c[0], c[3], u, g);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) store_out(A.gp[k], gi, g[k]);
-      }
-      __syncthreads();
-      ca = cb;
     }
+
+    // 3. pair phase: c = g / |m| in place, each pair once
+    if (nq > 0) {
+      const int m = ((nq + 63) >> 6) | 1;
+      int k = lane * m;
+      const int kend = min(k + m, nq);
+      if (k < kend) {
+        const int c = search_le32(ep, 0, ncp, k);
+        int o = eo[c], n = en[c];
+        int i, j;
+        decode_pair_small(k - ep[c], n, &i, &j);
+        int cn = c + 1;
+        int on = eo[cn], nn = en[cn];
+        for (; k < kend; ++k) {
+          const R4 a = cart[o + i], b = cart[o + j];
+          T w[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = a[q] + b[q];
+          gq[k] = pair_coef<T>(w, gq[k]);
+          if (++j == n) {
+            if (++i == n - 1) {
+              o = on;
+              n = nn;
+              i = 0;
+              cn = min(cn + 1, ncp);
+              on = eo[cn];
+              nn = en[cn];
+            }
+            j = i + 1;
+          }
+        }
+      }
+    }
+    wave_sync();
+
+    // 4. particle phase
+    for (int t = lane; t < np; t += 64) {
+      const int pe = pev[t];
+      T u[4] = {0, 0, 0, 0};
+      if (want_u) {
+        const R4 u4 = ut[pe];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = u4[q];
+      }
+      const R4 va = cart[t];
+      const int n = cen[pe];
+      if (pairs && n > 1) {
+        const int o = ceo[pe], p0 = cep[pe], ai = t - o;
+        // partners in ascending order: pair (b, a), b < a, sits at
+        // R(b) + a - b - 1, growing by n - b - 2 with b; pair (a, b), b > a,
+        // at R(a) + b - a - 1, consecutive from R(a) = a (2n - a - 1) / 2
+        T S[4] = {0, 0, 0, 0}, C = 0;
+        int qlo = p0 + ai - 1, qhi = p0 + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
+        for (int bj = 0; bj < n; ++bj) {
+          // branch-free: at bj == ai the slot read (at most nq, inside the
+          // slack) is replaced by 0, which adds exact zeros
+          const bool below = bj < ai;
+          const T cs = gq[below ? qlo : qhi];
+          const R4 vj = cart[o + bj];
+          const T cab = (bj == ai) ? T(0) : cs;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) S[q] += cab * vj[q];
+          C += cab;
+          qlo += below ? n - bj - 2 : 0;
+          qhi += bj > ai ? 1 : 0;
+        }
+        // sum of c_ab (v_a + v_b) = C v_a + S, with dm/dw = (-P, E) / |m|
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] -= C * va[q] + S[q];
+        u[3] += C * va[3] + S[3];
+      }
+      LegJ<T> L;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) L.v[q] = va[q];
+      if constexpr (kPolar) {
+        const R4 jj = jac[t];
+        L.cp = jj[0];
+        L.sp = jj[1];
+        L.sh = jj[2];
+        L.ch = jj[3];
+      } else {
+        L.cp = L.sp = L.sh = L.ch = T(0);
+      }
+      const R2 rw = raw[t];
+      T g[4];
+      chain_coords<COORDS, T>(L, rw[0], rw[1], u, g);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) store_out(A.gp[q], base + t, g[q]);
+    }
+    wave_sync();
+    ca = cb;
   }
 }
 
@@ -1175,7 +1274,7 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_bwd_big(BwdArgs<T, C
   __shared__ int count;
   for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
     const int64_t e = base + threadIdx.x;
-    const bool big = e < A.ne && bwd_big(A.off[e + 1] - A.off[e], A.cap, A.gpair != nullptr);
+    const bool big = e < A.ne && bwd_big(A.off[e + 1] - A.off[e], A.cap, A.qcap, A.gpair != nullptr);
     if (!__syncthreads_or(big)) continue;
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
@@ -1194,8 +1293,6 @@ int big_grid(int64_t ne) {
   return (int)std::min<int64_t>(std::max<int64_t>(1, (ne + kBigBlock - 1) / kBigBlock), 2048);
 }
 
-// The backward stages at most one particle per thread.
-int bwd_cap(const Tiling& t) { return std::min(t.lds_particles, t.block); }
 
 int grid_for(int64_t ne, int epb) {
   int64_t tiles = (ne + epb - 1) / epb;
@@ -1221,8 +1318,11 @@ hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.ne = ne;
   A.epb = t.events_per_tile;
   A.cap = t.lds_particles;
-  hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block),
-                     lds, s, A);
+  A.qcap = t.pairs_per_round;
+  A.wave_bytes = (int)wave_lds_bytes<T, MODE>(t.lds_particles, t.pairs_per_round, t.events_per_tile);
+  const int waves = t.block / 64;
+  const int64_t tiles = (ne + t.events_per_tile - 1) / t.events_per_tile;
+  hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE>), dim3(grid_for(tiles, waves)), dim3(t.block), lds, s, A);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_event_reduce_big<T, COORDS, MODE>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
@@ -1245,9 +1345,12 @@ hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.gpair = (const T*)gpair;
   A.ne = ne;
   A.epb = t.events_per_tile;
-  A.cap = bwd_cap(t);
-  hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block), lds,
-                     s, A);
+  A.cap = t.lds_particles;
+  A.qcap = t.pairs_per_round;
+  A.wave_bytes = (int)wave_lds_bytes_bwd<T>(t.lds_particles, t.pairs_per_round, t.events_per_tile);
+  const int64_t tiles = (ne + t.events_per_tile - 1) / t.events_per_tile;
+  hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(tiles, t.block / 64)), dim3(t.block), lds, s,
+                     A);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_event_reduce_bwd_big<T, COORDS>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
@@ -1291,23 +1394,22 @@ hipError_t bwd_dt(glv_coords co, int64_t ne, const int64_t* off, const int64_t* 
 }  // namespace
 
 size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
-  size_t tsz = (dt == GLV_F64) ? 8 : 4;
-  size_t cols = (mode == GLV_COMPENSATED) ? 10 : 4;
-  size_t nwaves = (size_t)t.block / 64;
-  size_t acc = (mode == GLV_COMPENSATED) ? nwaves * (size_t)t.events_per_tile * 8 : 0;
-  size_t redo = (mode == GLV_COMPENSATED && dt == GLV_F32) ? (size_t)t.events_per_tile * sizeof(int) : 0;
-  return 2 * ((size_t)t.events_per_tile + 1) * 8 + 16 * 8 + acc + ((size_t)t.events_per_tile + 1) * sizeof(EvRec) +
-         ((kColexPairs + 1) & ~1) * sizeof(unsigned short) + redo + cols * (size_t)t.lds_particles * tsz;
+  const size_t waves = (size_t)t.block / 64;
+  const int cap = t.lds_particles, qcap = t.pairs_per_round, epb = t.events_per_tile;
+  size_t per;
+  if (dt == GLV_F64)
+    per = mode == GLV_COMPENSATED ? wave_lds_bytes<double, GLV_COMPENSATED>(cap, qcap, epb)
+                                  : wave_lds_bytes<double, GLV_PLAIN>(cap, qcap, epb);
+  else
+    per = mode == GLV_COMPENSATED ? wave_lds_bytes<float, GLV_COMPENSATED>(cap, qcap, epb)
+                                  : wave_lds_bytes<float, GLV_PLAIN>(cap, qcap, epb);
+  return waves * per;
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
-  // the pair-gradient area is sized for pair gradients given; it is the
-  // bound the launch must satisfy either way
-  const size_t tsz = (dt == GLV_F64) ? 8 : 4;
-  const size_t cap = (size_t)bwd_cap(t), epb = (size_t)t.events_per_tile;
-  const size_t qcap = (size_t)kBwdPairsPerParticle * cap;
-  return 4 * (cap + epb) * tsz + (qcap + 2) * tsz + ((epb + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 +
-         (epb + 1) * sizeof(EvRec) + cap * sizeof(unsigned short);
+  const size_t waves = (size_t)t.block / 64;
+  const int cap = t.lds_particles, qcap = t.pairs_per_round, epb = t.events_per_tile;
+  return waves * (dt == GLV_F64 ? wave_lds_bytes_bwd<double>(cap, qcap, epb) : wave_lds_bytes_bwd<float>(cap, qcap, epb));
 }
 
 hipError_t launch_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, hipStream_t s) {

@@ -336,12 +336,18 @@ def glv_validate_offsets(offsets, n_particles):
 
 
 def _tiling(t):
+    """A glv_tiling from (block, events_per_tile, lds_particles[, pairs_per_round]);
+    0 or a missing pairs_per_round = the library's choice."""
     if t is None:
         return None
     if isinstance(t, glv_tiling):
         return ctypes.byref(t)
-    block, epb, cap = t
-    return ctypes.byref(glv_tiling(block, epb, cap, 0))
+    t = tuple(t) + (0,) * (4 - len(t))
+    return ctypes.byref(glv_tiling(*t))
+
+
+def _as_tuple(t):
+    return (t.block, t.events_per_tile, t.lds_particles, t.pairs_per_round)
 
 
 def glv_event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM", mode="plain", want_total=True,
@@ -400,7 +406,7 @@ def glv_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None, grad_ev
 def glv_autotune_event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM", mode="plain"):
     """Times candidate tilings on these inputs, keeps the fastest for this
     process (device, dtype, coords, mode) and returns it as (block,
-    events_per_tile, lds_particles)."""
+    events_per_tile, lds_particles, pairs_per_round)."""
     dev, dt = p[0].device, p[0].dtype
     _check_device(p[0])
     offsets = _offsets(offsets, dev)
@@ -417,21 +423,21 @@ def glv_autotune_event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM",
                                                 _ptr(offsets), _ptr(pair_offsets), P4(*[t.data_ptr() for t in p]),
                                                 P4(*[t.data_ptr() for t in total]), _ptr(em), _ptr(pm),
                                                 ctypes.byref(best), _stream(dev)))
-    return (best.block, best.events_per_tile, best.lds_particles)
+    return _as_tuple(best)
 
 
 def glv_current_tiling(dtype=torch.float64, coords="PtEtaPhiM", mode="plain"):
     t = glv_tiling()
     check("glv_current_tiling", _lib.load().glv_current_tiling(_dtype_code(dtype), _coords_code(coords),
                                                                _mode_code(mode), ctypes.byref(t)))
-    return (t.block, t.events_per_tile, t.lds_particles)
+    return _as_tuple(t)
 
 
 def glv_autotune_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None, grad_event_m=None,
                                   grad_pair_m=None, coords="PtEtaPhiM"):
     """Times the backward's candidate tilings on these inputs and upstreams,
     keeps the fastest for this process (device, dtype, coords) and returns
-    it as (block, events_per_tile, lds_particles)."""
+    it as (block, events_per_tile, lds_particles, pairs_per_round)."""
     dev, dt = p[0].device, p[0].dtype
     _check_device(p[0])
     offsets = _offsets(offsets, dev)
@@ -450,14 +456,14 @@ def glv_autotune_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None
               _dtype_code(dt), _coords_code(coords), ne, _ptr(offsets), _ptr(pair_offsets),
               P4(*[t.data_ptr() for t in p]), P4(*[t.data_ptr() for t in gt]) if gt else None, _ptr(gem),
               _ptr(gpm), P4(*[t.data_ptr() for t in gp]), ctypes.byref(best), _stream(dev)))
-    return (best.block, best.events_per_tile, best.lds_particles)
+    return _as_tuple(best)
 
 
 def glv_current_tiling_bwd(dtype=torch.float64, coords="PtEtaPhiM"):
     t = glv_tiling()
     check("glv_current_tiling_bwd", _lib.load().glv_current_tiling_bwd(_dtype_code(dtype), _coords_code(coords),
                                                                        ctypes.byref(t)))
-    return (t.block, t.events_per_tile, t.lds_particles)
+    return _as_tuple(t)
 
 
 def glv_abi_version():

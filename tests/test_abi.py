@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strings(lib):
-    assert lib.glv_abi_version() == 1
+    assert lib.glv_abi_version() == 2
     for code in range(11):
         assert lib.glv_status_str(code)
     assert lib.glv_status_str(0) == b"ok"
@@ -199,7 +199,8 @@ def test_jagged_validation(lib):
     assert f(2, 1, 0, -2, OFF, PO, cols(P), cols(T), EM, PM, None, None, None) == SIZE
     assert f(2, 1, 0, 10, OFF, PO, cols(P), cols(T), OFF, PM, None, None, None) == ALIAS    # event_m over offsets
     for bad in ((100, 0, 0, 0), (256, 512, 0, 0), (256, 128, 32, 0), (256, 128, 8192, 0), (256, 128, 1024, 1),
-                (1024, 16, 256, 0), (512, 512, 4096, 0)):
+                (1024, 16, 256, 0), (512, 512, 4096, 0), (256, 65, 128, 512), (256, 32, 128, 100),
+                (256, 32, 128, 8192), (256, 32, 128, 32), (256, 32, 4096, 512), (512, 32, 1024, 1024)):
         t = _lib.glv_tiling(*bad)
         assert f(2, 1, 0, 10, OFF, PO, cols(P), cols(T), EM, PM, None, ctypes.byref(t), None) == TILING, bad
     g = lib.glv_pair_offsets
@@ -208,6 +209,9 @@ def test_jagged_validation(lib):
     assert g(10, OFF, OFF + 8, None) == ALIAS
     h = lib.glv_event_reduce_bwd
     assert h(2, 1, 10, OFF, None, cols(P), None, None, PM, cols(T), None, None) == OFFSETS
+    for bad in ((128, 16, 128, 100), (128, 65, 128, 512), (128, 16, 32, 512), (512, 64, 512, 4096)):
+        t = _lib.glv_tiling(*bad)
+        assert h(2, 1, 10, OFF, PO, cols(P), None, None, PM, cols(T), ctypes.byref(t), None) == TILING, bad
     assert h(2, 1, 10, OFF, PO, cols(P), None, None, None, cols(P), None, None) == ALIAS
     v = lib.glv_validate_offsets
     assert v(10, OFF, -1, EM, None) == SIZE
@@ -225,7 +229,7 @@ def test_current_tiling_default(lib):
 def test_current_tiling_bwd_default_and_autotune_validation(lib):
     t = _lib.glv_tiling()
     assert lib.glv_current_tiling_bwd(2, 1, ctypes.byref(t)) == OK
-    assert (t.block, t.events_per_tile, t.lds_particles) == (128, 64, 128)
+    assert (t.block, t.events_per_tile, t.lds_particles, t.pairs_per_round) == (128, 32, 128, 512)
     assert lib.glv_current_tiling_bwd(3, 1, ctypes.byref(t)) == DTYPE
     assert lib.glv_current_tiling_bwd(2, 1, None) == NULL
     # host-side validation, before any device work: missing gradient outputs

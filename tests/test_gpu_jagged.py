@@ -119,11 +119,11 @@ def test_event_reduce_edge_events():
     off[1:] = np.cumsum(counts)
     a, _ = synth.pairs_generic(synth.rng(704), int(off[-1]))
     for dtype in (torch.float64, torch.float32):
-        for tiling in (None, (256, 4, 512), (64, 1, 64), (512, 13, 1024)):
+        for tiling in (None, (128, 4, 512, 64), (64, 1, 64, 64), (128, 13, 256, 1024)):
             total, em, pm = glv.glv_event_reduce(gpu(a, dtype), _off(off), tiling=tiling)
             _check_forward(off, a, dtype, "PtEtaPhiM", "plain", total, em, pm, f"edge {dtype} {tiling}")
         total, em, pm = glv.glv_event_reduce(gpu(a, torch.float32), _off(off), mode="compensated",
-                                             tiling=(128, 8, 256))
+                                             tiling=(128, 8, 256, 192))
         _check_forward(off, a, torch.float32, "PtEtaPhiM", "compensated", total, em, pm, "edge comp")
 
 
@@ -131,7 +131,8 @@ def test_tilings_give_identical_pair_masses_and_totals():
     off, p = _events(20000, 705)
     gp, go = gpu(p, torch.float64), _off(off)
     ref = None
-    for tiling in [(256, 128, 1024), (128, 32, 256), (512, 512, 1536), (64, 64, 512), (512, 100, 1024)]:
+    for tiling in [(256, 64, 128, 512), (128, 32, 256, 256), (64, 64, 512, 1024), (256, 17, 64, 64),
+                   (512, 5, 128, 192)]:
         total, em, pm = glv.glv_event_reduce(gp, go, tiling=tiling)
         out = [host(pm)] + [host(t) for t in total] + [host(em)]
         if ref is None:
@@ -142,7 +143,7 @@ def test_tilings_give_identical_pair_masses_and_totals():
     # compensated FP32: pair masses identical; event masses reproducible per tiling
     gp32 = gpu(p, torch.float32)
     ref = None
-    for tiling in [(256, 128, 1024), (128, 32, 256), (512, 256, 512)]:
+    for tiling in [(256, 64, 128, 512), (128, 32, 256, 256), (512, 7, 64, 128)]:
         _, em1, pm1 = glv.glv_event_reduce(gp32, go, mode="compensated", tiling=tiling)
         _, em2, pm2 = glv.glv_event_reduce(gp32, go, mode="compensated", tiling=tiling)
         assert torch.equal(em1, em2) and torch.equal(pm1, pm2)
@@ -205,7 +206,7 @@ def test_autotune_picks_a_valid_tiling():
     off, p = _events(1 << 16, 706)
     gp, go = gpu(p, torch.float64), _off(off)
     best = glv.glv_autotune_event_reduce(gp, go)
-    assert best[0] in (128, 256, 512) and 1 <= best[1] <= best[0]
+    assert best[0] in (64, 128, 256, 512) and 1 <= best[1] <= 64 and best[3] % 64 == 0, best
     assert glv.glv_current_tiling(torch.float64, "PtEtaPhiM", "plain") == best
     total, em, pm = glv.glv_event_reduce(gp, go)
     _, em2, pm2 = glv.glv_event_reduce(gp, go, tiling=best)
@@ -269,7 +270,7 @@ def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
     """Events of 40-50 particles against a tiling of 256 staged particles and
     1024 staged pair gradients: the pair cap, not the particle cap, ends the
     chunks, and 50-particle events (1225 pairs) take the separate path; with
-    128 staged particles (512 pair gradients) every event of 40 or more takes
+    128 staged particles and 512 pair gradients every event of 40 or more takes
     it.  Also without pair upstreams (no pair offsets needed) and without any
     upstream."""
     counts = np.array([40, 3, 50, 0, 45, 1, 2, 40, 41, 50, 7, 44] * 6, dtype=np.int64)
@@ -301,7 +302,7 @@ def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
                                        None if c_gt is None else widened(c_gt, dtype),
                                        None if c_gem is None else widened([c_gem], dtype)[0],
                                        None if c_gpr is None else widened([c_gpr], dtype)[0])
-        for tiling in ((256, 128, 256), (128, 16, 256), None):
+        for tiling in ((64, 64, 256, 1024), (128, 16, 128, 512), None):
             got = glv.glv_event_reduce_bwd(
                 gpu(p, dtype), _off(off), grad_total=None if c_gt is None else gpu(c_gt, dtype),
                 grad_event_m=None if c_gem is None else gpu([c_gem], dtype)[0],
@@ -395,7 +396,7 @@ def test_large_event_pair_masses_match_across_paths():
     go = _off(off)
     for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
         gp = gpu(p, dtype)
-        runs = [glv.glv_event_reduce(gp, go, mode=mode, tiling=t) for t in ((256, 64, 256), (512, 64, 1024))]
+        runs = [glv.glv_event_reduce(gp, go, mode=mode, tiling=t) for t in ((256, 64, 256, 512), (64, 64, 1024, 512))]
         a, b = host(runs[0][2]).astype(np.float64), host(runs[1][2]).astype(np.float64)
         if mode == "plain":
             assert np.array_equal(a, b)
@@ -422,7 +423,8 @@ def test_autotune_bwd_picks_a_valid_tiling():
     gem = gpu([g.standard_normal(ne)], torch.float64)[0]
     gpr = gpu([g.standard_normal(int(po[-1]))], torch.float64)[0]
     best = glv.glv_autotune_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr)
-    assert best[0] in (64, 128, 256, 512) and 16 <= best[1] <= best[0] and best[2] == best[0], best
+    assert best[0] in (64, 128) and best[1] in (16, 32, 64) and best[2] in (64, 128, 256), best
+    assert best[3] in (256, 512, 1024), best
     assert glv.glv_current_tiling_bwd(torch.float64, "PtEtaPhiM") == best
     a = glv.glv_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr)
     b = glv.glv_event_reduce_bwd(gp, go, grad_total=gt, grad_event_m=gem, grad_pair_m=gpr, tiling=best)
@@ -446,7 +448,8 @@ def test_random_layouts_and_tilings(seed):
     off[1:] = np.cumsum(counts)
     p, _ = synth.pairs_generic(synth.rng(seed), int(off[-1]))
     block = int(g.choice([64, 128, 256, 512]))
-    tiling = (block, int(g.integers(1, block + 1)), int(g.choice([64, 128, 256, 512, 1024])))
+    tiling = (block, int(g.integers(1, 65)), int(g.choice([64, 128, 256, 512, 1024])),
+              64 * int(g.integers(1, 17)))
     go = _off(off)
     for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
         try:
@@ -460,14 +463,14 @@ def test_random_layouts_and_tilings(seed):
     gem = g.standard_normal(ne)
     gpr = g.standard_normal(int(po[-1]))
     want = oracle.event_reduce_vjp("PtEtaPhiM", off, p, gt, gem, gpr)
-    bt = (block, tiling[1], block)
+    bt = tiling
     try:
         got = glv.glv_event_reduce_bwd(gpu(p, torch.float64), go, grad_total=gpu(gt, torch.float64),
                                        grad_event_m=gpu([gem], torch.float64)[0],
                                        grad_pair_m=gpu([gpr], torch.float64)[0], tiling=bt)
     except RuntimeError as e:
         assert "GLV_EINVAL_TILING" in str(e), e
-        bt = (block, min(tiling[1], 64), block)
+        bt = (64, tiling[1], min(tiling[2], 256), tiling[3])
         got = glv.glv_event_reduce_bwd(gpu(p, torch.float64), go, grad_total=gpu(gt, torch.float64),
                                        grad_event_m=gpu([gem], torch.float64)[0],
                                        grad_pair_m=gpu([gpr], torch.float64)[0], tiling=bt)
