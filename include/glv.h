@@ -342,36 +342,80 @@ glv_status glv_event_reduce_bwd(glv_dtype dtype, glv_coords coords, int64_t n_ev
 glv_status glv_validate_offsets(int64_t n_events, const int64_t* offsets, int64_t n_particles,
                                 long long* bad_count, void* stream);
 
-/* Times candidate tilings of glv_event_reduce on the caller's data (the
- * arguments are those of glv_event_reduce, outputs included, which end up
- * holding a valid result), keeps the fastest as this process's choice for
- * (current device, dtype, coords, mode) and writes it to *best if not NULL.
- * Synchronises `stream`. */
+/* Autotuning of the jagged reduction (not in the paper: its data are arrays
+ * of particles of varying size, Sec. 5.1).  The best tiling depends on the
+ * device and on the distribution of event sizes, so a tuned choice is kept
+ * under a key made of the device architecture, dtype, coordinate system,
+ * direction (forward with its mode, or backward) and a signature of the
+ * dataset: the order of magnitude of the event count and the share of events
+ * in each size class (0, then [2^(b-1), 2^b)), in 5 % steps, over all events
+ * or, beyond 65,536 events, over 32 evenly spread runs of 2,048 consecutive
+ * events (copied to the host: the autotuning calls synchronise `stream`).
+ *
+ * Persistent cache: if the environment variable GLV_AUTOTUNE_CACHE names a
+ * file, choices are read from and added to it, as JSON:
+ *   {"format": "glv-autotune-1", "entries": [
+ *     {"key": "<key>", "tiling": [block, events_per_tile, lds_particles,
+ *                                 pairs_per_round]}, ...]}
+ * A missing file is created.  A file that is not exactly this (or holds a
+ * tiling outside the allowed sets) is corrupt: it is reported on stderr,
+ * ignored and never rewritten, and the call goes on as without a file. */
+
+/* Tiling choice for a forward dataset: the one of this process's earlier
+ * choices or of the cache file under this dataset's key; otherwise times
+ * candidate tilings (workgroup size x events per tile x staged particles x
+ * pairs per round) on the caller's data -- the arguments are those of
+ * glv_event_reduce, outputs included, which end up holding a valid result --
+ * keeps the fastest under the key (and in the cache file).  The choice becomes
+ * this process's current one for (device, dtype, coords, mode) and is written
+ * to *best if not NULL.  Synchronises `stream`. */
 glv_status glv_autotune_event_reduce(glv_dtype dtype, glv_coords coords, glv_mode mode,
                                      int64_t n_events, const int64_t* offsets,
                                      const int64_t* pair_offsets, const void* const p[4],
                                      void* const total[4], void* event_m, void* pair_m,
                                      glv_tiling* best, void* stream);
 
-/* The tiling glv_event_reduce would use for these arguments (the autotuned
+/* The tiling glv_event_reduce would use for these arguments (the current
  * choice or the default), written to *out. */
 glv_status glv_current_tiling(glv_dtype dtype, glv_coords coords, glv_mode mode, glv_tiling* out);
 
-/* The same for glv_event_reduce_bwd: times its candidate tilings (64 to 512
- * threads, 16 to 256 events per tile, one staged particle per thread) on the
- * caller's data, with the arguments of glv_event_reduce_bwd (grad_p ends up
- * holding a valid result), keeps the fastest as this process's backward
- * choice for (current device, dtype, coords) and writes it to *best if not
- * NULL.  Synchronises `stream`. */
+/* The same for glv_event_reduce_bwd, with its arguments (grad_p ends up
+ * holding a valid result); the choice becomes the current backward one for
+ * (device, dtype, coords).  Synchronises `stream`. */
 glv_status glv_autotune_event_reduce_bwd(glv_dtype dtype, glv_coords coords, int64_t n_events,
                                          const int64_t* offsets, const int64_t* pair_offsets,
                                          const void* const p[4], const void* const grad_total[4],
                                          const void* grad_event_m, const void* grad_pair_m,
                                          void* const grad_p[4], glv_tiling* best, void* stream);
 
-/* The tiling glv_event_reduce_bwd would use (the autotuned backward choice or
+/* The tiling glv_event_reduce_bwd would use (the current backward choice or
  * the default), written to *out. */
 glv_status glv_current_tiling_bwd(glv_dtype dtype, glv_coords coords, glv_tiling* out);
+
+/* The cache key of a dataset (NUL-terminated, into buf of len bytes;
+ * GLV_EINVAL_SIZE if it does not fit).  backward = 0: the forward in `mode`;
+ * 1: the backward (mode ignored).  n_events = 0 needs no offsets and no GPU.
+ * Synchronises `stream` when it reads offsets. */
+glv_status glv_autotune_key(glv_dtype dtype, glv_coords coords, glv_mode mode, int32_t backward,
+                            int64_t n_events, const int64_t* offsets, char* buf, int64_t len,
+                            void* stream);
+
+/* Tiling choice without timing, for callers that must not time kernels
+ * (serving loops): looks the dataset's key up in this process's choices and
+ * in the cache file.  Found: *found = 1.  Not found -- no such entry, no
+ * GLV_AUTOTUNE_CACHE, a missing or a corrupt file -- *found = 0, the
+ * built-in default, a warning on stderr, and still GLV_OK.  Either way the
+ * result becomes the current choice (as glv_autotune_event_reduce /
+ * glv_autotune_event_reduce_bwd would make it) and is written to *out if not
+ * NULL.  Synchronises `stream` when it reads offsets (n_events > 0). */
+glv_status glv_autotune_lookup(glv_dtype dtype, glv_coords coords, glv_mode mode, int32_t backward,
+                               int64_t n_events, const int64_t* offsets, glv_tiling* out, int32_t* found,
+                               void* stream);
+
+/* Forgets this process's tuned choices (the cache file is left as it is):
+ * afterwards the calls above consult the cache file again and the current
+ * choices are the defaults. */
+void glv_autotune_forget(void);
 
 const char* glv_status_str(glv_status s);
 int glv_abi_version(void);

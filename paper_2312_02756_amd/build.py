@@ -20,7 +20,8 @@ REPO = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(REPO, "include")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["glv_abi.hip", "kernels_elementwise.hip", "kernels_jagged.hip", "kernels_analysis.hip"]
+SOURCES = ["glv_abi.hip", "glv_autotune.hip", "kernels_elementwise.hip", "kernels_jagged.hip",
+           "kernels_analysis.hip"]
 ARCH = "gfx950"
 
 

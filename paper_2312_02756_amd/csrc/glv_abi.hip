@@ -7,14 +7,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
 #include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
 #include "glv.h"
+#include "glv_autotune.h"
 #include "glv_launch.h"
 
 namespace {
@@ -160,6 +166,16 @@ constexpr size_t kMaxLds = 64 * 1024;
 
 bool block_ok(int b) { return (b == 64 || b == 128 || b == 256 || b == 512) && b <= glv::kMaxBlock; }
 
+// Every field inside its allowed set and the workgroup's LDS within kMaxLds.
+bool tiling_valid(glv_dtype dt, glv_mode mode, bool bwd, const glv::Tiling& t) {
+  if (!block_ok(t.block)) return false;
+  if (t.events_per_tile < 1 || t.events_per_tile > 64) return false;
+  if (t.lds_particles < 64 || t.lds_particles > 4096) return false;
+  if (t.pairs_per_round < 64 || t.pairs_per_round > 4096 || t.pairs_per_round % 64 != 0) return false;
+  const size_t lds = bwd ? glv::event_reduce_bwd_lds_bytes(dt, t) : glv::event_reduce_lds_bytes(dt, mode, t);
+  return lds <= kMaxLds;
+}
+
 // Resolve a user tiling (fields 0 = current choice) and validate it.
 glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,
                           glv::Tiling* out) {
@@ -177,13 +193,7 @@ glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_
     if (user->lds_particles) base.lds_particles = user->lds_particles;
     if (user->pairs_per_round) base.pairs_per_round = user->pairs_per_round;
   }
-  if (!block_ok(base.block)) return GLV_EINVAL_TILING;
-  if (base.events_per_tile < 1 || base.events_per_tile > 64) return GLV_EINVAL_TILING;
-  if (base.lds_particles < 64 || base.lds_particles > 4096) return GLV_EINVAL_TILING;
-  if (base.pairs_per_round < 64 || base.pairs_per_round > 4096 || base.pairs_per_round % 64 != 0)
-    return GLV_EINVAL_TILING;
-  size_t lds = bwd ? glv::event_reduce_bwd_lds_bytes(dt, base) : glv::event_reduce_lds_bytes(dt, mode, base);
-  if (lds > kMaxLds) return GLV_EINVAL_TILING;
+  if (!tiling_valid(dt, mode, bwd, base)) return GLV_EINVAL_TILING;
   *out = base;
   return GLV_OK;
 }
@@ -290,6 +300,110 @@ glv_status transform_bwd_args(glv_dtype dt, int64_t n, const void* const x[4], c
   if (gm)
     for (int k = 0; k < NN; ++k) outs.push_back(rng(gm[k], n, es));
   if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  return GLV_OK;
+}
+
+}  // namespace
+
+
+namespace {
+
+// ------------------------------------------------------------- autotuning
+
+// The persistent cache: the file named by GLV_AUTOTUNE_CACHE, if set.
+const char* cache_path() {
+  const char* p = getenv("GLV_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+enum class CacheFile { kUsable, kMissing, kCorrupt };
+
+// Reads the cache file; a corrupt file (or one holding a tiling that is not
+// valid here) is reported on stderr once per call and then ignored, and
+// never rewritten.
+CacheFile read_cache(const char* path, glv_dtype dt, glv_mode mode, bool bwd, glv::tune::Entries* entries) {
+  std::string why;
+  const glv::tune::FileState fs = glv::tune::load(path, entries, &why);
+  if (fs == glv::tune::FileState::kMissing) return CacheFile::kMissing;
+  if (fs == glv::tune::FileState::kCorrupt) {
+    fprintf(stderr, "glv: autotune cache %s is corrupt (%s); ignoring it\n", path, why.c_str());
+    entries->clear();
+    return CacheFile::kCorrupt;
+  }
+  (void)dt;
+  (void)mode;
+  (void)bwd;
+  for (const auto& e : *entries) {
+    // the key names dtype and direction; check the tiling against them
+    const bool e_bwd = e.first.find("|bwd|") != std::string::npos;
+    const glv_dtype e_dt = e.first.find("|f64|") != std::string::npos ? GLV_F64 : GLV_F32;
+    const glv_mode e_mode = e.first.find("|fwd-compensated|") != std::string::npos ? GLV_COMPENSATED : GLV_PLAIN;
+    if (!tiling_valid(e_dt, e_mode, e_bwd, e.second)) {
+      fprintf(stderr, "glv: autotune cache %s is corrupt (invalid tiling for %s); ignoring it\n", path,
+              e.first.c_str());
+      entries->clear();
+      return CacheFile::kCorrupt;
+    }
+  }
+  return CacheFile::kUsable;
+}
+
+// Cache key of a dataset for this device, dtype, coordinate system and
+// direction (the forward's mode included).
+glv_status dataset_key(glv_dtype dt, glv_coords co, glv_mode mode, bool bwd, int64_t ne, const int64_t* off,
+                       hipStream_t s, std::string* key) {
+  std::string sig;
+  if (ne > 0) {
+    const hipError_t e = glv::tune::signature(ne, off, s, &sig);
+    if (e != hipSuccess) return hip_status(e);
+  } else {
+    sig = glv::tune::signature_of_sizes(0, nullptr, 0);
+  }
+  const char* what = bwd ? "bwd" : (mode == GLV_COMPENSATED ? "fwd-compensated" : "fwd-plain");
+  *key = glv::tune::make_key(dt, co, what, sig);
+  return GLV_OK;
+}
+
+// The autotuners' common part: the dataset's key; its tiling from this
+// process's earlier choices or the cache file, else the fastest candidate
+// (timed on the caller's data, `launch` enqueueing one launch; the outputs
+// end up holding that tiling's result), added to the cache file.
+template <typename Launch>
+glv_status autotune_common(glv_dtype dt, glv_coords co, glv_mode mode, bool bwd, int64_t ne, const int64_t* off,
+                           const std::vector<glv::Tiling>& cands, const glv::Tiling& dflt, bool work, Launch launch,
+                           glv_tiling* best, hipStream_t s) {
+  std::string key;
+  glv_status st = dataset_key(dt, co, mode, bwd, ne, off, s, &key);
+  if (st != GLV_OK) return st;
+  glv::Tiling chosen = dflt;
+  bool hit = glv::tune::lookup_process(key, &chosen);
+  const char* path = cache_path();
+  glv::tune::Entries entries;
+  CacheFile cf = CacheFile::kMissing;
+  if (!hit && path) {
+    cf = read_cache(path, dt, mode, bwd, &entries);
+    for (const auto& e : entries) {
+      if (e.first == key) {
+        chosen = e.second;
+        hit = true;
+      }
+    }
+  }
+  if (work) {
+    hipError_t err = hipSuccess;
+    if (!hit) err = pick_fastest(cands, s, launch, &chosen);
+    if (err == hipSuccess) err = launch(chosen);  // the outputs hold the chosen tiling's result
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return hip_status(err);
+  }
+  if (!hit && work && path && cf != CacheFile::kCorrupt) {
+    entries.push_back({key, chosen});
+    if (!glv::tune::save(path, entries))
+      fprintf(stderr, "glv: could not write the autotune cache %s\n", path);
+  }
+  if (hit || work) glv::tune::remember_process(key, chosen);
+  remember_tiling(dt, co, bwd ? kBwdKey : (int)mode, chosen);
+  if (best) write_tiling(chosen, best);
   return GLV_OK;
 }
 
@@ -634,7 +748,7 @@ glv_status glv_autotune_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode,
   glv_status st = validate_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm);
   if (st != GLV_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  // candidates: workgroup size x events per tile x LDS capacity
+  // candidates: workgroup size x events per tile x staged particles x pairs per round
   std::vector<glv::Tiling> cands;
   const int blocks[] = {64, 256};
   const int epbs[] = {16, 32, 64};
@@ -645,23 +759,13 @@ glv_status glv_autotune_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode,
       for (int c : caps)
         for (int q : qcaps) {
           glv::Tiling t{b, e, c, q};
-          if (glv::event_reduce_lds_bytes(dt, mode, t) > kMaxLds) continue;
-          cands.push_back(t);
+          if (tiling_valid(dt, mode, false, t)) cands.push_back(t);
         }
-  glv::Tiling chosen = default_tiling(dt, mode);
-  if (ne > 0 && (total || em || pm)) {
-    auto launch = [&](const glv::Tiling& t) {
-      return glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
-    };
-    hipError_t err = pick_fastest(cands, s, launch, &chosen);
-    // leave the outputs holding the chosen tiling's result
-    if (err == hipSuccess) err = launch(chosen);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
-    if (err != hipSuccess) return hip_status(err);
-  }
-  remember_tiling(dt, co, (int)mode, chosen);
-  if (best) write_tiling(chosen, best);
-  return GLV_OK;
+  auto launch = [&](const glv::Tiling& t) {
+    return glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, nullptr, t, s);
+  };
+  const bool work = ne > 0 && (total || em || pm);
+  return autotune_common(dt, co, mode, false, ne, off, cands, default_tiling(dt, mode), work, launch, best, s);
 }
 
 glv_status glv_autotune_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,
@@ -682,22 +786,76 @@ glv_status glv_autotune_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne
       for (int c : caps)
         for (int q : qcaps) {
           glv::Tiling t{b, e, c, q};
-          if (glv::event_reduce_bwd_lds_bytes(dt, t) > kMaxLds) continue;
-          cands.push_back(t);
+          if (tiling_valid(dt, GLV_PLAIN, true, t)) cands.push_back(t);
         }
-  glv::Tiling chosen = default_tiling_bwd(dt);
-  if (ne > 0) {
-    auto launch = [&](const glv::Tiling& t) {
-      return glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t, s);
-    };
-    hipError_t err = pick_fastest(cands, s, launch, &chosen);
-    if (err == hipSuccess) err = launch(chosen);  // gp holds the chosen tiling's result
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
-    if (err != hipSuccess) return hip_status(err);
-  }
-  remember_tiling(dt, co, kBwdKey, chosen);
-  if (best) write_tiling(chosen, best);
+  auto launch = [&](const glv::Tiling& t) {
+    return glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t, s);
+  };
+  return autotune_common(dt, co, GLV_PLAIN, true, ne, off, cands, default_tiling_bwd(dt), ne > 0, launch, best, s);
+}
+
+glv_status glv_autotune_key(glv_dtype dt, glv_coords co, glv_mode mode, int32_t backward, int64_t ne,
+                            const int64_t* off, char* buf, int64_t len, void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  glv_status ms = mode_ok(backward ? GLV_PLAIN : mode, co);
+  if (ms != GLV_OK) return ms;
+  if (ne < 0 || len < 1) return GLV_EINVAL_SIZE;
+  if (!buf || (ne > 0 && !off)) return GLV_EINVAL_NULL;
+  std::string key;
+  const glv_status st = dataset_key(dt, co, mode, backward != 0, ne, off, (hipStream_t)stream, &key);
+  if (st != GLV_OK) return st;
+  if ((int64_t)key.size() + 1 > len) return GLV_EINVAL_SIZE;
+  memcpy(buf, key.c_str(), key.size() + 1);
   return GLV_OK;
+}
+
+glv_status glv_autotune_lookup(glv_dtype dt, glv_coords co, glv_mode mode, int32_t backward, int64_t ne,
+                               const int64_t* off, glv_tiling* out, int32_t* found, void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  const bool bwd = backward != 0;
+  if (bwd) mode = GLV_PLAIN;
+  glv_status ms = mode_ok(mode, co);
+  if (ms != GLV_OK) return ms;
+  if (ne < 0) return GLV_EINVAL_SIZE;
+  if (ne > 0 && !off) return GLV_EINVAL_NULL;
+  std::string key;
+  glv_status st = dataset_key(dt, co, mode, bwd, ne, off, (hipStream_t)stream, &key);
+  if (st != GLV_OK) return st;
+  glv::Tiling t = bwd ? default_tiling_bwd(dt) : default_tiling(dt, mode);
+  bool hit = glv::tune::lookup_process(key, &t);
+  if (!hit) {
+    const char* path = cache_path();
+    if (!path) {
+      fprintf(stderr, "glv: no autotuned tiling for %s (GLV_AUTOTUNE_CACHE not set); using the default\n",
+              key.c_str());
+    } else {
+      glv::tune::Entries entries;
+      const CacheFile cf = read_cache(path, dt, mode, bwd, &entries);
+      for (const auto& e : entries) {
+        if (e.first == key) {
+          t = e.second;
+          hit = true;
+        }
+      }
+      if (!hit && cf == CacheFile::kUsable)
+        fprintf(stderr, "glv: %s has no tiling for %s; using the default\n", path, key.c_str());
+      if (!hit && cf == CacheFile::kMissing)
+        fprintf(stderr, "glv: autotune cache %s does not exist; using the default tiling\n", path);
+    }
+    if (hit) glv::tune::remember_process(key, t);
+  }
+  remember_tiling(dt, co, bwd ? kBwdKey : (int)mode, t);
+  if (out) write_tiling(t, out);
+  if (found) *found = hit ? 1 : 0;
+  return GLV_OK;
+}
+
+void glv_autotune_forget(void) {
+  glv::tune::forget_process();
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tiles.clear();
 }
 
 }  // extern "C"

@@ -466,5 +466,40 @@ def glv_current_tiling_bwd(dtype=torch.float64, coords="PtEtaPhiM"):
     return _as_tuple(t)
 
 
+def _key_args(dtype, coords, mode, backward, offsets):
+    if offsets is None:
+        return _dtype_code(dtype), _coords_code(coords), _mode_code(mode), int(bool(backward)), 0, None, None
+    offsets = _offsets(offsets, offsets.device)
+    return (_dtype_code(dtype), _coords_code(coords), _mode_code(mode), int(bool(backward)), offsets.numel() - 1,
+            _ptr(offsets), _stream(offsets.device))
+
+
+def glv_autotune_key(offsets, dtype=torch.float64, coords="PtEtaPhiM", mode="plain", backward=False):
+    """The autotuning cache key of a CSR dataset (``offsets`` on the GPU, or
+    None for an empty dataset)."""
+    buf = ctypes.create_string_buffer(512)
+    dt, co, mo, bw, ne, po, st = _key_args(dtype, coords, mode, backward, offsets)
+    check("glv_autotune_key", _lib.load().glv_autotune_key(dt, co, mo, bw, ne, po, buf, len(buf), st))
+    return buf.value.decode()
+
+
+def glv_autotune_lookup(offsets, dtype=torch.float64, coords="PtEtaPhiM", mode="plain", backward=False):
+    """The tuned tiling of this dataset from this process's choices or the
+    GLV_AUTOTUNE_CACHE file, without timing: (tiling, found); not found gives
+    the default tiling (and a warning on stderr).  Either becomes the current
+    choice."""
+    t = glv_tiling()
+    found = ctypes.c_int32(0)
+    dt, co, mo, bw, ne, po, st = _key_args(dtype, coords, mode, backward, offsets)
+    check("glv_autotune_lookup", _lib.load().glv_autotune_lookup(dt, co, mo, bw, ne, po, ctypes.byref(t),
+                                                                 ctypes.byref(found), st))
+    return _as_tuple(t), bool(found.value)
+
+
+def glv_autotune_forget():
+    """Forget this process's tuned choices (the cache file stays)."""
+    _lib.load().glv_autotune_forget()
+
+
 def glv_abi_version():
     return _lib.load().glv_abi_version()

@@ -475,3 +475,58 @@ def test_random_layouts_and_tilings(seed):
                                        grad_event_m=gpu([gem], torch.float64)[0],
                                        grad_pair_m=gpu([gpr], torch.float64)[0], tiling=bt)
     _check_bwd(off, p, torch.float64, "PtEtaPhiM", [host(c) for c in got], want, f"seed {seed} bwd {bt}")
+
+
+def _signature(off):
+    """The documented dataset signature, recomputed from the offsets: order of
+    magnitude of the event count; share of sampled events per size class in
+    5 % steps (all events up to 65,536, else 32 evenly spread runs of 2,048)."""
+    ne = off.size - 1
+    sizes = np.diff(off)
+    if ne > 65536:
+        ln = 2048
+        sizes = np.concatenate([sizes[r * (ne - ln) // 31: r * (ne - ln) // 31 + ln] for r in range(32)])
+    cls = np.array([int(n).bit_length() for n in sizes])
+    parts = []
+    for b in range(41):
+        steps = (int(np.sum(cls == b)) * 20 + sizes.size // 2) // sizes.size
+        if steps:
+            parts.append(f"{b}:{steps * 5}")
+    return f"e{int(ne).bit_length() - 1};" + ",".join(parts)
+
+
+def test_autotune_cache_retunes_per_dataset_signature(tmp_path, monkeypatch):
+    """Two datasets with different multiplicity distributions get their own
+    entries in the GLV_AUTOTUNE_CACHE file; after forgetting, the lookup finds
+    each one's choice without timing; tuning a dataset again adds nothing."""
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("GLV_AUTOTUNE_CACHE", str(path))
+    glv.glv_autotune_forget()
+    try:
+        off_a, p_a = _events(1 << 14, 740)
+        off_b, p_b = _events(1 << 17, 741, mean=3.0)
+        ka, kb = glv.glv_autotune_key(_off(off_a)), glv.glv_autotune_key(_off(off_b))
+        assert ka.split("|")[4] == _signature(off_a) and kb.split("|")[4] == _signature(off_b)
+        assert ka != kb
+        ta = glv.glv_autotune_event_reduce(gpu(p_a, torch.float64), _off(off_a))
+        assert [e["key"] for e in json.loads(path.read_text())["entries"]] == [ka]
+        tb = glv.glv_autotune_event_reduce(gpu(p_b, torch.float64), _off(off_b))
+        entries = json.loads(path.read_text())["entries"]
+        assert [e["key"] for e in entries] == [ka, kb]
+        assert [tuple(e["tiling"]) for e in entries] == [ta, tb]
+        glv.glv_autotune_forget()
+        assert glv.glv_autotune_lookup(_off(off_a)) == (ta, True)
+        assert glv.glv_current_tiling(torch.float64, "PtEtaPhiM", "plain") == ta
+        assert glv.glv_autotune_lookup(_off(off_b)) == (tb, True)
+        assert glv.glv_autotune_event_reduce(gpu(p_a, torch.float64), _off(off_a)) == ta
+        assert len(json.loads(path.read_text())["entries"]) == 2
+        # the backward has keys of its own
+        kbw = glv.glv_autotune_key(_off(off_a), backward=True)
+        assert kbw.split("|")[3] == "bwd"
+        glv.glv_autotune_event_reduce_bwd(gpu(p_a, torch.float64), _off(off_a),
+                                          grad_pair_m=torch.ones(int(oracle.pair_offsets(off_a)[-1]),
+                                                                 dtype=torch.float64, device=DEV))
+        assert [e["key"] for e in json.loads(path.read_text())["entries"]] == [ka, kb, kbw]
+    finally:
+        glv.glv_autotune_forget()
