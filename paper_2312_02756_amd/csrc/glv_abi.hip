@@ -136,14 +136,13 @@ hipError_t pick_fastest(const std::vector<glv::Tiling>& cands, hipStream_t s, La
   return err;
 }
 
-// Forward: four independent wavefronts per workgroup, each taking tiles of 32
-// events, staging up to 128 particles and evaluating 512 pairs (8 per lane)
-// per round.
+// Forward: independent wavefronts, each taking tiles of 32 events, staging up
+// to 128 particles and evaluating 512 pairs (8 per lane) per round; four per
+// workgroup, or two for the FP64 compensated mode, whose wavefront stages
+// 18.8 KB (four would pass the 64 KiB workgroup limit).
 glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
-  (void)dt;
-  (void)mode;
   glv::Tiling t;
-  t.block = 256;
+  t.block = (dt == GLV_F64 && mode == GLV_COMPENSATED) ? 128 : 256;
   t.events_per_tile = 32;
   t.lds_particles = 128;
   t.pairs_per_round = 512;

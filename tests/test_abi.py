@@ -226,6 +226,18 @@ def test_current_tiling_default(lib):
     assert lib.glv_current_tiling(2, 0, 1, ctypes.byref(t)) == MODE
 
 
+def test_default_tilings_valid_for_every_combination(lib):
+    """The default tiling of every dtype, coordinate system and mode passes
+    the library's own validation (the FP64 compensated wavefront stages the
+    most LDS)."""
+    t = _lib.glv_tiling()
+    for dt in (1, 2):
+        for co in (0, 1, 2, 3):
+            assert lib.glv_current_tiling(dt, co, 0, ctypes.byref(t)) == OK, (dt, co)
+            assert lib.glv_current_tiling_bwd(dt, co, ctypes.byref(t)) == OK, (dt, co)
+        assert lib.glv_current_tiling(dt, 1, 1, ctypes.byref(t)) == OK, (dt, "compensated")
+
+
 def test_current_tiling_bwd_default_and_autotune_validation(lib):
     t = _lib.glv_tiling()
     assert lib.glv_current_tiling_bwd(2, 1, ctypes.byref(t)) == OK

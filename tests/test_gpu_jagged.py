@@ -396,7 +396,7 @@ def test_large_event_pair_masses_match_across_paths():
     go = _off(off)
     for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
         gp = gpu(p, dtype)
-        runs = [glv.glv_event_reduce(gp, go, mode=mode, tiling=t) for t in ((256, 64, 256, 512), (64, 64, 1024, 512))]
+        runs = [glv.glv_event_reduce(gp, go, mode=mode, tiling=t) for t in ((128, 64, 256, 512), (64, 64, 1024, 512))]
         a, b = host(runs[0][2]).astype(np.float64), host(runs[1][2]).astype(np.float64)
         if mode == "plain":
             assert np.array_equal(a, b)
