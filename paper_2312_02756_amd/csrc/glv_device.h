@@ -444,29 +444,33 @@ __device__ __forceinline__ T div_budgeted(T a, T b) {
 // multiplicative factors of the pair terms, and (times |delta|) to each
 // leg's rapidity shift delta: 16 each for products and quotients of
 // accurately computed factors, plus 4 for the FP32 hardware square roots
-// (mT, E) and reciprocals (t3, e^-x in sinh and cosh) and the unreduced
-// sine of the half azimuth difference (1.7 ulp) that replace correctly
-// rounded ones.
+// (mT, E) and reciprocals (the quotients of delta and of mT - pt, e^-x in
+// sinh and cosh) and the unreduced sine of the half azimuth difference
+// (1.7 ulp) that replace correctly rounded ones.
 constexpr float kFactorUnits = 20.0f;
 constexpr float kDeltaUnits = 20.0f;
 
-// Per-leg terms: pt, eta, phi, M^2, mT = sqrt(pt^2 + M^2) and
-// delta = y - eta = -asinh(M^2 sinh(eta) / (mT (pt cosh(eta) + E))).
+// Per-leg terms: pt, eta, phi, M^2, mT = sqrt(pt^2 + M^2),
+// delta = y - eta = -asinh(M^2 sinh(eta) / (mT (pt cosh(eta) + E))) and
+// dmt = mT - pt = M^2 / (mT + pt) (formed without the cancellation).
 template <typename T>
 struct LegC {
-  T pt, eta, phi, m2, mt, delta;
+  T pt, eta, phi, m2, mt, delta, dmt;
 };
 
-// mT and delta of a leg from pt, M^2, sinh(eta), pt cosh(eta) and E (pt^2 + M^2
-// with one explicit fused multiply-add, so that every kernel forms mT alike).
+// mT, delta and mT - pt of a leg from pt, M^2, sinh(eta), pt cosh(eta) and E
+// (pt^2 + M^2 with one explicit fused multiply-add, so that every kernel forms
+// mT alike).  The two quotients are budgeted ones (a times the hardware
+// reciprocal in FP32).
 template <typename T, bool kCold = false>
-__device__ __forceinline__ void leg_shift(T pt, T mm, T sh, T pc, T e, T* mt, T* delta) {
+__device__ __forceinline__ void leg_shift(T pt, T mm, T sh, T pc, T e, T* mt, T* delta, T* dmt) {
   if constexpr (sizeof(T) == 8)
     *mt = sqrt_budgeted(fma(pt, pt, mm));
   else
     *mt = sqrt_budgeted(fmaf(pt, pt, mm));
   const T den = *mt * (pc + e);
-  *delta = (den > T(0)) ? -small_asinh<kCold>(mm * sh / den) : T(0);
+  *delta = (den > T(0)) ? -small_asinh<kCold>(div_budgeted(mm * sh, den)) : T(0);
+  *dmt = (mm > T(0)) ? div_budgeted(mm, *mt + pt) : T(0);
 }
 
 // Compensated leg terms together with the Cartesian vector of a
@@ -475,8 +479,8 @@ __device__ __forceinline__ void leg_shift(T pt, T mm, T sh, T pc, T e, T* mt, T*
 template <typename T>
 __device__ __forceinline__ LegC<T> comp_leg_cart(T pt, T eta, T phi, T mass, T v[4]) {
   T sn, cs, sh, ch;
-  sincos_t<false>(phi, &sn, &cs);
-  sinhcosh_t<false>(eta, &sh, &ch);
+  sincos_t<true>(phi, &sn, &cs);
+  sinhcosh_t<true>(eta, &sh, &ch);
   const T pc = pt * ch;
   v[0] = pt * cs;
   v[1] = pt * sn;
@@ -487,7 +491,7 @@ __device__ __forceinline__ LegC<T> comp_leg_cart(T pt, T eta, T phi, T mass, T v
   L.eta = eta;
   L.phi = phi;
   L.m2 = mass * mass;
-  leg_shift<T>(pt, L.m2, sh, pc, v[3], &L.mt, &L.delta);
+  leg_shift<T>(pt, L.m2, sh, pc, v[3], &L.mt, &L.delta, &L.dmt);
   return L;
 }
 
@@ -507,7 +511,7 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
     fast_sinhcosh_rcp(eta, &sh, &ch);
   T pc = pt * ch;
   T e = sqrt_budgeted(pc * pc + mm);
-  leg_shift<T, kCold>(pt, mm, sh, pc, e, &L.mt, &L.delta);
+  leg_shift<T, kCold>(pt, mm, sh, pc, e, &L.mt, &L.delta, &L.dmt);
   return L;
 }
 
@@ -554,9 +558,8 @@ __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T*
     s1 = fast_sinh(T(0.5) * dy);
   T t1 = T(2) * a.mt * b.mt * (s1 * s1);
   T t2 = T(2) * a.pt * b.pt * sin2_half<T, kCold>(dphi_reduced(a.phi, b.phi));
-  T num = a.pt * a.pt * b.m2 + b.pt * b.pt * a.m2 + a.m2 * b.m2;
-  T den = a.mt * b.mt + a.pt * b.pt;
-  T t3 = (num == T(0)) ? T(0) : div_budgeted(num, den);
+  // mTa mTb - pta ptb = (mTa - pta) mTb + pta (mTb - ptb): two terms >= 0
+  T t3 = a.dmt * b.mt + a.pt * b.dmt;
   T kk = t1 + t2 + t3;
   T m2 = a.m2 + b.m2 + T(2) * kk;
   *k = kk;
@@ -594,7 +597,7 @@ __device__ __forceinline__ LegCJ<T> comp_leg_j(T pt, T eta, T phi, T mass) {
     fast_sinhcosh_rcp(eta, &L.sh, &L.ch);
   const T pc = pt * L.ch;
   L.e = sqrt_budgeted(pc * pc + mm);
-  leg_shift<T, false>(pt, mm, L.sh, pc, L.e, &L.c.mt, &L.c.delta);
+  leg_shift<T, false>(pt, mm, L.sh, pc, L.e, &L.c.mt, &L.c.delta, &L.c.dmt);
   return L;
 }
 

@@ -259,30 +259,6 @@ struct V2 {
   typedef T type __attribute__((ext_vector_type(2)));
 };
 
-template <typename T, int MODE>
-struct Stage {
-  typename V4<T>::type* cart;
-  typename V4<T>::type* legA;
-  typename V2<T>::type* legB;
-};
-
-template <typename T, int COORDS, int MODE>
-__device__ __forceinline__ void stage_particle(const Cols4<T>& p, int64_t gi, const Stage<T, MODE>& s,
-                                               int slot) {
-  T c0 = p.c[0][gi], c1 = p.c[1][gi], c2 = p.c[2][gi], c3 = p.c[3][gi];
-  if constexpr (MODE == GLV_COMPENSATED) {  // (pt, eta, phi, M)
-    T v[4];
-    const LegC<T> L = comp_leg_cart<T>(c0, c1, c2, c3, v);
-    s.cart[slot] = typename V4<T>::type{v[0], v[1], v[2], v[3]};
-    s.legA[slot] = typename V4<T>::type{c0, c1, c2, c3};
-    s.legB[slot] = typename V2<T>::type{L.mt, L.delta};
-  } else {
-    T v[4];
-    to_cart<COORDS>(c0, c1, c2, c3, v);
-    s.cart[slot] = typename V4<T>::type{v[0], v[1], v[2], v[3]};
-  }
-}
-
 // acc += rec[lo] + rec[lo+1] + ... + rec[hi-1], component-wise and in index
 // order (each component's additions stay sequential), two records read per
 // LDS wait (four would cost the kernel its sixth wavefront per SIMD).
@@ -301,22 +277,6 @@ __device__ __forceinline__ void sum_records(const V* rec, int lo, int hi, A acc[
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] += (A)r[k];
   }
-}
-
-// Compensated leg terms of a staged particle; *mass receives M.
-template <typename T, int MODE>
-__device__ __forceinline__ LegC<T> staged_leg(const Stage<T, MODE>& s, int slot, T* mass) {
-  const typename V4<T>::type a = s.legA[slot];
-  const typename V2<T>::type b = s.legB[slot];
-  LegC<T> L;
-  L.pt = a[0];
-  L.eta = a[1];
-  L.phi = a[2];
-  *mass = a[3];
-  L.m2 = a[3] * a[3];
-  L.mt = b[0];
-  L.delta = b[1];
-  return L;
 }
 
 // Compensated pair mass and K = E_i E_j - p_i.p_j (as double) from two legs,
@@ -553,8 +513,8 @@ __device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key
 // LDS of one wavefront of the forward reduction (cap particles, qcap pairs):
 //   cart[cap]  (px, py, pz, E)             staged Cartesian records
 //   legA[cap]  (pt, eta, phi, M)           compensated mode
-//   legB[cap]  (mT, delta)                 compensated mode
-//   pm[qcap]   pair masses of a round      (stored from here, coalesced)
+//   legB[cap]  (mT, delta, mT - pt, M^2)   compensated mode
+//   pm[qcap]   FP64: pair masses of a round (stored from here, coalesced)
 //   kp[qcap]   partial sums of K per lane  (compensated event mass)
 //   eo, en, ep [epb + 1] int               the chunk's events with pairs:
 //              first particle, size, first pair (chunk-relative), then a
@@ -563,7 +523,7 @@ template <typename T, int MODE>
 struct WaveLds {
   typename V4<T>::type* cart;
   typename V4<T>::type* legA;
-  typename V2<T>::type* legB;
+  typename V4<T>::type* legB;
   T* pm;
   double* kp;
   int* eo;
@@ -574,8 +534,9 @@ struct WaveLds {
 template <typename T, int MODE>
 __host__ __device__ __forceinline__ size_t wave_lds_bytes(int cap, int qcap, int epb) {
   size_t b = (size_t)cap * 4 * sizeof(T);
-  if (MODE == GLV_COMPENSATED) b += (size_t)cap * 6 * sizeof(T) + (size_t)qcap * sizeof(double);
-  b += (size_t)qcap * sizeof(T) + 3 * (size_t)(epb + 1) * sizeof(int);
+  if (MODE == GLV_COMPENSATED) b += (size_t)cap * 8 * sizeof(T) + (size_t)qcap * sizeof(double);
+  if (sizeof(T) == 8) b += (size_t)qcap * sizeof(T);  // staged pair masses
+  b += 3 * (size_t)(epb + 1) * sizeof(int);
   return (b + 31) & ~(size_t)31;
 }
 
@@ -587,8 +548,8 @@ __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int
   if constexpr (MODE == GLV_COMPENSATED) {
     w.legA = reinterpret_cast<typename V4<T>::type*>(p);
     p += (size_t)cap * 4 * sizeof(T);
-    w.legB = reinterpret_cast<typename V2<T>::type*>(p);
-    p += (size_t)cap * 2 * sizeof(T);
+    w.legB = reinterpret_cast<typename V4<T>::type*>(p);
+    p += (size_t)cap * 4 * sizeof(T);
     w.kp = reinterpret_cast<double*>(p);
     p += (size_t)qcap * sizeof(double);
   } else {
@@ -597,52 +558,135 @@ __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int
     w.kp = nullptr;
   }
   w.pm = reinterpret_cast<T*>(p);
-  p += (size_t)qcap * sizeof(T);
+  if (sizeof(T) == 8) p += (size_t)qcap * sizeof(T);
   w.eo = reinterpret_cast<int*>(p);
   w.en = w.eo + (epb + 1);
   w.ep = w.en + (epb + 1);
   return w;
 }
 
+// Particles of a chunk held in registers between their load and their
+// staging: lane t of the wavefront keeps particles t, t + 64, ...; FP64 keeps
+// one per lane (64 particles), FP32 two (128).  Particles of larger chunks
+// past these are loaded when staged.
+template <typename T>
+struct Prefetch {
+  static constexpr int kSlots = sizeof(T) == 8 ? 1 : 2;
+  T v[kSlots][4];
+};
+
+template <typename T>
+__device__ __forceinline__ void prefetch_chunk(const Cols4<T>& p, int64_t base, int np, int lane, Prefetch<T>* r) {
+#pragma unroll
+  for (int s = 0; s < Prefetch<T>::kSlots; ++s) {
+    const int t = lane + 64 * s;
+    if (t < np) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r->v[s][k] = __builtin_nontemporal_load(p.c[k] + base + t);
+    }
+  }
+}
+
+// Converts one particle and writes its staged records (slot t).
+template <typename T, int COORDS, int MODE>
+__device__ __forceinline__ void stage_one(const WaveLds<T, MODE>& W, int t, T c0, T c1, T c2, T c3) {
+  using R4 = typename V4<T>::type;
+  T v[4];
+  if constexpr (MODE == GLV_COMPENSATED) {  // (pt, eta, phi, M)
+    const LegC<T> L = comp_leg_cart<T>(c0, c1, c2, c3, v);
+    W.legA[t] = R4{c0, c1, c2, c3};
+    W.legB[t] = R4{L.mt, L.delta, L.dmt, L.m2};
+  } else {
+    to_cart<COORDS, T, true>(c0, c1, c2, c3, v);
+  }
+  W.cart[t] = R4{v[0], v[1], v[2], v[3]};
+}
+
+// Compensated leg terms of a staged particle; *mass receives M.
+template <typename T, int MODE>
+__device__ __forceinline__ LegC<T> staged_leg(const WaveLds<T, MODE>& W, int t, T* mass) {
+  const typename V4<T>::type a = W.legA[t];
+  const typename V4<T>::type b = W.legB[t];
+  LegC<T> L;
+  L.pt = a[0];
+  L.eta = a[1];
+  L.phi = a[2];
+  *mass = a[3];
+  L.mt = b[0];
+  L.delta = b[1];
+  L.dmt = b[2];
+  L.m2 = b[3];
+  return L;
+}
+
+// The chunk of a wavefront's tile that starts at the first event at or after
+// `from` small enough to stage (n <= cap): [*ca, *cb), the longest run of
+// consecutive events whose particles fit in cap slots.  *ca = nev: none left.
+__device__ __forceinline__ void next_chunk(int from, int nev, uint64_t valid, bool mine, int64_t olo, int64_t ohi,
+                                           int cap, int* ca, int* cb) {
+  const uint64_t after = from >= 64 ? 0ull : (valid & (~0ull << from));
+  const uint64_t small = __ballot(mine && (ohi - olo) <= (int64_t)cap) & after;
+  const int a = small ? (int)__builtin_ctzll(small) : nev;
+  int b = a;
+  if (a < nev) {
+    const int64_t base = readlane64(olo, a);
+    const uint64_t ge = valid & (~0ull << a);
+    const uint64_t fits = __ballot(mine && (ohi - base <= (int64_t)cap)) & ge;
+    const uint64_t stop = ge & ~fits;
+    b = stop ? (int)__builtin_ctzll(stop) : nev;
+  }
+  *ca = a;
+  *cb = b;
+}
+
+#ifndef GLV_FWD_WAVES
+#define GLV_FWD_WAVES 1
+#endif
+
 // The forward reduction.  Each wavefront of a workgroup independently takes a
 // tile of epb consecutive events (one per lane for their offsets) and walks it
-// in chunks of consecutive events holding at most cap particles:
-//   1. stage: the chunk's particles (contiguous in the columns) are loaded
-//      coalesced, converted once and written to the wave's LDS;
+// in chunks of consecutive events holding at most cap particles; the next
+// chunk's particles are loaded into registers while the current one is
+// reduced, so that their latency hides behind its arithmetic:
+//   1. stage: the chunk's particles are converted once and written to the
+//      wave's LDS;
 //   2. totals: the lane of each event sums its particles in CSR order (the
 //      plain event mass from that total; in the compensated mode also the
 //      sum of M^2);
-//   3. pairs, in rounds of qcap pairs: lane L takes the contiguous pairs
-//      [L m, (L + 1) m) of the round (m = qcap / 64, made odd), locates the
-//      first by a binary search over the chunk's events with pairs and the
-//      square-root decode of its rank, then steps to the lexicographic
-//      successor -- every lane the same number of pairs whatever the event
-//      sizes, and a handful of integer operations per step.  Masses go to the
-//      wave's LDS and from there to pair_m with coalesced stores; in the
-//      compensated mode each lane also sums K = E_i E_j - p_i.p_j of its pairs
-//      per event and leaves the partial sum at the slot of its last pair in
-//      that event, and the event's lane adds those partials (the lanes in
-//      order, then the rounds in order): deterministic for a tiling.
+//   3. pairs, in rounds: lane L takes the contiguous pairs [L m, (L + 1) m)
+//      of the round, locates the first by a binary search over the chunk's
+//      events with pairs and the square-root decode of its rank, then steps
+//      to the lexicographic successor -- every lane the same number of pairs
+//      whatever the event sizes, and a handful of integer operations per
+//      step.  FP64 masses go to the wave's LDS, in rounds of 64 m pairs with m
+//      odd (which spreads one LDS store instruction's lanes over distinct
+//      banks), and from there to pair_m with coalesced stores; FP32 masses
+//      (two lanes of a store instruction per 64-byte segment at m = 8) are
+//      stored by their lane, in one round (plain mode) or rounds of qcap
+//      (compensated mode, for the partial sums below).  In the compensated
+//      mode each
+//      lane also sums K = E_i E_j - p_i.p_j of its pairs per event and leaves
+//      the partial sum at the slot of its last pair in that event, and the
+//      event's lane adds those partials (the lanes in order, then the rounds
+//      in order): deterministic for a tiling.
 // Events with more than cap particles are left to k_event_reduce_big.  In
 // the FP32 compensated mode a pair whose error bound asks for FP64 makes its
 // K a NaN; the event's lane then writes a marker -- a quiet NaN with a fixed
 // payload -- into the event mass (or, without event masses, into the event's
 // first pair mass), and k_event_reduce_big recomputes the event.
 template <typename T, int COORDS, int MODE>
-__global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
+__global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   constexpr bool kComp = MODE == GLV_COMPENSATED;
   constexpr bool kDefer = kComp && (sizeof(T) == 4);
+  constexpr int kSlots = Prefetch<T>::kSlots;
+  constexpr bool kStageMasses = sizeof(T) == 8;
   using R4 = typename V4<T>::type;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nwaves = blockDim.x >> 6;
   const int epb = A.epb, cap = A.cap, qcap = A.qcap;
   const WaveLds<T, MODE> W = carve_wave_lds<T, MODE>(lds + (size_t)wid * A.wave_bytes, cap, qcap, epb);
-  Stage<T, MODE> st;
-  st.cart = W.cart;
-  st.legA = W.legA;
-  st.legB = W.legB;
 
   const int64_t e0 = ((int64_t)blockIdx.x * nwaves + wid) * epb;
   if (e0 >= A.ne) return;  // the whole wavefront: no workgroup barrier follows
@@ -666,18 +710,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
   const uint64_t valid = (nev >= 64) ? ~0ull : ((1ull << nev) - 1);
   unsigned fb = 0;
 
-  int ca = 0;
+  int ca, cb;
+  next_chunk(0, nev, valid, mine, olo, ohi, cap, &ca, &cb);
+  Prefetch<T> pre;
+  if (ca < nev) {
+    const int64_t b0 = readlane64(olo, ca);
+    prefetch_chunk(A.p, b0, (int)(readlane64(ohi, cb - 1) - b0), lane, &pre);
+  }
   while (ca < nev) {
-    // chunk [ca, cb): consecutive events ending within cap particles of event ca's start
     const int64_t base = readlane64(olo, ca);
-    const uint64_t ge = valid & (~0ull << ca);
-    const uint64_t fits = __ballot(mine && (ohi - base <= (int64_t)cap)) & ge;
-    const uint64_t stop = ge & ~fits;
-    const int cb = stop ? (int)__builtin_ctzll(stop) : nev;
-    if (cb == ca) {  // event ca exceeds the staging capacity: k_event_reduce_big's
-      ++ca;
-      continue;
-    }
     const int np = (int)(readlane64(ohi, cb - 1) - base);
     const int64_t q0 = need_po ? readlane64(plo, ca) : 0;
     const int nq = need_po ? (int)(readlane64(phi, cb - 1) - q0) : 0;
@@ -702,9 +743,26 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       }
     }
 
-    // 1. stage the chunk's particles
-    for (int t = lane; t < np; t += 64) stage_particle<T, COORDS, MODE>(A.p, base + t, st, t);
+    // 1. stage the chunk's particles: those held in registers, then any
+    //    beyond them straight from memory
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int t = lane + 64 * s;
+      if (t < np) stage_one<T, COORDS, MODE>(W, t, pre.v[s][0], pre.v[s][1], pre.v[s][2], pre.v[s][3]);
+    }
+    for (int t = lane + 64 * kSlots; t < np; t += 64) {
+      const int64_t gi = base + t;
+      stage_one<T, COORDS, MODE>(W, t, A.p.c[0][gi], A.p.c[1][gi], A.p.c[2][gi], A.p.c[3][gi]);
+    }
     wave_sync();
+
+    // the next chunk's particles into registers, in flight from here on
+    int na, nb;
+    next_chunk(cb, nev, valid, mine, olo, ohi, cap, &na, &nb);
+    if (na < nev) {
+      const int64_t b1 = readlane64(olo, na);
+      prefetch_chunk(A.p, b1, (int)(readlane64(ohi, nb - 1) - b1), lane, &pre);
+    }
 
     // 2. one lane per event: totals in CSR order, plain event mass
     double msum = 0.0;
@@ -716,15 +774,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
         double d[4] = {0, 0, 0, 0};
         int t = lo;
         for (; t + 2 <= hi; t += 2) {
-          const R4 r0 = st.cart[t], r1 = st.cart[t + 1];
-          const double m0 = (double)st.legA[t][3], m1 = (double)st.legA[t + 1][3];
+          const R4 r0 = W.cart[t], r1 = W.cart[t + 1];
+          const double m0 = (double)W.legA[t][3], m1 = (double)W.legA[t + 1][3];
 #pragma unroll
           for (int k = 0; k < 4; ++k) d[k] = (d[k] + (double)r0[k]) + (double)r1[k];
           msum = (msum + m0 * m0) + m1 * m1;
         }
         if (t < hi) {
-          const R4 r0 = st.cart[t];
-          const double m0 = (double)st.legA[t][3];
+          const R4 r0 = W.cart[t];
+          const double m0 = (double)W.legA[t][3];
 #pragma unroll
           for (int k = 0; k < 4; ++k) d[k] += (double)r0[k];
           msum += m0 * m0;
@@ -733,13 +791,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
         for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
       } else if constexpr (sizeof(T) == 4) {
         double d[4] = {0, 0, 0, 0};
-        sum_records(st.cart, lo, hi, d);
+        sum_records(W.cart, lo, hi, d);
 #pragma unroll
         for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) tot[k] = T(0);
-        sum_records(st.cart, lo, hi, tot);
+        sum_records(W.cart, lo, hi, tot);
       }
       const int64_t e = e0 + lane;
       if (A.total[0]) {
@@ -751,12 +809,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
       }
     }
 
-    // 3. pairs, in rounds of qcap
+    // 3. pairs, in rounds
     double ks = 0.0;  // the event lane's sum of K (compensated)
-    if (want_pairs || want_k) {
-      for (int r0 = 0; r0 < nq; r0 += qcap) {
-        const int qn = min(qcap, nq - r0);
-        const int m = ((qn + 63) >> 6) | 1;  // pairs per lane, odd: the LDS stores spread over the banks
+    if (need_po) {
+      const int rcap = kStageMasses ? 64 * (((qcap >> 6) - 1) | 1) : (kComp ? qcap : 0x3fffffff);
+      T* const pout = want_pairs ? A.pair_m + q0 : nullptr;
+      for (int r0 = 0; r0 < nq; r0 += rcap) {
+        const int qn = min(rcap, nq - r0);
+        // pairs per lane, odd where the masses pass through LDS
+        const int m = kStageMasses ? (((qn + 63) >> 6) | 1) : ((qn + 63) >> 6);
         int k = r0 + lane * m;
         const int kend = min(k + m, r0 + qn);
         if (k < kend) {
@@ -771,7 +832,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
             T mk;
             if constexpr (kComp) {
               T ma, mb;
-              const LegC<T> la = staged_leg<T, MODE>(st, o + i, &ma), lb = staged_leg<T, MODE>(st, o + j, &mb);
+              const LegC<T> la = staged_leg<T, MODE>(W, o + i, &ma), lb = staged_leg<T, MODE>(W, o + j, &mb);
               double kd;
               if constexpr (kDefer) {
                 bool redo;
@@ -782,13 +843,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
               }
               kacc += kd;
             } else {
-              const R4 a = st.cart[o + i], b = st.cart[o + j];
+              const R4 a = W.cart[o + i], b = W.cart[o + j];
               T w[4];
 #pragma unroll
               for (int q = 0; q < 4; ++q) w[q] = a[q] + b[q];
               mk = mass_of(w);
             }
-            W.pm[k - r0] = mk;
+            if constexpr (kStageMasses)
+              W.pm[k - r0] = mk;
+            else if (want_pairs)
+              pout[k] = mk;
             // lexicographic successor within the chunk
             bool fin = false;
             if (++j == n) {
@@ -812,7 +876,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
           }
         }
         wave_sync();
-        if (want_pairs) {
+        if (kStageMasses && want_pairs) {
           T* out = A.pair_m + q0 + r0;
           for (int t = lane; t < qn; t += 64) store_out(out, t, W.pm[t]);
         }
@@ -844,15 +908,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce(FwdArgs<T, COORDS, M
             // without event masses the mark goes to the event's first pair
             // mass, after this wavefront's own stores of the chunk's masses
             if (__ballot(marked)) {
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-              if (marked) store_out(A.pair_m, plo, redo_mark());
+              // every earlier store of the wavefront completes first
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+              if (marked) A.pair_m[plo] = redo_mark();
             }
           }
         }
       }
     }
     wave_sync();
-    ca = cb;
+    ca = na;
+    cb = nb;
   }
   if constexpr (kComp && sizeof(T) == 4) {
     if (A.fallback) {
