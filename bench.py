@@ -68,6 +68,7 @@ HBM_PEAK_GBS = 8000.0
 N_ITEMS = 1 << 24
 N_STRESS = 1 << 26
 N_EVENTS = 1 << 20
+TILING_FIELDS = ("block", "events_per_tile", "lds_particles", "pairs_per_round")
 KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_fwd32", "mass_bwd32", "boost_fwd32",
            "boost_bwd32", "mass_comp32", "event_reduce", "event_reduce32c", "event_reduce_bwd"]
 KERNEL_SYMBOL = {
@@ -98,7 +99,9 @@ TRANSFORM_CASES = {
 }
 # The analysis step, measured after the step: kernel symbols.
 ANALYSIS_SYMBOL = {"mass_histogram": "k_hist_lds<double, 2>", "event_best_pair": "k_best_pair<double>",
-                   "mass_comp32_bwd": "MassCompBwd<float>"}
+                   "mass_comp32_bwd": "MassCompBwd<float>",
+                   "mass_histogram_fused": "k_mass_hist<MassPlain<double, 1>, 2, true>",
+                   "event_best_pair_fused": "k_event_reduce<double, 1, 0, true>"}
 ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()},
                **{k: v[0] for k, v in TRANSFORM_CASES.items()}, **ANALYSIS_SYMBOL}
 
@@ -246,6 +249,7 @@ def summarize_pmc(fetch_csv, write_csv):
 KERNEL_SOURCES = {k: ["kernels_jagged.hip", "glv_abi.hip"] for k in ("event_reduce", "event_reduce32c",
                                                                        "event_reduce_bwd")}
 KERNEL_SOURCES.update({k: ["kernels_analysis.hip"] for k in ("mass_histogram", "event_best_pair")})
+KERNEL_SOURCES["event_best_pair_fused"] = ["kernels_jagged.hip", "glv_abi.hip"]
 SHARED_SOURCES = ["glv_device.h", "glv_math.h", "glv_launch.h"]
 
 
@@ -520,6 +524,24 @@ def main():
             stream, args.warmup, K, N_ITEMS, 68 * N_ITEMS)
         analysis["mass_histogram"]["bins"] = 1000
         analysis["event_best_pair"]["pairs"] = n_pairs
+        # the same analysis fused into the kernels: the step's 2^24 FP64 pairs
+        # binned as their masses are computed (legs read, nothing stored: 64
+        # B/pair against 72 + 8 B/pair for the mass kernel then the
+        # histogram), and each jagged event's best pair chosen inside the
+        # reduction (no pair masses written and read back: 32 B/particle,
+        # 16 B/event of offsets and 16 B/event of outputs)
+        analysis["mass_histogram_fused"] = time_launches(
+            "mass_histogram_fused", lambda: lib.glv_invariant_mass_histogram(
+                F64, PTM, PLAIN, N_ITEMS, cA, cB, 0.0, 200.0, 1000, counts.data_ptr(), None, sp),
+            stream, args.warmup, K, N_ITEMS, 64 * N_ITEMS)
+        analysis["mass_histogram_fused"]["unfused_alg_bytes"] = 80 * N_ITEMS
+        analysis["event_best_pair_fused"] = time_launches(
+            "event_best_pair_fused", lambda: lib.glv_event_reduce_best_pair(
+                F64, PTM, PLAIN, N_EVENTS, OFF.data_ptr(), PO.data_ptr(), cP, 91.1876, rank.data_ptr(),
+                best.data_ptr(), None, None, sp),
+            stream, args.warmup, K, N_EVENTS, 32 * n_part + 16 * (N_EVENTS + 1) + 16 * N_EVENTS)
+        analysis["event_best_pair_fused"]["unfused_alg_bytes"] = (
+            alg_bytes["event_reduce"] - 40 * N_EVENTS + 8 * n_pairs + 8 * (N_EVENTS + 1) + 16 * N_EVENTS)
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -541,12 +563,9 @@ def main():
             "step_alg_bytes": step_bytes,
             "step_alg_GBps": round(step_bytes / (elapsed / K) / 1e9, 1),
             "pairs_in_events": n_pairs, "particles": n_part,
-            "event_tiling": None if tiling is None else dict(zip(("block", "events_per_tile", "lds_particles"),
-                                                                 tiling)),
-            "event_tiling_fp32_comp": None if tiling32c is None else dict(
-                zip(("block", "events_per_tile", "lds_particles"), tiling32c)),
-            "event_tiling_bwd": None if tiling_bwd is None else dict(
-                zip(("block", "events_per_tile", "lds_particles"), tiling_bwd)),
+            "event_tiling": None if tiling is None else dict(zip(TILING_FIELDS, tiling)),
+            "event_tiling_fp32_comp": None if tiling32c is None else dict(zip(TILING_FIELDS, tiling32c)),
+            "event_tiling_bwd": None if tiling_bwd is None else dict(zip(TILING_FIELDS, tiling_bwd)),
             "parallelism": "single GPU", "input_gen_s": round(gen_s, 1),
         },
         "roofline": roofline,

@@ -92,7 +92,8 @@ typedef enum glv_coords { GLV_PXPYPZE = 0, GLV_PTETAPHIM = 1, GLV_PTETAPHIE = 2,
  * throughout (no fallback). */
 typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
 
-/* Work decomposition of glv_event_reduce / glv_event_reduce_bwd.  It changes
+/* Work decomposition of glv_event_reduce, glv_event_reduce_best_pair and
+ * glv_event_reduce_bwd.  It changes
  * speed only: pair masses, totals and gradients of every event that fits the
  * tiling's staging capacity, and plain event masses, are identical for every
  * such tiling; the compensated event mass (a sum of per-pair terms, summed in
@@ -109,9 +110,13 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  *   events_per_tile  events of one wavefront's tile: 1 .. 64
  *   lds_particles    particles a wavefront stages at once: 64 .. 4096
  *                    (larger events go to the second launch)
- *   pairs_per_round  pairs a wavefront evaluates per round, a multiple of 64
- *                    in 64 .. 4096 (pairs_per_round / 64 consecutive pairs
- *                    per lane)
+ *   pairs_per_round  a multiple of 64 in 64 .. 4096: pairs a wavefront
+ *                    evaluates per round, each lane a run of consecutive
+ *                    pairs.  FP64 masses pass through LDS in rounds of 64 m
+ *                    pairs, m the largest odd number <= pairs_per_round / 64;
+ *                    the FP32 plain mode takes a chunk's pairs in one round;
+ *                    the compensated mode and glv_event_reduce_best_pair
+ *                    take rounds of pairs_per_round
  * Backward (glv_event_reduce_bwd): the same wavefront tiles.
  *   block, events_per_tile, lds_particles   as for the forward
  *   pairs_per_round  pair upstreams a wavefront stages at once, a multiple of
@@ -120,11 +125,12 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  * Fields set to 0 take the library's current choice (the autotuned one if
  * glv_autotune_event_reduce, or glv_autotune_event_reduce_bwd for the
  * backward, ran for this device/dtype/coords/mode, otherwise a built-in
- * default).  A tiling whose workgroup would need more than 64 KiB of LDS is
+  * default).  A tiling whose workgroup would need more than 64 KiB of LDS is
  * rejected with GLV_EINVAL_TILING: per wavefront the forward keeps 4 values
- * per staged particle (10 in the compensated mode), one value per pair of a
- * round (plus 8 bytes in the compensated mode) and 12 bytes per event of the
- * tile; the backward 10 values and 4 bytes per staged particle, one value per
+ * per staged particle (12 in the compensated mode), per pair of a round one
+ * value in FP64 (none in FP32), 8 more bytes in the compensated mode and one
+ * value and 4 bytes for glv_event_reduce_best_pair (instead of the FP64
+ * value), and 12 bytes per event of the tile; the backward 10 values and 4 bytes per staged particle, one value per
  * staged pair upstream and 4 values and 24 bytes per event of the tile. */
 typedef struct glv_tiling {
   int32_t block;
@@ -297,13 +303,51 @@ glv_status glv_mass_histogram(glv_dtype dtype, int64_t n, const void* m, double 
 glv_status glv_event_best_pair(glv_dtype dtype, int64_t n_events, const int64_t* pair_offsets, const void* pair_m,
                                double target, int64_t* best_rank, void* best_m, void* stream);
 
+/* The per-event best pair of glv_event_best_pair chosen inside the jagged
+ * reduction, without writing pair masses (the analysis step fused into the
+ * reduction; not in the paper, whose Sec. 6 places GenVector inside ROOT).
+ * The pair masses are bitwise those glv_event_reduce writes for the same
+ * arguments and tiling; best_rank[e] (int64) and best_m[e] (dtype) follow
+ * glv_event_best_pair's rule (smallest |m - target| in binary64, lowest rank
+ * among equal distances, NaN masses never chosen, -1 and NaN for an event
+ * without a chosen pair).
+ *   offsets, pair_offsets (required), p, tiling, fallback_count
+ *                 as in glv_event_reduce; without a tiling the current
+ *                 choice for glv_event_reduce is taken if its LDS suffices
+ *                 for the selection, else the built-in default
+ * The outputs must not overlap each other, the offsets or the particle
+ * columns (GLV_EINVAL_ALIAS).  Errors as glv_event_reduce, and
+ * GLV_EINVAL_OFFSETS without pair_offsets. */
+glv_status glv_event_reduce_best_pair(glv_dtype dtype, glv_coords coords, glv_mode mode, int64_t n_events,
+                                      const int64_t* offsets, const int64_t* pair_offsets, const void* const p[4],
+                                      double target, int64_t* best_rank, void* best_m,
+                                      unsigned long long* fallback_count, const glv_tiling* tiling, void* stream);
+
+/* Pair masses binned into glv_mass_histogram's bins as they are computed,
+ * never stored (the histogram of the analysis step fused into the mass
+ * kernel; not in the paper): the masses are bitwise those glv_invariant_mass
+ * writes for the same dtype, coords, mode and legs, and each is counted as
+ * glv_mass_histogram counts a value (the call ADDS to counts, n_bins + 2
+ * uint64; NaN not counted).  fallback_count as in glv_invariant_mass.
+ * Errors: those of glv_invariant_mass for the legs and of
+ * glv_mass_histogram for the bins; counts must not overlap a leg column
+ * (GLV_EINVAL_ALIAS). */
+glv_status glv_invariant_mass_histogram(glv_dtype dtype, glv_coords coords, glv_mode mode, int64_t n,
+                                        const void* const a[4], const void* const b[4], double lo, double hi,
+                                        int64_t n_bins, unsigned long long* counts,
+                                        unsigned long long* fallback_count, void* stream);
+
 /* Pair offsets of CSR events: pair_offsets[0] = 0,
  * pair_offsets[e+1] = pair_offsets[e] + c_e (c_e - 1) / 2 with
  * c_e = offsets[e+1] - offsets[e].  Both arrays hold n_events + 1 int64. */
 glv_status glv_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* pair_offsets,
                             void* stream);
 
-/* Per-event reduction of CSR events, one launch.
+/* Per-event reduction of CSR events.  Two launches on `stream`: the main one
+ * reduces every event that fits the tiling's staging capacity; a short
+ * second one scans the offsets for larger events (and, in the FP32
+ * GLV_COMPENSATED mode, for events the first marked for the FP64 redo) and
+ * reduces those from global memory.
  *   offsets       n_events + 1 int64, offsets[0] = 0, non-decreasing
  *                 (trusted: see glv_validate_offsets)
  *   pair_offsets  from glv_pair_offsets; required when pair_m or a

@@ -30,7 +30,8 @@ EXPORTS = (
     "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd", "glv_lorentz_transform",
     "glv_lorentz_transform_bwd", "glv_rotate", "glv_rotate_bwd", "glv_rotate_axis_angle",
     "glv_rotate_axis_angle_bwd", "glv_mass_histogram", "glv_event_best_pair", "glv_invariant_mass_comp_bwd",
-    "glv_autotune_key", "glv_autotune_lookup", "glv_autotune_forget",
+    "glv_autotune_key", "glv_autotune_lookup", "glv_autotune_forget", "glv_invariant_mass_histogram",
+    "glv_event_reduce_best_pair",
 )
 
 
@@ -71,6 +72,9 @@ _SIGS = {
     "glv_rotate_axis_angle_bwd": [_i, _i64, _vp, _i64, _vp, _vp, _vp],
     "glv_mass_histogram": [_i, _i64, _vp, ctypes.c_double, ctypes.c_double, _i64, _vp, _vp],
     "glv_event_best_pair": [_i, _i64, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
+    "glv_invariant_mass_histogram": [_i, _i, _i, _i64, _vp, _vp, ctypes.c_double, ctypes.c_double, _i64, _vp, _vp,
+                                     _vp],
+    "glv_event_reduce_best_pair": [_i, _i, _i, _i64, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
     "glv_current_tiling_bwd": [_i, _i, _vp],
     "glv_autotune_key": [_i, _i, _i, ctypes.c_int32, _i64, _vp, ctypes.c_char_p, _i64, _vp],
     "glv_autotune_lookup": [_i, _i, _i, ctypes.c_int32, _i64, _vp, _vp, _vp, _vp],

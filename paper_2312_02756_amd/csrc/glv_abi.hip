@@ -166,18 +166,18 @@ constexpr size_t kMaxLds = 64 * 1024;
 bool block_ok(int b) { return (b == 64 || b == 128 || b == 256 || b == 512) && b <= glv::kMaxBlock; }
 
 // Every field inside its allowed set and the workgroup's LDS within kMaxLds.
-bool tiling_valid(glv_dtype dt, glv_mode mode, bool bwd, const glv::Tiling& t) {
+bool tiling_valid(glv_dtype dt, glv_mode mode, bool bwd, const glv::Tiling& t, bool best = false) {
   if (!block_ok(t.block)) return false;
   if (t.events_per_tile < 1 || t.events_per_tile > 64) return false;
   if (t.lds_particles < 64 || t.lds_particles > 4096) return false;
   if (t.pairs_per_round < 64 || t.pairs_per_round > 4096 || t.pairs_per_round % 64 != 0) return false;
-  const size_t lds = bwd ? glv::event_reduce_bwd_lds_bytes(dt, t) : glv::event_reduce_lds_bytes(dt, mode, t);
+  const size_t lds = bwd ? glv::event_reduce_bwd_lds_bytes(dt, t) : glv::event_reduce_lds_bytes(dt, mode, t, best);
   return lds <= kMaxLds;
 }
 
 // Resolve a user tiling (fields 0 = current choice) and validate it.
 glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,
-                          glv::Tiling* out) {
+                          glv::Tiling* out, bool best = false) {
   glv::Tiling base = bwd ? default_tiling_bwd(dt) : default_tiling(dt, mode);
   {
     int dev = 0;
@@ -192,7 +192,13 @@ glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_
     if (user->lds_particles) base.lds_particles = user->lds_particles;
     if (user->pairs_per_round) base.pairs_per_round = user->pairs_per_round;
   }
-  if (!tiling_valid(dt, mode, bwd, base)) return GLV_EINVAL_TILING;
+  if (!tiling_valid(dt, mode, bwd, base, best)) {
+    // the fused best-pair selection needs more LDS per pair than the choice
+    // made for glv_event_reduce: without a user tiling it takes the default
+    if (!(best && !user)) return GLV_EINVAL_TILING;
+    base = default_tiling(dt, mode);
+    if (!tiling_valid(dt, mode, bwd, base, best)) return GLV_EINVAL_TILING;
+  }
   *out = base;
   return GLV_OK;
 }
@@ -685,6 +691,57 @@ glv_status glv_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t 
   if (ne == 0 || (!total && !em && !pm)) return GLV_OK;
   return hip_status(
       glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, total, em, pm, fallback, t, (hipStream_t)stream));
+}
+
+glv_status glv_event_reduce_best_pair(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
+                                      const int64_t* poff, const void* const p[4], double target, int64_t* best_rank,
+                                      void* best_m, unsigned long long* fallback, const glv_tiling* tiling,
+                                      void* stream) {
+  glv_status st = check_event_args(dt, co, mode, ne, off, p);
+  if (st != GLV_OK || ne == 0) return st;
+  if (!poff) return GLV_EINVAL_OFFSETS;
+  if (!best_rank || !best_m) return GLV_EINVAL_NULL;
+  std::vector<Range> outs{rng(best_rank, ne, 8), rng(best_m, ne, elem(dt))};
+  std::vector<Range> ins{rng(off, ne + 1, 8), rng(poff, ne + 1, 8)};
+  if (fallback) outs.push_back(rng(fallback, 1, 8));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  for (int k = 0; k < 4; ++k) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p[k]);
+    for (const Range& r : outs)
+      if (a >= r.lo && a < r.hi) return GLV_EINVAL_ALIAS;
+  }
+  glv::Tiling t;
+  st = resolve_tiling(dt, co, mode, tiling, false, &t, true);
+  if (st != GLV_OK) return st;
+  const glv::BestOut b{best_rank, best_m, target};
+  return hip_status(glv::launch_event_reduce(dt, co, mode, ne, off, poff, p, nullptr, nullptr, nullptr, fallback, t,
+                                             (hipStream_t)stream, &b));
+}
+
+glv_status glv_invariant_mass_histogram(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                                        const void* const b[4], double lo, double hi, int64_t n_bins,
+                                        unsigned long long* counts, unsigned long long* fallback, void* stream) {
+  if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
+  if (!coords_ok(co)) return GLV_EINVAL_COORDS;
+  glv_status ms = mode_ok(mode, co);
+  if (ms != GLV_OK) return ms;
+  if (n < 0 || n_bins < 1) return GLV_EINVAL_SIZE;
+  const double scale = (double)n_bins / (hi - lo);
+  if (!(std::isfinite(lo) && std::isfinite(hi) && lo < hi && std::isfinite(scale) && scale > 0.0))
+    return GLV_EINVAL_SIZE;
+  if (n == 0) return GLV_OK;
+  if (!nonnull<4>(a) || !nonnull<4>(b) || !counts) return GLV_EINVAL_NULL;
+  const size_t es = elem(dt);
+  std::vector<Range> ins;
+  for (int k = 0; k < 4; ++k) {
+    ins.push_back(rng(a[k], n, es));
+    ins.push_back(rng(b[k], n, es));
+  }
+  std::vector<Range> outs{rng(counts, n_bins + 2, 8)};
+  if (fallback) outs.push_back(rng(fallback, 1, 8));
+  if (any_overlap(outs, ins)) return GLV_EINVAL_ALIAS;
+  return hip_status(glv::launch_mass_histogram(dt, co, mode, n, a, b, lo, hi, n_bins, counts, fallback,
+                                               (hipStream_t)stream));
 }
 
 glv_status validate_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,

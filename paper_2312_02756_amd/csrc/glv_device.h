@@ -80,6 +80,29 @@ __device__ __forceinline__ void store_pack(T* __restrict__ p, int64_t i, const P
   }
 }
 
+// ------------------------------------------------------------ histogram
+
+// Equal bins of [lo, hi) with under- and overflow counters.
+struct HistSpec {
+  double lo, hi, s;  // s = n_bins / (hi - lo), formed on the host
+  int64_t nb;
+};
+
+// Counters (bins plus under- and overflow) a workgroup keeps in LDS: 32 KiB.
+constexpr int kHistLdsSlots = 8192;
+
+// Counter slot of v: 0 below lo, nb + 1 at or above hi, else
+// 1 + floor((v - lo) s) clamped to nb; -1 for NaN (not counted).  Evaluated
+// in binary64 without contraction, as the definition states.
+__device__ __forceinline__ int64_t hist_slot(double v, const HistSpec& h) {
+#pragma clang fp contract(off)
+  if (v != v) return -1;
+  if (v < h.lo) return 0;
+  if (v >= h.hi) return h.nb + 1;
+  const int64_t b = (int64_t)floor((v - h.lo) * h.s);
+  return 1 + (b < h.nb - 1 ? b : h.nb - 1);
+}
+
 // ------------------------------------------------------------ scalar math
 
 // FP64 square root: the hardware reciprocal square root y ~ 1/sqrt(x)

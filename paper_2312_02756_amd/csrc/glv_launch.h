@@ -17,6 +17,12 @@ hipError_t launch_mass_bwd(glv_dtype dt, glv_coords co, int64_t n, const void* c
                            const void* const b[4], const void* gm, void* const ga[4],
                            void* const gb[4], hipStream_t s);
 
+// Pair masses binned into a histogram (added to counts[n_bins + 2]) as they
+// are computed, without storing them.
+hipError_t launch_mass_histogram(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                                 const void* const b[4], double lo, double hi, int64_t n_bins,
+                                 unsigned long long* counts, unsigned long long* fallback, hipStream_t s);
+
 // Reverse mode of the cancellation-free (compensated) pair mass, PtEtaPhiM legs.
 hipError_t launch_mass_comp_bwd(glv_dtype dt, int64_t n, const void* const a[4], const void* const b[4],
                                 const void* gm, void* const ga[4], void* const gb[4], hipStream_t s);
@@ -75,15 +81,25 @@ struct Tiling {
   int pairs_per_round;  // forward: pairs a wavefront evaluates per round (the backward ignores it)
 };
 
-// LDS bytes one workgroup of the forward reduction needs for a tiling.
-size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t);
+// LDS bytes one workgroup of the forward reduction needs for a tiling (with
+// the fused best-pair selection if `best`).
+size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t, bool best = false);
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t);
 
+// Outputs of the fused per-event best-pair selection.
+struct BestOut {
+  int64_t* rank;
+  void* mass;
+  double target;
+};
+
+// With `best`, the per-event best pair instead of pair masses (pair_m is
+// then ignored).
 hipError_t launch_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n_events,
                                const int64_t* offsets, const int64_t* pair_offsets,
                                const void* const p[4], void* const total[4], void* event_m,
                                void* pair_m, unsigned long long* fallback, const Tiling& t,
-                               hipStream_t s);
+                               hipStream_t s, const BestOut* best = nullptr);
 
 hipError_t launch_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t n_events,
                                    const int64_t* offsets, const int64_t* pair_offsets,

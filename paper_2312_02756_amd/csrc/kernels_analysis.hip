@@ -8,8 +8,6 @@ namespace glv {
 namespace {
 
 constexpr int kHistBlock = 1024;
-// Counters (bins plus under- and overflow) a workgroup keeps in LDS: 32 KiB.
-constexpr int kHistLdsSlots = 8192;
 // Workgroups of the LDS path (one per CU, 16 wavefronts each): each merges
 // its counters into the global ones once, so fewer, larger workgroups mean
 // fewer global atomics on each bin.
@@ -17,23 +15,6 @@ constexpr int64_t kHistGrid = 256;
 constexpr int kBestLanes = 8;    // lanes per event in the best-pair kernel
 constexpr int kBestBlock = 256;  // 32 events per workgroup
 constexpr int kBestUnroll = 4;   // pair loads in flight per lane
-
-struct HistSpec {
-  double lo, hi, s;  // s = n_bins / (hi - lo), formed on the host
-  int64_t nb;
-};
-
-// Counter slot of v: 0 below lo, nb + 1 at or above hi, else
-// 1 + floor((v - lo) s) clamped to nb; -1 for NaN (not counted).  Evaluated
-// in binary64 without contraction, as the definition states.
-__device__ __forceinline__ int64_t hist_slot(double v, const HistSpec& h) {
-#pragma clang fp contract(off)
-  if (v != v) return -1;
-  if (v < h.lo) return 0;
-  if (v >= h.hi) return h.nb + 1;
-  const int64_t b = (int64_t)floor((v - h.lo) * h.s);
-  return 1 + (b < h.nb - 1 ? b : h.nb - 1);
-}
 
 // Per-workgroup counters in LDS, merged with one global atomic per non-empty
 // slot.  Grid-stride over packs of V values (16-byte loads), then the tail.

@@ -68,17 +68,81 @@ hipError_t dispatch_width(const Op& op, bool all_aligned, int64_t n, unsigned lo
   return run_stream<Op, 1>(op, n, counter, s);
 }
 
+// ------------------------------------------------ mass -> histogram, fused
+
+// Pair masses binned as they are computed, never stored: the mass op's
+// masses<V>() over packs (grid-stride), each mass's counter slot in binary64
+// (hist_slot), counters in LDS per workgroup merged into the global ones
+// with one atomic per non-empty slot; with more slots than LDS holds, one
+// global atomic per mass.
+constexpr int kFusedHistBlock = 512;
+
+template <typename Op, int V, bool kLds>
+__global__ __launch_bounds__(kFusedHistBlock) void k_mass_hist(Op op, int64_t n, HistSpec h,
+                                                               unsigned long long* __restrict__ counts,
+                                                               unsigned long long* fb) {
+  __shared__ unsigned int bins[kLds ? kHistLdsSlots : 1];
+  const int nslot = (int)h.nb + 2;
+  if constexpr (kLds) {
+    for (int b = threadIdx.x; b < nslot; b += kFusedHistBlock) bins[b] = 0;
+    __syncthreads();
+  }
+  auto count = [&](double v) {
+    const int64_t sl = hist_slot(v, h);
+    if (sl >= 0) {
+      if constexpr (kLds)
+        atomicAdd(&bins[sl], 1u);
+      else
+        atomicAdd(&counts[sl], 1ull);
+    }
+  };
+  const int64_t nv = n / V;
+  const int64_t stride = (int64_t)gridDim.x * kFusedHistBlock;
+  const int64_t tid = (int64_t)blockIdx.x * kFusedHistBlock + threadIdx.x;
+  unsigned cnt = 0;
+  for (int64_t i = tid; i < nv; i += stride) {
+    Pack<typename Op::Scalar, V> m;
+    cnt += op.template masses<V>(i, m);
+#pragma unroll
+    for (int e = 0; e < V; ++e) count((double)m.v[e]);
+  }
+  if constexpr (V > 1) {
+    const int64_t t = nv * V + tid;
+    if (t < n) {
+      Pack<typename Op::Scalar, 1> m;
+      cnt += op.template masses<1>(t, m);
+      count((double)m.v[0]);
+    }
+  }
+  if constexpr (Op::kCounts) {
+    if (fb) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+      if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(fb, (unsigned long long)cnt);
+    }
+  }
+  if constexpr (kLds) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < nslot; b += kFusedHistBlock)
+      if (bins[b]) atomicAdd(&counts[b], (unsigned long long)bins[b]);
+  }
+}
+
 // ------------------------------------------------------------ pair mass
 
+// masses<V>(i, out) evaluates the masses of pack i (returning the number of
+// FP64 redos); run<V>(i) stores them.  The fused histogram kernel calls
+// masses<V> too, so both see bitwise the same masses.
 template <typename T, int COORDS>
 struct MassPlain {
+  using Scalar = T;
   static constexpr bool kCounts = false;
   static constexpr int kBlock = kBlockStream;
   Cols4<T> a, b;
   T* m;
   template <int V>
-  __device__ __forceinline__ unsigned run(int64_t i) const {
-    Pack<T, V> pa[4], pb[4], out;
+  __device__ __forceinline__ unsigned masses(int64_t i, Pack<T, V>& out) const {
+    Pack<T, V> pa[4], pb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       pa[k] = load_pack<T, V>(a.c[k], i);
@@ -92,8 +156,14 @@ struct MassPlain {
       add4<T>(va, vb, w);
       out.v[e] = mass_of(w);
     }
-    store_pack<T, V>(m, i, out);
     return 0;
+  }
+  template <int V>
+  __device__ __forceinline__ unsigned run(int64_t i) const {
+    Pack<T, V> out;
+    const unsigned c = masses<V>(i, out);
+    store_pack<T, V>(m, i, out);
+    return c;
   }
 };
 
@@ -101,13 +171,21 @@ struct MassPlain {
 // error bound exceeds kFallbackUnits are recomputed in FP64.
 template <typename T>
 struct MassComp {
+  using Scalar = T;
   static constexpr bool kCounts = true;
   static constexpr int kBlock = kBlockAlu;
   Cols4<T> a, b;
   T* m;
   template <int V>
   __device__ __forceinline__ unsigned run(int64_t i) const {
-    Pack<T, V> pa[4], pb[4], out;
+    Pack<T, V> out;
+    const unsigned c = masses<V>(i, out);
+    store_pack<T, V>(m, i, out);
+    return c;
+  }
+  template <int V>
+  __device__ __forceinline__ unsigned masses(int64_t i, Pack<T, V>& out) const {
+    Pack<T, V> pa[4], pb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       pa[k] = load_pack<T, V>(a.c[k], i);
@@ -136,7 +214,6 @@ struct MassComp {
         out.v[e] = d_sqrt(comp_pair_m2<T>(la, lb, &k, nullptr));
       }
     }
-    store_pack<T, V>(m, i, out);
     return cnt;
   }
 };
@@ -617,6 +694,48 @@ hipError_t mass_typed(glv_coords co, glv_mode mode, int64_t n, const void* const
   }
 }
 
+template <typename Op>
+hipError_t run_mass_hist(const Op& op, bool al, int64_t n, const HistSpec& h, unsigned long long* counts,
+                         unsigned long long* fb, hipStream_t s) {
+  using T = typename Op::Scalar;
+  constexpr int V = Vec16<T>::N;
+  const bool lds = h.nb + 2 <= kHistLdsSlots;
+  const int64_t packs = al ? n / V : n;
+  int64_t blocks = (packs + kFusedHistBlock - 1) / kFusedHistBlock;
+  // the LDS path merges once per workgroup: 1024 workgroups (32 wavefronts
+  // per CU) keep the streams busy without multiplying the merges
+  const int64_t cap = lds ? 1024 : 65536;
+  blocks = blocks < 1 ? 1 : (blocks > cap ? cap : blocks);
+  const dim3 g((unsigned)blocks), b(kFusedHistBlock);
+  if (al && lds)
+    hipLaunchKernelGGL((k_mass_hist<Op, V, true>), g, b, 0, s, op, n, h, counts, fb);
+  else if (al)
+    hipLaunchKernelGGL((k_mass_hist<Op, V, false>), g, b, 0, s, op, n, h, counts, fb);
+  else if (lds)
+    hipLaunchKernelGGL((k_mass_hist<Op, 1, true>), g, b, 0, s, op, n, h, counts, fb);
+  else
+    hipLaunchKernelGGL((k_mass_hist<Op, 1, false>), g, b, 0, s, op, n, h, counts, fb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mass_hist_typed(glv_coords co, glv_mode mode, int64_t n, const void* const a[4], const void* const b[4],
+                           const HistSpec& h, unsigned long long* counts, unsigned long long* fb, hipStream_t s) {
+  const bool al = all16<4>(a) && all16<4>(b);
+  Cols4<T> ca = cols4<T>(a), cb = cols4<T>(b);
+  if (mode == GLV_COMPENSATED) return run_mass_hist(MassComp<T>{ca, cb, nullptr}, al, n, h, counts, fb, s);
+  switch (co) {
+    case GLV_PXPYPZE:
+      return run_mass_hist(MassPlain<T, GLV_PXPYPZE>{ca, cb, nullptr}, al, n, h, counts, nullptr, s);
+    case GLV_PTETAPHIM:
+      return run_mass_hist(MassPlain<T, GLV_PTETAPHIM>{ca, cb, nullptr}, al, n, h, counts, nullptr, s);
+    case GLV_PXPYPZM:
+      return run_mass_hist(MassPlain<T, GLV_PXPYPZM>{ca, cb, nullptr}, al, n, h, counts, nullptr, s);
+    default:
+      return run_mass_hist(MassPlain<T, GLV_PTETAPHIE>{ca, cb, nullptr}, al, n, h, counts, nullptr, s);
+  }
+}
+
 template <typename T>
 hipError_t mass_bwd_typed(glv_coords co, int64_t n, const void* const a[4], const void* const b[4],
                           const void* gm, void* const ga[4], void* const gb[4], hipStream_t s) {
@@ -795,6 +914,15 @@ hipError_t launch_mass(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, co
                        const void* const b[4], void* m, unsigned long long* fb, hipStream_t s) {
   if (dt == GLV_F64) return mass_typed<double>(co, mode, n, a, b, m, nullptr, s);
   return mass_typed<float>(co, mode, n, a, b, m, fb, s);
+}
+
+hipError_t launch_mass_histogram(glv_dtype dt, glv_coords co, glv_mode mode, int64_t n, const void* const a[4],
+                                 const void* const b[4], double lo, double hi, int64_t n_bins,
+                                 unsigned long long* counts, unsigned long long* fb, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const HistSpec h{lo, hi, (double)n_bins / (hi - lo), n_bins};
+  if (dt == GLV_F64) return mass_hist_typed<double>(co, mode, n, a, b, h, counts, nullptr, s);
+  return mass_hist_typed<float>(co, mode, n, a, b, h, counts, fb, s);
 }
 
 hipError_t launch_mass_comp_bwd(glv_dtype dt, int64_t n, const void* const a[4], const void* const b[4],

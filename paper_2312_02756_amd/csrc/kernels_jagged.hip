@@ -407,6 +407,9 @@ struct FwdArgs {
   T* total[4];
   T* event_m;
   T* pair_m;
+  int64_t* best_rank;  // per-event best pair (fused selection), or NULL
+  T* best_m;
+  double target;
   unsigned long long* fallback;
   int64_t ne;
   int epb;         // events per wavefront tile
@@ -414,6 +417,37 @@ struct FwdArgs {
   int qcap;        // pairs evaluated per round (per wavefront)
   int wave_bytes;  // LDS bytes per wavefront
 };
+
+// Lexicographic minimum of (distance bits, rank) over the workgroup, the mass
+// travelling with it; every thread receives the result.  `red` holds 48
+// bytes per wavefront, for at most four wavefronts (the 256-thread workgroups
+// of k_event_reduce_big; it is the 16-double scratch of block_sum, reused).
+template <typename T>
+__device__ __forceinline__ void block_best(unsigned long long* bd, int64_t* br, T* bm, double* red) {
+  auto take = [&](unsigned long long od, int64_t orr, T om) {
+    if (od < *bd || (od == *bd && orr < *br)) {
+      *bd = od;
+      *br = orr;
+      *bm = om;
+    }
+  };
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1)
+    take(__shfl_xor(*bd, d), __shfl_xor(*br, d), __shfl_xor(*bm, d));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  unsigned long long* sd = reinterpret_cast<unsigned long long*>(red);
+  int64_t* sr = reinterpret_cast<int64_t*>(sd + 4);
+  double* sm = reinterpret_cast<double*>(sr + 4);
+  __syncthreads();
+  if (lane == 0) {
+    sd[wid] = *bd;
+    sr[wid] = *br;
+    sm[wid] = (double)*bm;
+  }
+  __syncthreads();
+  for (int w = 0; w < nw; ++w) take(sd[w], sr[w], (T)sm[w]);
+  __syncthreads();
+}
 
 // One event too large for LDS: the whole workgroup, from global memory.
 template <typename T, int COORDS, int MODE>
@@ -439,7 +473,11 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
   if constexpr (MODE == GLV_COMPENSATED) msum = block_sum(msum, red);
   double ksum = 0.0;
   const bool want_k = (MODE == GLV_COMPENSATED) && A.event_m;
-  if (A.pair_m || want_k) {
+  const bool want_best = A.best_rank != nullptr;
+  unsigned long long bd = ~0ull;  // this thread's best: distance bits, rank, mass
+  int64_t br = -1;
+  T bmass = T(0);
+  if (A.pair_m || want_k || want_best) {
     const int64_t q = npairs(n);
     const int64_t base = A.poff ? A.poff[e] : 0;
     for (int64_t r = threadIdx.x; r < q; r += blockDim.x) {
@@ -463,10 +501,24 @@ __device__ void big_event(const FwdArgs<T, COORDS, MODE>& A, int64_t e, int64_t 
         m = mass_of(w);
       }
       if (A.pair_m) store_out(A.pair_m, base + r, m);
+      if (want_best) {  // a thread's ranks only grow: a tie keeps the earlier one
+        const double d = fabs((double)m - A.target);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+        if (d == d && b < bd) {
+          bd = b;
+          br = r;
+          bmass = m;
+        }
+      }
     }
     if (want_k) ksum = block_sum(ksum, red);
+    if (want_best) block_best<T>(&bd, &br, &bmass, red);
   }
   if (threadIdx.x == 0) {
+    if (want_best) {
+      A.best_rank[e] = bd != ~0ull ? br : -1;
+      A.best_m[e] = bd != ~0ull ? bmass : (T)__builtin_nan("");
+    }
     if (totals && A.total[0]) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) A.total[k][e] = tot[k];
@@ -516,6 +568,9 @@ __device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key
 //   legB[cap]  (mT, delta, mT - pt, M^2)   compensated mode
 //   pm[qcap]   FP64: pair masses of a round (stored from here, coalesced)
 //   kp[qcap]   partial sums of K per lane  (compensated event mass)
+//   bm[qcap], br[qcap]  best pair of a lane's run within one event: mass
+//              and in-event rank (-1: none), at the run's last slot
+//              (fused best-pair selection)
 //   eo, en, ep [epb + 1] int               the chunk's events with pairs:
 //              first particle, size, first pair (chunk-relative), then a
 //              sentinel (np, 0, nq)
@@ -526,21 +581,26 @@ struct WaveLds {
   typename V4<T>::type* legB;
   T* pm;
   double* kp;
+  T* bm;
+  int* br;
   int* eo;
   int* en;
   int* ep;
 };
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool BEST>
 __host__ __device__ __forceinline__ size_t wave_lds_bytes(int cap, int qcap, int epb) {
   size_t b = (size_t)cap * 4 * sizeof(T);
   if (MODE == GLV_COMPENSATED) b += (size_t)cap * 8 * sizeof(T) + (size_t)qcap * sizeof(double);
-  if (sizeof(T) == 8) b += (size_t)qcap * sizeof(T);  // staged pair masses
+  if (BEST)
+    b += (size_t)qcap * (sizeof(T) + sizeof(int));  // run candidates
+  else if (sizeof(T) == 8)
+    b += (size_t)qcap * sizeof(T);  // staged pair masses
   b += 3 * (size_t)(epb + 1) * sizeof(int);
   return (b + 31) & ~(size_t)31;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool BEST>
 __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int cap, int qcap, int epb) {
   WaveLds<T, MODE> w;
   w.cart = reinterpret_cast<typename V4<T>::type*>(p);
@@ -558,7 +618,15 @@ __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int
     w.kp = nullptr;
   }
   w.pm = reinterpret_cast<T*>(p);
-  if (sizeof(T) == 8) p += (size_t)qcap * sizeof(T);
+  w.bm = reinterpret_cast<T*>(p);
+  if (BEST) {
+    p += (size_t)qcap * sizeof(T);
+    w.br = reinterpret_cast<int*>(p);
+    p += (size_t)qcap * sizeof(int);
+  } else {
+    w.br = nullptr;
+    if (sizeof(T) == 8) p += (size_t)qcap * sizeof(T);
+  }
   w.eo = reinterpret_cast<int*>(p);
   w.en = w.eo + (epb + 1);
   w.ep = w.en + (epb + 1);
@@ -674,27 +742,28 @@ __device__ __forceinline__ void next_chunk(int from, int nev, uint64_t valid, bo
 // K a NaN; the event's lane then writes a marker -- a quiet NaN with a fixed
 // payload -- into the event mass (or, without event masses, into the event's
 // first pair mass), and k_event_reduce_big recomputes the event.
-template <typename T, int COORDS, int MODE>
+template <typename T, int COORDS, int MODE, bool BEST>
 __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   constexpr bool kComp = MODE == GLV_COMPENSATED;
   constexpr bool kDefer = kComp && (sizeof(T) == 4);
   constexpr int kSlots = Prefetch<T>::kSlots;
-  constexpr bool kStageMasses = sizeof(T) == 8;
+  constexpr bool kStageMasses = sizeof(T) == 8 && !BEST;
   using R4 = typename V4<T>::type;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nwaves = blockDim.x >> 6;
   const int epb = A.epb, cap = A.cap, qcap = A.qcap;
-  const WaveLds<T, MODE> W = carve_wave_lds<T, MODE>(lds + (size_t)wid * A.wave_bytes, cap, qcap, epb);
+  const WaveLds<T, MODE> W = carve_wave_lds<T, MODE, BEST>(lds + (size_t)wid * A.wave_bytes, cap, qcap, epb);
 
   const int64_t e0 = ((int64_t)blockIdx.x * nwaves + wid) * epb;
   if (e0 >= A.ne) return;  // the whole wavefront: no workgroup barrier follows
   const int nev = (int)min((int64_t)epb, A.ne - e0);
-  const bool want_pairs = A.pair_m != nullptr;
+  const bool want_pairs = !BEST && A.pair_m != nullptr;
   // FP32 compensated: K is summed whenever pairs are evaluated (a NaN sum marks the redo)
-  const bool want_k = kComp && (A.event_m != nullptr || (kDefer && want_pairs));
-  const bool need_po = want_pairs || want_k;
+  const bool want_k = kComp && (A.event_m != nullptr || (kDefer && (want_pairs || BEST)));
+  const bool need_po = want_pairs || want_k || BEST;
+  const bool want_sums = A.total[0] != nullptr || A.event_m != nullptr;
 
   // this lane's event of the tile
   const bool mine = lane < nev;
@@ -766,7 +835,7 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
 
     // 2. one lane per event: totals in CSR order, plain event mass
     double msum = 0.0;
-    if (in_chunk) {
+    if (in_chunk && want_sums) {
       const int lo = lo_rel, hi = lo_rel + n_e;
       T tot[4];
       if constexpr (kComp) {
@@ -811,8 +880,11 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
 
     // 3. pairs, in rounds
     double ks = 0.0;  // the event lane's sum of K (compensated)
+    double ebd = 0.0;  // the event lane's best pair (ebr < 0: none yet)
+    int ebr = -1;
+    T ebm = T(0);
     if (need_po) {
-      const int rcap = kStageMasses ? 64 * (((qcap >> 6) - 1) | 1) : (kComp ? qcap : 0x3fffffff);
+      const int rcap = kStageMasses ? 64 * (((qcap >> 6) - 1) | 1) : ((kComp || BEST) ? qcap : 0x3fffffff);
       T* const pout = want_pairs ? A.pair_m + q0 : nullptr;
       for (int r0 = 0; r0 < nq; r0 += rcap) {
         const int qn = min(rcap, nq - r0);
@@ -828,6 +900,10 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
           int cn = c + 1;
           int on = W.eo[cn], nn = W.en[cn];  // the next event with pairs (or the sentinel)
           double kacc = 0.0;
+          int rk = k - W.ep[c];  // in-event rank of pair k
+          double bdist = 0.0;    // the run's best so far (brk < 0: none)
+          int brk = -1;
+          T bmass = T(0);
           for (; k < kend; ++k) {
             T mk;
             if constexpr (kComp) {
@@ -849,10 +925,20 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
               for (int q = 0; q < 4; ++q) w[q] = a[q] + b[q];
               mk = mass_of(w);
             }
-            if constexpr (kStageMasses)
+            if constexpr (BEST) {
+              // ranks grow along the run, so a tie keeps the earlier pair
+              const double d = fabs((double)mk - A.target);
+              if (d == d && (brk < 0 || d < bdist)) {
+                bdist = d;
+                brk = rk;
+                bmass = mk;
+              }
+              ++rk;
+            } else if constexpr (kStageMasses) {
               W.pm[k - r0] = mk;
-            else if (want_pairs)
+            } else if (want_pairs) {
               pout[k] = mk;
+            }
             // lexicographic successor within the chunk
             bool fin = false;
             if (++j == n) {
@@ -867,10 +953,16 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
               }
               j = i + 1;
             }
-            if constexpr (kComp) {
-              if (fin || k + 1 == kend) {  // leave the partial at the lane's last pair of the event
+            if (fin || k + 1 == kend) {  // leave the run's partials at its last pair of the event
+              if constexpr (kComp) {
                 W.kp[k - r0] = kacc;
                 kacc = 0.0;
+              }
+              if constexpr (BEST) {
+                W.bm[k - r0] = bmass;
+                W.br[k - r0] = brk;
+                brk = -1;
+                rk = 0;
               }
             }
           }
@@ -880,30 +972,44 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
           T* out = A.pair_m + q0 + r0;
           for (int t = lane; t < qn; t += 64) store_out(out, t, W.pm[t]);
         }
-        if constexpr (kComp) {
-          // the event lane adds the partial sums of the lanes that covered
-          // its pairs of this round, in lane order
-          if (want_k && in_chunk && n_e >= 2) {
-            const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
-            const int lo = max(plo_rel, r0) - r0, hi = min(phi_rel, r0 + qn) - r0;
-            if (lo < hi) {
-              for (int seg = lo / m; seg * m < hi; ++seg) ks += W.kp[min((seg + 1) * m, hi) - 1];
+        if ((kComp || BEST) && in_chunk && n_e >= 2) {
+          // the event lane takes the partials of the runs that covered its
+          // pairs of this round, in lane order (in rank order)
+          const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
+          const int lo = max(plo_rel, r0) - r0, hi = min(phi_rel, r0 + qn) - r0;
+          for (int seg = lo / m; seg * m < hi; ++seg) {
+            const int slot = min((seg + 1) * m, hi) - 1;
+            if constexpr (kComp) {
+              if (want_k) ks += W.kp[slot];
+            }
+            if constexpr (BEST) {
+              const int r = W.br[slot];
+              if (r >= 0) {
+                const T bmv = W.bm[slot];
+                const double d = fabs((double)bmv - A.target);
+                if (ebr < 0 || d < ebd) {
+                  ebd = d;
+                  ebr = r;
+                  ebm = bmv;
+                }
+              }
             }
           }
         }
         wave_sync();
       }
     }
+    bool marked = false;  // FP32 compensated: a pair of the event asked for the FP64 redo
     if constexpr (kComp) {
       if (want_k && in_chunk) {
-        const bool marked = kDefer && (ks != ks) && n_e >= 2;  // a pair asked for the FP64 redo
+        marked = kDefer && (ks != ks) && n_e >= 2;
         if (A.event_m) {
           T em = (T)sqrt(msum + 2.0 * ks);
           if constexpr (kDefer) {
             if (marked) em = redo_mark();
           }
           store_out(A.event_m, e0 + lane, em);
-        } else {
+        } else if (!BEST) {
           if constexpr (kDefer) {
             // without event masses the mark goes to the event's first pair
             // mass, after this wavefront's own stores of the chunk's masses
@@ -914,6 +1020,14 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
             }
           }
         }
+      }
+    }
+    if constexpr (BEST) {
+      // without event masses a redo mark goes to the event's best mass
+      if (in_chunk) {
+        const bool mark_here = marked && A.event_m == nullptr;
+        A.best_rank[e0 + lane] = ebr;
+        store_out(A.best_m, e0 + lane, mark_here ? redo_mark() : (ebr >= 0 ? ebm : (T)__builtin_nan("")));
       }
     }
     wave_sync();
@@ -956,6 +1070,8 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORD
         if (!big && n >= 2) {
           if (A.event_m)
             redo = is_redo_mark(A.event_m[e]);
+          else if (A.best_m)
+            redo = is_redo_mark(A.best_m[e]);
           else if (A.pair_m)
             redo = is_redo_mark(A.pair_m[A.poff[e]]);
         }
@@ -1369,9 +1485,12 @@ int grid_for(int64_t ne, int epb) {
 
 template <typename T, int COORDS, int MODE>
 hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
-                     void* const total[4], void* em, void* pm, unsigned long long* fb, const Tiling& t,
-                     size_t lds, hipStream_t s) {
+                     void* const total[4], void* em, void* pm, const BestOut* best, unsigned long long* fb,
+                     const Tiling& t, size_t lds, hipStream_t s) {
   FwdArgs<T, COORDS, MODE> A;
+  A.best_rank = best ? best->rank : nullptr;
+  A.best_m = best ? (T*)best->mass : nullptr;
+  A.target = best ? best->target : 0.0;
   for (int k = 0; k < 4; ++k) {
     A.p.c[k] = (const T*)p[k];
     A.total[k] = total ? (T*)total[k] : nullptr;
@@ -1385,10 +1504,17 @@ hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.epb = t.events_per_tile;
   A.cap = t.lds_particles;
   A.qcap = t.pairs_per_round;
-  A.wave_bytes = (int)wave_lds_bytes<T, MODE>(t.lds_particles, t.pairs_per_round, t.events_per_tile);
   const int waves = t.block / 64;
   const int64_t tiles = (ne + t.events_per_tile - 1) / t.events_per_tile;
-  hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE>), dim3(grid_for(tiles, waves)), dim3(t.block), lds, s, A);
+  if (best) {
+    A.wave_bytes = (int)wave_lds_bytes<T, MODE, true>(t.lds_particles, t.pairs_per_round, t.events_per_tile);
+    hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE, true>), dim3(grid_for(tiles, waves)), dim3(t.block), lds, s,
+                       A);
+  } else {
+    A.wave_bytes = (int)wave_lds_bytes<T, MODE, false>(t.lds_particles, t.pairs_per_round, t.events_per_tile);
+    hipLaunchKernelGGL((k_event_reduce<T, COORDS, MODE, false>), dim3(grid_for(tiles, waves)), dim3(t.block), lds, s,
+                       A);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_event_reduce_big<T, COORDS, MODE>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
@@ -1425,19 +1551,19 @@ hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
 
 template <typename T>
 hipError_t fwd_dt(glv_coords co, glv_mode mode, int64_t ne, const int64_t* off, const int64_t* poff,
-                  const void* const p[4], void* const total[4], void* em, void* pm, unsigned long long* fb,
-                  const Tiling& t, size_t lds, hipStream_t s) {
+                  const void* const p[4], void* const total[4], void* em, void* pm, const BestOut* b,
+                  unsigned long long* fb, const Tiling& t, size_t lds, hipStream_t s) {
   if (mode == GLV_COMPENSATED)
-    return fwd_typed<T, GLV_PTETAPHIM, GLV_COMPENSATED>(ne, off, poff, p, total, em, pm, fb, t, lds, s);
+    return fwd_typed<T, GLV_PTETAPHIM, GLV_COMPENSATED>(ne, off, poff, p, total, em, pm, b, fb, t, lds, s);
   switch (co) {
     case GLV_PXPYPZE:
-      return fwd_typed<T, GLV_PXPYPZE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+      return fwd_typed<T, GLV_PXPYPZE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, b, nullptr, t, lds, s);
     case GLV_PTETAPHIM:
-      return fwd_typed<T, GLV_PTETAPHIM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+      return fwd_typed<T, GLV_PTETAPHIM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, b, nullptr, t, lds, s);
     case GLV_PXPYPZM:
-      return fwd_typed<T, GLV_PXPYPZM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+      return fwd_typed<T, GLV_PXPYPZM, GLV_PLAIN>(ne, off, poff, p, total, em, pm, b, nullptr, t, lds, s);
     default:
-      return fwd_typed<T, GLV_PTETAPHIE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
+      return fwd_typed<T, GLV_PTETAPHIE, GLV_PLAIN>(ne, off, poff, p, total, em, pm, b, nullptr, t, lds, s);
   }
 }
 
@@ -1457,19 +1583,22 @@ hipError_t bwd_dt(glv_coords co, int64_t ne, const int64_t* off, const int64_t* 
   }
 }
 
+template <bool BEST>
+size_t fwd_wave_bytes(glv_dtype dt, glv_mode mode, int cap, int qcap, int epb) {
+  if (dt == GLV_F64)
+    return mode == GLV_COMPENSATED ? wave_lds_bytes<double, GLV_COMPENSATED, BEST>(cap, qcap, epb)
+                                   : wave_lds_bytes<double, GLV_PLAIN, BEST>(cap, qcap, epb);
+  return mode == GLV_COMPENSATED ? wave_lds_bytes<float, GLV_COMPENSATED, BEST>(cap, qcap, epb)
+                                 : wave_lds_bytes<float, GLV_PLAIN, BEST>(cap, qcap, epb);
+}
+
 }  // namespace
 
-size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t) {
+size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t, bool best) {
   const size_t waves = (size_t)t.block / 64;
   const int cap = t.lds_particles, qcap = t.pairs_per_round, epb = t.events_per_tile;
-  size_t per;
-  if (dt == GLV_F64)
-    per = mode == GLV_COMPENSATED ? wave_lds_bytes<double, GLV_COMPENSATED>(cap, qcap, epb)
-                                  : wave_lds_bytes<double, GLV_PLAIN>(cap, qcap, epb);
-  else
-    per = mode == GLV_COMPENSATED ? wave_lds_bytes<float, GLV_COMPENSATED>(cap, qcap, epb)
-                                  : wave_lds_bytes<float, GLV_PLAIN>(cap, qcap, epb);
-  return waves * per;
+  return waves * (best ? fwd_wave_bytes<true>(dt, mode, cap, qcap, epb)
+                       : fwd_wave_bytes<false>(dt, mode, cap, qcap, epb));
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
@@ -1500,10 +1629,11 @@ hipError_t launch_validate_offsets(int64_t ne, const int64_t* off, int64_t np, l
 
 hipError_t launch_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64_t ne, const int64_t* off,
                                const int64_t* poff, const void* const p[4], void* const total[4], void* em,
-                               void* pm, unsigned long long* fb, const Tiling& t, hipStream_t s) {
-  size_t lds = event_reduce_lds_bytes(dt, mode, t);
-  if (dt == GLV_F64) return fwd_dt<double>(co, mode, ne, off, poff, p, total, em, pm, nullptr, t, lds, s);
-  return fwd_dt<float>(co, mode, ne, off, poff, p, total, em, pm, fb, t, lds, s);
+                               void* pm, unsigned long long* fb, const Tiling& t, hipStream_t s,
+                               const BestOut* best) {
+  size_t lds = event_reduce_lds_bytes(dt, mode, t, best != nullptr);
+  if (dt == GLV_F64) return fwd_dt<double>(co, mode, ne, off, poff, p, total, em, pm, best, nullptr, t, lds, s);
+  return fwd_dt<float>(co, mode, ne, off, poff, p, total, em, pm, best, fb, t, lds, s);
 }
 
 hipError_t launch_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,

@@ -309,6 +309,51 @@ def glv_event_best_pair(pair_offsets, pair_m, target):
     return rank, bm
 
 
+def glv_invariant_mass_histogram(a, b, lo, hi, n_bins, coords="PtEtaPhiM", mode="plain", counts=None,
+                                 fallback_count=None):
+    """The pair masses of glv_invariant_mass(a, b, coords, mode) counted into
+    n_bins equal bins of [lo, hi) plus under- and overflow (n_bins + 2 int64)
+    without being stored; ``counts``, if given, is added to."""
+    dev, dt = a[0].device, a[0].dtype
+    _check_device(a[0])
+    n = a[0].numel()
+    a = _cols(a, n, dt, dev, "a")
+    b = _cols(b, n, dt, dev, "b")
+    if counts is None:
+        counts = torch.zeros(int(n_bins) + 2, dtype=torch.int64, device=dev)
+    elif counts.dtype != torch.int64 or counts.numel() != int(n_bins) + 2 or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous int64 tensor of n_bins + 2 elements")
+    check("glv_invariant_mass_histogram",
+          _lib.load().glv_invariant_mass_histogram(_dtype_code(dt), _coords_code(coords), _mode_code(mode), n,
+                                                   P4(*[t.data_ptr() for t in a]), P4(*[t.data_ptr() for t in b]),
+                                                   float(lo), float(hi), int(n_bins), _ptr(counts),
+                                                   _ptr(fallback_count), _stream(dev)))
+    return counts
+
+
+def glv_event_reduce_best_pair(p, offsets, target, pair_offsets=None, coords="PtEtaPhiM", mode="plain", tiling=None,
+                               fallback_count=None):
+    """(rank, mass) per event of its pair closest to ``target``, chosen inside
+    the jagged reduction without writing pair masses (rank -1 and NaN for an
+    event without one)."""
+    dev, dt = p[0].device, p[0].dtype
+    _check_device(p[0])
+    offsets = _offsets(offsets, dev)
+    ne = offsets.numel() - 1
+    p = _cols(p, p[0].numel(), dt, dev, "p")
+    if pair_offsets is None:
+        pair_offsets = glv_pair_offsets(offsets)
+    pair_offsets = _offsets(pair_offsets, dev)
+    rank = torch.empty(ne, dtype=torch.int64, device=dev)
+    bm = torch.empty(ne, dtype=dt, device=dev)
+    check("glv_event_reduce_best_pair",
+          _lib.load().glv_event_reduce_best_pair(_dtype_code(dt), _coords_code(coords), _mode_code(mode), ne,
+                                                 _ptr(offsets), _ptr(pair_offsets), P4(*[t.data_ptr() for t in p]),
+                                                 float(target), _ptr(rank), _ptr(bm), _ptr(fallback_count),
+                                                 _tiling(tiling), _stream(dev)))
+    return rank, bm
+
+
 def _offsets(offsets, dev):
     if offsets.dtype != torch.int64 or offsets.device != dev or not offsets.is_contiguous() or offsets.dim() != 1:
         raise ValueError("offsets must be a contiguous 1-D int64 tensor on the particles' device")

@@ -189,6 +189,43 @@ def test_analysis_validation(lib):
     assert b(2, 0, None, None, 91.0, None, None, None) == OK
 
 
+def test_fused_analysis_validation(lib):
+    """The fused entry points reject what their unfused halves reject."""
+    C, R, BM = 40 * GiB, 60 * GiB, 70 * GiB
+    h = lib.glv_invariant_mass_histogram
+    a, b = cols(A), cols(B)
+    assert h(7, 1, 0, N, a, b, 0.0, 1.0, 10, C, None, None) == DTYPE
+    assert h(2, 9, 0, N, a, b, 0.0, 1.0, 10, C, None, None) == COORDS
+    assert h(2, 0, 1, N, a, b, 0.0, 1.0, 10, C, None, None) == MODE        # compensated needs PtEtaPhiM
+    assert h(2, 1, 0, -1, a, b, 0.0, 1.0, 10, C, None, None) == SIZE
+    assert h(2, 1, 0, N, a, b, 0.0, 1.0, 0, C, None, None) == SIZE          # no bins
+    assert h(2, 1, 0, N, a, b, 1.0, 0.0, 10, C, None, None) == SIZE         # reversed range
+    assert h(2, 1, 0, N, a, b, 0.0, float("inf"), 10, C, None, None) == SIZE
+    assert h(2, 1, 0, N, None, b, 0.0, 1.0, 10, C, None, None) == NULL
+    assert h(2, 1, 0, N, a, b, 0.0, 1.0, 10, None, None, None) == NULL
+    assert h(2, 1, 0, N, a, b, 0.0, 1.0, 10, B + 8 * (N - 1), None, None) == ALIAS  # counts over leg b's column 0
+    assert h(2, 1, 1, N, a, b, 0.0, 1.0, 10, C, A, None) == ALIAS          # fallback counter over a leg
+    assert h(2, 1, 1, N, a, b, 0.0, 1.0, 10, C, C + 16, None) == ALIAS     # fallback counter inside counts
+    assert h(2, 1, 0, 0, None, None, 0.0, 1.0, 10, None, None, None) == OK  # empty
+    OFF, PO, P = 80 * GiB, 90 * GiB, 100 * GiB
+    f = lib.glv_event_reduce_best_pair
+    assert f(7, 1, 0, 10, OFF, PO, cols(P), 91.0, R, BM, None, None, None) == DTYPE
+    assert f(2, 0, 1, 10, OFF, PO, cols(P), 91.0, R, BM, None, None, None) == MODE
+    assert f(2, 1, 0, -3, OFF, PO, cols(P), 91.0, R, BM, None, None, None) == SIZE
+    assert f(2, 1, 0, 10, None, PO, cols(P), 91.0, R, BM, None, None, None) == OFFSETS
+    assert f(2, 1, 0, 10, OFF, None, cols(P), 91.0, R, BM, None, None, None) == OFFSETS   # pair offsets required
+    assert f(2, 1, 0, 10, OFF, PO, None, 91.0, R, BM, None, None, None) == NULL
+    assert f(2, 1, 0, 10, OFF, PO, cols(P), 91.0, None, BM, None, None, None) == NULL
+    assert f(2, 1, 0, 10, OFF, PO, cols(P), 91.0, R, R + 8, None, None, None) == ALIAS    # outputs overlap
+    assert f(2, 1, 0, 10, OFF, PO, cols(P), 91.0, PO + 8, BM, None, None, None) == ALIAS  # rank over pair offsets
+    assert f(2, 1, 0, 10, OFF, PO, cols(P), 91.0, R, P, None, None, None) == ALIAS        # mass over a column
+    assert f(2, 1, 1, 10, OFF, PO, cols(P), 91.0, R, BM, R + 8, None, None) == ALIAS      # counter inside rank
+    for bad in ((100, 0, 0, 0), (256, 65, 128, 512), (256, 32, 128, 100), (512, 64, 4096, 4096)):
+        t = _lib.glv_tiling(*bad)
+        assert f(2, 1, 0, 10, OFF, PO, cols(P), 91.0, R, BM, None, ctypes.byref(t), None) == TILING, bad
+    assert f(2, 1, 0, 0, None, None, None, 91.0, None, None, None, None, None) == OK
+
+
 def test_jagged_validation(lib):
     OFF, PO, P, T, EM, PM = A, B, 100 * GiB, 140 * GiB, 180 * GiB, 190 * GiB
     f = lib.glv_event_reduce
