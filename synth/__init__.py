@@ -23,6 +23,9 @@ of varying size, Sec. 5.1-5.2):
   offsets ~ U(-1e-3, 1e-3), eta clipped to [-4, 4], phi wrapped to [-pi, pi)).
 * ``jagged_events``  -- multiplicity ~ Poisson(8) clipped to [0, 64], CSR
   offsets (int64), particles drawn as ``pairs_generic`` legs.
+* ``leg_generic_device`` -- the ``pairs_generic`` leg distribution drawn
+  straight into GPU memory by torch's generator (for inputs of billions of
+  items, too large to draw on the host and copy); seeded like ``rng``.
 """
 
 import numpy as np
@@ -124,3 +127,30 @@ def jagged_events(g: np.random.Generator, n_events: int, mean: float = 8.0, cap:
 def as_dtype(cols, dtype):
     """Cast a tuple of columns to ``dtype`` (contiguous copies)."""
     return tuple(np.ascontiguousarray(c, dtype=dtype) for c in cols)
+
+
+def leg_generic_device(k: int, n: int, device, dtype):
+    """One PtEtaPhiM leg of ``n`` items drawn on ``device`` (a torch device)
+    with a torch generator seeded with ``SEED_BASE + k``: pt = 5 + Exp(scale
+    30) GeV, eta ~ U[-2.5, 2.5], phi ~ U[-pi, pi), M ~ U[0, 0.2] GeV, in that
+    order, each column drawn in ``dtype``.  Successive calls with one ``k``
+    give the same columns."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(SEED_BASE + int(k))
+    pt = torch.empty(n, dtype=dtype, device=device).exponential_(1.0 / 30.0, generator=g).add_(5.0)
+    eta = torch.empty(n, dtype=dtype, device=device).uniform_(-2.5, 2.5, generator=g)
+    phi = torch.empty(n, dtype=dtype, device=device).uniform_(-np.pi, np.pi, generator=g)
+    m = torch.empty(n, dtype=dtype, device=device).uniform_(0.0, 0.2, generator=g)
+    return pt, eta, phi, m
+
+
+def normal_device(k: int, n: int, device, dtype):
+    """``n`` N(0, 1) upstream gradients drawn on ``device`` with a torch
+    generator seeded with ``SEED_BASE + k``."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(SEED_BASE + int(k))
+    return torch.empty(n, dtype=dtype, device=device).normal_(generator=g)

@@ -53,16 +53,15 @@ def test_boost_broadcast_in_place_and_identity(dtype):
         assert np.array_equal(y0[k], np.asarray(x[k], dtype=_np(dtype)))
 
 
-def test_boost_full_size_sampled():
+def test_boost_full_size():
+    """2^24 per-item boosts in the benchmark's launch shape, every item."""
     n = 1 << 24
     x, beta = synth.boost_items(synth.rng(synth.LARGE), n)
     y = host(glv.glv_boost(gpu(x, torch.float64), gpu(beta, torch.float64)))
-    idx = np.sort(np.random.default_rng(9).choice(n, 65536, replace=False))
-    xs, bs = tuple(c[idx] for c in x), tuple(c[idx] for c in beta)
-    y_or, s = oracle.boost(xs, bs), oracle.boost_scale(xs, bs)
+    y_or, s = oracle.boost(x, beta), oracle.boost_scale(x, beta)
     for k in range(4):
-        r, _ = worst(np.abs(y[k][idx] - y_or[k]), boost_tol(s[k], np.float64))
-        assert r <= 1.0
+        r, i = worst(np.abs(y[k] - y_or[k]), boost_tol(s[k], np.float64))
+        assert r <= 1.0, (k, i)
 
 
 # -------------------------------------------------------------- mass bwd
@@ -106,20 +105,19 @@ def test_mass_bwd_against_oracle(coords, dtype):
     assert r <= 1.0, (i, [c[i] for c in g_gpu], [c[i] for c in g_or])
 
 
-def test_mass_bwd_full_size_sampled():
+def test_mass_bwd_full_size():
+    """The pair mass's reverse mode on 2^24 items, every item."""
     n = 1 << 24
     g = synth.rng(synth.GRADS)
     a, b = synth.pairs_generic(g, n)
     gm = g.standard_normal(n)
     ga, gb = glv.glv_invariant_mass_bwd(gpu(a, torch.float64), gpu(b, torch.float64), gpu([gm], torch.float64)[0])
-    ga, gb = host(ga), host(gb)
-    idx = np.sort(np.random.default_rng(10).choice(n, 65536, replace=False))
-    sa, sb = tuple(c[idx] for c in a), tuple(c[idx] for c in b)
-    oa, ob = oracle.mass_vjp("PtEtaPhiM", sa, sb, gm[idx])
+    got = np.stack([host(c) for c in list(ga) + list(gb)])
+    oa, ob = oracle.mass_vjp("PtEtaPhiM", a, b, gm)
     g_or = list(oa) + list(ob)
-    err = np.abs(np.stack([c[idx] for c in list(ga) + list(gb)]) - np.stack(g_or))
-    r, _ = worst(err.ravel(), _mass_vjp_tol(sa, sb, "PtEtaPhiM", torch.float64, g_or, gm[idx]).ravel())
-    assert r <= 1.0
+    err = np.abs(got - np.stack(g_or))
+    r, i = worst(err.ravel(), _mass_vjp_tol(a, b, "PtEtaPhiM", torch.float64, g_or, gm).ravel())
+    assert r <= 1.0, (i % n, i // n)
 
 
 # ------------------------------------------------------------- boost bwd
@@ -151,10 +149,9 @@ def test_boost_bwd_against_oracle(dtype):
         assert r <= 1.0, ("gbeta", k, i)
 
 
-def test_boost_bwd_full_size_sampled():
+def test_boost_bwd_full_size():
     """The boost's reverse mode on 2^24 items with the benchmark's upstreams
-    (the same draws, in the same order) and launch shape; 65,536 sampled items
-    against the oracle."""
+    (the same draws, in the same order) and launch shape, every item."""
     n = 1 << 24
     x, beta = synth.boost_items(synth.rng(synth.LARGE), n)
     gr = synth.rng(synth.GRADS)
@@ -162,15 +159,13 @@ def test_boost_bwd_full_size_sampled():
     gy = synth.upstream(gr, n, 4)
     gx, gbeta = glv.glv_boost_bwd(gpu(x, torch.float64), gpu(beta, torch.float64), gpu(gy, torch.float64))
     gx, gbeta = host(gx), host(gbeta)
-    idx = np.sort(np.random.default_rng(10).choice(n, 65536, replace=False))
-    xs, bs, gs = (tuple(c[idx] for c in cols) for cols in (x, beta, gy))
-    ox, ob = oracle.boost_vjp(xs, bs, gs)
-    sx, sb = _boost_vjp_scale(xs, bs, gs)
+    ox, ob = oracle.boost_vjp(x, beta, gy)
+    sx, sb = _boost_vjp_scale(x, beta, gy)
     for k in range(4):
-        r, i = worst(np.abs(gx[k][idx] - ox[k]), 1e-12 * sx[k])
+        r, i = worst(np.abs(gx[k] - ox[k]), 1e-12 * sx[k])
         assert r <= 1.0, ("gx", k, i)
     for k in range(3):
-        r, i = worst(np.abs(gbeta[k][idx] - ob[k]), 1e-12 * sb[k])
+        r, i = worst(np.abs(gbeta[k] - ob[k]), 1e-12 * sb[k])
         assert r <= 1.0, ("gbeta", k, i)
 
 
