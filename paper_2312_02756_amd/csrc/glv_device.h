@@ -125,6 +125,10 @@ __device__ __forceinline__ double d_sqrt(double x) {
 }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_abs(double x) { return fabs(x); }
+// a * b + c with one rounding, either precision: written out where a sum of
+// products must fuse the same way in every kernel that evaluates it.
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ float d_abs(float x) { return fabsf(x); }
 
 // ------------------------------------------------------------ conversion
@@ -487,6 +491,7 @@ struct LegC {
 // reciprocal in FP32).
 template <typename T, bool kCold = false>
 __device__ __forceinline__ void leg_shift(T pt, T mm, T sh, T pc, T e, T* mt, T* delta, T* dmt) {
+#pragma clang fp contract(off)
   if constexpr (sizeof(T) == 8)
     *mt = sqrt_budgeted(fma(pt, pt, mm));
   else
@@ -533,7 +538,7 @@ __device__ __forceinline__ LegC<T> comp_leg(T pt, T eta, T phi, T mass) {
   else
     fast_sinhcosh_rcp(eta, &sh, &ch);
   T pc = pt * ch;
-  T e = sqrt_budgeted(pc * pc + mm);
+  T e = sqrt_budgeted(fma_t(pc, pc, mm));
   leg_shift<T, kCold>(pt, mm, sh, pc, e, &L.mt, &L.delta, &L.dmt);
   return L;
 }
@@ -571,6 +576,9 @@ __device__ __forceinline__ T sin2_half(T d) {
 // taken at most as 4 mTa mTb |s1| (1 + |s1|).  A NaN bound asks for the redo.
 template <typename T, bool kCold = false>
 __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T* k, bool* redo) {
+  // no implicit contraction: every kernel (packed or not, staged or not)
+  // rounds these terms alike; the one fused product is written out
+#pragma clang fp contract(off)
   T d1 = a.eta - b.eta;
   T d2 = a.delta - b.delta;
   T dy = d1 + d2;
@@ -579,17 +587,18 @@ __device__ __forceinline__ T comp_pair_m2(const LegC<T>& a, const LegC<T>& b, T*
     s1 = fast_sinh<kCold>(T(0.5) * dy);
   else
     s1 = fast_sinh(T(0.5) * dy);
-  T t1 = T(2) * a.mt * b.mt * (s1 * s1);
-  T t2 = T(2) * a.pt * b.pt * sin2_half<T, kCold>(dphi_reduced(a.phi, b.phi));
+  const T mm = a.mt * b.mt;
+  T t1 = (T(2) * mm) * (s1 * s1);
+  T t2 = (T(2) * (a.pt * b.pt)) * sin2_half<T, kCold>(dphi_reduced(a.phi, b.phi));
   // mTa mTb - pta ptb = (mTa - pta) mTb + pta (mTb - ptb): two terms >= 0
-  T t3 = a.dmt * b.mt + a.pt * b.dmt;
-  T kk = t1 + t2 + t3;
-  T m2 = a.m2 + b.m2 + T(2) * kk;
+  T t3 = fma_t(a.dmt, b.mt, a.pt * b.dmt);
+  T kk = (t1 + t2) + t3;
+  T m2 = (a.m2 + b.m2) + T(2) * kk;
   *k = kk;
   if (redo) {
-    T edy = (d_abs(d1) + d_abs(d2) + d_abs(dy)) + T(kDeltaUnits) * (d_abs(a.delta) + d_abs(b.delta));
+    T edy = ((d_abs(d1) + d_abs(d2)) + d_abs(dy)) + T(kDeltaUnits) * (d_abs(a.delta) + d_abs(b.delta));
     const T as1 = d_abs(s1);
-    T sens = T(4) * a.mt * b.mt * (as1 * (T(1) + as1));  // >= 2 * d(t1)/d(dy)
+    T sens = (T(4) * mm) * (as1 * (T(1) + as1));  // >= 2 * d(t1)/d(dy)
     // bound = sens edy / m2 + kFactorUnits > kFallbackUnits, for m2 > 0
     *redo = (m2 > T(0)) && !(sens * edy <= T(kFallbackUnits - kFactorUnits) * m2);
   }
@@ -619,7 +628,7 @@ __device__ __forceinline__ LegCJ<T> comp_leg_j(T pt, T eta, T phi, T mass) {
   else
     fast_sinhcosh_rcp(eta, &L.sh, &L.ch);
   const T pc = pt * L.ch;
-  L.e = sqrt_budgeted(pc * pc + mm);
+  L.e = sqrt_budgeted(fma_t(pc, pc, mm));
   leg_shift<T, false>(pt, mm, L.sh, pc, L.e, &L.c.mt, &L.c.delta, &L.c.dmt);
   return L;
 }
@@ -641,12 +650,13 @@ __device__ __forceinline__ LegCJ<T> comp_leg_j(T pt, T eta, T phi, T mass) {
 template <typename T>
 __device__ __forceinline__ void comp_leg_rows(const LegCJ<T>& a, const LegCJ<T>& b, T sh2, T chdy, T shdy, T cf1,
                                               T sdphi, T g[4]) {
-  const T imt = (a.c.mt > T(0)) ? T(1) / a.c.mt : T(0);
-  const T ie = (a.e > T(0)) ? T(1) / a.e : T(0);
+#pragma clang fp contract(off)
+  const T imt = (a.c.mt > T(0)) ? div_budgeted(T(1), a.c.mt) : T(0);
+  const T ie = (a.e > T(0)) ? div_budgeted(T(1), a.e) : T(0);
   const T pp = a.c.mt * b.c.mt;
   const T w = pp * shdy * ie * imt * imt;  // mTa mTb sinh(dy) / (mTa^2 Ea)
   const T sden = (a.c.pt * b.c.mt + b.c.pt * a.c.mt) * a.c.mt;
-  const T diff = (sden > T(0)) ? (a.c.pt * a.c.pt * b.c.m2 - b.c.pt * b.c.pt * a.c.m2) / sden : T(0);
+  const T diff = (sden > T(0)) ? div_budgeted(a.c.pt * a.c.pt * b.c.m2 - b.c.pt * b.c.pt * a.c.m2, sden) : T(0);
   g[0] = a.c.pt * b.c.mt * imt * sh2 + b.c.pt * cf1 + diff + w * a.sh * a.c.m2;
   g[1] = pp * shdy * a.c.pt * a.ch * ie;
   g[2] = a.c.pt * b.c.pt * sdphi;
@@ -656,13 +666,14 @@ __device__ __forceinline__ void comp_leg_rows(const LegCJ<T>& a, const LegCJ<T>&
 // Both legs' gradients of the cancellation-free pair mass times gm.
 template <typename T>
 __device__ __forceinline__ void comp_pair_vjp(const LegCJ<T>& a, const LegCJ<T>& b, T gm, T ga[4], T gb[4]) {
+#pragma clang fp contract(off)
   const T dy = (a.c.eta - b.c.eta) + (a.c.delta - b.c.delta);
   T s1;
   if constexpr (sizeof(T) == 8)
     s1 = fast_sinh<false>(T(0.5) * dy);
   else
     s1 = fast_sinh(T(0.5) * dy);
-  const T c1 = d_sqrt(T(1) + s1 * s1);
+  const T c1 = sqrt_budgeted(T(1) + s1 * s1);
   const T sh2 = T(2) * s1 * s1;  // cosh(dy) - 1
   const T shdy = T(2) * s1 * c1;
   const T chdy = T(1) + sh2;
@@ -677,8 +688,10 @@ __device__ __forceinline__ void comp_pair_vjp(const LegCJ<T>& a, const LegCJ<T>&
     fast_sincos(h, &hs, &hc);
   const T cf1 = T(2) * hs * hs;  // 1 - cos(dphi)
   const T sdphi = T(2) * hs * hc;
-  T k;
-  const T m2 = comp_pair_m2<T>(a.c, b.c, &k, nullptr);
+  // m^2 of the forward form from the same pieces: t1 = mTa mTb (cosh dy - 1),
+  // t2 = pta ptb (1 - cos dphi), t3 = (mTa - pta) mTb + pta (mTb - ptb)
+  const T t3 = fma_t(a.c.dmt, b.c.mt, a.c.pt * b.c.dmt);
+  const T m2 = (a.c.m2 + b.c.m2) + T(2) * (((a.c.mt * b.c.mt) * sh2 + (a.c.pt * b.c.pt) * cf1) + t3);
   const T s = (m2 > T(0)) ? gm * inv_sqrt(m2) : T(0);
   T ra[4], rb[4];
   comp_leg_rows<T>(a, b, sh2, chdy, shdy, cf1, sdphi, ra);

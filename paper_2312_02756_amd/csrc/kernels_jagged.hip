@@ -1174,276 +1174,238 @@ __device__ __forceinline__ bool bwd_big(int64_t n, int cap, int qcap, bool pairs
   return n > cap || (pairs && npairs(n) > (int64_t)qcap);
 }
 
-template <int COORDS>
-constexpr bool polar_coords() {
-  return COORDS == GLV_PTETAPHIM || COORDS == GLV_PTETAPHIE;
-}
-
-// LDS of one wavefront of the backward (cap particles, qcap pairs, epb events):
-//   cart[cap]   (px, py, pz, E) of the staged particles
-//   jac[cap]    (cos phi, sin phi, sinh eta, cosh eta)     pt/eta/phi systems
-//   raw[cap]    (first, last coordinate): pt or px, and M or E
-//   ut[epb]     per chunk event: g_total + g_m dm(V)/dV
-//   gq[qcap+2]  the chunk's pair upstreams, then c = g/|m| in place (two
-//               slots of slack, read and discarded by the partner walk)
-//   pev[cap]    chunk-relative event of each staged particle
-//   ceo, cen, cep [epb]  per chunk event: first particle, size, first pair
-//   eo, en, ep [epb+1]   the chunk's events with pairs (compacted) + sentinel
-template <typename T>
-__host__ __device__ __forceinline__ size_t wave_lds_bytes_bwd(int cap, int qcap, int epb) {
-  size_t b = (size_t)cap * 10 * sizeof(T) + (size_t)epb * 4 * sizeof(T) + (size_t)(qcap + 2) * sizeof(T);
-  b += (size_t)cap * sizeof(int) + 3 * (size_t)epb * sizeof(int) + 3 * (size_t)(epb + 1) * sizeof(int);
-  return (b + 31) & ~(size_t)31;
-}
-
-// The backward.  Like the forward, every wavefront works alone on a tile of
-// epb consecutive events, in chunks of consecutive events holding at most
-// cap particles and (with pair upstreams) qcap pairs:
-//   1. stage: the chunk's particles are loaded coalesced and converted once
-//      with their Jacobian pieces (all kept in LDS), the chunk's pair
-//      upstreams -- contiguous in grad_pair -- copied to LDS;
-//   2. the lane of each event sums its particles' vectors V in CSR order and
-//      stages g_total + g_m dm(V)/dV, the upstream every particle of the
-//      event receives from the event outputs;
-//   3. pair phase: lane L takes the contiguous pairs [L m, (L + 1) m) of the
-//      chunk (as the forward does) and turns each upstream g into
-//      c = g / |m| in place, computed once per pair (dm(w)/dw = (-P, E)/|m|
-//      is the same for both legs);
-//   4. particle phase: particle t of the chunk (lane t mod 64) walks its
-//      event's particles in CSR order, stepping the lexicographic pair index
-//      incrementally, sums C = sum c_ab and S = sum c_ab v_b, forms
-//      (-1, -1, -1, 1) (C v_a + S) plus the event upstream and applies its
-//      own conversion Jacobian; gradients are stored coalesced.
+// LDS-staged backward.  A workgroup takes tiles of epb consecutive events and
+// walks each in chunks of consecutive events with at most cap particles (one
+// per thread: cap <= block) and, when pair upstreams are given, at most qcap
+// pairs:
+//   * thread t converts particle t of the chunk once, keeps its Cartesian
+//     vector and Jacobian pieces (cos phi, sin phi, sinh eta, cosh eta) in
+//     registers and stages the vector in LDS for its partners; the chunk's
+//     pair upstreams -- contiguous in grad_pair -- are copied to LDS, four
+//     loads in flight per thread; one lane per event records its particles'
+//     event;
+//   * pair phase: each pair's upstream g_ij becomes c_ij = g_ij / |m_ij| in
+//     place, computed once, by one of its two legs: particle a of an event of
+//     n takes the partners a + 1, ..., a + d cyclically, d = (n - 1) / 2
+//     rounded down, plus a + n/2 when n is even and a < n/2 -- every pair
+//     once, about n/2 per particle, whatever the particle's place;
+//   * in the same phase one lane per event (spread over the wavefronts; its
+//     g_total and g_m were loaded with the chunk) sums the event's vectors V
+//     in CSR order and stages g_total + g_m dm(V)/dV, the upstream every
+//     particle of the event receives from the event outputs;
+//   * thread t then walks its event's particles in CSR order and adds the
+//     pair terms c_ij (v_i + v_j) = c_ij v_i + c_ij v_j of its partners
+//     (dm(w)/dw = (-P, E) / |m|, the same 4-vector for both legs of a pair),
+//     stepping the pair indices incrementally, then the event's upstream, and
+//     applies its own conversion Jacobian.
 // Every sum has a fixed order and no atomics are needed.
 template <typename T, int COORDS>
 __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   using R4 = typename V4<T>::type;
-  using R2 = typename V2<T>::type;
   // event totals of FP32 data are summed in FP64
   using Acc = typename std::conditional<sizeof(T) == 4, double, T>::type;
-  constexpr bool kPolar = polar_coords<COORDS>();
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int nwaves = blockDim.x >> 6;
-  const int epb = A.epb, cap = A.cap, qcap = A.qcap;
-  unsigned char* wl = lds + (size_t)wid * A.wave_bytes;
-  R4* cart = reinterpret_cast<R4*>(wl);
-  R4* jac = cart + cap;
-  R2* raw = reinterpret_cast<R2*>(jac + cap);
-  R4* ut = reinterpret_cast<R4*>(raw + cap);
-  T* gq = reinterpret_cast<T*>(ut + epb);
-  int* pev = reinterpret_cast<int*>(gq + qcap + 2);
-  int* ceo = pev + cap;
-  int* cen = ceo + epb;
-  int* cep = cen + epb;
-  int* eo = cep + epb;
-  int* en = eo + (epb + 1);
-  int* ep = en + (epb + 1);
-
-  const int64_t e0 = ((int64_t)blockIdx.x * nwaves + wid) * epb;
-  if (e0 >= A.ne) return;  // the whole wavefront: no workgroup barrier follows
-  const int nev = (int)min((int64_t)epb, A.ne - e0);
+  const int epb = A.epb, cap = A.cap;  // cap <= blockDim.x
   const bool pairs = A.gpair != nullptr;
   const bool want_v = A.gem != nullptr;
-  const bool want_t = A.gt[0] != nullptr;
-  const bool want_u = want_v || want_t;
+  const int qcap = pairs ? A.qcap : 0;
+  const int tid = (int)threadIdx.x;
+  const bool want_u = want_v || A.gt[0] != nullptr;
+  // LDS: cart[cap], s_ut[epb] (R4), s_g[qcap + 2] (T; qcap is even, one
+  //      slot of slack), s_gm[epb rounded up to even] (T), s_off[epb+1],
+  //      s_poff[epb+1] (int64), ch[epb+1] (EvRec), ev_of[cap] (uint16)
+  R4* cart = reinterpret_cast<R4*>(lds);
+  R4* s_ut = cart + cap;
+  T* s_g = reinterpret_cast<T*>(s_ut + epb);
+  T* s_gm = s_g + A.qcap + 2;
+  int64_t* s_off = reinterpret_cast<int64_t*>(s_gm + ((epb + 1) & ~1));
+  int64_t* s_poff = s_off + (epb + 1);
+  EvRec* ch = reinterpret_cast<EvRec*>(s_poff + (epb + 1));
+  unsigned short* ev_of = reinterpret_cast<unsigned short*>(ch + (epb + 1));
+  // event lanes: event t of a chunk belongs to thread (t % nw) * 64 + t / nw,
+  // spread over the workgroup's nw wavefronts (the block is a power of two
+  // >= 64 and a chunk has at most epb <= block events); tev is the inverse
+  const int nw = (int)blockDim.x >> 6;
+  const int tev = (tid & 63) * nw + (tid >> 6);
+  const int64_t ntiles = (A.ne + epb - 1) / epb;
 
-  // this lane's event of the tile and its upstreams
-  const bool mine = lane < nev;
-  int64_t olo = 0, ohi = 0, plo = 0, phi = 0;
-  T gtv[4] = {0, 0, 0, 0}, gmv = 0;
-  if (mine) {
-    olo = A.off[e0 + lane];
-    ohi = A.off[e0 + lane + 1];
-    if (pairs) {
-      plo = A.poff[e0 + lane];
-      phi = A.poff[e0 + lane + 1];
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t e0 = tile * epb;
+    const int nev = (int)min((int64_t)epb, A.ne - e0);
+    for (int i = tid; i <= nev; i += blockDim.x) {
+      s_off[i] = A.off[e0 + i];
+      if (pairs) s_poff[i] = A.poff[e0 + i];
     }
-    if (want_t) {
+    __syncthreads();
+    int ca = 0;
+    while (ca < nev) {
+      if (bwd_big(s_off[ca + 1] - s_off[ca], cap, qcap, pairs)) {  // k_event_reduce_bwd_big's event
+        ++ca;
+        continue;
+      }
+      // largest cb with at most cap particles (and qcap pairs) from ca
+      int cb = search_le(s_off, ca + 1, nev + 1, s_off[ca] + cap);
+      if (pairs) cb = min(cb, search_le(s_poff, ca + 1, nev + 1, s_poff[ca] + qcap));
+      const int nch = cb - ca;
+      const int64_t pbase = s_off[ca];
+      const int64_t q0 = pairs ? s_poff[ca] : 0;
+      const int np = (int)(s_off[cb] - pbase);
+      const int nq = pairs ? (int)(s_poff[cb] - q0) : 0;
+      const bool mine = tid < np;
+      const int64_t gi = pbase + tid;
+      // loads first: own particle, the first pair upstreams
+      T c[4] = {0, 0, 0, 0};
+      if (mine) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) gtv[k] = A.gt[k][e0 + lane];
-    }
-    if (want_v) gmv = A.gem[e0 + lane];
-  }
-  const uint64_t valid = (nev >= 64) ? ~0ull : ((1ull << nev) - 1);
+        for (int k = 0; k < 4; ++k) c[k] = A.p.c[k][gi];
+      }
+      constexpr int kG = 4;  // pair upstreams per thread in flight
+      T gv[kG];
+#pragma unroll
+      for (int r = 0; r < kG; ++r) {
+        const int idx = tid + r * (int)blockDim.x;
+        gv[r] = (idx < nq) ? A.gpair[q0 + idx] : T(0);
+      }
+      // the event lane's upstreams (g_total, g_m), staged with the rest
+      const bool evl = want_u && tev < nch;
+      T gtv[4] = {0, 0, 0, 0}, gmv = 0;
+      if (evl) {
+        const int64_t e = e0 + ca + tev;
+        if (A.gt[0]) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) gtv[k] = A.gt[k][e];
+        }
+        if (want_v) gmv = A.gem[e];
+      }
+      for (int t = tid; t <= nch; t += blockDim.x)
+        ch[t] = EvRec{(int)(s_off[ca + t] - pbase), pairs ? (int)(s_poff[ca + t] - q0) : 0};
+      for (int t = tid; t < nch; t += blockDim.x) {
+        const int lo = (int)(s_off[ca + t] - pbase), hi = (int)(s_off[ca + t + 1] - pbase);
+        for (int i = lo; i < hi; ++i) ev_of[i] = (unsigned short)t;
+      }
+#pragma unroll
+      for (int r = 0; r < kG; ++r) {
+        const int idx = tid + r * (int)blockDim.x;
+        if (idx < nq) s_g[idx] = gv[r];
+      }
+      // upstreams past the first kG per thread (pairs_per_round > kG block)
+      for (int base = kG * (int)blockDim.x; base < nq; base += kG * (int)blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < kG; ++r) {
+          const int idx = base + tid + r * (int)blockDim.x;
+          gv[r] = (idx < nq) ? A.gpair[q0 + idx] : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < kG; ++r) {
+          const int idx = base + tid + r * (int)blockDim.x;
+          if (idx < nq) s_g[idx] = gv[r];
+        }
+      }
+      if (evl) {
+        s_ut[tev] = R4{gtv[0], gtv[1], gtv[2], gtv[3]};
+        s_gm[tev] = gmv;
+      }
+      LegJ<T> L = to_cart_j<COORDS, T, true>(c[0], c[1], c[2], c[3]);
+      if (mine) cart[tid] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
+      __syncthreads();
 
-  int ca = 0;
-  while (ca < nev) {
-    const int64_t base = readlane64(olo, ca);
-    const int64_t q0 = pairs ? readlane64(plo, ca) : 0;
-    const uint64_t ge = valid & (~0ull << ca);
-    const bool fit = mine && (ohi - base <= (int64_t)cap) && (!pairs || phi - q0 <= (int64_t)qcap);
-    const uint64_t fits = __ballot(fit) & ge;
-    const uint64_t stop = ge & ~fits;
-    const int cb = stop ? (int)__builtin_ctzll(stop) : nev;
-    if (cb == ca) {  // k_event_reduce_bwd_big's event
-      ++ca;
-      continue;
-    }
-    const int np = (int)(readlane64(ohi, cb - 1) - base);
-    const int nq = pairs ? (int)(readlane64(phi, cb - 1) - q0) : 0;
-    const bool in_chunk = lane >= ca && lane < cb;
-    const int ce = lane - ca;
-    const int lo_rel = (int)(olo - base), n_e = (int)(ohi - olo);
-    const bool has_pairs = pairs && in_chunk && n_e >= 2;
-    const uint64_t hp = __ballot(has_pairs);
-    const int ncp = __builtin_popcountll(hp);
-    if (in_chunk) {
-      ceo[ce] = lo_rel;
-      cen[ce] = n_e;
-      cep[ce] = (int)(plo - q0);
-    }
-    if (has_pairs) {
-      const int c = __builtin_popcountll(hp & ((1ull << lane) - 1));
-      eo[c] = lo_rel;
-      en[c] = n_e;
-      ep[c] = (int)(plo - q0);
-    }
-    if (pairs && lane == 0) {
-      eo[ncp] = np;
-      en[ncp] = 0;
-      ep[ncp] = nq;
-    }
-
-    // 1. stage: particles with their Jacobian pieces, the pair upstreams
-    for (int t = lane; t < np; t += 64) {
-      const int64_t gi = base + t;
-      const T c0 = A.p.c[0][gi], c1 = A.p.c[1][gi], c2 = A.p.c[2][gi], c3 = A.p.c[3][gi];
-      const LegJ<T> L = to_cart_j<COORDS, T, true>(c0, c1, c2, c3);
-      cart[t] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
-      if constexpr (kPolar) jac[t] = R4{L.cp, L.sp, L.sh, L.ch};
-      raw[t] = R2{c0, c3};
-    }
-    if (pairs) {
-      for (int t = lane; t < nq; t += 64) gq[t] = A.gpair[q0 + t];
-    }
-    wave_sync();
-
-    // 2. one lane per event: the event upstream, and the particles' event
-    if (in_chunk) {
-      Acc vt[4] = {0, 0, 0, 0};
-      const int hi = lo_rel + n_e;
-      int i = lo_rel;
-      for (; i + 1 < hi; i += 2) {  // both reads first
-        pev[i] = ce;
-        pev[i + 1] = ce;
-        if (want_v) {
+      // one lane per event: the upstream every particle's 4-vector receives
+      // from the event outputs, g_total + g_m dm(V)/dV, with V summed in CSR
+      // order
+      if (evl && want_v) {
+        const int lo = ch[tev].o, hi = ch[tev + 1].o;
+        Acc vt[4] = {0, 0, 0, 0};
+        int i = lo;
+        for (; i + 1 < hi; i += 2) {  // both reads first
           const R4 v0 = cart[i], v1 = cart[i + 1];
 #pragma unroll
           for (int k = 0; k < 4; ++k) vt[k] = (vt[k] + (Acc)v0[k]) + (Acc)v1[k];
         }
-      }
-      if (i < hi) {
-        pev[i] = ce;
-        if (want_v) {
+        if (i < hi) {
           const R4 v0 = cart[i];
 #pragma unroll
           for (int k = 0; k < 4; ++k) vt[k] += (Acc)v0[k];
         }
-      }
-      if (want_u) {
-        T ud[4] = {0, 0, 0, 0};
-        if (want_v) {
-          T tot[4];
+        T tot[4], ud[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
-          dmass<T>(tot, gmv, ud);
-        }
-        ut[ce] = R4{ud[0] + gtv[0], ud[1] + gtv[1], ud[2] + gtv[2], ud[3] + gtv[3]};
+        for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
+        dmass<T>(tot, s_gm[tev], ud);
+        const R4 gt4 = s_ut[tev];
+        s_ut[tev] = R4{ud[0] + gt4[0], ud[1] + gt4[1], ud[2] + gt4[2], ud[3] + gt4[3]};
       }
-    }
 
-    // 3. pair phase: c = g / |m| in place, each pair once
-    if (nq > 0) {
-      const int m = ((nq + 63) >> 6) | 1;
-      int k = lane * m;
-      const int kend = min(k + m, nq);
-      if (k < kend) {
-        const int c = search_le32(ep, 0, ncp, k);
-        int o = eo[c], n = en[c];
-        int i, j;
-        decode_pair_small(k - ep[c], n, &i, &j);
-        int cn = c + 1;
-        int on = eo[cn], nn = en[cn];
-        for (; k < kend; ++k) {
-          const R4 a = cart[o + i], b = cart[o + j];
-          T w[4];
+      // Pair ranks inside an event: pair (b, a), b < a, sits at
+      // R(b) + a - b - 1, which grows by n - b - 2 with b; pair (a, b), b > a,
+      // at R(a) + b - a - 1, consecutive from R(a) = a (2n - a - 1) / 2.
+      int ev = 0, n = 0, ai = 0;
+      EvRec rc{0, 0};
+      if (mine) {
+        ev = ev_of[tid];
+        rc = ch[ev];
+        n = ch[ev + 1].o - rc.o;
+        ai = tid - rc.o;
+      }
+      const int qrow = rc.p + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
+      if (pairs) {
+        if (mine) {
+          const int cnt = ((n - 1) >> 1) + ((n & 1) == 0 && 2 * ai < n ? 1 : 0);
+          int qlo = rc.p + ai - 1, qhi = qrow;
+          for (int t = 0, b = ai + 1; t < cnt; ++t, ++b) {
+            const bool wrap = b >= n;
+            const int bb = wrap ? b - n : b;
+            const int q = wrap ? qlo : qhi;
+            const T g = s_g[q];
+            const R4 vj = cart[rc.o + bb];
+            T w[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = a[q] + b[q];
-          gq[k] = pair_coef<T>(w, gq[k]);
-          if (++j == n) {
-            if (++i == n - 1) {
-              o = on;
-              n = nn;
-              i = 0;
-              cn = min(cn + 1, ncp);
-              on = eo[cn];
-              nn = en[cn];
-            }
-            j = i + 1;
+            for (int k = 0; k < 4; ++k) w[k] = L.v[k] + vj[k];
+            s_g[q] = pair_coef<T>(w, g);
+            if (wrap)
+              qlo += n - bb - 2;
+            else
+              ++qhi;
           }
         }
       }
-    }
-    wave_sync();
+      if (pairs || want_u) __syncthreads();  // s_g and s_ut complete
 
-    // 4. particle phase
-    for (int t = lane; t < np; t += 64) {
-      const int pe = pev[t];
-      T u[4] = {0, 0, 0, 0};
-      if (want_u) {
-        const R4 u4 = ut[pe];
+      if (mine) {
+        T u[4] = {0, 0, 0, 0};
+        if (want_u) {
+          const R4 ut = s_ut[ev];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) u[q] = u4[q];
-      }
-      const R4 va = cart[t];
-      const int n = cen[pe];
-      if (pairs && n > 1) {
-        const int o = ceo[pe], p0 = cep[pe], ai = t - o;
-        // partners in ascending order: pair (b, a), b < a, sits at
-        // R(b) + a - b - 1, growing by n - b - 2 with b; pair (a, b), b > a,
-        // at R(a) + b - a - 1, consecutive from R(a) = a (2n - a - 1) / 2
-        T S[4] = {0, 0, 0, 0}, C = 0;
-        int qlo = p0 + ai - 1, qhi = p0 + (int)(__umul24(ai, 2 * n - ai - 1) >> 1);
-        for (int bj = 0; bj < n; ++bj) {
-          // branch-free: at bj == ai the slot read (at most nq, inside the
-          // slack) is replaced by 0, which adds exact zeros
-          const bool below = bj < ai;
-          const T cs = gq[below ? qlo : qhi];
-          const R4 vj = cart[o + bj];
-          const T cab = (bj == ai) ? T(0) : cs;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) S[q] += cab * vj[q];
-          C += cab;
-          qlo += below ? n - bj - 2 : 0;
-          qhi += bj > ai ? 1 : 0;
+          for (int k = 0; k < 4; ++k) u[k] = ut[k];
         }
-        // sum of c_ab (v_a + v_b) = C v_a + S, with dm/dw = (-P, E) / |m|
+        if (pairs && n > 1) {
+          // partners in ascending order: S = sum of c_ab v_b, C = sum of c_ab
+          T S[4] = {0, 0, 0, 0}, C = 0;
+          int qlo = rc.p + ai - 1, qhi = qrow;
+          for (int bj = 0; bj < n; ++bj) {
+            // branch-free: at bj == ai the slot read (at most nq, the slack
+            // slot) is replaced by 0, which adds exact zeros
+            const bool below = bj < ai;
+            const T cs = s_g[below ? qlo : qhi];
+            const R4 vj = cart[rc.o + bj];
+            const T cab = (bj == ai) ? T(0) : cs;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) u[q] -= C * va[q] + S[q];
-        u[3] += C * va[3] + S[3];
+            for (int k = 0; k < 4; ++k) S[k] += cab * vj[k];
+            C += cab;
+            qlo += below ? n - bj - 2 : 0;
+            qhi += bj > ai ? 1 : 0;
+          }
+          // sum of c_ab (v_a + v_b) = C v_a + S, with dm/dw = (-P, E) / |m|
+#pragma unroll
+          for (int k = 0; k < 3; ++k) u[k] -= C * L.v[k] + S[k];
+          u[3] += C * L.v[3] + S[3];
+        }
+        T g[4];
+        chain_coords<COORDS, T>(L, c[0], c[3], u, g);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store_out(A.gp[k], gi, g[k]);
       }
-      LegJ<T> L;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) L.v[q] = va[q];
-      if constexpr (kPolar) {
-        const R4 jj = jac[t];
-        L.cp = jj[0];
-        L.sp = jj[1];
-        L.sh = jj[2];
-        L.ch = jj[3];
-      } else {
-        L.cp = L.sp = L.sh = L.ch = T(0);
-      }
-      const R2 rw = raw[t];
-      T g[4];
-      chain_coords<COORDS, T>(L, rw[0], rw[1], u, g);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) store_out(A.gp[q], base + t, g[q]);
+      __syncthreads();
+      ca = cb;
     }
-    wave_sync();
-    ca = cb;
   }
 }
 
@@ -1521,6 +1483,9 @@ hipError_t fwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   return hipGetLastError();
 }
 
+// The backward stages at most one particle per thread.
+int bwd_cap(const Tiling& t) { return std::min(t.lds_particles, t.block); }
+
 template <typename T, int COORDS>
 hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
                      const void* const gt[4], const void* gem, const void* gpair, void* const gp[4],
@@ -1537,12 +1502,11 @@ hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const 
   A.gpair = (const T*)gpair;
   A.ne = ne;
   A.epb = t.events_per_tile;
-  A.cap = t.lds_particles;
+  A.cap = bwd_cap(t);
   A.qcap = t.pairs_per_round;
-  A.wave_bytes = (int)wave_lds_bytes_bwd<T>(t.lds_particles, t.pairs_per_round, t.events_per_tile);
-  const int64_t tiles = (ne + t.events_per_tile - 1) / t.events_per_tile;
-  hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(tiles, t.block / 64)), dim3(t.block), lds, s,
-                     A);
+  A.wave_bytes = 0;
+  hipLaunchKernelGGL((k_event_reduce_bwd<T, COORDS>), dim3(grid_for(ne, t.events_per_tile)), dim3(t.block), lds,
+                     s, A);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_event_reduce_bwd_big<T, COORDS>), dim3(big_grid(ne)), dim3(kBigBlock), 0, s, A);
@@ -1602,9 +1566,10 @@ size_t event_reduce_lds_bytes(glv_dtype dt, glv_mode mode, const Tiling& t, bool
 }
 
 size_t event_reduce_bwd_lds_bytes(glv_dtype dt, const Tiling& t) {
-  const size_t waves = (size_t)t.block / 64;
-  const int cap = t.lds_particles, qcap = t.pairs_per_round, epb = t.events_per_tile;
-  return waves * (dt == GLV_F64 ? wave_lds_bytes_bwd<double>(cap, qcap, epb) : wave_lds_bytes_bwd<float>(cap, qcap, epb));
+  const size_t tsz = (dt == GLV_F64) ? 8 : 4;
+  const size_t cap = (size_t)bwd_cap(t), epb = (size_t)t.events_per_tile, qcap = (size_t)t.pairs_per_round;
+  return 4 * (cap + epb) * tsz + (qcap + 2) * tsz + ((epb + 1) & ~(size_t)1) * tsz + 2 * (epb + 1) * 8 +
+         (epb + 1) * sizeof(EvRec) + cap * sizeof(unsigned short);
 }
 
 hipError_t launch_pair_offsets(int64_t ne, const int64_t* off, int64_t* po, hipStream_t s) {

@@ -246,7 +246,7 @@ def test_jagged_validation(lib):
     assert g(10, OFF, OFF + 8, None) == ALIAS
     h = lib.glv_event_reduce_bwd
     assert h(2, 1, 10, OFF, None, cols(P), None, None, PM, cols(T), None, None) == OFFSETS
-    for bad in ((128, 16, 128, 100), (128, 65, 128, 512), (128, 16, 32, 512), (512, 64, 512, 4096)):
+    for bad in ((128, 16, 128, 100), (128, 65, 128, 512), (128, 16, 32, 512), (512, 64, 512, 4160)):
         t = _lib.glv_tiling(*bad)
         assert h(2, 1, 10, OFF, PO, cols(P), None, None, PM, cols(T), ctypes.byref(t), None) == TILING, bad
     assert h(2, 1, 10, OFF, PO, cols(P), None, None, None, cols(P), None, None) == ALIAS
