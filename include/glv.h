@@ -117,21 +117,25 @@ typedef enum glv_mode { GLV_PLAIN = 0, GLV_COMPENSATED = 1 } glv_mode;
  *                    the FP32 plain mode takes a chunk's pairs in one round;
  *                    the compensated mode and glv_event_reduce_best_pair
  *                    take rounds of pairs_per_round
- * Backward (glv_event_reduce_bwd): the same wavefront tiles.
- *   block, events_per_tile, lds_particles   as for the forward
- *   pairs_per_round  pair upstreams a wavefront stages at once, a multiple of
- *                    64 in 64 .. 4096 (events with more pairs, or more
- *                    particles than lds_particles, go to the second launch)
+ * Backward (glv_event_reduce_bwd): a workgroup takes tiles of
+ * events_per_tile consecutive events and stages at most one particle per
+ * thread.
+ *   block, events_per_tile   as for the forward
+ *   lds_particles    particles staged at once, clamped to block
+ *   pairs_per_round  pair upstreams staged at once, a multiple of 64 in
+ *                    64 .. 4096 (events with more pairs, or more particles
+ *                    than the staging capacity, go to the second launch)
  * Fields set to 0 take the library's current choice (the autotuned one if
  * glv_autotune_event_reduce, or glv_autotune_event_reduce_bwd for the
  * backward, ran for this device/dtype/coords/mode, otherwise a built-in
-  * default).  A tiling whose workgroup would need more than 64 KiB of LDS is
+ * default).  A tiling whose workgroup would need more than 64 KiB of LDS is
  * rejected with GLV_EINVAL_TILING: per wavefront the forward keeps 4 values
  * per staged particle (12 in the compensated mode), per pair of a round one
- * value in FP64 (none in FP32), 8 more bytes in the compensated mode and one
+ * value in FP64 (none in FP32), 8 more bytes in the compensated mode, one
  * value and 4 bytes for glv_event_reduce_best_pair (instead of the FP64
- * value), and 12 bytes per event of the tile; the backward 10 values and 4 bytes per staged particle, one value per
- * staged pair upstream and 4 values and 24 bytes per event of the tile. */
+ * value), and 12 bytes per event of the tile; per workgroup the backward
+ * keeps 4 values and 2 bytes per staged particle, one value per staged pair
+ * upstream (plus 2), and 4.5 values and 32 bytes per event of the tile. */
 typedef struct glv_tiling {
   int32_t block;
   int32_t events_per_tile;

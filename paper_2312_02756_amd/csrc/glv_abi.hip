@@ -149,13 +149,13 @@ glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
   return t;
 }
 
-// Backward: two independent wavefronts per workgroup, each taking tiles of 32
-// events and staging up to 128 particles and 512 pair upstreams.
+// Backward: 128-thread workgroups taking tiles of 64 events, staging one
+// particle per thread and 512 pair upstreams.
 glv::Tiling default_tiling_bwd(glv_dtype dt) {
   (void)dt;
   glv::Tiling t;
   t.block = 128;
-  t.events_per_tile = 32;
+  t.events_per_tile = 64;
   t.lds_particles = 128;
   t.pairs_per_round = 512;
   return t;
@@ -833,17 +833,17 @@ glv_status glv_autotune_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne
   hipStream_t s = (hipStream_t)stream;
   // candidates: workgroup size x events per tile x staged particles x staged pairs
   std::vector<glv::Tiling> cands;
-  const int blocks[] = {64, 128};
+  // one staged particle per thread: the staging capacity is the workgroup;
+  // two or four staged pair upstreams per thread
+  const int blocks[] = {64, 128, 256, 512};
   const int epbs[] = {16, 32, 64};
-  const int caps[] = {64, 128, 256};
-  const int qcaps[] = {256, 512, 1024};
+  const int per_thread[] = {2, 4};
   for (int b : blocks)
     for (int e : epbs)
-      for (int c : caps)
-        for (int q : qcaps) {
-          glv::Tiling t{b, e, c, q};
-          if (tiling_valid(dt, GLV_PLAIN, true, t)) cands.push_back(t);
-        }
+      for (int k : per_thread) {
+        glv::Tiling t{b, e, b, std::min(k * b, 4096)};
+        if (tiling_valid(dt, GLV_PLAIN, true, t)) cands.push_back(t);
+      }
   auto launch = [&](const glv::Tiling& t) {
     return glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t, s);
   };

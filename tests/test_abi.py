@@ -278,7 +278,7 @@ def test_default_tilings_valid_for_every_combination(lib):
 def test_current_tiling_bwd_default_and_autotune_validation(lib):
     t = _lib.glv_tiling()
     assert lib.glv_current_tiling_bwd(2, 1, ctypes.byref(t)) == OK
-    assert (t.block, t.events_per_tile, t.lds_particles, t.pairs_per_round) == (128, 32, 128, 512)
+    assert (t.block, t.events_per_tile, t.lds_particles, t.pairs_per_round) == (128, 64, 128, 512)
     assert lib.glv_current_tiling_bwd(3, 1, ctypes.byref(t)) == DTYPE
     assert lib.glv_current_tiling_bwd(2, 1, None) == NULL
     # host-side validation, before any device work: missing gradient outputs

@@ -10,7 +10,7 @@ import torch
 from paper_2312_02756_amd import glv
 
 DEFAULT_FWD = (256, 32, 128, 512)
-DEFAULT_BWD = (128, 32, 128, 512)
+DEFAULT_BWD = (128, 64, 128, 512)
 
 
 @pytest.fixture
