@@ -75,7 +75,7 @@ KERNEL_SYMBOL = {
     "mass_fwd": "MassPlain<double, 1>", "mass_bwd": "MassBwd<double, 1>", "boost_fwd": "BoostFwd<double, 1>",
     "boost_bwd": "BoostBwd<double, 1, true>", "mass_fwd32": "MassPlain<float, 1>", "mass_bwd32": "MassBwd<float, 1>",
     "boost_fwd32": "BoostFwd<float, 1>", "boost_bwd32": "BoostBwd<float, 1, true>", "mass_comp32": "MassComp<float>",
-    "event_reduce": "k_event_reduce<double, 1, 0>", "event_reduce32c": "k_event_reduce<float, 1, 1>",
+    "event_reduce": "k_event_reduce<double, 1, 0, false>", "event_reduce32c": "k_event_reduce<float, 1, 1, false>",
     "event_reduce_bwd": "k_event_reduce_bwd<double, 1>",
 }
 # Coordinate conversions, measured after the step: (dtype, from, to, reverse mode) and kernel symbol.
@@ -125,6 +125,8 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calib-copy run into profiles/hbm_traffic.txt and exit")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="COUNTER_CSV",
+                    help="write profiles/jagged_sq_counters.md from rocprofv3 SQ counter passes")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
                     help="turn a rocprofv3 --kernel-trace kernel_trace.csv and the JSON line the same run printed "
                          "into profiles/step_kernel_trace.md and exit")
@@ -245,6 +247,81 @@ def summarize_pmc(fetch_csv, write_csv):
     print("\n".join(lines))
 
 
+SQ_PASSES = [
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_BUSY_CYCLES SQ_WAVE_CYCLES",
+    "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_ANY SQ_WAIT_INST_LDS SQ_WAIT_ANY SQ_LDS_BANK_CONFLICT "
+    "SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_VALU_TRANS_F64",
+    "SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 "
+    "SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_ADD_F32",
+]
+SQ_KERNELS = ("event_reduce", "event_reduce32c", "event_reduce_bwd", "event_best_pair_fused", "mass_comp32")
+SIMDS, CLOCK_GHZ = 1024, 2.4  # MI355X: 256 CUs x 4 SIMDs
+
+
+def summarize_sq(csvs):
+    """Per-kernel averages of SQ counters over the dispatches of each pass and
+    the VALU issue time they imply (a wave64 VALU instruction occupies a SIMD
+    for 4 cycles), next to the dispatch's own duration in the same run."""
+    import collections
+    import csv
+    import re
+
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(list)
+    meta = {}
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            name = re.sub(r"glv::\(anonymous namespace\)::", "", r["Kernel_Name"])
+            key = next((k for k in SQ_KERNELS if ALL_SYMBOLS[k] in name), None)
+            if key is None:
+                continue
+            vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            dur[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+            meta[key] = (r["Workgroup_Size"], r["Grid_Size"], r["LDS_Block_Size"], r["VGPR_Count"], r["SGPR_Count"])
+    cmd = " ".join(f'"{p}"' for p in SQ_PASSES)
+    lines = ["# SQ counters of the jagged kernels and the compensated FP32 mass (2^20 Poisson(8) events, 2^26 pairs)",
+             "",
+             "Commands (from the repository root `R` on one MI355X; one rocprofv3 pass per counter group):",
+             "",
+             "```",
+             f"i=0; for P in {cmd}; do",
+             "  i=$((i+1)); cd /tmp && export TMPDIR=/tmp && timeout -s KILL 240 rocprofv3 --pmc $P --output-format csv "
+             "-d $R/gpurun_out/sq_$i -o sq -- python3 $R/bench.py --kernels event_reduce,event_reduce32c,"
+             "event_reduce_bwd,mass_comp32 --steps 2 --warmup 1 --no-cpu --no-compare --no-convert --no-transform",
+             "done",
+             "python3 bench.py --summarize-sq gpurun_out/sq_*/sq_counter_collection.csv",
+             "```",
+             "",
+             "Counters are per dispatch, averaged over the dispatches of each pass (the autotuners' trial launches "
+             "included); `VALU issue` = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz), the time the VALU "
+             "instructions alone occupy the SIMDs; `dispatch` = the dispatch's duration under counter collection.",
+             ""]
+    derived = ["| kernel | block, grid, LDS B, VGPR, SGPR | dispatch us | VALU insts | VALU issue us | "
+               "VALU/dispatch | LDS insts | LDS bank-conflict cycles | SALU insts |",
+               "|---|---|---|---|---|---|---|---|---|"]
+    for k in SQ_KERNELS:
+        if k not in vals:
+            continue
+        c = {n: float(np.mean(v)) for n, v in vals[k].items()}
+        d = float(np.median(dur[k]))
+        vi = c.get("SQ_INSTS_VALU", 0.0)
+        issue = vi * 4 / (SIMDS * CLOCK_GHZ * 1e3)
+        derived.append(f"| {k} (`{ALL_SYMBOLS[k]}`) | {', '.join(meta[k])} | {d:.0f} | {vi:.3g} | {issue:.0f} | "
+                       f"{issue / d:.2f} | {c.get('SQ_INSTS_LDS', 0):.3g} | {c.get('SQ_LDS_BANK_CONFLICT', 0):.3g} | "
+                       f"{c.get('SQ_INSTS_SALU', 0):.3g} |")
+    lines += derived + ["", "All counters (per dispatch):", ""]
+    names = sorted({n for k in vals for n in vals[k]})
+    lines.append("| counter | " + " | ".join(k for k in SQ_KERNELS if k in vals) + " |")
+    lines.append("|---|" + "---|" * sum(1 for k in SQ_KERNELS if k in vals))
+    for n in names:
+        row = [f"{float(np.mean(vals[k][n])):.4g}" if vals[k].get(n) else "-" for k in SQ_KERNELS if k in vals]
+        lines.append(f"| {n} | " + " | ".join(row) + " |")
+    path = os.path.join(ROOT, "profiles", "jagged_sq_counters.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 # Sources that define each kernel and its launch configuration.
 KERNEL_SOURCES = {k: ["kernels_jagged.hip", "glv_abi.hip"] for k in ("event_reduce", "event_reduce32c",
                                                                        "event_reduce_bwd")}
@@ -289,6 +366,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no cross-GPU step: "

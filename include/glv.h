@@ -316,9 +316,9 @@ glv_status glv_event_best_pair(glv_dtype dtype, int64_t n_events, const int64_t*
  * among equal distances, NaN masses never chosen, -1 and NaN for an event
  * without a chosen pair).
  *   offsets, pair_offsets (required), p, tiling, fallback_count
- *                 as in glv_event_reduce; without a tiling the current
- *                 choice for glv_event_reduce is taken if its LDS suffices
- *                 for the selection, else the built-in default
+ *                 as in glv_event_reduce; fields set to 0 take this
+ *                 call's built-in default (64, 64, 128, 512), not the
+ *                 autotuned choice of glv_event_reduce
  * The outputs must not overlap each other, the offsets or the particle
  * columns (GLV_EINVAL_ALIAS).  Errors as glv_event_reduce, and
  * GLV_EINVAL_OFFSETS without pair_offsets. */

@@ -149,6 +149,19 @@ glv::Tiling default_tiling(glv_dtype dt, glv_mode mode) {
   return t;
 }
 
+// Fused best-pair selection: one wavefront per workgroup, tiles of 64
+// events, 128 staged particles and rounds of 512 pairs (its own choice: the
+// selection keeps a candidate per run of a round in LDS, and on 2^20
+// Poisson(8) events the smallest workgroups measured fastest).
+glv::Tiling default_tiling_best() {
+  glv::Tiling t;
+  t.block = 64;
+  t.events_per_tile = 64;
+  t.lds_particles = 128;
+  t.pairs_per_round = 512;
+  return t;
+}
+
 // Backward: 128-thread workgroups taking tiles of 64 events, staging one
 // particle per thread and 512 pair upstreams.
 glv::Tiling default_tiling_bwd(glv_dtype dt) {
@@ -178,8 +191,8 @@ bool tiling_valid(glv_dtype dt, glv_mode mode, bool bwd, const glv::Tiling& t, b
 // Resolve a user tiling (fields 0 = current choice) and validate it.
 glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_tiling* user, bool bwd,
                           glv::Tiling* out, bool best = false) {
-  glv::Tiling base = bwd ? default_tiling_bwd(dt) : default_tiling(dt, mode);
-  {
+  glv::Tiling base = bwd ? default_tiling_bwd(dt) : best ? default_tiling_best() : default_tiling(dt, mode);
+  if (!best) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     std::lock_guard<std::mutex> lk(g_tile_mu);
@@ -192,13 +205,7 @@ glv_status resolve_tiling(glv_dtype dt, glv_coords co, glv_mode mode, const glv_
     if (user->lds_particles) base.lds_particles = user->lds_particles;
     if (user->pairs_per_round) base.pairs_per_round = user->pairs_per_round;
   }
-  if (!tiling_valid(dt, mode, bwd, base, best)) {
-    // the fused best-pair selection needs more LDS per pair than the choice
-    // made for glv_event_reduce: without a user tiling it takes the default
-    if (!(best && !user)) return GLV_EINVAL_TILING;
-    base = default_tiling(dt, mode);
-    if (!tiling_valid(dt, mode, bwd, base, best)) return GLV_EINVAL_TILING;
-  }
+  if (!tiling_valid(dt, mode, bwd, base, best)) return GLV_EINVAL_TILING;
   *out = base;
   return GLV_OK;
 }
