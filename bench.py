@@ -72,9 +72,11 @@ TILING_FIELDS = ("block", "events_per_tile", "lds_particles", "pairs_per_round")
 KERNELS = ["mass_fwd", "mass_bwd", "boost_fwd", "boost_bwd", "mass_fwd32", "mass_bwd32", "boost_fwd32",
            "boost_bwd32", "mass_comp32", "event_reduce", "event_reduce32c", "event_reduce_bwd"]
 KERNEL_SYMBOL = {
-    "mass_fwd": "MassPlain<double, 1>", "mass_bwd": "MassBwd<double, 1>", "boost_fwd": "BoostFwd<double, 1>",
-    "boost_bwd": "BoostBwd<double, 1, true>", "mass_fwd32": "MassPlain<float, 1>", "mass_bwd32": "MassBwd<float, 1>",
-    "boost_fwd32": "BoostFwd<float, 1>", "boost_bwd32": "BoostBwd<float, 1, true>", "mass_comp32": "MassComp<float>",
+    "mass_fwd": "k_stream<MassPlain<double, 1>, 2>", "mass_bwd": "k_stream<MassBwd<double, 1>, 2>",
+    "boost_fwd": "k_stream<BoostFwd<double, 1>, 2>", "boost_bwd": "k_stream<BoostBwd<double, 1, true>, 2>",
+    "mass_fwd32": "k_stream<MassPlain<float, 1>, 4>", "mass_bwd32": "k_stream<MassBwd<float, 1>, 4>",
+    "boost_fwd32": "k_stream<BoostFwd<float, 1>, 4>", "boost_bwd32": "k_stream<BoostBwd<float, 1, true>, 4>",
+    "mass_comp32": "k_stream<MassComp<float>, 4>",
     "event_reduce": "k_event_reduce<double, 1, 0, false>", "event_reduce32c": "k_event_reduce<float, 1, 1, false>",
     "event_reduce_bwd": "k_event_reduce_bwd<double, 1>",
 }
@@ -99,7 +101,7 @@ TRANSFORM_CASES = {
 }
 # The analysis step, measured after the step: kernel symbols.
 ANALYSIS_SYMBOL = {"mass_histogram": "k_hist_lds<double, 2>", "event_best_pair": "k_best_pair<double>",
-                   "mass_comp32_bwd": "MassCompBwd<float>",
+                   "mass_comp32_bwd": "k_stream<MassCompBwd<float>, 4>",
                    "mass_histogram_fused": "k_mass_hist<MassPlain<double, 1>, 2, true>",
                    "event_best_pair_fused": "k_event_reduce<double, 1, 0, true>"}
 ALL_SYMBOLS = {**KERNEL_SYMBOL, **{k: v[4] for k, v in CONVERT_CASES.items()},
@@ -277,7 +279,7 @@ def summarize_sq(csvs):
                 continue
             vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
             dur[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
-            meta[key] = (r["Workgroup_Size"], r["Grid_Size"], r["LDS_Block_Size"], r["VGPR_Count"], r["SGPR_Count"])
+            meta[key] = (r["Workgroup_Size"], r["Grid_Size"], r["VGPR_Count"], r["SGPR_Count"])
     cmd = " ".join(f'"{p}"' for p in SQ_PASSES)
     lines = ["# SQ counters of the jagged kernels and the compensated FP32 mass (2^20 Poisson(8) events, 2^26 pairs)",
              "",
@@ -296,7 +298,7 @@ def summarize_sq(csvs):
              "included); `VALU issue` = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz), the time the VALU "
              "instructions alone occupy the SIMDs; `dispatch` = the dispatch's duration under counter collection.",
              ""]
-    derived = ["| kernel | block, grid, LDS B, VGPR, SGPR | dispatch us | VALU insts | VALU issue us | "
+    derived = ["| kernel | block, grid (work-items), VGPR, SGPR | dispatch us | VALU insts | VALU issue us | "
                "VALU/dispatch | LDS insts | LDS bank-conflict cycles | SALU insts |",
                "|---|---|---|---|---|---|---|---|---|"]
     for k in SQ_KERNELS:
