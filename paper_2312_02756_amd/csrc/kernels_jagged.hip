@@ -4,27 +4,20 @@
 // GenVectorX Fig. 1 applied to every i < j inside an event) -- with its
 // reverse mode.
 //
-// Work decomposition of the reduction.  A workgroup takes a tile of
-// consecutive events.  Their particles are contiguous in the columns, so the
-// workgroup streams them once (coalesced), converts each particle once and
-// stages the results in LDS in event-aligned chunks of at most
-// `lds_particles` particles.  Then
-//   * one lane per event sums its particles in CSR order (totals, and the
-//     event mass of the plain mode);
-//   * the chunk's pairs -- contiguous in the output too -- are split into
-//     equal contiguous slices, one per wavefront; lanes take consecutive pair
-//     indices (two per lane and iteration: k and k + 64 in the plain mode,
-//     k and k + 1 in the compensated mode), locate their event (binary
-//     search once, then stepping forward over the staged per-event records),
-//     turn the in-event rank into (i, j) through a table of co-lexicographic
-//     pairs and store the pair mass (a wavefront's stores cover consecutive
-//     addresses);
-//   * in the compensated mode the event mass is
-//     m^2 = sum_i M_i^2 + 2 sum_{i<j} K_ij (all terms >= 0); each wavefront
-//     folds its lanes' K_ij by a segmented lane-move (DPP) scan keyed by
-//     event and adds the segment sums to a per-(wavefront, event) LDS slot,
-//     and the event lane adds the slots in wavefront order: the result
-//     depends on the tiling only, never on timing.
+// Work decomposition of the reduction.  Each wavefront takes its own tile of
+// consecutive events and walks it in event-aligned chunks of at most
+// `lds_particles` particles, staging each particle once, converted, in its
+// own slice of LDS (no workgroup barrier: the wavefronts of a workgroup never
+// share data).  One lane per event sums its particles in CSR order; the
+// chunk's pairs -- contiguous in the output too -- are dealt out as equal
+// contiguous runs, one per lane, each lane stepping its run in lexicographic
+// order across event boundaries, so every lane has the same work whatever the
+// event sizes.  In the compensated mode each lane also sums K_ij over its run
+// per event, and the event's lane adds those partial sums in lane order:
+// deterministic for a tiling, never dependent on timing.  The same kernel can
+// choose, per event, the pair whose mass lies closest to a target (candidates
+// per run, combined in rank order) instead of storing pair masses.
+// The reverse mode stages one particle per thread of a workgroup (below).
 // An event with more particles than fit in LDS is left to a second, small
 // launch (k_event_reduce_big), where a whole workgroup takes it straight from
 // global memory (correct for any size, slower); on collider-sized events that
@@ -189,52 +182,11 @@ __device__ __forceinline__ void decode_pair_small(int r, int n, int* pi, int* pj
   *pj = i + 1 + (r - row_start32(i, n));
 }
 
-// Pair of lexicographic rank r among n particles, through the mirrored pair
-// (n-1-j, n-1-i): the mirror reverses the order, so its rank in
-// co-lexicographic order (by the larger index, then the smaller) is
-// P - 1 - r with P = n(n-1)/2, and co-lexicographic ranks do not depend on
-// n.  One table of the kColexN(kColexN-1)/2 co-lexicographic pairs, built once
-// per workgroup in LDS, therefore serves every event of at most kColexN
-// particles; larger events take the square-root decode.
-constexpr int kColexN = 32;
-constexpr int kColexPairs = kColexN * (kColexN - 1) / 2;
-
-// Entry r of the table: the pair (a, b), a < b, with b(b-1)/2 + a = r, as
-// a | b << 8.
-__device__ __forceinline__ unsigned short colex_entry(int r) {
-  int b = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)r)) * 0.5f);
-  while (b * (b - 1) / 2 > r) --b;
-  while ((b + 1) * b / 2 <= r) ++b;
-  return (unsigned short)((r - b * (b - 1) / 2) | (b << 8));
-}
-
-__device__ __forceinline__ void pair_of_rank(int r, int n, const unsigned short* colex, int* pi, int* pj) {
-  if (n <= kColexN) {
-    const unsigned t = colex[(int)(__umul24(n, n - 1) >> 1) - 1 - r];
-    *pi = n - 1 - (int)(t >> 8);
-    *pj = n - 1 - (int)(t & 0xffu);
-  } else {
-    decode_pair_small(r, n, pi, pj);
-  }
-}
-
 // Per event of a chunk: first particle and first pair, relative to the chunk.
 struct EvRec {
   int o;
   int p;
 };
-
-// Last event e in [lo, hi) with rec[e].p <= key (p non-decreasing).
-__device__ __forceinline__ int search_rec(const EvRec* rec, int lo, int hi, int key) {
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (rec[mid].p <= key)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 __device__ __forceinline__ int search_le(const int64_t* a, int lo, int hi, int64_t key) {
   while (hi - lo > 1) {
@@ -249,14 +201,11 @@ __device__ __forceinline__ int search_le(const int64_t* a, int lo, int hi, int64
 
 // Per-particle staged records in LDS, read with 16-byte LDS loads:
 //   cart[t] = (px, py, pz, E)                       every mode
-//   legA[t] = (pt, eta, phi, M), legB[t] = (mT, delta)   compensated mode
+//   legA[t] = (pt, eta, phi, M), legB[t] = (mT, delta, mT - pt, M^2)
+//                                                    compensated mode
 template <typename T>
 struct V4 {
   typedef T type __attribute__((ext_vector_type(4)));
-};
-template <typename T>
-struct V2 {
-  typedef T type __attribute__((ext_vector_type(2)));
 };
 
 // acc += rec[lo] + rec[lo+1] + ... + rec[hi-1], component-wise and in index
@@ -324,53 +273,6 @@ __device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC
 constexpr unsigned kRedoMarkBits = 0x7fd2e6b1u;
 __device__ __forceinline__ float redo_mark() { return __builtin_bit_cast(float, kRedoMarkBits); }
 __device__ __forceinline__ bool is_redo_mark(float x) { return __builtin_bit_cast(unsigned, x) == kRedoMarkBits; }
-
-// Cross-lane moves within a wavefront (GFX9 DPP controls): shift right by d
-// lanes within each row of 16 lanes, lane 15 of each row to the next row,
-// lane 31 to rows 2 and 3, and the whole wavefront left or right by one
-// lane.  A lane
-// whose source does not exist, or whose row is masked off, receives `old`.
-constexpr int kDppRowShr = 0x110;
-constexpr int kDppRowBcast15 = 0x142;
-constexpr int kDppRowBcast31 = 0x143;
-constexpr int kDppWaveShl1 = 0x130;
-constexpr int kDppWaveShr1 = 0x138;
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i32(int x, int old) {
-  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xf, false);
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_f64(double x) {  // old = +0
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-  const unsigned lo = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)b, 0);
-  const unsigned hi = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)(b >> 32), 0);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_scan_step(double& x, int key) {
-  const double y = dpp_f64<CTRL, ROWS>(x);
-  const int ky = dpp_i32<CTRL, ROWS>(key, -1);  // -1: never a key
-  x = (ky == key) ? x + y : x;
-}
-
-// Inclusive segmented sum over a full wavefront: keys do not decrease with the
-// lane, and each lane receives the sum of x over the lanes at or below it with
-// its key.  Sums within rows by shifts of 1, 2, 4 and 8, then the running row
-// totals carried across rows (lane 15 into rows 1 and 3, lane 31 into rows 2
-// and 3); a source with another key adds nothing (keys are monotone, so the
-// lanes between agree too).  No LDS traffic; all 64 lanes must be active.
-__device__ __forceinline__ double seg_scan_wave(double x, int key) {
-  seg_scan_step<kDppRowShr + 1, 0xf>(x, key);
-  seg_scan_step<kDppRowShr + 2, 0xf>(x, key);
-  seg_scan_step<kDppRowShr + 4, 0xf>(x, key);
-  seg_scan_step<kDppRowShr + 8, 0xf>(x, key);
-  seg_scan_step<kDppRowBcast15, 0xa>(x, key);
-  seg_scan_step<kDppRowBcast31, 0xc>(x, key);
-  return x;
-}
 
 // Deterministic workgroup sum of one double per thread (fixed tree).
 __device__ __forceinline__ double block_sum(double v, double* red) {
