@@ -256,7 +256,9 @@ SQ_PASSES = [
     "SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 "
     "SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_ADD_F32",
 ]
-SQ_KERNELS = ("event_reduce", "event_reduce32c", "event_reduce_bwd", "event_best_pair_fused", "mass_comp32")
+SQ_KERNELS = ("event_reduce", "event_reduce32c", "event_reduce_bwd", "event_best_pair_fused", "mass_comp32",
+              "mass_comp32_bwd")
+SQ_LAST = 5  # dispatches per kernel and pass: the timed steps, after the autotuners' trials
 SIMDS, CLOCK_GHZ = 1024, 2.4  # MI355X: 256 CUs x 4 SIMDs
 
 
@@ -272,14 +274,21 @@ def summarize_sq(csvs):
     dur = collections.defaultdict(list)
     meta = {}
     for path in csvs:
+        # per kernel, the last SQ_LAST dispatches of this pass (the timed
+        # steps, not the autotuners' trial tilings)
+        rows = collections.defaultdict(lambda: collections.defaultdict(list))
         for r in csv.DictReader(open(path)):
             name = re.sub(r"glv::\(anonymous namespace\)::", "", r["Kernel_Name"])
             key = next((k for k in SQ_KERNELS if ALL_SYMBOLS[k] in name), None)
-            if key is None:
-                continue
-            vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
-            dur[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
-            meta[key] = (r["Workgroup_Size"], r["Grid_Size"], r["VGPR_Count"], r["SGPR_Count"])
+            if key is not None:
+                rows[key][int(r["Dispatch_Id"])].append(r)
+        for key, by_id in rows.items():
+            for d in sorted(by_id)[-SQ_LAST:]:
+                for r in by_id[d]:
+                    vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                    meta[key] = (r["Workgroup_Size"], r["Grid_Size"], r["VGPR_Count"], r["SGPR_Count"])
+                r = by_id[d][0]
+                dur[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
     cmd = " ".join(f'"{p}"' for p in SQ_PASSES)
     lines = ["# SQ counters of the jagged kernels and the compensated FP32 mass (2^20 Poisson(8) events, 2^26 pairs)",
              "",
@@ -294,8 +303,8 @@ def summarize_sq(csvs):
              "python3 bench.py --summarize-sq gpurun_out/sq_*/sq_counter_collection.csv",
              "```",
              "",
-             "Counters are per dispatch, averaged over the dispatches of each pass (the autotuners' trial launches "
-             "included); `VALU issue` = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz), the time the VALU "
+             f"Counters are per dispatch, averaged over the last {SQ_LAST} dispatches of each kernel in each pass (the "
+             "timed steps, after the autotuners' trial launches); `VALU issue` = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz), the time the VALU "
              "instructions alone occupy the SIMDs; `dispatch` = the dispatch's duration under counter collection.",
              ""]
     derived = ["| kernel | block, grid (work-items), VGPR, SGPR | dispatch us | VALU insts | VALU issue us | "

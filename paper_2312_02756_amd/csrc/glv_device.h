@@ -392,7 +392,9 @@ __device__ __forceinline__ void dcoords_dcart(const T v[4], const T gc[4], T u[4
 
 // ------------------------------------------------- cancellation-free mass
 
-// sinh alone (small arguments by the odd polynomial, else from one exp).
+// sinh alone: FP64 small arguments by the odd polynomial, else from one exp;
+// FP32 by the odd polynomial up to |x| = 4 (one path for every argument of a
+// collider pair's half rapidity difference), else from one exp.
 template <bool kCold = false>
 __device__ __forceinline__ double fast_sinh(double x) {
   if (fabs(x) < 0.5) return poly_sinh_d<kCold>(x);
@@ -401,7 +403,7 @@ __device__ __forceinline__ double fast_sinh(double x) {
   return sh;
 }
 __device__ __forceinline__ float fast_sinh(float x) {
-  if (fabsf(x) < 0.5f) return poly_sinh_f(x);
+  if (fabsf(x) <= 4.0f) return poly_sinh19_f(x);
   float sh, ch;
   fast_sinhcosh_rcp(x, &sh, &ch);
   return sh;
@@ -472,8 +474,9 @@ __device__ __forceinline__ T div_budgeted(T a, T b) {
 // leg's rapidity shift delta: 16 each for products and quotients of
 // accurately computed factors, plus 4 for the FP32 hardware square roots
 // (mT, E) and reciprocals (the quotients of delta and of mT - pt, e^-x in
-// sinh and cosh) and the unreduced sine of the half azimuth difference
-// (1.7 ulp) that replace correctly rounded ones.
+// sinh and cosh), the unreduced sine of the half azimuth difference
+// (1.7 ulp) and the unreduced sinh of the half rapidity difference (3.5 units)
+// that replace correctly rounded ones.
 constexpr float kFactorUnits = 20.0f;
 constexpr float kDeltaUnits = 20.0f;
 

@@ -201,7 +201,7 @@ __device__ __forceinline__ int search_le(const int64_t* a, int lo, int hi, int64
 
 // Per-particle staged records in LDS, read with 16-byte LDS loads:
 //   cart[t] = (px, py, pz, E)                       every mode
-//   legA[t] = (pt, eta, phi, M), legB[t] = (mT, delta, mT - pt, M^2)
+//   leg[2t] = (pt, eta, phi, M), leg[2t+1] = (mT, delta, mT - pt, M^2)
 //                                                    compensated mode
 template <typename T>
 struct V4 {
@@ -253,16 +253,6 @@ __device__ __forceinline__ T comp_pair(const LegC<T>& a, const LegC<T>& b, T ma,
     *kout = (double)k;
     return d_sqrt(m2);
   }
-}
-
-// FP32 compensated pair with the redo left to k_event_reduce_big: *redo is
-// set when the error bound asks for FP64.
-__device__ __forceinline__ float comp_pair_fp32(const LegC<float>& a, const LegC<float>& b, double* kout,
-                                                bool* redo) {
-  float k;
-  const float m2 = comp_pair_m2<float>(a, b, &k, redo);
-  *kout = (double)k;
-  return sqrt_budgeted(m2);
 }
 
 // Marks an event of the tiled FP32 compensated reduction that holds a pair
@@ -466,8 +456,8 @@ __device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key
 
 // LDS of one wavefront of the forward reduction (cap particles, qcap pairs):
 //   cart[cap]  (px, py, pz, E)             staged Cartesian records
-//   legA[cap]  (pt, eta, phi, M)           compensated mode
-//   legB[cap]  (mT, delta, mT - pt, M^2)   compensated mode
+//   leg[2 cap] (pt, eta, phi, M), (mT, delta, mT - pt, M^2) per particle,
+//              adjacent (one address for both reads)   compensated mode
 //   pm[qcap]   FP64: pair masses of a round (stored from here, coalesced)
 //   kp[qcap]   partial sums of K per lane  (compensated event mass)
 //   bm[qcap], br[qcap]  best pair of a lane's run within one event: mass
@@ -479,8 +469,7 @@ __device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key
 template <typename T, int MODE>
 struct WaveLds {
   typename V4<T>::type* cart;
-  typename V4<T>::type* legA;
-  typename V4<T>::type* legB;
+  typename V4<T>::type* leg;
   T* pm;
   double* kp;
   T* bm;
@@ -508,15 +497,12 @@ __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int
   w.cart = reinterpret_cast<typename V4<T>::type*>(p);
   p += (size_t)cap * 4 * sizeof(T);
   if constexpr (MODE == GLV_COMPENSATED) {
-    w.legA = reinterpret_cast<typename V4<T>::type*>(p);
-    p += (size_t)cap * 4 * sizeof(T);
-    w.legB = reinterpret_cast<typename V4<T>::type*>(p);
-    p += (size_t)cap * 4 * sizeof(T);
+    w.leg = reinterpret_cast<typename V4<T>::type*>(p);
+    p += (size_t)cap * 8 * sizeof(T);
     w.kp = reinterpret_cast<double*>(p);
     p += (size_t)qcap * sizeof(double);
   } else {
-    w.legA = nullptr;
-    w.legB = nullptr;
+    w.leg = nullptr;
     w.kp = nullptr;
   }
   w.pm = reinterpret_cast<T*>(p);
@@ -564,8 +550,8 @@ __device__ __forceinline__ void stage_one(const WaveLds<T, MODE>& W, int t, T c0
   T v[4];
   if constexpr (MODE == GLV_COMPENSATED) {  // (pt, eta, phi, M)
     const LegC<T> L = comp_leg_cart<T>(c0, c1, c2, c3, v);
-    W.legA[t] = R4{c0, c1, c2, c3};
-    W.legB[t] = R4{L.mt, L.delta, L.dmt, L.m2};
+    W.leg[2 * t] = R4{c0, c1, c2, c3};
+    W.leg[2 * t + 1] = R4{L.mt, L.delta, L.dmt, L.m2};
   } else {
     to_cart<COORDS, T, true>(c0, c1, c2, c3, v);
   }
@@ -575,8 +561,8 @@ __device__ __forceinline__ void stage_one(const WaveLds<T, MODE>& W, int t, T c0
 // Compensated leg terms of a staged particle; *mass receives M.
 template <typename T, int MODE>
 __device__ __forceinline__ LegC<T> staged_leg(const WaveLds<T, MODE>& W, int t, T* mass) {
-  const typename V4<T>::type a = W.legA[t];
-  const typename V4<T>::type b = W.legB[t];
+  const typename V4<T>::type a = W.leg[2 * t];
+  const typename V4<T>::type b = W.leg[2 * t + 1];
   LegC<T> L;
   L.pt = a[0];
   L.eta = a[1];
@@ -746,14 +732,14 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
         int t = lo;
         for (; t + 2 <= hi; t += 2) {
           const R4 r0 = W.cart[t], r1 = W.cart[t + 1];
-          const double m0 = (double)W.legA[t][3], m1 = (double)W.legA[t + 1][3];
+          const double m0 = (double)W.leg[2 * t][3], m1 = (double)W.leg[2 * t + 2][3];
 #pragma unroll
           for (int k = 0; k < 4; ++k) d[k] = (d[k] + (double)r0[k]) + (double)r1[k];
           msum = (msum + m0 * m0) + m1 * m1;
         }
         if (t < hi) {
           const R4 r0 = W.cart[t];
-          const double m0 = (double)W.legA[t][3];
+          const double m0 = (double)W.leg[2 * t][3];
 #pragma unroll
           for (int k = 0; k < 4; ++k) d[k] += (double)r0[k];
           msum += m0 * m0;
@@ -806,6 +792,8 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
           double bdist = 0.0;    // the run's best so far (brk < 0: none)
           int brk = -1;
           T bmass = T(0);
+          // the row particle i is held in registers while j runs along its
+          // row (about half of the LDS reads)
           for (; k < kend; ++k) {
             T mk;
             if constexpr (kComp) {
@@ -814,17 +802,18 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
               double kd;
               if constexpr (kDefer) {
                 bool redo;
-                mk = comp_pair_fp32(la, lb, &kd, &redo);
-                if (redo) kd = __builtin_nan("");
+                float kf;
+                mk = sqrt_budgeted(comp_pair_m2<float>(la, lb, &kf, &redo));
+                kd = (double)(redo ? __builtin_nanf("") : kf);
               } else {
                 mk = comp_pair<T>(la, lb, ma, mb, &kd, &fb);
               }
               kacc += kd;
             } else {
-              const R4 a = W.cart[o + i], b = W.cart[o + j];
+              const R4 ra = W.cart[o + i], b = W.cart[o + j];
               T w[4];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) w[q] = a[q] + b[q];
+              for (int q = 0; q < 4; ++q) w[q] = ra[q] + b[q];
               mk = mass_of(w);
             }
             if constexpr (BEST) {
