@@ -143,8 +143,8 @@ TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats 
 def summarize_trace(trace_csv, bench_json):
     """Per-kernel launch durations from a rocprofv3 kernel trace beside the
     benchmark's own HIP-event averages of the same run.  For the step's
-    kernels only their last warmup + steps dispatches count (the jagged
-    autotuner's trial launches come before them)."""
+    kernels only their last warmup + steps dispatches of the step's launch
+    shape count (the jagged autotuner's trial launches come before them)."""
     import collections
     import csv
     import re
@@ -163,6 +163,12 @@ def summarize_trace(trace_csv, bench_json):
         ds.sort()
         short = re.sub(r"glv::\(anonymous namespace\)::", "", name)
         key = next((k for k, sym in ALL_SYMBOLS.items() if sym in short), None)
+        if key:
+            # the step's own launch shape (the most frequent grid: the settle
+            # and timed steps), so that launches of the same kernel on other
+            # sizes -- autotuner trials, the analysis inputs -- do not count
+            grid = collections.Counter(d[3] for d in ds).most_common(1)[0][0]
+            ds = [d for d in ds if d[3] == grid]
         extra = len(ds) - n_step if key else 0
         if key:
             ds = ds[-n_step:]
@@ -172,7 +178,7 @@ def summarize_trace(trace_csv, bench_json):
     out = ["# Kernel trace: one benchmark step (2^24 items per element-wise kernel, 2^20 jagged events)", "",
            "Command (from the repository root `R` on one MI355X):", "", "```", TRACE_CMD, "```", "",
            f"Source: `bench_kernel_trace.csv`; per step kernel its last {bench['warmup']} warm-up + "
-           f"{bench['steps']} timed dispatches; jagged tilings (block, events per tile, LDS particles) "
+           f"{bench['steps']} timed dispatches of the step's launch shape; jagged tilings (block, events per tile, LDS particles) "
            f"{tuple((bench['config'].get('event_tiling') or {}).values())} FP64, "
            f"{tuple((bench['config'].get('event_tiling_fp32_comp') or {}).values())} FP32 compensated, "
            f"{tuple((bench['config'].get('event_tiling_bwd') or {}).values())} backward (autotuned on "
