@@ -1072,7 +1072,7 @@ __device__ __forceinline__ bool bwd_big(int64_t n, int cap, int qcap, bool pairs
 //   * thread t converts particle t of the chunk once, keeps its Cartesian
 //     vector and Jacobian pieces (cos phi, sin phi, sinh eta, cosh eta) in
 //     registers and stages the vector in LDS for its partners; the chunk's
-//     pair upstreams -- contiguous in grad_pair -- are copied to LDS, four
+//     pair upstreams -- contiguous in grad_pair -- are copied to LDS, two
 //     loads in flight per thread; one lane per event records its particles'
 //     event;
 //   * pair phase: each pair's upstream g_ij becomes c_ij = g_ij / |m_ij| in
@@ -1150,7 +1150,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_event_reduce_bwd(BwdArgs<T, COORD
 #pragma unroll
         for (int k = 0; k < 4; ++k) c[k] = A.p.c[k][gi];
       }
-      constexpr int kG = 4;  // pair upstreams per thread in flight
+      // pair upstreams per thread in flight (two: 317 against 325 us for four
+      // on 2^20 events, whose registers cost occupancy)
+      constexpr int kG = 2;
       T gv[kG];
 #pragma unroll
       for (int r = 0; r < kG; ++r) {
