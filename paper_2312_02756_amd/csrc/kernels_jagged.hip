@@ -637,6 +637,10 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
   constexpr bool kDefer = kComp && (sizeof(T) == 4);
   constexpr int kSlots = Prefetch<T>::kSlots;
   constexpr bool kStageMasses = sizeof(T) == 8 && !BEST;
+#ifndef GLV_KCOLL
+#define GLV_KCOLL 4
+#endif
+  constexpr int kColl = GLV_KCOLL;  // partial-sum slots per LDS wait of an event lane
   using R4 = typename V4<T>::type;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -868,20 +872,39 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
           // pairs of this round, in lane order (in rank order)
           const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
           const int lo = max(plo_rel, r0) - r0, hi = min(phi_rel, r0 + qn) - r0;
-          for (int seg = lo / m; seg * m < hi; ++seg) {
-            const int slot = min((seg + 1) * m, hi) - 1;
-            if constexpr (kComp) {
-              if (want_k) ks += W.kp[slot];
+          // kColl segments' slots read per LDS wait (a serial chain of waits
+          // per event otherwise), then taken in order
+          const int seg_end = (hi + m - 1) / m;  // the segments with seg m < hi
+          for (int seg = lo / m; seg < seg_end; seg += kColl) {
+            int slot[kColl];
+#pragma unroll
+            for (int u = 0; u < kColl; ++u) slot[u] = min((min(seg + u, seg_end - 1) + 1) * m, hi) - 1;
+            double kv[kColl];
+            int rv[kColl];
+            T mv[kColl];
+#pragma unroll
+            for (int u = 0; u < kColl; ++u) {
+              if constexpr (kComp) kv[u] = W.kp[slot[u]];
+              if constexpr (BEST) {
+                rv[u] = W.br[slot[u]];
+                mv[u] = W.bm[slot[u]];
+              }
             }
-            if constexpr (BEST) {
-              const int r = W.br[slot];
-              if (r >= 0) {
-                const T bmv = W.bm[slot];
-                const double d = fabs((double)bmv - A.target);
-                if (ebr < 0 || d < ebd) {
-                  ebd = d;
-                  ebr = r;
-                  ebm = bmv;
+#pragma unroll
+            for (int u = 0; u < kColl; ++u) {
+              if (seg + u < seg_end) {
+                if constexpr (kComp) {
+                  if (want_k) ks += kv[u];
+                }
+                if constexpr (BEST) {
+                  if (rv[u] >= 0) {
+                    const double d = fabs((double)mv[u] - A.target);
+                    if (ebr < 0 || d < ebd) {
+                      ebd = d;
+                      ebr = rv[u];
+                      ebm = mv[u];
+                    }
+                  }
                 }
               }
             }
