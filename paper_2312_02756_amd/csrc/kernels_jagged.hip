@@ -264,6 +264,51 @@ constexpr unsigned kRedoMarkBits = 0x7fd2e6b1u;
 __device__ __forceinline__ float redo_mark() { return __builtin_bit_cast(float, kRedoMarkBits); }
 __device__ __forceinline__ bool is_redo_mark(float x) { return __builtin_bit_cast(unsigned, x) == kRedoMarkBits; }
 
+// Cross-lane moves within a wavefront (GFX9 DPP controls): shift right by d
+// lanes within each row of 16 lanes, lane 15 of each row to the next row,
+// lane 31 to rows 2 and 3, and the whole wavefront right by one lane.  A lane
+// whose source does not exist, or whose row is masked off, receives `old`.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int x, int old) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x) {  // old = +0
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)b, 0);
+  const unsigned hi = (unsigned)dpp_i32<CTRL, ROWS>((int)(unsigned)(b >> 32), 0);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(double& x, int key) {
+  const double y = dpp_f64<CTRL, ROWS>(x);
+  const int ky = dpp_i32<CTRL, ROWS>(key, -1);  // -1: never a key
+  x = (ky == key) ? x + y : x;
+}
+
+// Inclusive segmented sum over a full wavefront: keys do not decrease with the
+// lane, and each lane receives the sum of x over the lanes at or below it with
+// its key.  Sums within rows by shifts of 1, 2, 4 and 8, then the running row
+// totals carried across rows (lane 15 into rows 1 and 3, lane 31 into rows 2
+// and 3); a source with another key adds nothing (keys are monotone, so the
+// lanes between agree too).  No LDS traffic; all 64 lanes must be active.
+__device__ __forceinline__ double seg_scan_wave(double x, int key) {
+  seg_scan_step<kDppRowShr + 1, 0xf>(x, key);
+  seg_scan_step<kDppRowShr + 2, 0xf>(x, key);
+  seg_scan_step<kDppRowShr + 4, 0xf>(x, key);
+  seg_scan_step<kDppRowShr + 8, 0xf>(x, key);
+  seg_scan_step<kDppRowBcast15, 0xa>(x, key);
+  seg_scan_step<kDppRowBcast31, 0xc>(x, key);
+  return x;
+}
+
 // Deterministic workgroup sum of one double per thread (fixed tree).
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -459,7 +504,8 @@ __device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key
 //   leg[2 cap] (pt, eta, phi, M), (mT, delta, mT - pt, M^2) per particle,
 //              adjacent (one address for both reads)   compensated mode
 //   pm[qcap]   FP64: pair masses of a round (stored from here, coalesced)
-//   kp[qcap]   partial sums of K per lane  (compensated event mass)
+//   kev[epb+1] K of each of the chunk's events with pairs in a round
+//              (compensated event mass)
 //   bm[qcap], br[qcap]  best pair of a lane's run within one event: mass
 //              and in-event rank (-1: none), at the run's last slot
 //              (fused best-pair selection)
@@ -471,7 +517,7 @@ struct WaveLds {
   typename V4<T>::type* cart;
   typename V4<T>::type* leg;
   T* pm;
-  double* kp;
+  double* kev;
   T* bm;
   int* br;
   int* eo;
@@ -482,7 +528,7 @@ struct WaveLds {
 template <typename T, int MODE, bool BEST>
 __host__ __device__ __forceinline__ size_t wave_lds_bytes(int cap, int qcap, int epb) {
   size_t b = (size_t)cap * 4 * sizeof(T);
-  if (MODE == GLV_COMPENSATED) b += (size_t)cap * 8 * sizeof(T) + (size_t)qcap * sizeof(double);
+  if (MODE == GLV_COMPENSATED) b += (size_t)cap * 8 * sizeof(T) + (size_t)(epb + 1) * sizeof(double);
   if (BEST)
     b += (size_t)qcap * (sizeof(T) + sizeof(int));  // run candidates
   else if (sizeof(T) == 8)
@@ -499,11 +545,11 @@ __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int
   if constexpr (MODE == GLV_COMPENSATED) {
     w.leg = reinterpret_cast<typename V4<T>::type*>(p);
     p += (size_t)cap * 8 * sizeof(T);
-    w.kp = reinterpret_cast<double*>(p);
-    p += (size_t)qcap * sizeof(double);
+    w.kev = reinterpret_cast<double*>(p);
+    p += (size_t)(epb + 1) * sizeof(double);
   } else {
     w.leg = nullptr;
-    w.kp = nullptr;
+    w.kev = nullptr;
   }
   w.pm = reinterpret_cast<T*>(p);
   w.bm = reinterpret_cast<T*>(p);
@@ -697,9 +743,10 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
     const bool has_pairs = in_chunk && n_e >= 2;
     const uint64_t hp = __ballot(has_pairs);
     const int ncp = __builtin_popcountll(hp);
+    const int my_c = __builtin_popcountll(hp & ((1ull << lane) - 1));  // this event among those with pairs
     if (need_po) {
       if (has_pairs) {
-        const int c = __builtin_popcountll(hp & ((1ull << lane) - 1));
+        const int c = my_c;
         W.eo[c] = lo_rel;
         W.en[c] = n_e;
         W.ep[c] = (int)(plo - q0);
@@ -791,6 +838,14 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
         const int m = kStageMasses ? (((qn + 63) >> 6) | 1) : ((qn + 63) >> 6);
         int k = r0 + lane * m;
         const int kend = min(k + m, r0 + qn);
+        // the run's K partials of events it shares with other runs: the head
+        // (the end of an event begun before the run) and the tail (the start
+        // of an event that goes on after it); events wholly inside the run go
+        // to kev directly
+        double head = 0.0, tail = 0.0;
+        bool has_head = false, has_tail = false, first_seg = true, began_before = false;
+        int head_c = 0, cur_c = ncp;  // cur_c: the run's current event (after a closing pair: the next)
+        const bool ran = k < kend;
         if (k < kend) {
           int c = search_le32(W.ep, 0, ncp, k);
           int o = W.eo[c], n = W.en[c];
@@ -800,11 +855,11 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
           int on = W.eo[cn], nn = W.en[cn];  // the next event with pairs (or the sentinel)
           double kacc = 0.0;
           int rk = k - W.ep[c];  // in-event rank of pair k
+          cur_c = c;
+          began_before = rk > 0;
           double bdist = 0.0;    // the run's best so far (brk < 0: none)
           int brk = -1;
           T bmass = T(0);
-          // the row particle i is held in registers while j runs along its
-          // row (about half of the LDS reads)
           for (; k < kend; ++k) {
             T mk;
             if constexpr (kComp) {
@@ -842,6 +897,7 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
               pout[k] = mk;
             }
             // lexicographic successor within the chunk
+            const int seg_c = cur_c;  // pair k's event
             bool fin = false;
             if (++j == n) {
               if (++i == n - 1) {
@@ -849,15 +905,28 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
                 o = on;
                 n = nn;
                 i = 0;
+                cur_c = cn;
                 cn = min(cn + 1, ncp);
                 on = W.eo[cn];
                 nn = W.en[cn];
               }
               j = i + 1;
             }
-            if (fin || k + 1 == kend) {  // leave the run's partials at its last pair of the event
+            if (fin || k + 1 == kend) {  // the run's partials at its last pair of the event
               if constexpr (kComp) {
-                W.kp[k - r0] = kacc;
+                if (fin) {
+                  if (first_seg && began_before) {
+                    head = kacc;  // the end of an event begun in an earlier run
+                    has_head = true;
+                    head_c = seg_c;
+                  } else {
+                    W.kev[seg_c] = kacc;  // an event wholly inside this run
+                  }
+                } else {
+                  tail = kacc;  // the event goes on in the next run
+                  has_tail = true;
+                }
+                first_seg = false;
                 kacc = 0.0;
               }
               if constexpr (BEST) {
@@ -869,12 +938,34 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
             }
           }
         }
+        if constexpr (kComp) {
+          if (want_k) {
+            // each shared event's K: the tails of the runs it spans, summed by
+            // a segmented scan keyed by event, plus the head of the run where
+            // it ends; an event that goes on into the next round takes the
+            // scan at the round's last run.  Keys grow with the lane: 2e for a
+            // tail on event e, 2e + 1 for a run whose last event e closed in
+            // it (cur_c is then e + 1), past every event for a run without pairs.
+            const int key = has_tail ? 2 * cur_c : (ran ? 2 * cur_c - 1 : 2 * ncp + 1);
+            const double sc = seg_scan_wave(has_tail ? tail : 0.0, key);
+            const double sp = dpp_f64<kDppWaveShr1, 0xf>(sc);
+            const int kp = dpp_i32<kDppWaveShr1, 0xf>(key, -1);
+            if (has_head) W.kev[head_c] = (kp == 2 * head_c ? sp : 0.0) + head;
+            if (has_tail && kend == r0 + qn) W.kev[cur_c] = sc;
+          }
+        }
         wave_sync();
         if (kStageMasses && want_pairs) {
           T* out = A.pair_m + q0 + r0;
           for (int t = lane; t < qn; t += 64) store_out(out, t, W.pm[t]);
         }
-        if ((kComp || BEST) && in_chunk && n_e >= 2) {
+        if constexpr (kComp) {
+          if (want_k && in_chunk && n_e >= 2) {
+            const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
+            if (max(plo_rel, r0) < min(phi_rel, r0 + qn)) ks += W.kev[my_c];  // pairs in this round
+          }
+        }
+        if (BEST && in_chunk && n_e >= 2) {
           // the event lane takes the partials of the runs that covered its
           // pairs of this round, in lane order (in rank order)
           const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
@@ -886,24 +977,17 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
             int slot[kColl];
 #pragma unroll
             for (int u = 0; u < kColl; ++u) slot[u] = min((min(seg + u, seg_end - 1) + 1) * m, hi) - 1;
-            double kv[kColl];
             int rv[kColl];
             T mv[kColl];
 #pragma unroll
             for (int u = 0; u < kColl; ++u) {
-              if constexpr (kComp) kv[u] = W.kp[slot[u]];
-              if constexpr (BEST) {
-                rv[u] = W.br[slot[u]];
-                mv[u] = W.bm[slot[u]];
-              }
+              rv[u] = W.br[slot[u]];
+              mv[u] = W.bm[slot[u]];
             }
 #pragma unroll
             for (int u = 0; u < kColl; ++u) {
               if (seg + u < seg_end) {
-                if constexpr (kComp) {
-                  if (want_k) ks += kv[u];
-                }
-                if constexpr (BEST) {
+                {
                   if (rv[u] >= 0) {
                     const double d = fabs((double)mv[u] - A.target);
                     if (ebr < 0 || d < ebd) {
