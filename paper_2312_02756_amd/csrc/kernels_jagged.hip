@@ -309,6 +309,47 @@ __device__ __forceinline__ double seg_scan_wave(double x, int key) {
   return x;
 }
 
+// A best-pair candidate (distance, in-event rank (-1: none), mass) and the
+// strict order that picks it: any candidate over none, then the smaller
+// distance, then the lower rank.  A total order, so that any grouping of a
+// minimum gives the same candidate.
+template <typename T>
+__device__ __forceinline__ bool cand_better(double d, int r, double od, int orr) {
+  return r >= 0 && (orr < 0 || d < od || (d == od && r < orr));
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_t(T x) {  // old = +0
+  if constexpr (sizeof(T) == 8)
+    return dpp_f64<CTRL, ROWS>(x);
+  else
+    return __builtin_bit_cast(T, dpp_i32<CTRL, ROWS>(__builtin_bit_cast(int, x), 0));
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ void best_scan_step(double& d, int& r, T& m, int key) {
+  const double yd = dpp_f64<CTRL, ROWS>(d);
+  const int yr = dpp_i32<CTRL, ROWS>(r, -1);
+  const T ym = dpp_t<CTRL, ROWS, T>(m);
+  const int ky = dpp_i32<CTRL, ROWS>(key, -1);
+  const bool take = ky == key && cand_better<T>(yd, yr, d, r);
+  d = take ? yd : d;
+  r = take ? yr : r;
+  m = take ? ym : m;
+}
+
+// Inclusive segmented minimum of candidates over a full wavefront, the network
+// of seg_scan_wave.
+template <typename T>
+__device__ __forceinline__ void best_scan_wave(double& d, int& r, T& m, int key) {
+  best_scan_step<kDppRowShr + 1, 0xf, T>(d, r, m, key);
+  best_scan_step<kDppRowShr + 2, 0xf, T>(d, r, m, key);
+  best_scan_step<kDppRowShr + 4, 0xf, T>(d, r, m, key);
+  best_scan_step<kDppRowShr + 8, 0xf, T>(d, r, m, key);
+  best_scan_step<kDppRowBcast15, 0xa, T>(d, r, m, key);
+  best_scan_step<kDppRowBcast31, 0xc, T>(d, r, m, key);
+}
+
 // Deterministic workgroup sum of one double per thread (fixed tree).
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -506,8 +547,8 @@ __device__ __forceinline__ int search_le32(const int* a, int lo, int hi, int key
 //   pm[qcap]   FP64: pair masses of a round (stored from here, coalesced)
 //   kev[epb+1] K of each of the chunk's events with pairs in a round
 //              (compensated event mass)
-//   bm[qcap], br[qcap]  best pair of a lane's run within one event: mass
-//              and in-event rank (-1: none), at the run's last slot
+//   bm[epb+1], br[epb+1]  best pair of each of the chunk's events with
+//              pairs in a round: mass and in-event rank (-1: none)
 //              (fused best-pair selection)
 //   eo, en, ep [epb + 1] int               the chunk's events with pairs:
 //              first particle, size, first pair (chunk-relative), then a
@@ -530,7 +571,7 @@ __host__ __device__ __forceinline__ size_t wave_lds_bytes(int cap, int qcap, int
   size_t b = (size_t)cap * 4 * sizeof(T);
   if (MODE == GLV_COMPENSATED) b += (size_t)cap * 8 * sizeof(T) + (size_t)(epb + 1) * sizeof(double);
   if (BEST)
-    b += (size_t)qcap * (sizeof(T) + sizeof(int));  // run candidates
+    b += (size_t)(epb + 1) * (sizeof(T) + sizeof(int));  // each event's best of a round
   else if (sizeof(T) == 8)
     b += (size_t)qcap * sizeof(T);  // staged pair masses
   b += 3 * (size_t)(epb + 1) * sizeof(int);
@@ -554,9 +595,9 @@ __device__ __forceinline__ WaveLds<T, MODE> carve_wave_lds(unsigned char* p, int
   w.pm = reinterpret_cast<T*>(p);
   w.bm = reinterpret_cast<T*>(p);
   if (BEST) {
-    p += (size_t)qcap * sizeof(T);
+    p += (size_t)(epb + 1) * sizeof(T);
     w.br = reinterpret_cast<int*>(p);
-    p += (size_t)qcap * sizeof(int);
+    p += (size_t)(epb + 1) * sizeof(int);
   } else {
     w.br = nullptr;
     if (sizeof(T) == 8) p += (size_t)qcap * sizeof(T);
@@ -685,10 +726,6 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
   constexpr bool kDefer = kComp && (sizeof(T) == 4);
   constexpr int kSlots = Prefetch<T>::kSlots;
   constexpr bool kStageMasses = sizeof(T) == 8 && !BEST;
-#ifndef GLV_KCOLL
-#define GLV_KCOLL 4
-#endif
-  constexpr int kColl = GLV_KCOLL;  // partial-sum slots per LDS wait of an event lane
   using R4 = typename V4<T>::type;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -843,6 +880,9 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
         // of an event that goes on after it); events wholly inside the run go
         // to kev directly
         double head = 0.0, tail = 0.0;
+        double hd = 0.0, td = 0.0;  // best pair: the head's and the tail's candidates
+        int hr = -1, tr = -1;
+        T hm = T(0), tm = T(0);
         bool has_head = false, has_tail = false, first_seg = true, began_before = false;
         int head_c = 0, cur_c = ncp;  // cur_c: the run's current event (after a closing pair: the next)
         const bool ran = k < kend;
@@ -913,40 +953,80 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
               j = i + 1;
             }
             if (fin || k + 1 == kend) {  // the run's partials at its last pair of the event
+              // the head ends an event begun in an earlier run, the tail starts
+              // one that goes on in the next run; an event wholly inside the
+              // run goes to its slot directly
+              const bool is_head = fin && first_seg && began_before;
               if constexpr (kComp) {
-                if (fin) {
-                  if (first_seg && began_before) {
-                    head = kacc;  // the end of an event begun in an earlier run
-                    has_head = true;
-                    head_c = seg_c;
-                  } else {
-                    W.kev[seg_c] = kacc;  // an event wholly inside this run
-                  }
-                } else {
-                  tail = kacc;  // the event goes on in the next run
-                  has_tail = true;
-                }
-                first_seg = false;
+                if (is_head)
+                  head = kacc;
+                else if (fin)
+                  W.kev[seg_c] = kacc;
+                else
+                  tail = kacc;
                 kacc = 0.0;
               }
               if constexpr (BEST) {
-                W.bm[k - r0] = bmass;
-                W.br[k - r0] = brk;
+                if (is_head) {
+                  hd = bdist;
+                  hr = brk;
+                  hm = bmass;
+                } else if (fin) {
+                  W.bm[seg_c] = bmass;
+                  W.br[seg_c] = brk;
+                } else {
+                  td = bdist;
+                  tr = brk;
+                  tm = bmass;
+                }
                 brk = -1;
                 rk = 0;
               }
+              if (is_head) {
+                has_head = true;
+                head_c = seg_c;
+              }
+              has_tail = !fin;
+              first_seg = false;
             }
+          }
+        }
+        // Each shared event's K (best pair): the tails of the runs it spans,
+        // combined by a segmented scan keyed by event, then with the head of
+        // the run where it ends; an event that goes on into the next round
+        // takes the scan at the round's last run.  Keys grow with the lane: 2e
+        // for a tail on event e, 2e + 1 for a run whose last event e closed in
+        // it (cur_c is then e + 1), past every event for a run without pairs.
+        const int key = has_tail ? 2 * cur_c : (ran ? 2 * cur_c - 1 : 2 * ncp + 1);
+        if constexpr (BEST) {
+          double sd = has_tail ? td : 0.0;
+          int sr = has_tail ? tr : -1;
+          T sm = has_tail ? tm : T(0);
+          best_scan_wave<T>(sd, sr, sm, key);
+          const double pd = dpp_f64<kDppWaveShr1, 0xf>(sd);
+          const int pr = dpp_i32<kDppWaveShr1, 0xf>(sr, -1);
+          const T pmv = dpp_t<kDppWaveShr1, 0xf, T>(sm);
+          const int pk = dpp_i32<kDppWaveShr1, 0xf>(key, -1);
+          if (has_head) {
+            // the earlier runs' best, unless the head's is strictly better
+            const bool from_prev = pk == 2 * head_c;
+            double bd = from_prev ? pd : 0.0;
+            int brr = from_prev ? pr : -1;
+            T bmv = from_prev ? pmv : T(0);
+            if (cand_better<T>(hd, hr, bd, brr)) {
+              brr = hr;
+              bmv = hm;
+            }
+            W.bm[head_c] = bmv;
+            W.br[head_c] = brr;
+          }
+          if (has_tail && kend == r0 + qn) {
+            W.bm[cur_c] = sm;
+            W.br[cur_c] = sr;
           }
         }
         if constexpr (kComp) {
           if (want_k) {
-            // each shared event's K: the tails of the runs it spans, summed by
-            // a segmented scan keyed by event, plus the head of the run where
-            // it ends; an event that goes on into the next round takes the
-            // scan at the round's last run.  Keys grow with the lane: 2e for a
-            // tail on event e, 2e + 1 for a run whose last event e closed in
-            // it (cur_c is then e + 1), past every event for a run without pairs.
-            const int key = has_tail ? 2 * cur_c : (ran ? 2 * cur_c - 1 : 2 * ncp + 1);
             const double sc = seg_scan_wave(has_tail ? tail : 0.0, key);
             const double sp = dpp_f64<kDppWaveShr1, 0xf>(sc);
             const int kp = dpp_i32<kDppWaveShr1, 0xf>(key, -1);
@@ -965,37 +1045,18 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
             if (max(plo_rel, r0) < min(phi_rel, r0 + qn)) ks += W.kev[my_c];  // pairs in this round
           }
         }
-        if (BEST && in_chunk && n_e >= 2) {
-          // the event lane takes the partials of the runs that covered its
-          // pairs of this round, in lane order (in rank order)
-          const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
-          const int lo = max(plo_rel, r0) - r0, hi = min(phi_rel, r0 + qn) - r0;
-          // kColl segments' slots read per LDS wait (a serial chain of waits
-          // per event otherwise), then taken in order
-          const int seg_end = (hi + m - 1) / m;  // the segments with seg m < hi
-          for (int seg = lo / m; seg < seg_end; seg += kColl) {
-            int slot[kColl];
-#pragma unroll
-            for (int u = 0; u < kColl; ++u) slot[u] = min((min(seg + u, seg_end - 1) + 1) * m, hi) - 1;
-            int rv[kColl];
-            T mv[kColl];
-#pragma unroll
-            for (int u = 0; u < kColl; ++u) {
-              rv[u] = W.br[slot[u]];
-              mv[u] = W.bm[slot[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kColl; ++u) {
-              if (seg + u < seg_end) {
-                {
-                  if (rv[u] >= 0) {
-                    const double d = fabs((double)mv[u] - A.target);
-                    if (ebr < 0 || d < ebd) {
-                      ebd = d;
-                      ebr = rv[u];
-                      ebm = mv[u];
-                    }
-                  }
+        if constexpr (BEST) {
+          if (in_chunk && n_e >= 2) {
+            const int plo_rel = (int)(plo - q0), phi_rel = (int)(phi - q0);
+            if (max(plo_rel, r0) < min(phi_rel, r0 + qn)) {  // pairs in this round (in rank order)
+              const int r = W.br[my_c];
+              if (r >= 0) {
+                const T bmv = W.bm[my_c];
+                const double d = fabs((double)bmv - A.target);
+                if (ebr < 0 || d < ebd) {
+                  ebd = d;
+                  ebr = r;
+                  ebm = bmv;
                 }
               }
             }
