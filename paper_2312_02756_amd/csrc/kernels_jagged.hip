@@ -13,10 +13,12 @@
 // contiguous runs, one per lane, each lane stepping its run in lexicographic
 // order across event boundaries, so every lane has the same work whatever the
 // event sizes.  In the compensated mode each lane also sums K_ij over its run
-// per event, and the event's lane adds those partial sums in lane order:
-// deterministic for a tiling, never dependent on timing.  The same kernel can
-// choose, per event, the pair whose mass lies closest to a target (candidates
-// per run, combined in rank order) instead of storing pair masses.
+// per event, and the partial sums of an event that spans runs are combined
+// across lanes by a segmented scan keyed by event: deterministic for a
+// tiling, never dependent on timing.  The same kernel can choose, per event,
+// the pair whose mass lies closest to a target (a candidate per run and
+// event, combined by the same scheme under a total order) instead of storing
+// pair masses.
 // The reverse mode stages one particle per thread of a workgroup (below).
 // An event with more particles than fit in LDS is left to a second, small
 // launch (k_event_reduce_big), where a whole workgroup takes it straight from
@@ -708,12 +710,13 @@ __device__ __forceinline__ void next_chunk(int from, int nev, uint64_t valid, bo
 //      banks), and from there to pair_m with coalesced stores; FP32 masses
 //      (two lanes of a store instruction per 64-byte segment at m = 8) are
 //      stored by their lane, in one round (plain mode) or rounds of qcap
-//      (compensated mode, for the partial sums below).  In the compensated
-//      mode each
-//      lane also sums K = E_i E_j - p_i.p_j of its pairs per event and leaves
-//      the partial sum at the slot of its last pair in that event, and the
-//      event's lane adds those partials (the lanes in order, then the rounds
-//      in order): deterministic for a tiling.
+//      (compensated mode and best pair, whose chunks hold at most one round
+//      of pairs unless a single event has more).  In the compensated mode
+//      each lane also sums K = E_i E_j - p_i.p_j of its pairs per event: an
+//      event inside one run takes the lane's sum, an event spanning runs the
+//      scan of their tails (keyed by event over the lanes) plus the head of
+//      the run where it ends; the event's lane adds its K per round:
+//      deterministic for a tiling.
 // Events with more than cap particles are left to k_event_reduce_big.  In
 // the FP32 compensated mode a pair whose error bound asks for FP64 makes its
 // K a NaN; the event's lane then writes a marker -- a quiet NaN with a fixed
