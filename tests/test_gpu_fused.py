@@ -231,3 +231,71 @@ def test_fused_empty_inputs():
     z = torch.zeros(1, dtype=torch.int64, device=DEV)
     r, m = glv.glv_event_reduce_best_pair((e64,) * 4, z, TARGET, pair_offsets=z)
     assert r.numel() == 0 and m.numel() == 0
+
+
+def _spanning_layout(seed):
+    """Events laid out so that the lanes' runs of pairs cross many events and
+    events cross many runs and rounds: blocks of one-pair events (n = 2),
+    events of 12 to 20 particles (66 to 190 pairs: several 64-pair rounds on
+    their own), one- and zero-particle events, and Poisson(8) events."""
+    g = np.random.default_rng(seed)
+    counts = []
+    for _ in range(60):
+        kind = int(g.integers(0, 4))
+        if kind == 0:
+            counts += [2] * int(g.integers(1, 50))
+        elif kind == 1:
+            counts += [int(g.integers(12, 21))]
+        elif kind == 2:
+            counts += [int(c) for c in g.integers(0, 2, int(g.integers(1, 6)))]
+        else:
+            counts += [int(c) for c in np.minimum(g.poisson(8, int(g.integers(1, 20))), 64)]
+    counts = np.array(counts, dtype=np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    return off, g
+
+
+@pytest.mark.parametrize("tiling", [(64, 64, 128, 64), (64, 16, 64, 128), (256, 32, 256, 192),
+                                    (64, 64, 128, 1024)])
+def test_cross_run_combines(tiling):
+    """The compensated event mass and the fused best pair combine each event's
+    partial results across the lanes' runs of pairs (a segmented scan over the
+    lanes plus the run where the event ends) and across rounds.  On layouts
+    that make runs cross many events and events cross many runs and rounds:
+    compensated event masses against the oracle's accurate masses (FP32 and
+    FP64), reproducible bit for bit for the tiling, with pair masses
+    independent of it; the fused best pair bitwise the unfused selection."""
+    off, g = _spanning_layout(977 + tiling[3])
+    a, _, _ = synth.pairs_stress(synth.rng(977), int(off[-1]))
+    go = torch.from_numpy(off).to(DEV)
+    po = glv.glv_pair_offsets(go)
+    for dtype in (torch.float32, torch.float64):
+        gp = gpu(a, dtype)
+        try:
+            _, em, pm = glv.glv_event_reduce(gp, go, pair_offsets=po, mode="compensated", tiling=tiling)
+        except RuntimeError as e:  # a tiling beyond the LDS limit is refused, never run
+            assert "GLV_EINVAL_TILING" in str(e), e
+            continue
+        _, em2, pm2 = glv.glv_event_reduce(gp, go, pair_offsets=po, mode="compensated", tiling=tiling)
+        assert torch.equal(em, em2) and torch.equal(pm, pm2)
+        _, _, pm_d = glv.glv_event_reduce(gp, go, pair_offsets=po, mode="compensated")
+        assert torch.equal(pm, pm_d), "pair masses do not depend on the tiling"
+        wa = widened(a, dtype)
+        _, em_or, _, _ = oracle.event_reduce("PtEtaPhiM", off, wa, mode=oracle.ACCURATE)
+        got = host(em).astype(np.float64)
+        tol = mass_tol_comp_f32(em_or) if dtype == torch.float32 else 64 * U64 * np.abs(em_or) + 1e-300
+        bad = np.nonzero(~(np.abs(got - em_or) <= tol))[0]
+        assert bad.size == 0, (dtype, tiling, bad[:5], got[bad[:5]], em_or[bad[:5]])
+    for dtype, mode in ((torch.float64, "plain"), (torch.float32, "compensated")):
+        gp = gpu(a, dtype)
+        try:
+            rank, bm = glv.glv_event_reduce_best_pair(gp, go, TARGET, pair_offsets=po, mode=mode, tiling=tiling)
+        except RuntimeError as e:
+            assert "GLV_EINVAL_TILING" in str(e), e
+            continue
+        _, _, pm = glv.glv_event_reduce(gp, go, pair_offsets=po, mode=mode, tiling=tiling, want_total=False,
+                                        want_event_m=False)
+        r2, m2 = glv.glv_event_best_pair(po, pm, TARGET)
+        assert np.array_equal(host(rank), host(r2)), (dtype, mode, tiling)
+        assert np.array_equal(host(bm), host(m2), equal_nan=True), (dtype, mode, tiling)
