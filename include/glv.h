@@ -384,6 +384,25 @@ glv_status glv_event_reduce_bwd(glv_dtype dtype, glv_coords coords, int64_t n_ev
                                 const void* grad_event_m, const void* grad_pair_m,
                                 void* const grad_p[4], const glv_tiling* tiling, void* stream);
 
+/* The same reverse mode given the forward's event totals (not in the paper):
+ * total[4] holds each event's total 4-vector as glv_event_reduce wrote it for
+ * these particles, in dtype, n_events entries per column, so that the
+ * event-mass term g_m dm(V)/dV takes V from it instead of summing the event's
+ * particles again -- what a caller that saved the forward's outputs (as
+ * autograd does) can pass.  The forward sums an event in the same order and
+ * precision as the backward would, so the result is bitwise that of
+ * glv_event_reduce_bwd wherever both staged the event (an event beyond the
+ * staging capacity of either is summed in another order).  total is read
+ * only when grad_event_m is given; it must be 4 non-NULL columns (else
+ * GLV_EINVAL_NULL) that do not overlap grad_p (GLV_EINVAL_ALIAS).  All other
+ * arguments and errors as in glv_event_reduce_bwd. */
+glv_status glv_event_reduce_bwd_totals(glv_dtype dtype, glv_coords coords, int64_t n_events,
+                                       const int64_t* offsets, const int64_t* pair_offsets,
+                                       const void* const p[4], const void* const total[4],
+                                       const void* const grad_total[4], const void* grad_event_m,
+                                       const void* grad_pair_m, void* const grad_p[4],
+                                       const glv_tiling* tiling, void* stream);
+
 /* Debug helper: counts violations of offsets[0] = 0, offsets non-decreasing,
  * offsets[n_events] = n_particles, and ADDS the count to *bad_count (device
  * int64, zeroed by the caller).  Asynchronous like every other call. */

@@ -25,7 +25,7 @@ GLV_PLAIN, GLV_COMPENSATED = 0, 1
 # Every symbol include/glv.h declares.
 EXPORTS = (
     "glv_invariant_mass", "glv_invariant_mass_bwd", "glv_boost", "glv_boost_bwd", "glv_pair_offsets",
-    "glv_event_reduce", "glv_event_reduce_bwd", "glv_validate_offsets", "glv_autotune_event_reduce",
+    "glv_event_reduce", "glv_event_reduce_bwd", "glv_event_reduce_bwd_totals", "glv_validate_offsets", "glv_autotune_event_reduce",
     "glv_current_tiling", "glv_autotune_event_reduce_bwd", "glv_current_tiling_bwd", "glv_status_str",
     "glv_abi_version", "glv_last_hip_error", "glv_convert", "glv_convert_bwd", "glv_lorentz_transform",
     "glv_lorentz_transform_bwd", "glv_rotate", "glv_rotate_bwd", "glv_rotate_axis_angle",
@@ -58,6 +58,7 @@ _SIGS = {
     "glv_pair_offsets": [_i64, _vp, _vp, _vp],
     "glv_event_reduce": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_event_reduce_bwd": [_i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "glv_event_reduce_bwd_totals": [_i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_validate_offsets": [_i64, _vp, _i64, _vp, _vp],
     "glv_autotune_event_reduce": [_i, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "glv_current_tiling": [_i, _i, _i, _vp],

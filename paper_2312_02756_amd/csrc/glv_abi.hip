@@ -781,6 +781,23 @@ glv_status glv_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const i
       glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t, (hipStream_t)stream));
 }
 
+glv_status glv_event_reduce_bwd_totals(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,
+                                       const int64_t* poff, const void* const p[4], const void* const tot[4],
+                                       const void* const gt[4], const void* gem, const void* gpair,
+                                       void* const gp[4], const glv_tiling* tiling, void* stream) {
+  glv_status st = validate_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp);
+  if (st != GLV_OK || ne == 0) return st;
+  if (!tot || !nonnull<4>(tot)) return GLV_EINVAL_NULL;
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j)
+      if (overlap(rng(tot[j], ne, elem(dt)), rng(gp[k], 1, elem(dt)))) return GLV_EINVAL_ALIAS;
+  glv::Tiling t;
+  st = resolve_tiling(dt, co, GLV_PLAIN, tiling, true, &t);
+  if (st != GLV_OK) return st;
+  return hip_status(glv::launch_event_reduce_bwd(dt, co, ne, off, poff, p, gt, gem, gpair, gp, t,
+                                                 (hipStream_t)stream, gem ? tot : nullptr));
+}
+
 glv_status glv_current_tiling(glv_dtype dt, glv_coords co, glv_mode mode, glv_tiling* out) {
   if (!dtype_ok(dt)) return GLV_EINVAL_DTYPE;
   if (!coords_ok(co)) return GLV_EINVAL_COORDS;

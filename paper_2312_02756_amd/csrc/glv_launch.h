@@ -105,6 +105,6 @@ hipError_t launch_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t n_events
                                    const int64_t* offsets, const int64_t* pair_offsets,
                                    const void* const p[4], const void* const gt[4],
                                    const void* gem, const void* gpair, void* const gp[4],
-                                   const Tiling& t, hipStream_t s);
+                                   const Tiling& t, hipStream_t s, const void* const tot[4] = nullptr);
 
 }  // namespace glv

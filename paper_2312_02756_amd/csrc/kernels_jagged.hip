@@ -1177,6 +1177,7 @@ struct BwdArgs {
   const T* gt[4];
   const T* gem;
   const T* gpair;
+  const T* tot[4];  // the forward's event totals, or null: recomputed
   T* gp[4];
   int64_t ne;
   int epb;         // events per wavefront tile
@@ -1207,19 +1208,26 @@ __device__ __forceinline__ void partner_sum_global(const BwdArgs<T, COORDS>& A, 
 template <typename T, int COORDS>
 __device__ void big_event_bwd(const BwdArgs<T, COORDS>& A, int64_t e, int64_t lo, int64_t hi, double* red) {
   const int64_t n = hi - lo;
-  // total 4-vector for the event-mass term
-  double acc[4] = {0, 0, 0, 0};
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    T v[4];
-    to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], v);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += (double)v[k];
-  }
-  T tot[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
+  // total 4-vector for the event-mass term: the forward's, or summed here
   T ut[4] = {0, 0, 0, 0};
-  if (A.gem) dmass<T>(tot, A.gem[e], ut);
+  if (A.gem) {
+    T tot[4];
+    if (A.tot[0]) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) tot[k] = A.tot[k][e];
+    } else {
+      double acc[4] = {0, 0, 0, 0};
+      for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        T v[4];
+        to_cart<COORDS>(A.p.c[0][i], A.p.c[1][i], A.p.c[2][i], A.p.c[3][i], v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += (double)v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) tot[k] = (T)block_sum(acc[k], red);
+    }
+    dmass<T>(tot, A.gem[e], ut);
+  }
   if (A.gt[0]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) ut[k] += A.gt[k][e];
@@ -1342,7 +1350,8 @@ __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, CO
       }
       // the event lane's upstreams (g_total, g_m), staged with the rest
       const bool evl = want_u && tev < nch;
-      T gtv[4] = {0, 0, 0, 0}, gmv = 0;
+      const bool given_v = want_v && A.tot[0] != nullptr;  // the forward's totals: no sum here
+      T gtv[4] = {0, 0, 0, 0}, gmv = 0, tv[4] = {0, 0, 0, 0};
       if (evl) {
         const int64_t e = e0 + ca + tev;
         if (A.gt[0]) {
@@ -1350,6 +1359,10 @@ __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, CO
           for (int k = 0; k < 4; ++k) gtv[k] = A.gt[k][e];
         }
         if (want_v) gmv = A.gem[e];
+        if (given_v) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) tv[k] = A.tot[k][e];
+        }
       }
       for (int t = tid; t <= nch; t += blockDim.x)
         ch[t] = EvRec{(int)(s_off[ca + t] - pbase), pairs ? (int)(s_poff[ca + t] - q0) : 0};
@@ -1376,7 +1389,13 @@ __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, CO
         }
       }
       if (evl) {
-        s_ut[tev] = R4{gtv[0], gtv[1], gtv[2], gtv[3]};
+        if (given_v) {  // g_total + g_m dm(V)/dV at once, from the forward's V
+          T ud[4];
+          dmass<T>(tv, gmv, ud);
+          s_ut[tev] = R4{ud[0] + gtv[0], ud[1] + gtv[1], ud[2] + gtv[2], ud[3] + gtv[3]};
+        } else {
+          s_ut[tev] = R4{gtv[0], gtv[1], gtv[2], gtv[3]};
+        }
         s_gm[tev] = gmv;
       }
       LegJ<T> L = to_cart_j<COORDS, T, true>(c[0], c[1], c[2], c[3]);
@@ -1386,7 +1405,7 @@ __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, CO
       // one lane per event: the upstream every particle's 4-vector receives
       // from the event outputs, g_total + g_m dm(V)/dV, with V summed in CSR
       // order
-      if (evl && want_v) {
+      if (evl && want_v && !given_v) {
         const int lo = ch[tev].o, hi = ch[tev + 1].o;
         Acc vt[4] = {0, 0, 0, 0};
         int i = lo;
@@ -1575,11 +1594,12 @@ int bwd_cap(const Tiling& t) { return std::min(t.lds_particles, t.block); }
 template <typename T, int COORDS>
 hipError_t bwd_typed(int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
                      const void* const gt[4], const void* gem, const void* gpair, void* const gp[4],
-                     const Tiling& t, size_t lds, hipStream_t s) {
+                     const void* const tot[4], const Tiling& t, size_t lds, hipStream_t s) {
   BwdArgs<T, COORDS> A;
   for (int k = 0; k < 4; ++k) {
     A.p.c[k] = (const T*)p[k];
     A.gt[k] = gt ? (const T*)gt[k] : nullptr;
+    A.tot[k] = tot ? (const T*)tot[k] : nullptr;
     A.gp[k] = (T*)gp[k];
   }
   A.off = off;
@@ -1620,16 +1640,16 @@ hipError_t fwd_dt(glv_coords co, glv_mode mode, int64_t ne, const int64_t* off, 
 template <typename T>
 hipError_t bwd_dt(glv_coords co, int64_t ne, const int64_t* off, const int64_t* poff, const void* const p[4],
                   const void* const gt[4], const void* gem, const void* gpair, void* const gp[4],
-                  const Tiling& t, size_t lds, hipStream_t s) {
+                  const void* const tot[4], const Tiling& t, size_t lds, hipStream_t s) {
   switch (co) {
     case GLV_PXPYPZE:
-      return bwd_typed<T, GLV_PXPYPZE>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+      return bwd_typed<T, GLV_PXPYPZE>(ne, off, poff, p, gt, gem, gpair, gp, tot, t, lds, s);
     case GLV_PTETAPHIM:
-      return bwd_typed<T, GLV_PTETAPHIM>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+      return bwd_typed<T, GLV_PTETAPHIM>(ne, off, poff, p, gt, gem, gpair, gp, tot, t, lds, s);
     case GLV_PXPYPZM:
-      return bwd_typed<T, GLV_PXPYPZM>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+      return bwd_typed<T, GLV_PXPYPZM>(ne, off, poff, p, gt, gem, gpair, gp, tot, t, lds, s);
     default:
-      return bwd_typed<T, GLV_PTETAPHIE>(ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+      return bwd_typed<T, GLV_PTETAPHIE>(ne, off, poff, p, gt, gem, gpair, gp, tot, t, lds, s);
   }
 }
 
@@ -1690,10 +1710,10 @@ hipError_t launch_event_reduce(glv_dtype dt, glv_coords co, glv_mode mode, int64
 hipError_t launch_event_reduce_bwd(glv_dtype dt, glv_coords co, int64_t ne, const int64_t* off,
                                    const int64_t* poff, const void* const p[4], const void* const gt[4],
                                    const void* gem, const void* gpair, void* const gp[4], const Tiling& t,
-                                   hipStream_t s) {
+                                   hipStream_t s, const void* const tot[4]) {
   size_t lds = event_reduce_bwd_lds_bytes(dt, t);
-  if (dt == GLV_F64) return bwd_dt<double>(co, ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
-  return bwd_dt<float>(co, ne, off, poff, p, gt, gem, gpair, gp, t, lds, s);
+  if (dt == GLV_F64) return bwd_dt<double>(co, ne, off, poff, p, gt, gem, gpair, gp, tot, t, lds, s);
+  return bwd_dt<float>(co, ne, off, poff, p, gt, gem, gpair, gp, tot, t, lds, s);
 }
 
 }  // namespace glv

@@ -426,7 +426,10 @@ def glv_event_reduce(p, offsets, pair_offsets=None, coords="PtEtaPhiM", mode="pl
 
 
 def glv_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None, grad_event_m=None, grad_pair_m=None,
-                         coords="PtEtaPhiM", tiling=None):
+                         coords="PtEtaPhiM", tiling=None, total=None):
+    """Reverse mode of glv_event_reduce (plain).  `total`: the forward's event
+    totals (4 columns), if at hand -- then glv_event_reduce_bwd_totals, which
+    takes the event-mass term's V from them instead of summing it again."""
     dev, dt = p[0].device, p[0].dtype
     _check_device(p[0])
     offsets = _offsets(offsets, dev)
@@ -440,11 +443,19 @@ def glv_event_reduce_bwd(p, offsets, pair_offsets=None, grad_total=None, grad_ev
     gpm = _cols([grad_pair_m], None, dt, dev, "grad_pair_m")[0] if grad_pair_m is not None else None
     gp = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
     lib = _lib.load()
+    gtp = P4(*[t.data_ptr() for t in gt]) if gt else None
+    if total is not None:
+        tot = _cols(total, ne, dt, dev, "total")
+        check("glv_event_reduce_bwd_totals",
+              lib.glv_event_reduce_bwd_totals(_dtype_code(dt), _coords_code(coords), ne, _ptr(offsets),
+                                              _ptr(pair_offsets), P4(*[t.data_ptr() for t in p]),
+                                              P4(*[t.data_ptr() for t in tot]), gtp, _ptr(gem), _ptr(gpm),
+                                              P4(*[t.data_ptr() for t in gp]), _tiling(tiling), _stream(dev)))
+        return gp
     check("glv_event_reduce_bwd",
           lib.glv_event_reduce_bwd(_dtype_code(dt), _coords_code(coords), ne, _ptr(offsets), _ptr(pair_offsets),
-                                   P4(*[t.data_ptr() for t in p]), P4(*[t.data_ptr() for t in gt]) if gt else None,
-                                   _ptr(gem), _ptr(gpm), P4(*[t.data_ptr() for t in gp]), _tiling(tiling),
-                                   _stream(dev)))
+                                   P4(*[t.data_ptr() for t in p]), gtp, _ptr(gem), _ptr(gpm),
+                                   P4(*[t.data_ptr() for t in gp]), _tiling(tiling), _stream(dev)))
     return gp
 
 

@@ -250,6 +250,15 @@ def test_jagged_validation(lib):
         t = _lib.glv_tiling(*bad)
         assert h(2, 1, 10, OFF, PO, cols(P), None, None, PM, cols(T), ctypes.byref(t), None) == TILING, bad
     assert h(2, 1, 10, OFF, PO, cols(P), None, None, None, cols(P), None, None) == ALIAS
+    # the reverse mode given the forward's totals: 4 columns required, not over grad_p
+    b = lib.glv_event_reduce_bwd_totals
+    G = 200 * GiB
+    assert b(2, 1, 10, OFF, PO, cols(P), None, None, EM, None, cols(G), None, None) == NULL
+    assert b(2, 1, 10, OFF, PO, cols(P), _lib.P4(T, T + GiB, T + 2 * GiB, None), None, EM, None, cols(G), None,
+             None) == NULL
+    assert b(2, 1, 10, OFF, PO, cols(P), cols(G), None, EM, None, cols(G), None, None) == ALIAS
+    assert b(2, 1, 10, OFF, None, cols(P), cols(T), None, EM, PM, cols(G), None, None) == OFFSETS
+    assert b(2, 1, 10, OFF, PO, cols(P), cols(T), None, EM, None, cols(P), None, None) == ALIAS
     v = lib.glv_validate_offsets
     assert v(10, OFF, -1, EM, None) == SIZE
     assert v(10, OFF, 5, None, None) == NULL

@@ -266,6 +266,45 @@ def test_event_reduce_bwd(coords, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PxPyPzM"])
+def test_event_reduce_bwd_with_forward_totals(coords, dtype):
+    """The reverse mode fed the forward's event totals: bitwise the
+    recomputing call on every event both launches stage (the same CSR-order
+    sum), within the oracle's bound on the rest (a 300-particle event beyond
+    the staged capacity of the small tiling)."""
+    counts = np.concatenate([np.minimum(synth.rng(717).poisson(8, 1500), 64), [0, 1, 300, 2, 0]]).astype(np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    g = synth.rng(718)
+    p, _ = synth.pairs_generic(g, int(off[-1]))
+    if coords != "PtEtaPhiM":
+        c = oracle.to_cartesian("PtEtaPhiM", p)
+        p = c if coords == "PxPyPzE" else (c[0], c[1], c[2], p[3])
+    ne = counts.size
+    po = oracle.pair_offsets(off)
+    gt = synth.upstream(g, ne, 4)
+    gem = g.standard_normal(ne)
+    gpr = g.standard_normal(int(po[-1]))
+    wp = widened(p, dtype)
+    want = oracle.event_reduce_vjp(coords, off, wp, widened(gt, dtype), widened([gem], dtype)[0],
+                                   widened([gpr], dtype)[0])
+    pg, og = gpu(p, dtype), _off(off)
+    small = np.repeat(counts <= 64, counts)
+    for tiling in (None, (128, 16, 128)):
+        tot, _, _ = glv.glv_event_reduce(pg, og, coords=coords, want_event_m=False, want_pair_m=False,
+                                         tiling=tiling)
+        for with_gt, with_gpr in ((True, True), (False, False)):
+            kw = dict(grad_total=gpu(gt, dtype) if with_gt else None, grad_event_m=gpu([gem], dtype)[0],
+                      grad_pair_m=gpu([gpr], dtype)[0] if with_gpr else None, coords=coords, tiling=tiling)
+            ref = [host(c) for c in glv.glv_event_reduce_bwd(pg, og, **kw)]
+            got = [host(c) for c in glv.glv_event_reduce_bwd(pg, og, total=tot, **kw)]
+            for k in range(4):
+                np.testing.assert_array_equal(got[k][small], ref[k][small], err_msg=f"{tiling} {with_gt} col {k}")
+            if with_gt and with_gpr:
+                _check_bwd(off, wp, dtype, coords, [c.astype(np.float64) for c in got], want, tiling)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_event_reduce_bwd_pair_cap_and_missing_upstreams(dtype):
     """Events of 40-50 particles against a tiling of 256 staged particles and
     1024 staged pair gradients: the pair cap, not the particle cap, ends the
