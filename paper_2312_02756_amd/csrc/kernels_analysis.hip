@@ -12,12 +12,30 @@ constexpr int kHistBlock = 1024;
 // its counters into the global ones once, so fewer, larger workgroups mean
 // fewer global atomics on each bin.
 constexpr int64_t kHistGrid = 256;
+constexpr int kHistUnroll = 4;   // value packs in flight per thread
 constexpr int kBestLanes = 8;    // lanes per event in the best-pair kernel
 constexpr int kBestBlock = 256;  // 32 events per workgroup
 constexpr int kBestUnroll = 4;   // pair loads in flight per lane
 
+// Counts one value: the in-range bins by LDS atomics, the under- and
+// overflow in the lane's registers.  Values outside [lo, hi) all land on two
+// slots, whose atomics serialise within an instruction; where they are
+// common (41 % overflow in the 2^26-pair stress masses over [0, 200) GeV)
+// they dominated the kernel.
+__device__ __forceinline__ void hist_count(double x, const HistSpec& h, unsigned* bins, unsigned* n_lo,
+                                           unsigned* n_hi) {
+  const int64_t s = hist_slot(x, h);
+  if (s == 0)
+    ++*n_lo;
+  else if (s == h.nb + 1)
+    ++*n_hi;
+  else if (s > 0)
+    atomicAdd(&bins[s], 1u);
+}
+
 // Per-workgroup counters in LDS, merged with one global atomic per non-empty
-// slot.  Grid-stride over packs of V values (16-byte loads), then the tail.
+// slot.  Grid-stride over packs of V values (16-byte loads, kHistUnroll in
+// flight per thread before their counts), then the rest and the tail.
 template <typename T, int V>
 __global__ __launch_bounds__(kHistBlock) void k_hist_lds(const T* __restrict__ v, int64_t n, HistSpec h,
                                                          unsigned long long* __restrict__ counts) {
@@ -28,21 +46,28 @@ __global__ __launch_bounds__(kHistBlock) void k_hist_lds(const T* __restrict__ v
   const int64_t nv = n / V;
   const int64_t tid = (int64_t)blockIdx.x * kHistBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kHistBlock;
-  for (int64_t i = tid; i < nv; i += stride) {
+  unsigned n_lo = 0, n_hi = 0;
+  int64_t i = tid;
+  for (; i + (kHistUnroll - 1) * stride < nv; i += kHistUnroll * stride) {
+    Pack<T, V> p[kHistUnroll];
+#pragma unroll
+    for (int u = 0; u < kHistUnroll; ++u) p[u] = load_pack<T, V>(v, i + u * stride);
+#pragma unroll
+    for (int u = 0; u < kHistUnroll; ++u)
+#pragma unroll
+      for (int e = 0; e < V; ++e) hist_count((double)p[u].v[e], h, bins, &n_lo, &n_hi);
+  }
+  for (; i < nv; i += stride) {
     const Pack<T, V> p = load_pack<T, V>(v, i);
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      const int64_t s = hist_slot((double)p.v[e], h);
-      if (s >= 0) atomicAdd(&bins[s], 1u);
-    }
+    for (int e = 0; e < V; ++e) hist_count((double)p.v[e], h, bins, &n_lo, &n_hi);
   }
   if constexpr (V > 1) {
     const int64_t t = nv * V + tid;
-    if (t < n) {
-      const int64_t s = hist_slot((double)v[t], h);
-      if (s >= 0) atomicAdd(&bins[s], 1u);
-    }
+    if (t < n) hist_count((double)v[t], h, bins, &n_lo, &n_hi);
   }
+  if (n_lo) atomicAdd(&bins[0], n_lo);
+  if (n_hi) atomicAdd(&bins[nslot - 1], n_hi);
   __syncthreads();
   for (int b = threadIdx.x; b < nslot; b += kHistBlock)
     if (bins[b]) atomicAdd(&counts[b], (unsigned long long)bins[b]);
