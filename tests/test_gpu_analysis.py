@@ -52,6 +52,23 @@ def test_histogram_accumulates_and_full_size():
     assert np.array_equal(host(c).astype(np.uint64), want + oracle.histogram(m[: n // 2], 0.0, 200.0, 1000))
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_histogram_mostly_outside_the_range(dtype):
+    """Nearly every value under- or overflows (their counts are kept per lane
+    and added once per thread): sizes past several full rounds of four packs
+    per thread of the whole grid, a ragged tail and a misaligned start."""
+    n = 5 * (1 << 20) + 37
+    m = _masses(n - len(SPECIAL), 961)
+    mt = torch.from_numpy(m).to(DEV).to(dtype)
+    wide = host(mt).astype(np.float64)
+    for lo, hi, nb in ((100.0, 101.0, 10), (0.0, 1.0, 1000), (150.0, 1e9, 3)):
+        for sl in (slice(None), slice(1, None), slice(5, n - 11)):
+            c = host(glv.glv_mass_histogram(mt[sl], lo, hi, nb)).astype(np.uint64)
+            want = oracle.histogram(wide[sl], lo, hi, nb)
+            assert np.array_equal(c, want), (lo, hi, nb, sl)
+            assert want[0] + want[-1] > 0.5 * want.sum()
+
+
 def _events(n_events, seed, nan_frac=0.01):
     g = synth.rng(seed)
     counts = np.minimum(g.poisson(8, n_events), 64)
