@@ -1121,6 +1121,29 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
 // mass without event masses) and recomputes their pair masses and event mass
 // with the redo, counting the redone pairs; their totals stay as computed.
 constexpr int kBigBlock = 256;
+// Events each thread of the second launch sizes per pass (kBigScan coalesced
+// slices of kBigBlock events): all their offsets are read at once, so the
+// scan of 2^20 events takes one memory latency per workgroup and a grid that
+// fits the GPU at once (it took several rounds at one event per thread).
+constexpr int kBigScan = 8;
+
+// Sizes of events base + k kBigBlock + threadIdx.x, k < kBigScan, or -1 past
+// the last event.
+__device__ __forceinline__ void scan_sizes(const int64_t* off, int64_t ne, int64_t base, int64_t n[kBigScan]) {
+  int64_t lo[kBigScan], hi[kBigScan];
+#pragma unroll
+  for (int k = 0; k < kBigScan; ++k) {
+    const int64_t e = base + k * kBigBlock + threadIdx.x;
+    lo[k] = 0;
+    hi[k] = -1;
+    if (e < ne) {
+      lo[k] = off[e];
+      hi[k] = off[e + 1];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kBigScan; ++k) n[k] = hi[k] - lo[k];
+}
 
 template <typename T, int COORDS, int MODE>
 __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORDS, MODE> A) {
@@ -1129,14 +1152,19 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORD
   __shared__ int64_t list[kBigBlock];  // event << 1 | (1: redo only)
   __shared__ int count;
   unsigned fb = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
-    const int64_t e = base + threadIdx.x;
-    bool big = false, redo = false;
-    if (e < A.ne) {
-      const int64_t n = A.off[e + 1] - A.off[e];
-      big = n > A.cap;
+  const int64_t step = (int64_t)gridDim.x * kBigBlock * kBigScan;
+  for (int64_t base = (int64_t)blockIdx.x * kBigBlock * kBigScan; base < A.ne; base += step) {
+    // kBigScan coalesced slices of kBigBlock events, all offsets in flight at once
+    int64_t n[kBigScan];
+    scan_sizes(A.off, A.ne, base, n);
+    unsigned bigm = 0, redom = 0;  // bit k: event k of this thread
+#pragma unroll
+    for (int k = 0; k < kBigScan; ++k) {
+      if (n[k] > A.cap) bigm |= 1u << k;
       if constexpr (kDefer) {
-        if (!big && n >= 2) {
+        const int64_t e = base + k * kBigBlock + threadIdx.x;
+        bool redo = false;
+        if (n[k] >= 2 && n[k] <= A.cap) {
           if (A.event_m)
             redo = is_redo_mark(A.event_m[e]);
           else if (A.best_m)
@@ -1144,19 +1172,25 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_big(FwdArgs<T, COORD
           else if (A.pair_m)
             redo = is_redo_mark(A.pair_m[A.poff[e]]);
         }
+        if (redo) redom |= 1u << k;
       }
     }
-    if (!__syncthreads_or(big || redo)) continue;
-    if (threadIdx.x == 0) count = 0;
-    __syncthreads();
-    if (big || redo) list[atomicAdd(&count, 1)] = (e << 1) | (redo ? 1 : 0);
-    __syncthreads();
-    const int nbig = count;
-    for (int b = 0; b < nbig; ++b) {
-      const int64_t eb = list[b] >> 1;
-      big_event<T, COORDS, MODE>(A, eb, A.off[eb], A.off[eb + 1], red, &fb, (list[b] & 1) == 0);
+#pragma unroll 1
+    for (int k = 0; k < kBigScan; ++k) {
+      const int64_t e = base + k * kBigBlock + threadIdx.x;
+      const bool big = (bigm >> k) & 1u, redo = (redom >> k) & 1u;
+      if (!__syncthreads_or(big || redo)) continue;
+      if (threadIdx.x == 0) count = 0;
+      __syncthreads();
+      if (big || redo) list[atomicAdd(&count, 1)] = (e << 1) | (redo ? 1 : 0);
+      __syncthreads();
+      const int nbig = count;
+      for (int b = 0; b < nbig; ++b) {
+        const int64_t eb = list[b] >> 1;
+        big_event<T, COORDS, MODE>(A, eb, A.off[eb], A.off[eb + 1], red, &fb, (list[b] & 1) == 0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if constexpr (MODE == GLV_COMPENSATED && sizeof(T) == 4) {
     if (A.fallback) {
@@ -1521,25 +1555,36 @@ __global__ __launch_bounds__(kBigBlock) void k_event_reduce_bwd_big(BwdArgs<T, C
   __shared__ double red[16];
   __shared__ int64_t list[kBigBlock];
   __shared__ int count;
-  for (int64_t base = (int64_t)blockIdx.x * kBigBlock; base < A.ne; base += (int64_t)gridDim.x * kBigBlock) {
-    const int64_t e = base + threadIdx.x;
-    const bool big = e < A.ne && bwd_big(A.off[e + 1] - A.off[e], A.cap, A.qcap, A.gpair != nullptr);
-    if (!__syncthreads_or(big)) continue;
-    if (threadIdx.x == 0) count = 0;
-    __syncthreads();
-    if (big) list[atomicAdd(&count, 1)] = e;
-    __syncthreads();
-    const int nbig = count;
-    for (int b = 0; b < nbig; ++b) {
-      const int64_t eb = list[b];
-      big_event_bwd<T, COORDS>(A, eb, A.off[eb], A.off[eb + 1], red);
+  const int64_t step = (int64_t)gridDim.x * kBigBlock * kBigScan;
+  for (int64_t base = (int64_t)blockIdx.x * kBigBlock * kBigScan; base < A.ne; base += step) {
+    int64_t n[kBigScan];
+    scan_sizes(A.off, A.ne, base, n);
+    unsigned bigm = 0;  // bit k: event k of this thread
+#pragma unroll
+    for (int k = 0; k < kBigScan; ++k)
+      if (n[k] >= 0 && bwd_big(n[k], A.cap, A.qcap, A.gpair != nullptr)) bigm |= 1u << k;
+#pragma unroll 1
+    for (int k = 0; k < kBigScan; ++k) {
+      const int64_t e = base + k * kBigBlock + threadIdx.x;
+      const bool big = (bigm >> k) & 1u;
+      if (!__syncthreads_or(big)) continue;
+      if (threadIdx.x == 0) count = 0;
+      __syncthreads();
+      if (big) list[atomicAdd(&count, 1)] = e;
+      __syncthreads();
+      const int nbig = count;
+      for (int b = 0; b < nbig; ++b) {
+        const int64_t eb = list[b];
+        big_event_bwd<T, COORDS>(A, eb, A.off[eb], A.off[eb + 1], red);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
 int big_grid(int64_t ne) {
-  return (int)std::min<int64_t>(std::max<int64_t>(1, (ne + kBigBlock - 1) / kBigBlock), 2048);
+  constexpr int64_t per = (int64_t)kBigBlock * kBigScan;
+  return (int)std::min<int64_t>(std::max<int64_t>(1, (ne + per - 1) / per), 2048);
 }
 
 
