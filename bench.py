@@ -390,7 +390,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path has no cross-GPU step: "
-              "shards would run independently, see the design notes)", file=sys.stderr)
+              "each GPU would reduce its own share of items and events independently)", file=sys.stderr)
         sys.exit(2)
 
     import torch

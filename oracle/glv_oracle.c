@@ -24,7 +24,7 @@
  * per-event (jagged) reduction are not in the paper; each function below says
  * what it is derived from.
  *
- * Readings of points the paper leaves open (listed in the design notes):
+ * Readings of points the paper leaves open:
  *   - conversions are the standard collider definitions:
  *       px = pt cos(phi), py = pt sin(phi), pz = pt sinh(eta),
  *       E  = sqrt((pt cosh(eta))^2 + M^2)      (PtEtaPhiM), E given (PtEtaPhiE);
