@@ -8,7 +8,8 @@
 // consecutive events and walks it in event-aligned chunks of at most
 // `lds_particles` particles, staging each particle once, converted, in its
 // own slice of LDS (no workgroup barrier: the wavefronts of a workgroup never
-// share data).  One lane per event sums its particles in CSR order; the
+// share data).  Four lanes per event sum its particles, one residue class of
+// the particle index modulo 4 each, combined in a fixed order; the
 // chunk's pairs -- contiguous in the output too -- are dealt out as equal
 // contiguous runs, one per lane, each lane stepping its run in lexicographic
 // order across event boundaries, so every lane has the same work whatever the
@@ -210,23 +211,35 @@ struct V4 {
   typedef T type __attribute__((ext_vector_type(4)));
 };
 
-// acc += rec[lo] + rec[lo+1] + ... + rec[hi-1], component-wise and in index
-// order (each component's additions stay sequential), two records read per
-// LDS wait (four would cost the kernel its sixth wavefront per SIMD).
-template <typename A, typename V>
-__device__ __forceinline__ void sum_records(const V* rec, int lo, int hi, A acc[4]) {
-  int t = lo;
-  for (; t + 2 <= hi; t += 2) {
-    const V r0 = rec[t], r1 = rec[t + 1];
+// The total of an event's records rec[lo..hi) is ((P0 + P1) + (P2 + P3)), P_r
+// the sum from zero, component-wise and in index order, of the records
+// lo + r, lo + r + 4, ...  Forward and reverse mode both give each event a
+// quad of lanes, one residue each, and combine the quad's sums in this order
+// (lane ^ 1, then lane ^ 2), so that their totals agree bit for bit.
+// residue_sum adds P_r to acc (two records read per LDS wait); with a
+// non-null `legs` (compensated mode) it also adds the residue's sum of M^2
+// (the mass is the fourth component of leg[2t]) to *m2.
+template <typename V>
+__device__ __forceinline__ void residue_sum(const V* rec, int lo, int hi, int r, double acc[4],
+                                            const V* legs = nullptr, double* m2 = nullptr) {
+  int t = lo + r;
+  for (; t + 4 < hi; t += 8) {
+    const V r0 = rec[t], r1 = rec[t + 4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += (A)r0[k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += (A)r1[k];
+    for (int k = 0; k < 4; ++k) acc[k] = (acc[k] + (double)r0[k]) + (double)r1[k];
+    if (legs) {
+      const double m0 = (double)legs[2 * t][3], m1 = (double)legs[2 * t + 8][3];
+      *m2 = (*m2 + m0 * m0) + m1 * m1;
+    }
   }
-  for (; t < hi; ++t) {
-    const V r = rec[t];
+  if (t < hi) {
+    const V r0 = rec[t];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += (A)r[k];
+    for (int k = 0; k < 4; ++k) acc[k] += (double)r0[k];
+    if (legs) {
+      const double m0 = (double)legs[2 * t][3];
+      *m2 += m0 * m0;
+    }
   }
 }
 
@@ -274,6 +287,10 @@ constexpr int kDppRowShr = 0x110;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
 constexpr int kDppWaveShr1 = 0x138;
+// Within each quad of lanes: lane ^ 1 and lane ^ 2 (quad_perm [1,0,3,2] and
+// [2,3,0,1]).
+constexpr int kDppQuadXor1 = 0xb1;
+constexpr int kDppQuadXor2 = 0x4e;
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_i32(int x, int old) {
@@ -697,9 +714,10 @@ __device__ __forceinline__ void next_chunk(int from, int nev, uint64_t valid, bo
 // reduced, so that their latency hides behind its arithmetic:
 //   1. stage: the chunk's particles are converted once and written to the
 //      wave's LDS;
-//   2. totals: the lane of each event sums its particles in CSR order (the
-//      plain event mass from that total; in the compensated mode also the
-//      sum of M^2);
+//   2. totals: four lanes per event, each summing one residue class of the
+//      particle index modulo 4 in index order, combined as
+//      ((P0 + P1) + (P2 + P3)) (the plain event mass from that total; in the
+//      compensated mode also the sum of M^2);
 //   3. pairs, in rounds: lane L takes the contiguous pairs [L m, (L + 1) m)
 //      of the round, locates the first by a binary search over the chunk's
 //      events with pairs and the square-root decode of its rank, then steps
@@ -819,48 +837,52 @@ __global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdAr
       prefetch_chunk(A.p, b1, (int)(readlane64(ohi, nb - 1) - b1), lane, &pre);
     }
 
-    // 2. one lane per event: totals in CSR order, plain event mass
+    // 2. totals: four lanes per event, one residue sum each (residue_sum),
+    //    combined across the lane quad in the fixed order, 16 events per
+    //    pass; the plain event mass from the total; in the compensated mode
+    //    also the sum of M^2, handed to the event's lane
     double msum = 0.0;
-    if (in_chunk && want_sums) {
-      const int lo = lo_rel, hi = lo_rel + n_e;
-      T tot[4];
-      if constexpr (kComp) {
-        // totals and sum of M^2 in one pass, two particles per LDS wait
-        double d[4] = {0, 0, 0, 0};
-        int t = lo;
-        for (; t + 2 <= hi; t += 2) {
-          const R4 r0 = W.cart[t], r1 = W.cart[t + 1];
-          const double m0 = (double)W.leg[2 * t][3], m1 = (double)W.leg[2 * t + 2][3];
+    if (want_sums) {
+      const int nk = cb - ca;  // events in the chunk
+      const int rr = lane & 3;
+      const R4* legs = nullptr;
+      if constexpr (kComp) legs = W.leg;
+      for (int c0 = 0; c0 < nk; c0 += 16) {
+        const int c = c0 + (lane >> 2);
+        const bool act = c < nk;
+        const int src = min(ca + c, 63);
+        const int glo = __shfl(lo_rel, src), gn = __shfl(n_e, src);
+        const int lo = act ? glo : 0, hi = act ? glo + gn : 0;
+        double tot[4] = {0, 0, 0, 0}, ms = 0.0;
+        residue_sum(W.cart, lo, hi, rr, tot, legs, &ms);
+        // (P0 + P1) + (P2 + P3): partner lane ^ 1, then lane ^ 2, of the quad
 #pragma unroll
-          for (int k = 0; k < 4; ++k) d[k] = (d[k] + (double)r0[k]) + (double)r1[k];
-          msum = (msum + m0 * m0) + m1 * m1;
+        for (int k = 0; k < 4; ++k) tot[k] = tot[k] + dpp_f64<kDppQuadXor1, 0xf>(tot[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot[k] = tot[k] + dpp_f64<kDppQuadXor2, 0xf>(tot[k]);
+        if constexpr (kComp) {
+          ms = ms + dpp_f64<kDppQuadXor1, 0xf>(ms);
+          ms = ms + dpp_f64<kDppQuadXor2, 0xf>(ms);
         }
-        if (t < hi) {
-          const R4 r0 = W.cart[t];
-          const double m0 = (double)W.leg[2 * t][3];
+        if (act && rr == 0) {
+          const int64_t e = e0 + ca + c;
+          T tt[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) d[k] += (double)r0[k];
-          msum += m0 * m0;
+          for (int k = 0; k < 4; ++k) tt[k] = (T)tot[k];
+          if (A.total[0]) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) store_out(A.total[k], e, tt[k]);
+          }
+          if constexpr (!kComp) {
+            if (A.event_m) store_out(A.event_m, e, mass_of(tt));
+          }
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
-      } else if constexpr (sizeof(T) == 4) {
-        double d[4] = {0, 0, 0, 0};
-        sum_records(W.cart, lo, hi, d);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) tot[k] = (T)d[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) tot[k] = T(0);
-        sum_records(W.cart, lo, hi, tot);
-      }
-      const int64_t e = e0 + lane;
-      if (A.total[0]) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) store_out(A.total[k], e, tot[k]);
-      }
-      if constexpr (!kComp) {
-        if (A.event_m) store_out(A.event_m, e, mass_of(tot));
+        if constexpr (kComp) {
+          // the event lanes of this pass take their quad's sum of M^2
+          const int q = lane - ca - c0;
+          const double mq = __shfl(ms, min(max(q, 0), 15) << 2);
+          if (q >= 0 && q < 16 && in_chunk) msum = mq;
+        }
       }
     }
 
@@ -1302,7 +1324,8 @@ __device__ __forceinline__ bool bwd_big(int64_t n, int cap, int qcap, bool pairs
 //     once, about n/2 per particle, whatever the particle's place;
 //   * in the same phase one lane per event (spread over the wavefronts; its
 //     g_total and g_m were loaded with the chunk) sums the event's vectors V
-//     in CSR order and stages g_total + g_m dm(V)/dV, the upstream every
+//     as the forward does (or takes the forward's totals) and stages
+//     g_total + g_m dm(V)/dV, the upstream every
 //     particle of the event receives from the event outputs;
 //   * thread t then walks its event's particles in CSR order and adds the
 //     pair terms c_ij (v_i + v_j) = c_ij v_i + c_ij v_j of its partners
@@ -1317,8 +1340,6 @@ template <typename T, int COORDS>
 __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   using R4 = typename V4<T>::type;
-  // event totals of FP32 data are summed in FP64
-  using Acc = typename std::conditional<sizeof(T) == 4, double, T>::type;
   const int epb = A.epb, cap = A.cap;  // cap <= blockDim.x
   const bool pairs = A.gpair != nullptr;
   const bool want_v = A.gem != nullptr;
@@ -1436,29 +1457,36 @@ __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, CO
       if (mine) cart[tid] = R4{L.v[0], L.v[1], L.v[2], L.v[3]};
       __syncthreads();
 
-      // one lane per event: the upstream every particle's 4-vector receives
-      // from the event outputs, g_total + g_m dm(V)/dV, with V summed in CSR
-      // order
-      if (evl && want_v && !given_v) {
-        const int lo = ch[tev].o, hi = ch[tev + 1].o;
-        Acc vt[4] = {0, 0, 0, 0};
-        int i = lo;
-        for (; i + 1 < hi; i += 2) {  // both reads first
-          const R4 v0 = cart[i], v1 = cart[i + 1];
+      // four lanes per event (events spread over the wavefronts like the
+      // event lanes): the upstream every particle's 4-vector receives from
+      // the event outputs, g_total + g_m dm(V)/dV, with V summed as the
+      // forward sums it (the same residue sums, combined in the same order)
+      if (want_v && !given_v) {
+        const int rr = tid & 3;
+        const int qe = ((tid & 63) >> 2) * nw + (tid >> 6);
+        for (int c0 = 0; c0 < nch; c0 += (int)blockDim.x >> 2) {
+          const int c = c0 + qe;
+          const bool act = c < nch;
+          int lo = 0, hi = 0;
+          if (act) {
+            lo = ch[c].o;
+            hi = ch[c + 1].o;
+          }
+          double vt[4] = {0, 0, 0, 0};
+          residue_sum(cart, lo, hi, rr, vt);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) vt[k] = (vt[k] + (Acc)v0[k]) + (Acc)v1[k];
+          for (int k = 0; k < 4; ++k) vt[k] = vt[k] + dpp_f64<kDppQuadXor1, 0xf>(vt[k]);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) vt[k] = vt[k] + dpp_f64<kDppQuadXor2, 0xf>(vt[k]);
+          if (act && rr == 0) {
+            T tot[4], ud[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
+            dmass<T>(tot, s_gm[c], ud);
+            const R4 gt4 = s_ut[c];
+            s_ut[c] = R4{ud[0] + gt4[0], ud[1] + gt4[1], ud[2] + gt4[2], ud[3] + gt4[3]};
+          }
         }
-        if (i < hi) {
-          const R4 v0 = cart[i];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) vt[k] += (Acc)v0[k];
-        }
-        T tot[4], ud[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) tot[k] = (T)vt[k];
-        dmass<T>(tot, s_gm[tev], ud);
-        const R4 gt4 = s_ut[tev];
-        s_ut[tev] = R4{ud[0] + gt4[0], ud[1] + gt4[1], ud[2] + gt4[2], ud[3] + gt4[3]};
       }
 
       // Pair ranks inside an event: pair (b, a), b < a, sits at
