@@ -358,7 +358,10 @@ glv_status glv_pair_offsets(int64_t n_events, const int64_t* offsets, int64_t* p
  *                 GLV_COMPENSATED event mass is requested
  *   p             4 particle columns in `coords`, offsets[n_events] entries
  * Outputs (each may be NULL = not wanted):
- *   total[4]  per-event sum of the particles' Cartesian vectors, in CSR order
+ *   total[4]  per-event sum of the particles' Cartesian vectors: four sums of
+ *             the particles whose index in the event is r mod 4, each in index
+ *             order, combined as ((P0 + P1) + (P2 + P3)); events beyond the
+ *             staging capacity by a fixed-tree workgroup sum
  *   event_m   mass of the total: GLV_PLAIN from total; GLV_COMPENSATED as
  *             m^2 = sum_i M_i^2 + 2 sum_{i<j} (E_i E_j - p_i.p_j) with each pair
  *             product from the cancellation-free form

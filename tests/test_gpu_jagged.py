@@ -269,8 +269,8 @@ def test_event_reduce_bwd(coords, dtype):
 @pytest.mark.parametrize("coords", ["PtEtaPhiM", "PxPyPzE", "PxPyPzM"])
 def test_event_reduce_bwd_with_forward_totals(coords, dtype):
     """The reverse mode fed the forward's event totals: bitwise the
-    recomputing call on every event both launches stage (the same CSR-order
-    sum), within the oracle's bound on the rest (a 300-particle event beyond
+    recomputing call on every event both launches stage (the same order of
+    summation), within the oracle's bound on the rest (a 300-particle event beyond
     the staged capacity of the small tiling)."""
     counts = np.concatenate([np.minimum(synth.rng(717).poisson(8, 1500), 64), [0, 1, 300, 2, 0]]).astype(np.int64)
     off = np.zeros(counts.size + 1, dtype=np.int64)
