@@ -703,9 +703,17 @@ __device__ __forceinline__ void next_chunk(int from, int nev, uint64_t valid, bo
   *cb = b;
 }
 
-#ifndef GLV_FWD_WAVES
-#define GLV_FWD_WAVES 1
-#endif
+// Wavefronts per SIMD the compiler must leave room for (its register budget):
+// five for the FP32 compensated reduction and the plain best pair, which
+// otherwise take 107 and 101 VGPRs and four wavefronts (a few bytes then
+// spill; on 2^20 events FP32 compensated 233 -> 218 us, fused best pair
+// 205 -> 198 us); none for the FP64 compensated mode and the compensated best
+// pair, which would spill more (the FP32 one measured 257 -> 292 us); the
+// plain reductions fit six anyway.
+template <typename T, int MODE, bool BEST>
+constexpr int fwd_waves() {
+  return (MODE == GLV_COMPENSATED && (sizeof(T) == 8 || BEST)) ? 1 : 5;
+}
 
 // The forward reduction.  Each wavefront of a workgroup independently takes a
 // tile of epb consecutive events (one per lane for their offsets) and walks it
@@ -741,7 +749,7 @@ __device__ __forceinline__ void next_chunk(int from, int nev, uint64_t valid, bo
 // payload -- into the event mass (or, without event masses, into the event's
 // first pair mass), and k_event_reduce_big recomputes the event.
 template <typename T, int COORDS, int MODE, bool BEST>
-__global__ __launch_bounds__(kMaxBlock, GLV_FWD_WAVES) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
+__global__ __launch_bounds__(kMaxBlock, (fwd_waves<T, MODE, BEST>())) void k_event_reduce(FwdArgs<T, COORDS, MODE> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   constexpr bool kComp = MODE == GLV_COMPENSATED;
   constexpr bool kDefer = kComp && (sizeof(T) == 4);
