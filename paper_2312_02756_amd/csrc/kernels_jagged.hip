@@ -664,11 +664,12 @@ __device__ __forceinline__ void stage_one(const WaveLds<T, MODE>& W, int t, T c0
   W.cart[t] = R4{v[0], v[1], v[2], v[3]};
 }
 
-// Compensated leg terms of a staged particle; *mass receives M.
-template <typename T, int MODE>
-__device__ __forceinline__ LegC<T> staged_leg(const WaveLds<T, MODE>& W, int t, T* mass) {
-  const typename V4<T>::type a = W.leg[2 * t];
-  const typename V4<T>::type b = W.leg[2 * t + 1];
+// Compensated leg terms of a staged particle, from its two leg records at q;
+// *mass receives M.
+template <typename T>
+__device__ __forceinline__ LegC<T> staged_leg(const typename V4<T>::type* q, T* mass) {
+  const typename V4<T>::type a = q[0];
+  const typename V4<T>::type b = q[1];
   LegC<T> L;
   L.pt = a[0];
   L.eta = a[1];
@@ -900,6 +901,10 @@ __global__ __launch_bounds__(kMaxBlock, (fwd_waves<T, MODE, BEST>())) void k_eve
     int ebr = -1;
     T ebm = T(0);
     if (need_po) {
+      // the records the pair loop reads per particle: the compensated legs
+      // (two records each) or the Cartesian vectors
+      constexpr int kStride = kComp ? 2 : 1;
+      const R4* const recs = kComp ? W.leg : W.cart;
       const int rcap = kStageMasses ? 64 * (((qcap >> 6) - 1) | 1) : ((kComp || BEST) ? qcap : 0x3fffffff);
       T* const pout = want_pairs ? A.pair_m + q0 : nullptr;
       for (int r0 = 0; r0 < nq; r0 += rcap) {
@@ -921,11 +926,16 @@ __global__ __launch_bounds__(kMaxBlock, (fwd_waves<T, MODE, BEST>())) void k_eve
         const bool ran = k < kend;
         if (k < kend) {
           int c = search_le32(W.ep, 0, ncp, k);
-          int o = W.eo[c], n = W.en[c];
+          const int o = W.eo[c], n = W.en[c];
           int i, j;
           decode_pair_small(k - W.ep[c], n, &i, &j);
           int cn = c + 1;
           int on = W.eo[cn], nn = W.en[cn];  // the next event with pairs (or the sentinel)
+          // the staged records of the pair's two particles and the end of
+          // their event, stepped directly (kStride records per particle)
+          const R4* qa = recs + kStride * (o + i);
+          const R4* qb = recs + kStride * (o + j);
+          const R4* qe = recs + kStride * (o + n);
           double kacc = 0.0;
           int rk = k - W.ep[c];  // in-event rank of pair k
           cur_c = c;
@@ -937,7 +947,7 @@ __global__ __launch_bounds__(kMaxBlock, (fwd_waves<T, MODE, BEST>())) void k_eve
             T mk;
             if constexpr (kComp) {
               T ma, mb;
-              const LegC<T> la = staged_leg<T, MODE>(W, o + i, &ma), lb = staged_leg<T, MODE>(W, o + j, &mb);
+              const LegC<T> la = staged_leg<T>(qa, &ma), lb = staged_leg<T>(qb, &mb);
               double kd;
               if constexpr (kDefer) {
                 bool redo;
@@ -949,7 +959,7 @@ __global__ __launch_bounds__(kMaxBlock, (fwd_waves<T, MODE, BEST>())) void k_eve
               }
               kacc += kd;
             } else {
-              const R4 ra = W.cart[o + i], b = W.cart[o + j];
+              const R4 ra = *qa, b = *qb;
               T w[4];
 #pragma unroll
               for (int q = 0; q < 4; ++q) w[q] = ra[q] + b[q];
@@ -972,18 +982,19 @@ __global__ __launch_bounds__(kMaxBlock, (fwd_waves<T, MODE, BEST>())) void k_eve
             // lexicographic successor within the chunk
             const int seg_c = cur_c;  // pair k's event
             bool fin = false;
-            if (++j == n) {
-              if (++i == n - 1) {
+            qb += kStride;
+            if (qb == qe) {  // the row's last partner: the next row
+              qa += kStride;
+              if (qa + kStride == qe) {  // the event's last pair: the next event
                 fin = true;
-                o = on;
-                n = nn;
-                i = 0;
+                qa = recs + kStride * on;
+                qe = qa + kStride * nn;
                 cur_c = cn;
                 cn = min(cn + 1, ncp);
                 on = W.eo[cn];
                 nn = W.en[cn];
               }
-              j = i + 1;
+              qb = qa + kStride;
             }
             if (fin || k + 1 == kend) {  // the run's partials at its last pair of the event
               // the head ends an event begun in an earlier run, the tail starts
