@@ -13,8 +13,7 @@ collider-shaped input already resident in HBM:
   event_reduce FP64 jagged reduction, 2^20 Poisson(8) events:
                totals, event mass and all pair masses           (~568 B/event)
   event_reduce32c  the same events in FP32, compensated mode     (~292 B/event)
-  event_reduce_bwd FP64 reverse mode of the jagged reduction, fed
-                   the forward's event totals                  (~856 B/event)
+  event_reduce_bwd FP64 reverse mode of the jagged reduction     (~824 B/event)
 
 value = kernel-items processed per second, in Gevents/s: every kernel of the
 step counts the items it processes (a pair, a vector or a collider event), so
@@ -503,13 +502,10 @@ def main():
         "event_reduce32c": lambda: lib.glv_event_reduce(F32, PTM, COMP, N_EVENTS, OFF.data_ptr(), PO.data_ptr(),
                                                         cP32, cTOT32, EM32.data_ptr(), PM32.data_ptr(),
                                                         FBJ.data_ptr(), None, sp),
-        # the reverse mode takes the event totals the forward of the same step wrote
-        "event_reduce_bwd": lambda: lib.glv_event_reduce_bwd_totals(F64, PTM, N_EVENTS, OFF.data_ptr(),
-                                                                    PO.data_ptr(), cP, cTOT, cGTOT, GEM.data_ptr(),
-                                                                    GPAIR.data_ptr(), cGP, None, sp),
+        "event_reduce_bwd": lambda: lib.glv_event_reduce_bwd(F64, PTM, N_EVENTS, OFF.data_ptr(), PO.data_ptr(), cP,
+                                                             cGTOT, GEM.data_ptr(), GPAIR.data_ptr(), cGP, None,
+                                                             sp),
     }
-    if "event_reduce_bwd" in run and calls["event_reduce"]() != 0:  # totals also when the forward is not run
-        raise RuntimeError("event_reduce: setup launch failed")
     # algorithmic bytes per launch: what each kernel must read and write once
     alg_bytes = {
         "mass_fwd": 72 * N_ITEMS, "mass_bwd": 136 * N_ITEMS, "boost_fwd": 88 * N_ITEMS,
@@ -517,7 +513,7 @@ def main():
         "boost_fwd32": 44 * N_ITEMS, "boost_bwd32": 72 * N_ITEMS, "mass_comp32": 36 * N_STRESS,
         "event_reduce": 32 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
         "event_reduce32c": 16 * n_part + 16 * (N_EVENTS + 1) + 20 * N_EVENTS + 4 * n_pairs,
-        "event_reduce_bwd": 64 * n_part + 16 * (N_EVENTS + 1) + 72 * N_EVENTS + 8 * n_pairs,
+        "event_reduce_bwd": 64 * n_part + 16 * (N_EVENTS + 1) + 40 * N_EVENTS + 8 * n_pairs,
     }
     units = {k: (N_EVENTS if k.startswith("event_reduce") else N_STRESS if k == "mass_comp32" else N_ITEMS)
              for k in KERNELS}

@@ -53,20 +53,17 @@ class EventReduce(torch.autograd.Function):
     def forward(ctx, offsets, pair_offsets, coords, *p):
         total, em, pm = glv.glv_event_reduce(p, offsets, pair_offsets, coords=coords, mode="plain")
         ctx.coords = coords
-        # the totals too: the backward's event-mass term takes V from them
-        ctx.save_for_backward(offsets, pair_offsets, *p, *total)
+        ctx.save_for_backward(offsets, pair_offsets, *p)
         return (*total, em, pm)
 
     @staticmethod
     def backward(ctx, g0, g1, g2, g3, gem, gpm):
-        offsets, pair_offsets, *pt = ctx.saved_tensors
-        p, total = pt[:4], pt[4:]
+        offsets, pair_offsets, *p = ctx.saved_tensors
         ne = offsets.numel() - 1
         gt = [g if g is not None else torch.zeros(ne, dtype=p[0].dtype, device=p[0].device) for g in (g0, g1, g2, g3)]
         gp = glv.glv_event_reduce_bwd(p, offsets, pair_offsets, grad_total=[g.contiguous() for g in gt],
                                       grad_event_m=gem.contiguous() if gem is not None else None,
-                                      grad_pair_m=gpm.contiguous() if gpm is not None else None, coords=ctx.coords,
-                                      total=total)
+                                      grad_pair_m=gpm.contiguous() if gpm is not None else None, coords=ctx.coords)
         return (None, None, None) + tuple(gp)
 
 
