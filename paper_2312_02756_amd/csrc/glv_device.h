@@ -278,9 +278,10 @@ __device__ __forceinline__ void add4(const T a[4], const T b[4], T w[4]) {
 template <typename T>
 __device__ __forceinline__ T mass_of(const T w[4]) {
   T q = w[3] * w[3] - w[0] * w[0] - w[1] * w[1] - w[2] * w[2];
-  // one square root of |q|, then the sign (a zero q gives +0)
-  T m = d_sqrt(d_abs(q));
-  return (q < T(0)) ? -m : m;
+  // one square root of |q|, then q's sign bit (one instruction).  q is never
+  // -0: E^2 is +0 or positive and each product subtracted after it leaves
+  // +0 where it cancels exactly, so a zero q still gives +0.
+  return __builtin_copysign(d_sqrt(d_abs(q)), q);
 }
 
 // 1/sqrt(a) for a > 0: the hardware reciprocal square root (relative error
