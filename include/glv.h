@@ -391,8 +391,8 @@ glv_status glv_event_reduce_bwd(glv_dtype dtype, glv_coords coords, int64_t n_ev
  * total[4] holds each event's total 4-vector as glv_event_reduce wrote it for
  * these particles, in dtype, n_events entries per column, so that the
  * event-mass term g_m dm(V)/dV takes V from it instead of summing the event's
- * particles again -- what a caller that saved the forward's outputs (as
- * autograd does) can pass.  The forward sums an event in the same order and
+ * particles again -- for a caller that kept the forward's outputs.  The
+ * forward sums an event in the same order and
  * precision as the backward would, so the result is bitwise that of
  * glv_event_reduce_bwd wherever both staged the event (an event beyond the
  * staging capacity of either is summed in another order).  total is read
