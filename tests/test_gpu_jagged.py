@@ -153,6 +153,43 @@ def test_tilings_give_identical_pair_masses_and_totals():
             assert np.array_equal(host(pm1), ref), tiling
 
 
+def _quad_order_total(x):
+    """((P0 + P1) + (P2 + P3)) in binary64, P_r the index-order sum of the
+    event's values whose index is r mod 4: the documented order of the GPU's
+    event totals."""
+    parts = []
+    for r in range(4):
+        acc = 0.0
+        for v in x[r::4]:
+            acc = acc + float(v)
+        parts.append(acc)
+    return (parts[0] + parts[1]) + (parts[2] + parts[3])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_event_totals_follow_the_documented_order(dtype):
+    """Cartesian inputs (staged as given), events of 0 to 64 particles: every
+    total is bitwise the four residue-class sums combined as documented (FP32
+    data summed in binary64, then rounded), for two tilings."""
+    g = synth.rng(741)
+    counts = np.concatenate([np.minimum(g.poisson(9, 3000), 64), [0, 1, 2, 3, 4, 5, 63, 64]]).astype(np.int64)
+    off = np.zeros(counts.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    n = int(off[-1])
+    # cancellation-prone sums: mixed signs and magnitudes
+    cols = [g.standard_normal(n) * np.exp(g.uniform(-8, 8, n)) for _ in range(4)]
+    pg = gpu(cols, dtype)
+    vals = [host(c).astype(np.float64) for c in pg]
+    for tiling in (None, (128, 16, 128, 256)):
+        total, _, _ = glv.glv_event_reduce(pg, _off(off), coords="PxPyPzE", want_event_m=False, want_pair_m=False,
+                                           tiling=tiling)
+        got = [host(t) for t in total]
+        for k in range(4):
+            want = np.array([_quad_order_total(vals[k][off[e]:off[e + 1]]) for e in range(counts.size)])
+            want = want.astype(np.float32) if dtype == torch.float32 else want
+            assert np.array_equal(got[k], want), (tiling, k)
+
+
 def test_event_reduce_full_size_sampled():
     """2^20 events (Poisson(8), clipped at 64) in the benchmark's launch shape;
     a sample of events checked against the oracle, every pair of each."""
