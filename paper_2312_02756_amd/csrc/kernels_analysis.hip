@@ -13,9 +13,12 @@ constexpr int kHistBlock = 1024;
 // fewer global atomics on each bin.
 constexpr int64_t kHistGrid = 256;
 constexpr int kHistUnroll = 4;   // value packs in flight per thread
-constexpr int kBestLanes = 8;    // lanes per event in the best-pair kernel
-constexpr int kBestBlock = 256;  // 32 events per workgroup
-constexpr int kBestUnroll = 4;   // pair loads in flight per lane
+// Best pair: four lanes per event with eight pair loads in flight each (a
+// wavefront covers 16 events and reads an average event in one step): 79 ->
+// 70 us on 2^20 Poisson(8) events against eight lanes with four loads.
+constexpr int kBestLanes = 4;    // lanes per event in the best-pair kernel
+constexpr int kBestBlock = 256;  // 64 events per workgroup
+constexpr int kBestUnroll = 8;   // pair loads in flight per lane
 
 // Counts one value: the in-range bins by LDS atomics, the under- and
 // overflow in the lane's registers.  Values outside [lo, hi) all land on two
