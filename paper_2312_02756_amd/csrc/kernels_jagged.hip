@@ -1341,21 +1341,22 @@ __device__ __forceinline__ bool bwd_big(int64_t n, int cap, int qcap, bool pairs
 //     n takes the partners a + 1, ..., a + d cyclically, d = (n - 1) / 2
 //     rounded down, plus a + n/2 when n is even and a < n/2 -- every pair
 //     once, about n/2 per particle, whatever the particle's place;
-//   * in the same phase one lane per event (spread over the wavefronts; its
-//     g_total and g_m were loaded with the chunk) sums the event's vectors V
-//     as the forward does (or takes the forward's totals) and stages
-//     g_total + g_m dm(V)/dV, the upstream every
-//     particle of the event receives from the event outputs;
-//   * thread t then walks its event's particles in CSR order and adds the
-//     pair terms c_ij (v_i + v_j) = c_ij v_i + c_ij v_j of its partners
-//     (dm(w)/dw = (-P, E) / |m|, the same 4-vector for both legs of a pair),
-//     stepping the pair indices incrementally, then the event's upstream, and
-//     applies its own conversion Jacobian.
-// Every sum has a fixed order and no atomics are needed.
+//   * in the same phase a quad of threads per event sums the event's vectors
+//     V as the forward does (or the event's lane, which loaded its g_total
+//     and g_m with the chunk, takes V from the forward's totals), and
+//     g_total + g_m dm(V)/dV, the upstream every particle of the event
+//     receives from the event outputs, is staged;
+//   * thread t sums the pair terms c_ij (v_i + v_j) = c_ij v_i + c_ij v_j
+//     (dm(w)/dw = (-P, E) / |m|, the same 4-vector for both legs of a pair)
+//     of its own pairs while evaluating them, then walks the partners that
+//     evaluated its other pairs (b = a - d cyclically, stepping the pair
+//     indices incrementally), adds the event's upstream and applies its own
+//     conversion Jacobian.
+// Every sum has a fixed order and no atomics are needed.  Six wavefronts per
+// SIMD (what the LDS of the default tiling allows): the compiler keeps the
+// registers within that (a few bytes spilled in FP64), 318 -> 309 us on 2^20
+// events against its own choice of five.
 template <typename T, int COORDS>
-// Six wavefronts per SIMD (what the LDS of the default tiling allows): the
-// compiler keeps the registers within that (a few bytes spilled in FP64),
-// 318 -> 309 us on 2^20 events against its own choice of five.
 __global__ __launch_bounds__(kMaxBlock, 6) void k_event_reduce_bwd(BwdArgs<T, COORDS> A) {
   extern __shared__ __align__(32) unsigned char lds[];
   using R4 = typename V4<T>::type;
