@@ -317,7 +317,7 @@ glv_status glv_event_best_pair(glv_dtype dtype, int64_t n_events, const int64_t*
  * without a chosen pair).
  *   offsets, pair_offsets (required), p, tiling, fallback_count
  *                 as in glv_event_reduce; fields set to 0 take this
- *                 call's built-in default (64, 64, 128, 512), not the
+ *                 call's built-in default (64, 64, 128, 1024), not the
  *                 autotuned choice of glv_event_reduce
  * The outputs must not overlap each other, the offsets or the particle
  * columns (GLV_EINVAL_ALIAS).  Errors as glv_event_reduce, and
