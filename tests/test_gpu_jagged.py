@@ -190,6 +190,28 @@ def test_event_totals_follow_the_documented_order(dtype):
             assert np.array_equal(got[k], want), (tiling, k)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_tiny_events_take_several_total_passes(dtype):
+    """Events of 0 to 6 particles: a chunk then holds up to 64 events, whose
+    totals take four passes of 16 quads; the totals keep the documented order
+    and the compensated event masses (sum of M^2 handed from each pass's
+    quads to the event lanes) stay within the oracle's bound."""
+    off, p = _events(4000, 742, mean=1.5, cap=6)
+    pg, og = gpu(p, dtype), _off(off)
+    for tiling in (None, (128, 64, 128, 256), (64, 64, 256, 128)):
+        total, em, pm = glv.glv_event_reduce(pg, og, mode="compensated", tiling=tiling)
+        _check_forward(off, p, dtype, "PtEtaPhiM", "compensated", total, em, pm, f"tiny comp {dtype} {tiling}")
+    c = oracle.to_cartesian("PtEtaPhiM", widened(p, dtype))
+    cg = gpu(c, dtype)
+    vals = [host(x).astype(np.float64) for x in cg]
+    total, _, _ = glv.glv_event_reduce(cg, og, coords="PxPyPzE", want_event_m=False, want_pair_m=False,
+                                       tiling=(128, 64, 128, 256))
+    for k in range(4):
+        want = np.array([_quad_order_total(vals[k][off[e]:off[e + 1]]) for e in range(off.size - 1)])
+        want = want.astype(np.float32) if dtype == torch.float32 else want
+        assert np.array_equal(host(total[k]), want), k
+
+
 def test_event_reduce_full_size_sampled():
     """2^20 events (Poisson(8), clipped at 64) in the benchmark's launch shape;
     a sample of events checked against the oracle, every pair of each."""
